@@ -1,0 +1,197 @@
+"""ctypes wrapper of the C oracle (test infrastructure only).
+
+Every function takes numpy arrays and returns numpy arrays / Python ints. Maps
+are passed to C as FP64 copies: Y complex [T][F] -> interleaved (re, im)
+doubles, sigma -> doubles (exact widening of FP32 inputs).
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+
+import numpy as np
+
+from .build import build, lib_path
+
+NORM_SQRT_N = 0
+NORM_N = 1
+FBITS = 8  # control frequencies are in units of 1/256 row
+DTAU_UNIT_S = 2.0 ** -28  # time delays are integers in units of 2^-28 s
+
+TRACK_DTYPE = np.dtype([("t0", "<i4"), ("t2", "<i4"), ("f0", "<u4"), ("f1", "<u4"),
+                        ("f2", "<u4"), ("dtau", "<i4")])
+
+
+class _Track(C.Structure):
+    _fields_ = [("t0", C.c_int32), ("t2", C.c_int32), ("f0", C.c_uint32), ("f1", C.c_uint32),
+                ("f2", C.c_uint32), ("dtau", C.c_int32)]
+
+
+class _Map(C.Structure):
+    _fields_ = [("Y", C.c_void_p), ("sigma", C.c_void_p), ("T", C.c_int32), ("F", C.c_int32),
+                ("ld", C.c_int64), ("fq4_lo", C.c_int32), ("dfq4", C.c_int32)]
+
+
+_lib = None
+
+
+def lib():
+    global _lib
+    if _lib is None:
+        path = lib_path()
+        if not os.path.exists(path):
+            build()
+        L = C.CDLL(path)
+        u32p = np.ctypeslib.ndpointer(np.uint32, flags="C_CONTIGUOUS")
+        L.orc_philox4x32_10.argtypes = [u32p, u32p, u32p]
+        L.orc_philox4x32_10.restype = None
+        L.orc_npairs.argtypes = [C.c_int32, C.c_int32]
+        L.orc_npairs.restype = C.c_int64
+        L.orc_unrank.argtypes = [C.c_uint64, C.c_int32, C.POINTER(C.c_int32), C.POINTER(C.c_int32)]
+        L.orc_unrank.restype = None
+        L.orc_draw.argtypes = [C.c_uint64, C.c_uint32, C.c_uint64, C.c_int32, C.c_int32, C.c_int32,
+                               C.c_int32, C.POINTER(_Track)]
+        L.orc_draw.restype = C.c_int
+        L.orc_rows.argtypes = [C.POINTER(_Track), C.c_int32, C.c_void_p]
+        L.orc_rows.restype = C.c_int
+        L.orc_phase_turns.argtypes = [C.c_int64, C.c_int32]
+        L.orc_phase_turns.restype = C.c_double
+        L.orc_score.argtypes = [C.POINTER(_Map), C.POINTER(_Track), C.c_int32]
+        L.orc_score.restype = C.c_double
+        L.orc_score_gen.argtypes = [C.POINTER(_Map), C.c_uint64, C.c_uint32, C.c_int32, C.c_int32,
+                                    C.c_uint64, C.c_int64, C.c_int32, C.c_void_p]
+        L.orc_score_gen.restype = C.c_int
+        L.orc_score_gen_idx.argtypes = [C.POINTER(_Map), C.c_uint64, C.c_uint32, C.c_int32, C.c_int32,
+                                        C.c_void_p, C.c_int64, C.c_int32, C.c_void_p]
+        L.orc_score_gen_idx.restype = C.c_int
+        L.orc_score_list.argtypes = [C.POINTER(_Map), C.c_void_p, C.c_int64, C.c_int32, C.c_void_p]
+        L.orc_score_list.restype = C.c_int
+        L.orc_argmax.argtypes = [C.c_void_p, C.c_int64]
+        L.orc_argmax.restype = C.c_int64
+        _bind_ext(L)
+        _lib = L
+    return _lib
+
+
+def _bind_ext(L):
+    """Bind the extension entry points when present (top-K, FP16 emulation, bilinear)."""
+    if hasattr(L, "orc_topk"):
+        L.orc_topk.argtypes = [C.c_void_p, C.c_int64, C.c_int32, C.c_void_p]
+        L.orc_topk.restype = C.c_int
+
+
+# --------------------------------------------------------------------------- primitives
+
+def philox4x32_10(ctr, key) -> np.ndarray:
+    c = np.ascontiguousarray(np.asarray(ctr, dtype=np.uint32).reshape(4))
+    k = np.ascontiguousarray(np.asarray(key, dtype=np.uint32).reshape(2))
+    out = np.zeros(4, dtype=np.uint32)
+    lib().orc_philox4x32_10(c, k, out)
+    return out
+
+
+def npairs(T: int, L: int) -> int:
+    return int(lib().orc_npairs(T, L))
+
+
+def unrank(k: int, L: int) -> tuple[int, int]:
+    a, b = C.c_int32(), C.c_int32()
+    lib().orc_unrank(k, L, C.byref(a), C.byref(b))
+    return a.value, b.value
+
+
+def dtau_units(dtau_max_s: float) -> int:
+    """Delay bound in 2^-28 s units, rounded to nearest (10 ms -> 2684355)."""
+    return int(round(dtau_max_s / DTAU_UNIT_S))
+
+
+def draw(seed: int, stream: int, j: int, T: int, F: int, L: int, D: int) -> np.ndarray:
+    t = _Track()
+    if lib().orc_draw(seed, stream, j, T, F, L, D, C.byref(t)) != 0:
+        raise ValueError("invalid draw parameters")
+    out = np.zeros((), dtype=TRACK_DTYPE)
+    for name in TRACK_DTYPE.names:
+        out[name] = getattr(t, name)
+    return out
+
+
+def draw_many(seed: int, stream: int, first: int, n: int, T: int, F: int, L: int, D: int) -> np.ndarray:
+    out = np.zeros(n, dtype=TRACK_DTYPE)
+    t = _Track()
+    fn = lib().orc_draw
+    for i in range(n):
+        if fn(seed, stream, first + i, T, F, L, D, C.byref(t)) != 0:
+            raise ValueError("invalid draw parameters")
+        out[i] = (t.t0, t.t2, t.f0, t.f1, t.f2, t.dtau)
+    return out
+
+
+def _as_track(tr) -> _Track:
+    tr = np.asarray(tr, dtype=TRACK_DTYPE)
+    return _Track(int(tr["t0"]), int(tr["t2"]), int(tr["f0"]), int(tr["f1"]), int(tr["f2"]),
+                  int(tr["dtau"]))
+
+
+def rows(tr, F: int) -> np.ndarray:
+    t = _as_track(tr)
+    N = t.t2 - t.t0 + 1
+    out = np.zeros(max(N, 1), dtype=np.int32)
+    if lib().orc_rows(C.byref(t), F, out.ctypes.data) != N:
+        raise ValueError("invalid track")
+    return out[:N]
+
+
+def phase_turns(fq4: int, dtau: int) -> float:
+    return float(lib().orc_phase_turns(fq4, dtau))
+
+
+# --------------------------------------------------------------------------- maps and scores
+
+class Map:
+    """FP64 copy of a (Y, sigma) map for the oracle; keeps the buffers alive."""
+
+    def __init__(self, Y: np.ndarray, sigma: np.ndarray, fq4_lo: int = 1600, dfq4: int = 16):
+        Y = np.asarray(Y)
+        sigma = np.asarray(sigma)
+        if Y.ndim != 2 or Y.shape != sigma.shape:
+            raise ValueError("Y and sigma must be [T][F] arrays of the same shape")
+        self.T, self.F = Y.shape
+        self.Yd = np.ascontiguousarray(Y.astype(np.complex128)).view(np.float64)
+        self.sd = np.ascontiguousarray(sigma.astype(np.float64))
+        self.fq4_lo, self.dfq4 = int(fq4_lo), int(dfq4)
+        self.c = _Map(self.Yd.ctypes.data, self.sd.ctypes.data, self.T, self.F, self.F,
+                      self.fq4_lo, self.dfq4)
+
+
+def score(m: Map, tr, norm: int = NORM_SQRT_N) -> float:
+    t = _as_track(tr)
+    return float(lib().orc_score(C.byref(m.c), C.byref(t), norm))
+
+
+def score_gen(m: Map, seed: int, stream: int, L: int, D: int, first: int, n: int,
+              norm: int = NORM_SQRT_N) -> np.ndarray:
+    z = np.zeros(n, dtype=np.float64)
+    if lib().orc_score_gen(C.byref(m.c), seed, stream, L, D, first, n, norm, z.ctypes.data) != 0:
+        raise ValueError("invalid parameters")
+    return z
+
+
+def score_gen_idx(m: Map, seed: int, stream: int, L: int, D: int, idx, norm: int = NORM_SQRT_N) -> np.ndarray:
+    idx = np.ascontiguousarray(np.asarray(idx, dtype=np.uint64))
+    z = np.zeros(idx.size, dtype=np.float64)
+    if lib().orc_score_gen_idx(C.byref(m.c), seed, stream, L, D, idx.ctypes.data, idx.size, norm,
+                               z.ctypes.data) != 0:
+        raise ValueError("invalid parameters")
+    return z
+
+
+def score_list(m: Map, tracks: np.ndarray, norm: int = NORM_SQRT_N) -> np.ndarray:
+    tracks = np.ascontiguousarray(np.asarray(tracks, dtype=TRACK_DTYPE))
+    z = np.zeros(tracks.size, dtype=np.float64)
+    lib().orc_score_list(C.byref(m.c), tracks.ctypes.data, tracks.size, norm, z.ctypes.data)
+    return z
+
+
+def argmax(z: np.ndarray) -> int:
+    z = np.ascontiguousarray(np.asarray(z, dtype=np.float64))
+    return int(lib().orc_argmax(z.ctypes.data, z.size))
