@@ -1,0 +1,161 @@
+/*
+ * stt.h -- C ABI of libstt, an MI355X (gfx950) implementation of the template
+ * search of "all-sky stochtrack" (Thrane & Coughlin, arXiv:1401.8060): very
+ * many random quadratic-Bezier tracks are scored on a complex cross-power
+ * ft-map with the random-phase-factor statistic of Eq. 8 and reduced by
+ * max/argmax (Sec. III; Sec. V records the maximum per spectrogram).
+ *
+ * Conventions shared by every entry point
+ * ---------------------------------------
+ *  - Ownership: every bulk buffer is caller-owned DEVICE memory (for example
+ *    a torch tensor's data pointer). The library never frees it and touches it
+ *    only in work it enqueues. Host-side arguments (structs, small arrays
+ *    marked "host") are read before the call returns.
+ *  - Streams: work is enqueued asynchronously on the context's stream and is
+ *    ordered after earlier work on that stream. Results are valid once the
+ *    stream has been synchronised (stt_sync, or the caller's own sync).
+ *  - Errors: argument, shape and range errors are detected on the host before
+ *    anything is enqueued and returned as a negative stt_status; nothing is
+ *    written then. HIP launch failures return STT_EHIP. Device-side faults
+ *    surface at the next synchronisation. stt_last_error() gives a message.
+ *  - Threads: a context is not thread-safe; use one context per host thread.
+ *  - Map layout: pixel (t, r) -- time column t in [0, T), frequency row r in
+ *    [0, F) -- sits at element t*ld + r (time-major, frequency contiguous).
+ *    Row r has frequency (fq4_lo + r*dfq4)/16 Hz.
+ *  - Template (track) format, a reading of Eq. 6 with t_mid at the midpoint:
+ *    the track covers columns t0..t2 (N = t2-t0+1 pixels, one per column).
+ *    Column t0+k takes row floor(B(k/(t2-t0))/256) where B is the quadratic
+ *    Bezier through the control frequencies f0, f1, f2 given in 1/256-row
+ *    units; the floor is exact (integer arithmetic). dtau is the template's
+ *    time delay (Eq. 8) in units of 2^-28 s.
+ *  - Statistic (Eq. 8, with the complex SNR p = Y/sigma of Eq. 7 and the
+ *    appendix): S = sum over the N pixels of Re[exp(2 pi i f dtau) Y/sigma];
+ *    z = S/sqrt(N) (STT_NORM_SQRT_N, standard normal on noise) or S/N
+ *    (STT_NORM_N, the paper's literal 1/N).
+ *  - Best key: a 64-bit word (ordered bits of the FP32 score << 32) |
+ *    (0xFFFFFFFF - j) where j is the track index. A larger key is a higher
+ *    score, then a lower index. NaN scores count as -inf, -0 as +0. Every
+ *    real key is > 0, so a buffer initialised to 0 means "empty"; entry points
+ *    that take best_key_dev max-merge into it (never overwrite), which is the
+ *    paper's Sec. V combination of runs by their maximum.
+ */
+#ifndef STT_H
+#define STT_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef int32_t stt_status;
+#define STT_OK 0
+#define STT_EINVAL (-1)      /* bad argument: null pointer, bad enum, bad shape */
+#define STT_ERANGE (-2)      /* size outside the supported range */
+#define STT_ENOMEM (-3)      /* device allocation of internal scratch failed */
+#define STT_EHIP (-4)        /* a HIP runtime call failed */
+#define STT_EUNSUPPORTED (-5) /* valid request this build does not support */
+
+#define STT_NORM_SQRT_N 0
+#define STT_NORM_N 1
+
+#define STT_C64F32 0 /* Y: complex64 (re, im float32 interleaved); sigma: float32 */
+#define STT_C16F16 1 /* Y: FP16 (re, im) pairs scaled by 2^-scale_exp; sigma slot: FP16 1/sigma */
+
+#define STT_FBITS 8        /* fractional bits of control frequencies */
+#define STT_MAX_T 2896     /* largest map duration (columns) */
+#define STT_MAX_F 32767    /* largest map bandwidth (rows) */
+
+typedef struct {
+    int32_t t0, t2;       /* first and last column, 0 <= t0 < t2 < T */
+    uint32_t f0, f1, f2;  /* control frequencies, 1/256-row units, < F*256 */
+    int32_t dtau;         /* time delay, units of 2^-28 s */
+} stt_track;              /* 24 bytes */
+
+typedef struct {
+    uint64_t seed;     /* Philox4x32-10 key (low word, high word) */
+    uint32_t stream;   /* Philox counter word 2: an independent sequence per map */
+    int32_t min_len;   /* L: minimum pixels per track (the paper's t_min), >= 2 */
+    int32_t dtau_max;  /* delays are uniform on [-dtau_max, dtau_max], 2^-28 s units; 0 = targeted (Eq. 5) */
+    int32_t reserved;  /* must be 0 */
+} stt_gen;
+
+typedef struct {
+    int32_t T, F;         /* columns, rows */
+    int64_t ld;           /* elements between columns, ld >= F */
+    int32_t dtype;        /* STT_C64F32 or STT_C16F16 */
+    int32_t scale_exp;    /* STT_C16F16 only: Y = stored * 2^scale_exp */
+    const void *Y;        /* device: [T][ld] complex */
+    const void *sigma;    /* device: [T][ld] sigma (C64F32) or 1/sigma (C16F16) */
+    int32_t fq4_lo;       /* frequency of row 0 in 1/16 Hz (1600 = 100 Hz) */
+    int32_t dfq4;         /* row spacing in 1/16 Hz (16 = 1 Hz) */
+} stt_map;
+
+typedef struct stt_ctx stt_ctx;
+
+/* Lifecycle. stt_create binds the context to HIP device `device` and to the
+ * stream `hip_stream` (a hipStream_t; NULL = the device's null stream), which
+ * the context borrows and never destroys. The context owns only its internal
+ * scratch memory. Returns STT_EHIP if the device cannot be selected. */
+stt_status stt_create(int device, void *hip_stream, stt_ctx **out);
+stt_status stt_destroy(stt_ctx *ctx);
+stt_status stt_set_stream(stt_ctx *ctx, void *hip_stream);
+stt_status stt_sync(stt_ctx *ctx);
+const char *stt_strerror(stt_status s);
+const char *stt_last_error(const stt_ctx *ctx);
+
+/* Pre-size internal scratch for calls of up to max_tracks tracks, so that
+ * later calls of that size allocate nothing. */
+stt_status stt_reserve(stt_ctx *ctx, int64_t max_tracks);
+
+/* Kernel timing. When on, the context records HIP events around its stages
+ * on its stream: `which` = 0 scoring kernel, 1 binning kernels, 2 whole call.
+ * stt_kernel_ms gives the last call's stage time; stt_kernel_ms_total sums the
+ * stage over every call since timing was switched on or last totalled (and
+ * forgets them). Both synchronise the stream. stt_set_timing resets. */
+stt_status stt_set_timing(stt_ctx *ctx, int32_t on);
+stt_status stt_kernel_ms(stt_ctx *ctx, int32_t which, float *ms);
+stt_status stt_kernel_ms_total(stt_ctx *ctx, int32_t which, double *total_ms, int32_t *count);
+
+/* Scorer selection, for tests and tuning: path 0 = automatic, 1 = direct
+ * gathers from global memory, 2 = LDS time slabs (STT_EUNSUPPORTED when one
+ * column of the map does not fit lds_bytes). lds_bytes (0 = keep) is the slab
+ * budget per workgroup, in [1024, 163840]; default 81920 (two per CU). */
+stt_status stt_set_path(stt_ctx *ctx, int32_t path, int32_t lds_bytes);
+
+/* Template generation (Sec. III: each template from six random numbers plus
+ * a random delay, before Eq. 8). Writes out_dev[i] = track j = first + i for
+ * i in [0, n): Philox4x32-10 with key = seed, counter = (j, stream, b) for
+ * blocks b = 0, 1; the time extent is uniform over the pairs (t0, t2) with
+ * t2 - t0 + 1 >= min_len, the control frequencies are uniform on [0, F) and
+ * the delay uniform on the integers [-dtau_max, dtau_max]. Requires
+ * 2 <= min_len <= T <= STT_MAX_T, 1 <= F <= STT_MAX_F, 0 <= dtau_max < 2^30,
+ * first + n <= 2^32. n = 0 is a no-op. */
+stt_status stt_make_tracks(stt_ctx *ctx, const stt_gen *gen, int32_t T, int32_t F, int64_t first,
+                           int64_t n, stt_track *out_dev);
+
+/* Score tracks on one map (Eq. 8) and reduce them (Sec. III, Sec. V).
+ * Tracks are either generated (tracks_dev == NULL: j = first + i drawn as by
+ * stt_make_tracks with `gen`) or given (tracks_dev[i] has index j = first + i;
+ * `gen` may then be NULL). For i in [0, n): if snr_dev is non-NULL,
+ * snr_dev[i] = z_j (FP32); if best_key_dev is non-NULL, *best_key_dev is
+ * max-merged with the best key over the n tracks. Given tracks are validated
+ * on the device: an out-of-range track scores NaN (never wins). Requires
+ * first + n <= 2^32 and a valid map (T, F within range, ld >= F). */
+stt_status stt_score(stt_ctx *ctx, const stt_map *map, const stt_gen *gen, const stt_track *tracks_dev,
+                     int64_t first, int64_t n, int32_t norm, float *snr_dev, uint64_t *best_key_dev);
+
+/* Max/argmax over an existing score array: *best_key_dev is max-merged with
+ * the best key over snr_dev[0..n), the index of element i being first + i. */
+stt_status stt_argmax(stt_ctx *ctx, const float *snr_dev, int64_t n, int64_t first,
+                      uint64_t *best_key_dev);
+
+/* Host helpers for the key format (no device work). */
+uint64_t stt_key_encode(float z, uint32_t j);
+void stt_key_decode(uint64_t key, float *z, uint32_t *j);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* STT_H */

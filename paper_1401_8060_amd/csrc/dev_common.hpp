@@ -1,0 +1,208 @@
+// dev_common.hpp -- arithmetic shared by the libstt kernels (gfx950).
+//
+// Everything here is __host__ __device__ so that the host-side unit tests can
+// exercise the exact same integer code the kernels run (generator, unranking,
+// DDA rasteriser, phase) against the independent CPU reference.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace stt {
+
+#define STT_HD __host__ __device__ __forceinline__
+
+// ----------------------------------------------------------------------------
+// Philox4x32-10 (Salmon, Moraes, Dror, Shaw, SC'11): counter-based, so track j
+// is a pure function of (seed, stream, j) -- any index range can be scored on
+// any device in any order and runs merge by a max (paper, Sec. V).
+// ----------------------------------------------------------------------------
+STT_HD uint32_t mulhi32(uint32_t a, uint32_t b) { return (uint32_t)(((uint64_t)a * b) >> 32); }
+
+// floor(a * b / 2^64), exact, from four 32x32 -> 64 products.
+STT_HD uint64_t mulhi64(uint64_t a, uint64_t b)
+{
+    const uint64_t al = (uint32_t)a, ah = a >> 32, bl = (uint32_t)b, bh = b >> 32;
+    const uint64_t p0 = al * bl, p1 = al * bh, p2 = ah * bl, p3 = ah * bh;
+    const uint64_t mid = (p0 >> 32) + (uint32_t)p1 + (uint32_t)p2;
+    return p3 + (p1 >> 32) + (p2 >> 32) + (mid >> 32);
+}
+
+struct u32x4 { uint32_t x, y, z, w; };
+
+STT_HD u32x4 philox4x32_10(u32x4 c, uint32_t k0, uint32_t k1)
+{
+#pragma unroll
+    for (int r = 0; r < 10; ++r) {
+        if (r) { k0 += 0x9E3779B9u; k1 += 0xBB67AE85u; }
+        const uint32_t lo0 = 0xD2511F53u * c.x, hi0 = mulhi32(0xD2511F53u, c.x);
+        const uint32_t lo1 = 0xCD9E8D57u * c.z, hi1 = mulhi32(0xCD9E8D57u, c.z);
+        c = u32x4{hi1 ^ c.y ^ k0, lo1, hi0 ^ c.w ^ k1, lo0};
+    }
+    return c;
+}
+
+// A template: columns t0..t2, control frequencies in 1/256-row units, delay in
+// 2^-28 s units. Same layout as stt_track in the public header.
+struct Trk {
+    int32_t t0, t2;
+    uint32_t f0, f1, f2;
+    int32_t dtau;
+};
+
+// Parameters of the random template law, precomputed on the host.
+struct GenP {
+    uint32_t key0, key1;  // Philox key = seed
+    uint32_t stream;      // counter word 2
+    uint32_t npairs;      // number of (t0, t2) pairs with >= L pixels
+    int32_t L;            // minimum pixels
+    uint32_t frange;      // F << 8
+    int32_t dmax;         // delay bound (2^-28 s units)
+    uint32_t dspan;       // 2*dmax + 1
+};
+
+// Pair number k -> (t0, t2): pairs ordered by t2 then t0, i.e. k = e(e+1)/2 + a
+// with t2 = e + L - 1, t0 = a, 0 <= a <= e. The float square root is within
+// one of the exact integer square root for k < 2^26; two exact integer
+// comparisons fix it.
+STT_HD void unrank_pair(uint32_t k, int32_t L, int32_t &t0, int32_t &t2)
+{
+    uint32_t e = (uint32_t)((sqrtf(8.0f * (float)k + 1.0f) - 1.0f) * 0.5f);
+    if ((uint64_t)e * (e + 1) / 2 > k) --e;
+    if ((uint64_t)(e + 1) * (e + 2) / 2 <= k) ++e;
+    t0 = (int32_t)(k - e * (e + 1) / 2);
+    t2 = (int32_t)e + L - 1;
+}
+
+STT_HD u32x4 philox_block(const GenP &g, uint64_t j, uint32_t b)
+{
+    return philox4x32_10(u32x4{(uint32_t)j, (uint32_t)(j >> 32), g.stream, b}, g.key0, g.key1);
+}
+
+// Time extent only (block 0): what the binning pass needs.
+STT_HD void draw_extent(const GenP &g, uint64_t j, int32_t &t0, int32_t &t2)
+{
+    const u32x4 x = philox_block(g, j, 0);
+    const uint64_t u = ((uint64_t)x.x << 32) | x.y;
+    unrank_pair((uint32_t)mulhi64(u, g.npairs), g.L, t0, t2);
+}
+
+STT_HD Trk draw_track(const GenP &g, uint64_t j)
+{
+    const u32x4 x0 = philox_block(g, j, 0);
+    const u32x4 x1 = philox_block(g, j, 1);
+    Trk t;
+    const uint64_t u = ((uint64_t)x0.x << 32) | x0.y;
+    unrank_pair((uint32_t)mulhi64(u, g.npairs), g.L, t.t0, t.t2);
+    t.f0 = mulhi32(x0.z, g.frange);
+    t.f1 = mulhi32(x0.w, g.frange);
+    t.f2 = mulhi32(x1.x, g.frange);
+    const uint64_t u2 = ((uint64_t)x1.y << 32) | x1.z;
+    t.dtau = (int32_t)((int64_t)mulhi64(u2, g.dspan) - g.dmax);
+    return t;
+}
+
+// ----------------------------------------------------------------------------
+// Exact rasteriser of Eq. 6 as a second-order DDA.
+// With Dt = t2 - t0 and k = 0..Dt, row(k) = floor(num(k) / Q) where
+//   num(k) = (Dt-k)^2 f0 + 2 (Dt-k) k f1 + k^2 f2 = A + B k + C k^2,
+//   A = Dt^2 f0, B = 2 Dt (f1 - f0), C = f0 - 2 f1 + f2, Q = Dt^2 * 256.
+// num(k+1) - num(k) = B + C (2k + 1) =: Delta_k and Delta_{k+1} - Delta_k = 2C.
+// The state keeps num(k) = row*Q + rem and Delta_k = dq*Q + dr with
+// 0 <= rem, dr < Q (floor division), so one step is two carry-propagating
+// adds of 32-bit quantities. Q < 2^31 for Dt <= 2895 keeps every sum < 2^32.
+// ----------------------------------------------------------------------------
+struct Dda {
+    int32_t row;
+    uint32_t rem;
+    int32_t dq;
+    uint32_t dr;
+    int32_t ddq;
+    uint32_t ddr;
+    uint32_t Q;
+};
+
+STT_HD void floor_divmod(int64_t a, uint32_t q, int32_t &quo, uint32_t &rem)
+{
+    int64_t d = a / (int64_t)q;
+    int64_t r = a - d * (int64_t)q;
+    if (r < 0) { r += q; --d; }
+    quo = (int32_t)d;
+    rem = (uint32_t)r;
+}
+
+STT_HD Dda dda_init(const Trk &t)
+{
+    Dda s;
+    const uint32_t Dt = (uint32_t)(t.t2 - t.t0);
+    const uint32_t D2 = Dt * Dt;
+    s.Q = D2 << 8;
+    s.row = (int32_t)(t.f0 >> 8);
+    s.rem = D2 * (t.f0 & 255u);
+    const int64_t C = (int64_t)t.f0 - 2 * (int64_t)t.f1 + (int64_t)t.f2;
+    const int64_t B = 2 * (int64_t)Dt * ((int64_t)t.f1 - (int64_t)t.f0);
+    floor_divmod(B + C, s.Q, s.dq, s.dr);
+    floor_divmod(2 * C, s.Q, s.ddq, s.ddr);
+    return s;
+}
+
+STT_HD void dda_step(Dda &s)
+{
+    uint32_t r = s.rem + s.dr;
+    const bool c1 = r >= s.Q;
+    s.rem = c1 ? r - s.Q : r;
+    s.row += s.dq + (c1 ? 1 : 0);
+    uint32_t d = s.dr + s.ddr;
+    const bool c2 = d >= s.Q;
+    s.dr = c2 ? d - s.Q : d;
+    s.dq += s.ddq + (c2 ? 1 : 0);
+}
+
+// ----------------------------------------------------------------------------
+// Phase factor of Eq. 8. f dtau = (fq4/16 Hz)(dtau 2^-28 s) = fq4*dtau 2^-32
+// turns, so the phase is the 32-bit wrap of fq4*dtau: exact. Per track,
+// fq4(row) = fq4_lo + row*dfq4, hence phase(row) = pa + row*pb (mod 2^32).
+// ----------------------------------------------------------------------------
+STT_HD uint32_t phase_a(int32_t fq4_lo, int32_t dtau) { return (uint32_t)fq4_lo * (uint32_t)dtau; }
+STT_HD uint32_t phase_b(int32_t dfq4, int32_t dtau) { return (uint32_t)dfq4 * (uint32_t)dtau; }
+
+// Re[exp(2 pi i ph/2^32) (pr + i pi)]. The half-turn bit h = [ph in [1/4,3/4)
+// turn] is split off exactly in integers, leaving |angle| <= pi/2 where the
+// polynomials (near-minimax, from gen_sincos_coeffs.py) are accurate to about
+// 1.5e-7; exp(i pi h) = (-1)^h flips the sign of the result.
+STT_HD float rot_re(uint32_t ph, float pr, float pim)
+{
+    const uint32_t u = ph + 0x40000000u;
+    const uint32_t h = u & 0x80000000u;
+    const int32_t r = (int32_t)(ph - h);  // in [-2^30, 2^30): a quarter turn each side
+    const float x = (float)r * 1.4629180792671596e-9f;  // 2 pi / 2^32
+    const float s = x * x;
+    float ps = 2.634815473e-06f;
+    ps = fmaf(ps, s, -1.982276153e-04f);
+    ps = fmaf(ps, s, 8.333242498e-03f);
+    ps = fmaf(ps, s, -1.666666567e-01f);
+    const float sn = fmaf(x * s, ps, x);
+    float pc = -2.629789719e-07f;
+    pc = fmaf(pc, s, 2.477459748e-05f);
+    pc = fmaf(pc, s, -1.388865174e-03f);
+    pc = fmaf(pc, s, 4.166666046e-02f);
+    pc = fmaf(pc, s, -5.000000000e-01f);
+    const float cs = fmaf(s, pc, 1.0f);
+    const float v = fmaf(cs, pr, -sn * pim);
+    return __builtin_bit_cast(float, __builtin_bit_cast(uint32_t, v) ^ h);
+}
+
+// ----------------------------------------------------------------------------
+// Best-key encoding (see the public header): order-preserving bits of the FP32
+// score in the high word, 0xFFFFFFFF - j in the low word.
+// ----------------------------------------------------------------------------
+STT_HD uint64_t key_encode(float z, uint32_t j)
+{
+    if (z != z) z = -__builtin_huge_valf();
+    if (z == 0.0f) z = 0.0f;
+    const uint32_t b = __builtin_bit_cast(uint32_t, z);
+    const uint32_t o = (b & 0x80000000u) ? ~b : (b | 0x80000000u);
+    return ((uint64_t)o << 32) | (uint64_t)(0xFFFFFFFFu - j);
+}
+
+}  // namespace stt

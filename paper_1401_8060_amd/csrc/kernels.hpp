@@ -1,0 +1,335 @@
+// kernels.hpp -- the libstt device kernels for gfx950 (wave64, 160 KB LDS per CU).
+//
+// Hot path of the template search (paper Sec. III, Eq. 6 and Eq. 8):
+//   k_make_tracks   materialise templates (Philox4x32-10 + exact unranking)
+//   k_bin_count     \  counting sort of templates by (start, end) column bucket,
+//   k_bin_scan       > so that a workgroup's templates cover nearly the same
+//   k_bin_scatter   /  columns and its lanes stay busy through a time sweep
+//   k_score_slab    time-slab scorer: the workgroup stages S columns of the map
+//                   (coalesced along frequency, p = Y/sigma folded on the way)
+//                   into LDS and every lane gathers its templates' pixels there
+//   k_score_direct  one lane per template, pixels gathered straight from the
+//                   map in global memory (small calls, very wide maps)
+//   k_argmax        max/argmax of an existing score array
+// Reductions use the packed 64-bit key (score bits, ~index): wave shuffles,
+// then one 64-bit atomic max per wave, so results do not depend on scheduling.
+#pragma once
+
+#include "dev_common.hpp"
+
+namespace stt {
+
+struct MapP {
+    const float2 *Y;   // [T][ld] complex64
+    const float *sig;  // [T][ld]
+    int32_t T, F;
+    int64_t ld;
+    int32_t fq4_lo, dfq4;
+};
+
+constexpr int kMaxDt = 2895;  // Dt * Dt * 256 < 2^31
+constexpr int kWG = 256;      // threads per workgroup of the scorers
+
+__device__ __forceinline__ bool track_ok(const Trk &t, const MapP &m)
+{
+    const uint32_t frange = (uint32_t)m.F << 8;
+    return t.t0 >= 0 && t.t2 < m.T && t.t2 > t.t0 && t.t2 - t.t0 <= kMaxDt && t.f0 < frange &&
+           t.f1 < frange && t.f2 < frange;
+}
+
+__device__ __forceinline__ uint64_t wave_max_u64(uint64_t v)
+{
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) {
+        const uint64_t o = __shfl_xor(v, off);
+        v = o > v ? o : v;
+    }
+    return v;
+}
+
+__device__ __forceinline__ int wave_min_i32(int v)
+{
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) v = min(v, __shfl_xor(v, off));
+    return v;
+}
+
+__device__ __forceinline__ int wave_max_i32(int v)
+{
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) v = max(v, __shfl_xor(v, off));
+    return v;
+}
+
+__device__ __forceinline__ void merge_key(uint64_t *best, uint64_t key)
+{
+    key = wave_max_u64(key);
+    if (best && (threadIdx.x & 63) == 0 && key) atomicMax((unsigned long long *)best, (unsigned long long)key);
+}
+
+__device__ __forceinline__ float finish(double S, int32_t N, int32_t norm)
+{
+    return (float)(norm == 1 ? S / (double)N : S / sqrt((double)N));
+}
+
+// A fill kernel rather than a memset node, so that captured graphs replay it faithfully.
+__global__ __launch_bounds__(256) void k_fill_u32(uint32_t *p, int64_t n, uint32_t v)
+{
+    const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    if (i < n) p[i] = v;
+}
+
+// ---------------------------------------------------------------- generation
+
+__global__ __launch_bounds__(256) void k_make_tracks(GenP g, uint64_t first, int64_t n, Trk *out)
+{
+    const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    if (i < n) out[i] = draw_track(g, first + (uint64_t)i);
+}
+
+// ---------------------------------------------------------------- direct scorer
+
+template <bool EXPL>
+__global__ __launch_bounds__(kWG) void k_score_direct(MapP m, GenP g, const Trk *tr, uint64_t first, int64_t n,
+                                                      int32_t norm, float *snr, uint64_t *best)
+{
+    const int64_t i = (int64_t)blockIdx.x * kWG + threadIdx.x;
+    uint64_t key = 0;
+    if (i < n) {
+        const Trk t = EXPL ? tr[i] : draw_track(g, first + (uint64_t)i);
+        float z = __builtin_nanf("");
+        if (!EXPL || track_ok(t, m)) {
+            Dda s = dda_init(t);
+            const uint32_t pa = phase_a(m.fq4_lo, t.dtau), pb = phase_b(m.dfq4, t.dtau);
+            const int32_t N = t.t2 - t.t0 + 1;
+            const float2 *Yc = m.Y + (int64_t)t.t0 * m.ld;
+            const float *Sc = m.sig + (int64_t)t.t0 * m.ld;
+            double acc = 0.0;
+            float part = 0.0f;
+            for (int32_t k = 0; k < N; ++k) {
+                const float2 y = Yc[s.row];
+                const float w = 1.0f / Sc[s.row];
+                part += rot_re(pa + (uint32_t)s.row * pb, y.x * w, y.y * w);
+                if ((k & 15) == 15) { acc += part; part = 0.0f; }
+                dda_step(s);
+                Yc += m.ld;
+                Sc += m.ld;
+            }
+            z = finish(acc + part, N, norm);
+        }
+        if (snr) snr[i] = z;
+        key = key_encode(z, (uint32_t)(first + (uint64_t)i));
+    }
+    merge_key(best, key);
+}
+
+// ---------------------------------------------------------------- argmax of an array
+
+__global__ __launch_bounds__(256) void k_argmax(const float *z, int64_t n, uint64_t first, uint64_t *best)
+{
+    uint64_t key = 0;
+    for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < n; i += (int64_t)gridDim.x * 256) {
+        const uint64_t k = key_encode(z[i], (uint32_t)(first + (uint64_t)i));
+        key = k > key ? k : key;
+    }
+    merge_key(best, key);
+}
+
+// ---------------------------------------------------------------- binning by time extent
+// Bucket of a template: b0 = t0 >> wb, b2 = t2 >> wb (b0 <= b2), numbered on
+// the triangle as b2 (b2 + 1) / 2 + b0. Invalid given templates go to bucket 0.
+
+constexpr int kBinPerThread = 32;                 // templates per thread in the sort passes
+constexpr int kBinChunk = 256 * kBinPerThread;    // templates per workgroup
+constexpr int kMaxBins = 64 * 65 / 2;             // at most 64 buckets per axis
+
+template <bool EXPL>
+__device__ __forceinline__ uint32_t bin_of(const GenP &g, const Trk *tr, const MapP &m, uint64_t first, int64_t i,
+                                           int wb)
+{
+    int32_t t0, t2;
+    if (EXPL) {
+        const Trk t = tr[i];
+        if (!track_ok(t, m)) return 0;
+        t0 = t.t0;
+        t2 = t.t2;
+    } else {
+        draw_extent(g, first + (uint64_t)i, t0, t2);
+    }
+    const uint32_t b0 = (uint32_t)t0 >> wb, b2 = (uint32_t)t2 >> wb;
+    return b2 * (b2 + 1) / 2 + b0;
+}
+
+template <bool EXPL>
+__global__ __launch_bounds__(256) void k_bin_count(MapP m, GenP g, const Trk *tr, uint64_t first, int64_t n, int wb,
+                                                   int nbins, uint32_t *totals)
+{
+    __shared__ uint32_t hist[kMaxBins];
+    for (int b = threadIdx.x; b < nbins; b += 256) hist[b] = 0;
+    __syncthreads();
+    const int64_t base = (int64_t)blockIdx.x * kBinChunk;
+    for (int q = 0; q < kBinPerThread; ++q) {
+        const int64_t i = base + q * 256 + threadIdx.x;
+        if (i < n) atomicAdd(&hist[bin_of<EXPL>(g, tr, m, first, i, wb)], 1u);
+    }
+    __syncthreads();
+    for (int b = threadIdx.x; b < nbins; b += 256)
+        if (hist[b]) atomicAdd(&totals[b], hist[b]);
+}
+
+// Exclusive scan of the bucket totals into the scatter cursors (one workgroup).
+__global__ __launch_bounds__(1024) void k_bin_scan(const uint32_t *totals, int nbins, uint32_t *cursor)
+{
+    __shared__ uint32_t part[1024];
+    const int per = (nbins + 1023) / 1024;
+    const int lo = threadIdx.x * per, hi = min(nbins, lo + per);
+    uint32_t s = 0;
+    for (int b = lo; b < hi; ++b) s += totals[b];
+    part[threadIdx.x] = s;
+    __syncthreads();
+    for (int off = 1; off < 1024; off <<= 1) {
+        const uint32_t v = threadIdx.x >= off ? part[threadIdx.x - off] : 0;
+        __syncthreads();
+        part[threadIdx.x] += v;
+        __syncthreads();
+    }
+    uint32_t run = part[threadIdx.x] - s;
+    for (int b = lo; b < hi; ++b) {
+        cursor[b] = run;
+        run += totals[b];
+    }
+}
+
+template <bool EXPL>
+__global__ __launch_bounds__(256) void k_bin_scatter(MapP m, GenP g, const Trk *tr, uint64_t first, int64_t n, int wb,
+                                                     int nbins, uint32_t *cursor, uint32_t *order)
+{
+    __shared__ uint32_t cnt[kMaxBins];
+    for (int b = threadIdx.x; b < nbins; b += 256) cnt[b] = 0;
+    __syncthreads();
+    const int64_t base = (int64_t)blockIdx.x * kBinChunk;
+    uint32_t bin[kBinPerThread], rank[kBinPerThread];
+#pragma unroll
+    for (int q = 0; q < kBinPerThread; ++q) {
+        const int64_t i = base + q * 256 + threadIdx.x;
+        bin[q] = 0;
+        rank[q] = 0;
+        if (i < n) {
+            bin[q] = bin_of<EXPL>(g, tr, m, first, i, wb);
+            rank[q] = atomicAdd(&cnt[bin[q]], 1u);
+        }
+    }
+    __syncthreads();
+    for (int b = threadIdx.x; b < nbins; b += 256)
+        if (cnt[b]) cnt[b] = atomicAdd(&cursor[b], cnt[b]);
+    __syncthreads();
+#pragma unroll
+    for (int q = 0; q < kBinPerThread; ++q) {
+        const int64_t i = base + q * 256 + threadIdx.x;
+        if (i < n) order[cnt[bin[q]] + rank[q]] = (uint32_t)i;
+    }
+}
+
+// ---------------------------------------------------------------- time-slab scorer
+// One workgroup = 256 lanes x TPT templates taken consecutively from the
+// binned order, so they start and end in nearly the same columns. The
+// workgroup sweeps its column range in slabs of S columns: all lanes stage a
+// slab (F rows x S columns of p = Y/sigma, 8 B per pixel) into LDS with
+// coalesced loads, then each lane walks its templates one column at a time,
+// gathering its pixel from LDS, applying the exact phase and accumulating.
+// Per-template partial sums are FP32 within a slab and FP64 across slabs.
+
+template <int TPT, bool EXPL>
+__global__ __launch_bounds__(kWG) void k_score_slab(MapP m, GenP g, const Trk *tr, const uint32_t *order,
+                                                    uint64_t first, int64_t n, int S, int32_t norm, float *snr,
+                                                    uint64_t *best)
+{
+    extern __shared__ float2 slab[];
+    __shared__ int blo, bhi;
+    if (threadIdx.x == 0) { blo = 0x7fffffff; bhi = -1; }
+
+    int32_t t0[TPT];
+    uint32_t span[TPT], pa[TPT], pb[TPT], idx[TPT];
+    bool ok[TPT], live[TPT];
+    Dda st[TPT];
+    float part[TPT];
+    double acc[TPT];
+    int lo = 0x7fffffff, hi = -1;
+    const int64_t base = (int64_t)blockIdx.x * (kWG * TPT);
+#pragma unroll
+    for (int q = 0; q < TPT; ++q) {
+        const int64_t e = base + q * kWG + threadIdx.x;
+        live[q] = e < n;
+        idx[q] = live[q] ? order[e] : 0u;
+        Trk t = EXPL ? tr[live[q] ? idx[q] : 0] : draw_track(g, first + idx[q]);
+        ok[q] = live[q] && (!EXPL || track_ok(t, m));
+        if (!ok[q]) t = Trk{0, 1, 0u, 0u, 0u, 0};  // never active: (c - t0) > span below
+        st[q] = dda_init(t);
+        t0[q] = ok[q] ? t.t0 : 0x7fffffff;
+        span[q] = ok[q] ? (uint32_t)(t.t2 - t.t0) : 0u;
+        pa[q] = phase_a(m.fq4_lo, t.dtau);
+        pb[q] = phase_b(m.dfq4, t.dtau);
+        part[q] = 0.0f;
+        acc[q] = 0.0;
+        if (ok[q]) {
+            lo = min(lo, t.t0);
+            hi = max(hi, t.t2);
+        }
+    }
+    lo = wave_min_i32(lo);
+    hi = wave_max_i32(hi);
+    __syncthreads();
+    if ((threadIdx.x & 63) == 0) {
+        atomicMin(&blo, lo);
+        atomicMax(&bhi, hi);
+    }
+    __syncthreads();
+    const int c_first = blo, c_last = bhi;
+    const int F = m.F;
+
+    for (int c0 = c_first; c0 <= c_last; c0 += S) {
+        const int ncol = min(S, c_last - c0 + 1);
+        __syncthreads();  // the previous slab has been consumed
+        for (int col = 0; col < ncol; ++col) {
+            const float2 *Yc = m.Y + (int64_t)(c0 + col) * m.ld;
+            const float *Sc = m.sig + (int64_t)(c0 + col) * m.ld;
+            float2 *dst = slab + col * F;
+            for (int r = threadIdx.x; r < F; r += kWG) {
+                const float2 y = Yc[r];
+                const float w = 1.0f / Sc[r];
+                dst[r] = make_float2(y.x * w, y.y * w);
+            }
+        }
+        __syncthreads();
+        const int ca = max(c0, lo), cb = min(c0 + ncol - 1, hi);  // this wave's columns in the slab
+        for (int c = ca; c <= cb; ++c) {
+            const float2 *col = slab + (c - c0) * F;
+#pragma unroll
+            for (int q = 0; q < TPT; ++q) {
+                if ((uint32_t)c - (uint32_t)t0[q] <= span[q]) {
+                    const float2 p = col[st[q].row];
+                    part[q] += rot_re(pa[q] + (uint32_t)st[q].row * pb[q], p.x, p.y);
+                    dda_step(st[q]);
+                }
+            }
+        }
+#pragma unroll
+        for (int q = 0; q < TPT; ++q) {
+            acc[q] += part[q];
+            part[q] = 0.0f;
+        }
+    }
+
+    uint64_t key = 0;
+#pragma unroll
+    for (int q = 0; q < TPT; ++q) {
+        if (!live[q]) continue;
+        const float z = ok[q] ? finish(acc[q], (int32_t)span[q] + 1, norm) : __builtin_nanf("");
+        if (snr) snr[idx[q]] = z;
+        const uint64_t k = key_encode(z, (uint32_t)(first + idx[q]));
+        key = k > key ? k : key;
+    }
+    merge_key(best, key);
+}
+
+}  // namespace stt

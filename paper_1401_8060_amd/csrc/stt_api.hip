@@ -1,0 +1,418 @@
+// stt_api.hip -- host side of libstt: contexts, argument validation, scratch,
+// launch configuration and the extern "C" entry points declared in stt.h.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cstdarg>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "stt.h"
+#include "kernels.hpp"
+
+using namespace stt;
+
+struct stt_ctx {
+    int device = 0;
+    hipStream_t stream = nullptr;
+    std::string err;
+    void *scratch = nullptr;
+    size_t scratch_bytes = 0;
+    int path = 0;  // 0 auto, 1 direct, 2 slab
+    int lds_bytes = 80 * 1024;  // slab budget per workgroup (two workgroups per CU)
+    // Timing: every call takes six events from a pool (start/end of the scoring
+    // kernel, of the binning kernels and of the whole call); queries sum them.
+    bool timing = false;
+    std::vector<hipEvent_t> pool;
+    size_t next = 0;         // first free event of the pool
+    size_t last = 0;         // first event of the last call
+    bool used[3] = {false, false, false};
+    struct Rec { size_t base; bool used[3]; };
+    std::vector<Rec> recs;   // calls since the last total query
+};
+
+namespace {
+
+stt_status fail(stt_ctx *c, stt_status s, const char *fmt, ...)
+    __attribute__((format(printf, 3, 4)));
+
+stt_status fail(stt_ctx *c, stt_status s, const char *fmt, ...)
+{
+    if (c) {
+        char buf[512];
+        va_list ap;
+        va_start(ap, fmt);
+        vsnprintf(buf, sizeof buf, fmt, ap);
+        va_end(ap);
+        c->err = buf;
+    }
+    return s;
+}
+
+#define STT_HIP(c, call)                                                                      \
+    do {                                                                                      \
+        hipError_t e_ = (call);                                                               \
+        if (e_ != hipSuccess) return fail((c), STT_EHIP, "%s: %s", #call, hipGetErrorString(e_)); \
+    } while (0)
+
+stt_status ensure_scratch(stt_ctx *c, size_t bytes)
+{
+    if (bytes <= c->scratch_bytes) return STT_OK;
+    if (c->scratch) {
+        hipError_t e = hipStreamSynchronize(c->stream);
+        if (e != hipSuccess) return fail(c, STT_EHIP, "hipStreamSynchronize: %s", hipGetErrorString(e));
+        (void)hipFree(c->scratch);
+        c->scratch = nullptr;
+        c->scratch_bytes = 0;
+    }
+    size_t want = std::max(bytes, (size_t)1 << 20);
+    if (hipMalloc(&c->scratch, want) != hipSuccess) {
+        (void)hipGetLastError();
+        c->scratch = nullptr;
+        return fail(c, STT_ENOMEM, "cannot allocate %zu bytes of scratch", want);
+    }
+    c->scratch_bytes = want;
+    return STT_OK;
+}
+
+stt_status check_map(stt_ctx *c, const stt_map *m)
+{
+    if (!m) return fail(c, STT_EINVAL, "map is NULL");
+    if (m->dtype != STT_C64F32) return fail(c, STT_EUNSUPPORTED, "map dtype %d not supported here", m->dtype);
+    if (m->T < 2 || m->T > STT_MAX_T) return fail(c, STT_ERANGE, "T=%d outside [2, %d]", m->T, STT_MAX_T);
+    if (m->F < 1 || m->F > STT_MAX_F) return fail(c, STT_ERANGE, "F=%d outside [1, %d]", m->F, STT_MAX_F);
+    if (m->ld < m->F) return fail(c, STT_EINVAL, "ld=%lld < F=%d", (long long)m->ld, m->F);
+    if (!m->Y || !m->sigma) return fail(c, STT_EINVAL, "map Y or sigma is NULL");
+    const int64_t fmax = std::llabs((int64_t)m->fq4_lo) + (int64_t)(m->F - 1) * std::llabs((int64_t)m->dfq4);
+    if (fmax >= ((int64_t)1 << 31)) return fail(c, STT_ERANGE, "row frequencies overflow 32 bits");
+    return STT_OK;
+}
+
+stt_status make_genp(stt_ctx *c, const stt_gen *g, int32_t T, int32_t F, GenP &p)
+{
+    if (!g) return fail(c, STT_EINVAL, "gen is NULL");
+    if (g->reserved != 0) return fail(c, STT_EINVAL, "gen.reserved must be 0");
+    if (T < 2 || T > STT_MAX_T) return fail(c, STT_ERANGE, "T=%d outside [2, %d]", T, STT_MAX_T);
+    if (F < 1 || F > STT_MAX_F) return fail(c, STT_ERANGE, "F=%d outside [1, %d]", F, STT_MAX_F);
+    if (g->min_len < 2 || g->min_len > T) return fail(c, STT_ERANGE, "min_len=%d outside [2, T=%d]", g->min_len, T);
+    if (g->dtau_max < 0 || g->dtau_max >= (1 << 30)) return fail(c, STT_ERANGE, "dtau_max=%d outside [0, 2^30)", g->dtau_max);
+    const int64_t npos = (int64_t)T - g->min_len + 1;
+    p.key0 = (uint32_t)g->seed;
+    p.key1 = (uint32_t)(g->seed >> 32);
+    p.stream = g->stream;
+    p.npairs = (uint32_t)(npos * (npos + 1) / 2);
+    p.L = g->min_len;
+    p.frange = (uint32_t)F << 8;
+    p.dmax = g->dtau_max;
+    p.dspan = 2u * (uint32_t)g->dtau_max + 1u;
+    return STT_OK;
+}
+
+stt_status check_range(stt_ctx *c, int64_t first, int64_t n)
+{
+    if (first < 0 || n < 0) return fail(c, STT_EINVAL, "first=%lld, n=%lld must be >= 0", (long long)first, (long long)n);
+    if (first + n > ((int64_t)1 << 32)) return fail(c, STT_ERANGE, "track indices must stay below 2^32");
+    return STT_OK;
+}
+
+MapP to_mapp(const stt_map *m)
+{
+    MapP p;
+    p.Y = (const float2 *)m->Y;
+    p.sig = (const float *)m->sigma;
+    p.T = m->T;
+    p.F = m->F;
+    p.ld = m->ld;
+    p.fq4_lo = m->fq4_lo;
+    p.dfq4 = m->dfq4;
+    return p;
+}
+
+// Reserve six events for this call (growing the pool when needed).
+stt_status ev_begin(stt_ctx *c)
+{
+    for (bool &u : c->used) u = false;
+    if (!c->timing) return STT_OK;
+    while (c->pool.size() < c->next + 6) {
+        hipEvent_t e;
+        STT_HIP(c, hipEventCreate(&e));
+        c->pool.push_back(e);
+    }
+    c->last = c->next;
+    c->next += 6;
+    return STT_OK;
+}
+
+void ev_record(stt_ctx *c, int i)
+{
+    if (c->timing) (void)hipEventRecord(c->pool[c->last + i], c->stream);
+}
+
+void ev_end(stt_ctx *c)
+{
+    if (!c->timing) return;
+    stt_ctx::Rec r;
+    r.base = c->last;
+    for (int i = 0; i < 3; ++i) r.used[i] = c->used[i];
+    c->recs.push_back(r);
+}
+
+// Bucket shift so that at most 64 buckets cover T columns.
+int bucket_shift(int T)
+{
+    int wb = 0;
+    while (((T - 1) >> wb) + 1 > 64) ++wb;
+    return wb;
+}
+
+template <bool EXPL>
+stt_status score_impl(stt_ctx *c, const stt_map *map, const GenP &g, const Trk *tr, int64_t first, int64_t n,
+                      int32_t norm, float *snr, uint64_t *best)
+{
+    const MapP m = to_mapp(map);
+    // the slab plus the kernel's few static LDS words must fit the 160 KB of a CU
+    const int slab_cols = std::min<int>(64, (c->lds_bytes - 256) / (8 * m.F));
+    bool slab = slab_cols >= 1;
+    if (c->path == 1) slab = false;
+    if (c->path == 0 && n < 4096) slab = false;
+    if (c->path == 2 && !slab)
+        return fail(c, STT_EUNSUPPORTED, "F=%d too wide for an LDS slab of %d bytes", m.F, c->lds_bytes);
+
+    {
+        stt_status s0 = ev_begin(c);
+        if (s0 != STT_OK) return s0;
+    }
+    ev_record(c, 4);
+    if (!slab) {
+        ev_record(c, 0);
+        const unsigned grid = (unsigned)((n + kWG - 1) / kWG);
+        hipLaunchKernelGGL(k_score_direct<EXPL>, dim3(grid), dim3(kWG), 0, c->stream, m, g, tr, (uint64_t)first, n,
+                           norm, snr, best);
+        STT_HIP(c, hipGetLastError());
+        ev_record(c, 1);
+        c->used[0] = true;
+    } else {
+        const int wb = bucket_shift(m.T);
+        const int nb = ((m.T - 1) >> wb) + 1;
+        const int nbins = nb * (nb + 1) / 2;
+        const size_t need = sizeof(uint32_t) * (2 * (size_t)kMaxBins + (size_t)n);
+        stt_status s = ensure_scratch(c, need);
+        if (s != STT_OK) return s;
+        uint32_t *totals = (uint32_t *)c->scratch;
+        uint32_t *cursor = totals + kMaxBins;
+        uint32_t *order = cursor + kMaxBins;
+        const unsigned bgrid = (unsigned)((n + kBinChunk - 1) / kBinChunk);
+        ev_record(c, 2);
+        hipLaunchKernelGGL(k_fill_u32, dim3((nbins + 255) / 256), dim3(256), 0, c->stream, totals, nbins, 0u);
+        hipLaunchKernelGGL(k_bin_count<EXPL>, dim3(bgrid), dim3(256), 0, c->stream, m, g, tr, (uint64_t)first, n, wb,
+                           nbins, totals);
+        hipLaunchKernelGGL(k_bin_scan, dim3(1), dim3(1024), 0, c->stream, (const uint32_t *)totals, nbins, cursor);
+        hipLaunchKernelGGL(k_bin_scatter<EXPL>, dim3(bgrid), dim3(256), 0, c->stream, m, g, tr, (uint64_t)first, n,
+                           wb, nbins, cursor, order);
+        STT_HIP(c, hipGetLastError());
+        ev_record(c, 3);
+        c->used[1] = true;
+        constexpr int TPT = 4;
+        const unsigned grid = (unsigned)((n + kWG * TPT - 1) / (kWG * TPT));
+        const int S = std::min(slab_cols, m.T);
+        const size_t shm = sizeof(float2) * (size_t)S * m.F;
+        if (shm > 64 * 1024)
+            STT_HIP(c, hipFuncSetAttribute((const void *)k_score_slab<TPT, EXPL>,
+                                           hipFuncAttributeMaxDynamicSharedMemorySize, (int)shm));
+        ev_record(c, 0);
+        hipLaunchKernelGGL((k_score_slab<TPT, EXPL>), dim3(grid), dim3(kWG), shm, c->stream, m, g, tr,
+                           (const uint32_t *)order, (uint64_t)first, n, S, norm, snr, best);
+        STT_HIP(c, hipGetLastError());
+        ev_record(c, 1);
+        c->used[0] = true;
+    }
+    ev_record(c, 5);
+    c->used[2] = true;
+    ev_end(c);
+    return STT_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+const char *stt_strerror(stt_status s)
+{
+    switch (s) {
+    case STT_OK: return "ok";
+    case STT_EINVAL: return "invalid argument";
+    case STT_ERANGE: return "size out of supported range";
+    case STT_ENOMEM: return "out of device memory";
+    case STT_EHIP: return "HIP runtime error";
+    case STT_EUNSUPPORTED: return "unsupported";
+    default: return "unknown status";
+    }
+}
+
+const char *stt_last_error(const stt_ctx *c) { return c ? c->err.c_str() : "no context"; }
+
+stt_status stt_create(int device, void *hip_stream, stt_ctx **out)
+{
+    if (!out) return STT_EINVAL;
+    *out = nullptr;
+    int ndev = 0;
+    if (hipGetDeviceCount(&ndev) != hipSuccess || device < 0 || device >= ndev) return STT_EHIP;
+    if (hipSetDevice(device) != hipSuccess) return STT_EHIP;
+    stt_ctx *c = new stt_ctx;
+    c->device = device;
+    c->stream = (hipStream_t)hip_stream;
+    *out = c;
+    return STT_OK;
+}
+
+stt_status stt_destroy(stt_ctx *c)
+{
+    if (!c) return STT_EINVAL;
+    (void)hipSetDevice(c->device);
+    (void)hipStreamSynchronize(c->stream);
+    if (c->scratch) (void)hipFree(c->scratch);
+    for (auto &e : c->pool) (void)hipEventDestroy(e);
+    delete c;
+    return STT_OK;
+}
+
+stt_status stt_set_stream(stt_ctx *c, void *hip_stream)
+{
+    if (!c) return STT_EINVAL;
+    c->stream = (hipStream_t)hip_stream;
+    return STT_OK;
+}
+
+stt_status stt_sync(stt_ctx *c)
+{
+    if (!c) return STT_EINVAL;
+    STT_HIP(c, hipStreamSynchronize(c->stream));
+    return STT_OK;
+}
+
+stt_status stt_reserve(stt_ctx *c, int64_t max_tracks)
+{
+    if (!c || max_tracks < 0) return fail(c, STT_EINVAL, "bad reserve request");
+    return ensure_scratch(c, sizeof(uint32_t) * (2 * (size_t)kMaxBins + (size_t)max_tracks));
+}
+
+stt_status stt_set_timing(stt_ctx *c, int32_t on)
+{
+    if (!c) return STT_EINVAL;
+    c->timing = on != 0;
+    c->recs.clear();
+    c->next = c->last = 0;
+    return STT_OK;
+}
+
+static const int kEvPair[3] = {0, 2, 4};  // start event of each stage within a call's six
+
+stt_status stt_kernel_ms(stt_ctx *c, int32_t which, float *ms)
+{
+    if (!c || !ms || which < 0 || which > 2) return fail(c, STT_EINVAL, "bad timing query");
+    if (!c->timing || c->recs.empty() || !c->recs.back().used[which])
+        return fail(c, STT_EINVAL, "no timed stage %d in the last call", which);
+    STT_HIP(c, hipStreamSynchronize(c->stream));
+    const size_t a = c->recs.back().base + kEvPair[which];
+    STT_HIP(c, hipEventElapsedTime(ms, c->pool[a], c->pool[a + 1]));
+    return STT_OK;
+}
+
+stt_status stt_kernel_ms_total(stt_ctx *c, int32_t which, double *total_ms, int32_t *count)
+{
+    if (!c || !total_ms || !count || which < 0 || which > 2) return fail(c, STT_EINVAL, "bad timing query");
+    if (!c->timing) return fail(c, STT_EINVAL, "timing is off");
+    STT_HIP(c, hipStreamSynchronize(c->stream));
+    double tot = 0.0;
+    int32_t n = 0;
+    for (const auto &r : c->recs) {
+        if (!r.used[which]) continue;
+        float ms = 0.0f;
+        const size_t a = r.base + kEvPair[which];
+        STT_HIP(c, hipEventElapsedTime(&ms, c->pool[a], c->pool[a + 1]));
+        tot += ms;
+        ++n;
+    }
+    *total_ms = tot;
+    *count = n;
+    c->recs.clear();
+    c->next = c->last = 0;
+    return STT_OK;
+}
+
+// Internal knob used by tests and tuning: 0 auto, 1 direct gathers, 2 LDS slabs.
+stt_status stt_set_path(stt_ctx *c, int32_t path, int32_t lds_bytes)
+{
+    if (!c || path < 0 || path > 2) return STT_EINVAL;
+    if (lds_bytes != 0 && (lds_bytes < 1024 || lds_bytes > 160 * 1024))
+        return fail(c, STT_ERANGE, "lds_bytes=%d outside [1024, 163840]", lds_bytes);
+    c->path = path;
+    if (lds_bytes) c->lds_bytes = lds_bytes;
+    return STT_OK;
+}
+
+stt_status stt_make_tracks(stt_ctx *c, const stt_gen *gen, int32_t T, int32_t F, int64_t first, int64_t n,
+                           stt_track *out_dev)
+{
+    if (!c) return STT_EINVAL;
+    GenP g;
+    stt_status s = make_genp(c, gen, T, F, g);
+    if (s != STT_OK) return s;
+    if ((s = check_range(c, first, n)) != STT_OK) return s;
+    if (n == 0) return STT_OK;
+    if (!out_dev) return fail(c, STT_EINVAL, "out_dev is NULL");
+    STT_HIP(c, hipSetDevice(c->device));
+    const unsigned grid = (unsigned)((n + 255) / 256);
+    hipLaunchKernelGGL(k_make_tracks, dim3(grid), dim3(256), 0, c->stream, g, (uint64_t)first, n, (Trk *)out_dev);
+    STT_HIP(c, hipGetLastError());
+    return STT_OK;
+}
+
+stt_status stt_score(stt_ctx *c, const stt_map *map, const stt_gen *gen, const stt_track *tracks_dev, int64_t first,
+                     int64_t n, int32_t norm, float *snr_dev, uint64_t *best_key_dev)
+{
+    if (!c) return STT_EINVAL;
+    stt_status s = check_map(c, map);
+    if (s != STT_OK) return s;
+    if ((s = check_range(c, first, n)) != STT_OK) return s;
+    if (norm != STT_NORM_SQRT_N && norm != STT_NORM_N) return fail(c, STT_EINVAL, "norm=%d", norm);
+    GenP g{};
+    if (!tracks_dev) {
+        if ((s = make_genp(c, gen, map->T, map->F, g)) != STT_OK) return s;
+    }
+    if (n == 0) return STT_OK;
+    STT_HIP(c, hipSetDevice(c->device));
+    if (tracks_dev)
+        return score_impl<true>(c, map, g, (const Trk *)tracks_dev, first, n, norm, snr_dev, best_key_dev);
+    return score_impl<false>(c, map, g, nullptr, first, n, norm, snr_dev, best_key_dev);
+}
+
+stt_status stt_argmax(stt_ctx *c, const float *snr_dev, int64_t n, int64_t first, uint64_t *best_key_dev)
+{
+    if (!c) return STT_EINVAL;
+    stt_status s = check_range(c, first, n);
+    if (s != STT_OK) return s;
+    if (n == 0) return STT_OK;
+    if (!snr_dev || !best_key_dev) return fail(c, STT_EINVAL, "snr_dev and best_key_dev must be non-NULL");
+    STT_HIP(c, hipSetDevice(c->device));
+    const int64_t blocks = std::min<int64_t>((n + 255) / 256, 4096);
+    hipLaunchKernelGGL(k_argmax, dim3((unsigned)blocks), dim3(256), 0, c->stream, snr_dev, n, (uint64_t)first,
+                       best_key_dev);
+    STT_HIP(c, hipGetLastError());
+    return STT_OK;
+}
+
+uint64_t stt_key_encode(float z, uint32_t j) { return key_encode(z, j); }
+
+void stt_key_decode(uint64_t key, float *z, uint32_t *j)
+{
+    const uint32_t o = (uint32_t)(key >> 32);
+    const uint32_t b = (o & 0x80000000u) ? (o & 0x7FFFFFFFu) : ~o;
+    if (z) std::memcpy(z, &b, sizeof b);
+    if (j) *j = 0xFFFFFFFFu - (uint32_t)key;
+}
+
+}  // extern "C"

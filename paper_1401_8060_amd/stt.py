@@ -1,0 +1,276 @@
+"""Python binding of libstt (the C ABI in include/stt.h).
+
+Argument marshalling only: every step of the search runs in the HIP kernels
+of libstt.so. torch provides device memory and streams; tensors are passed by
+data pointer. There is no fallback: if libstt.so is missing or fails to load
+this module raises.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+from dataclasses import dataclass
+
+import torch
+
+_PKG = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_PKG, "libstt.so")
+
+OK, EINVAL, ERANGE, ENOMEM, EHIP, EUNSUPPORTED = 0, -1, -2, -3, -4, -5
+NORM_SQRT_N, NORM_N = 0, 1
+C64F32, C16F16 = 0, 1
+FBITS = 8
+MAX_T, MAX_F = 2896, 32767
+DTAU_UNIT_S = 2.0 ** -28
+PATH_AUTO, PATH_DIRECT, PATH_SLAB = 0, 1, 2
+STAGE_SCORE, STAGE_BIN, STAGE_CALL = 0, 1, 2
+
+
+class SttError(RuntimeError):
+    def __init__(self, status: int, msg: str):
+        super().__init__(f"stt error {status}: {msg}")
+        self.status = status
+
+
+class Track(C.Structure):
+    _fields_ = [("t0", C.c_int32), ("t2", C.c_int32), ("f0", C.c_uint32), ("f1", C.c_uint32),
+                ("f2", C.c_uint32), ("dtau", C.c_int32)]
+
+
+class _Gen(C.Structure):
+    _fields_ = [("seed", C.c_uint64), ("stream", C.c_uint32), ("min_len", C.c_int32),
+                ("dtau_max", C.c_int32), ("reserved", C.c_int32)]
+
+
+class _Map(C.Structure):
+    _fields_ = [("T", C.c_int32), ("F", C.c_int32), ("ld", C.c_int64), ("dtype", C.c_int32),
+                ("scale_exp", C.c_int32), ("Y", C.c_void_p), ("sigma", C.c_void_p),
+                ("fq4_lo", C.c_int32), ("dfq4", C.c_int32)]
+
+
+_lib = None
+
+
+def lib():
+    """Load libstt.so (raises if it has not been built)."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise ImportError(f"{LIB_PATH} is missing: build it with __graft_entry__.build() "
+                              "or python -m paper_1401_8060_amd.build")
+        L = C.CDLL(LIB_PATH)
+        vp, i32, i64, u64 = C.c_void_p, C.c_int32, C.c_int64, C.c_uint64
+        sigs = {
+            "stt_create": ([C.c_int, vp, C.POINTER(vp)], i32),
+            "stt_destroy": ([vp], i32),
+            "stt_set_stream": ([vp, vp], i32),
+            "stt_sync": ([vp], i32),
+            "stt_strerror": ([i32], C.c_char_p),
+            "stt_last_error": ([vp], C.c_char_p),
+            "stt_reserve": ([vp, i64], i32),
+            "stt_set_timing": ([vp, i32], i32),
+            "stt_kernel_ms": ([vp, i32, C.POINTER(C.c_float)], i32),
+            "stt_kernel_ms_total": ([vp, i32, C.POINTER(C.c_double), C.POINTER(C.c_int32)], i32),
+            "stt_set_path": ([vp, i32, i32], i32),
+            "stt_make_tracks": ([vp, C.POINTER(_Gen), i32, i32, i64, i64, vp], i32),
+            "stt_score": ([vp, C.POINTER(_Map), C.POINTER(_Gen), vp, i64, i64, i32, vp, vp], i32),
+            "stt_argmax": ([vp, vp, i64, i64, vp], i32),
+            "stt_key_encode": ([C.c_float, C.c_uint32], u64),
+            "stt_key_decode": ([u64, C.POINTER(C.c_float), C.POINTER(C.c_uint32)], None),
+        }
+        for name, (args, res) in sigs.items():
+            fn = getattr(L, name)
+            fn.argtypes = args
+            fn.restype = res
+        _bind_ext(L)
+        _lib = L
+    return _lib
+
+
+def _bind_ext(L):
+    """Entry points of the extensions (precision, batching, differentiation), bound when exported."""
+    from . import stt_ext
+    stt_ext.bind(L)
+
+
+EXPORTED = [
+    "stt_create", "stt_destroy", "stt_set_stream", "stt_sync", "stt_strerror", "stt_last_error",
+    "stt_reserve", "stt_set_timing", "stt_kernel_ms", "stt_kernel_ms_total", "stt_set_path", "stt_make_tracks", "stt_score",
+    "stt_argmax", "stt_key_encode", "stt_key_decode",
+]
+
+
+# ----------------------------------------------------------------------------- plain data
+
+@dataclass
+class Gen:
+    """Template law: Philox seed/stream, minimum length L (pixels), delay bound (2^-28 s units)."""
+    seed: int = 1
+    stream: int = 0
+    min_len: int = 10
+    dtau_max: int = 2684355  # 10 ms
+
+    def c(self) -> _Gen:
+        return _Gen(self.seed, self.stream, self.min_len, self.dtau_max, 0)
+
+
+def dtau_units(seconds: float) -> int:
+    return int(round(seconds / DTAU_UNIT_S))
+
+
+class Map:
+    """A (Y, sigma) ft-map on the GPU: Y complex64 [T][F] (or [T][ld]), sigma float32 same shape."""
+
+    def __init__(self, Y: torch.Tensor, sigma: torch.Tensor, fq4_lo: int = 1600, dfq4: int = 16):
+        if Y.dtype != torch.complex64 or sigma.dtype != torch.float32:
+            raise TypeError("Y must be complex64 and sigma float32")
+        if Y.dim() != 2 or Y.shape != sigma.shape:
+            raise ValueError("Y and sigma must be [T][F] tensors of the same shape")
+        if not (Y.is_cuda and sigma.is_cuda):
+            raise ValueError("Y and sigma must be on the GPU")
+        if Y.stride(1) != 1 or sigma.stride(1) != 1 or Y.stride(0) != sigma.stride(0):
+            raise ValueError("frequency must be contiguous and both arrays share the column stride")
+        self.Y, self.sigma = Y, sigma
+        self.T, self.F = Y.shape
+        self.ld = Y.stride(0)
+        self.fq4_lo, self.dfq4 = fq4_lo, dfq4
+
+    def c(self) -> _Map:
+        return _Map(self.T, self.F, self.ld, C64F32, 0, self.Y.data_ptr(), self.sigma.data_ptr(),
+                    self.fq4_lo, self.dfq4)
+
+
+def key_decode(key: int) -> tuple[float, int]:
+    z, j = C.c_float(), C.c_uint32()
+    lib().stt_key_decode(C.c_uint64(int(key) & 0xFFFFFFFFFFFFFFFF), C.byref(z), C.byref(j))
+    return z.value, j.value
+
+
+def key_encode(z: float, j: int) -> int:
+    return int(lib().stt_key_encode(z, j))
+
+
+def tracks_tensor(n: int, device="cuda") -> torch.Tensor:
+    """An uninitialised [n][6] int32 tensor laid out as stt_track records."""
+    return torch.empty((n, 6), dtype=torch.int32, device=device)
+
+
+# ----------------------------------------------------------------------------- context
+
+class Context:
+    """An stt_ctx bound to a device and (by default) torch's current stream on it."""
+
+    def __init__(self, device: int = 0, stream: torch.cuda.Stream | None = None):
+        self._L = lib()
+        self.device = device
+        s = stream if stream is not None else torch.cuda.current_stream(device)
+        self._stream = s
+        h = C.c_void_p()
+        st = self._L.stt_create(device, C.c_void_p(s.cuda_stream), C.byref(h))
+        if st != OK:
+            raise SttError(st, "stt_create failed")
+        self.h = h
+
+    def close(self):
+        if getattr(self, "h", None):
+            self._L.stt_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def _chk(self, st: int):
+        if st != OK:
+            raise SttError(st, self._L.stt_last_error(self.h).decode())
+
+    # -- configuration
+    def set_stream(self, stream: torch.cuda.Stream):
+        self._stream = stream
+        self._chk(self._L.stt_set_stream(self.h, C.c_void_p(stream.cuda_stream)))
+
+    def sync(self):
+        self._chk(self._L.stt_sync(self.h))
+
+    def reserve(self, max_tracks: int):
+        self._chk(self._L.stt_reserve(self.h, max_tracks))
+
+    def set_timing(self, on: bool):
+        self._chk(self._L.stt_set_timing(self.h, 1 if on else 0))
+
+    def kernel_ms(self, which: int = STAGE_SCORE) -> float:
+        ms = C.c_float()
+        self._chk(self._L.stt_kernel_ms(self.h, which, C.byref(ms)))
+        return ms.value
+
+    def kernel_ms_total(self, which: int = STAGE_SCORE) -> tuple[float, int]:
+        """(summed milliseconds, number of calls) of a stage since the last total."""
+        tot, cnt = C.c_double(), C.c_int32()
+        self._chk(self._L.stt_kernel_ms_total(self.h, which, C.byref(tot), C.byref(cnt)))
+        return tot.value, cnt.value
+
+    def set_path(self, path: int, lds_bytes: int = 0):
+        self._chk(self._L.stt_set_path(self.h, path, lds_bytes))
+
+    # -- entry points
+    def make_tracks(self, gen: Gen, T: int, F: int, first: int, n: int, out: torch.Tensor | None = None):
+        if out is None:
+            out = tracks_tensor(n)
+        if out.dtype != torch.int32 or out.shape != (n, 6) or not out.is_contiguous():
+            raise ValueError("out must be a contiguous [n][6] int32 tensor")
+        g = gen.c()
+        self._chk(self._L.stt_make_tracks(self.h, C.byref(g), T, F, first, n, C.c_void_p(out.data_ptr())))
+        return out
+
+    def score(self, m: Map, gen: Gen | None = None, tracks: torch.Tensor | None = None, first: int = 0,
+              n: int | None = None, norm: int = NORM_SQRT_N, snr: torch.Tensor | bool | None = True,
+              best_key: torch.Tensor | None = None):
+        """Score n tracks (generated from gen, or the given [n][6] int32 tracks).
+
+        Returns (snr tensor or None, best_key tensor). ``snr=True`` allocates the
+        output; pass a float32 tensor of n elements to reuse one, or None to skip
+        it. ``best_key`` is a 1-element int64 tensor that is max-merged into
+        (created as 0 when not given).
+        """
+        if tracks is not None:
+            if tracks.dtype != torch.int32 or tracks.dim() != 2 or tracks.shape[1] != 6 or not tracks.is_contiguous():
+                raise ValueError("tracks must be a contiguous [n][6] int32 tensor")
+            if n is None:
+                n = tracks.shape[0]
+            if n > tracks.shape[0]:
+                raise ValueError("n exceeds the number of given tracks")
+        if n is None:
+            raise ValueError("n is required with generated tracks")
+        if snr is True:
+            snr = torch.empty(n, dtype=torch.float32, device=m.Y.device)
+        if snr is not None and snr is not False:
+            if snr.dtype != torch.float32 or snr.numel() < n or not snr.is_contiguous():
+                raise ValueError("snr must be a contiguous float32 tensor of at least n elements")
+        else:
+            snr = None
+        if best_key is None:
+            best_key = torch.zeros(1, dtype=torch.int64, device=m.Y.device)
+        mc = m.c()
+        g = gen.c() if gen is not None else None
+        self._chk(self._L.stt_score(self.h, C.byref(mc), C.byref(g) if g is not None else None,
+                                    C.c_void_p(tracks.data_ptr()) if tracks is not None else None,
+                                    first, n, norm,
+                                    C.c_void_p(snr.data_ptr()) if snr is not None else None,
+                                    C.c_void_p(best_key.data_ptr())))
+        return snr, best_key
+
+    def argmax(self, snr: torch.Tensor, first: int = 0, best_key: torch.Tensor | None = None) -> torch.Tensor:
+        if snr.dtype != torch.float32 or not snr.is_contiguous():
+            raise ValueError("snr must be a contiguous float32 tensor")
+        if best_key is None:
+            best_key = torch.zeros(1, dtype=torch.int64, device=snr.device)
+        self._chk(self._L.stt_argmax(self.h, C.c_void_p(snr.data_ptr()), snr.numel(), first,
+                                     C.c_void_p(best_key.data_ptr())))
+        return best_key
+
+
+def decode_best(best_key: torch.Tensor) -> tuple[float, int]:
+    """(score, track index) of a best-key tensor (synchronises)."""
+    return key_decode(int(best_key.item()) & 0xFFFFFFFFFFFFFFFF)

@@ -1,0 +1,68 @@
+// Host harness around the kernels' own arithmetic (dev_common.hpp is
+// __host__ __device__): reads commands from stdin, prints results, so that the
+// tests can compare the code the GPU runs with the CPU oracle without a GPU.
+//
+//   draw  seed stream j T F L D        -> t0 t2 f0 f1 f2 dtau
+//   rows  t0 t2 f0 f1 f2               -> N rows (DDA walk)
+//   rot   ph pr pi                     -> Re[exp(2 pi i ph/2^32)(pr + i pi)] as %.9e
+//   key   z j                          -> 64-bit key (hex)
+#include <cstdio>
+#include <cstring>
+#include <vector>
+
+#include "dev_common.hpp"
+
+using namespace stt;
+
+int main()
+{
+    char cmd[16];
+    while (std::scanf("%15s", cmd) == 1) {
+        if (!std::strcmp(cmd, "draw")) {
+            unsigned long long seed, j;
+            unsigned stream;
+            int T, F, L, D;
+            if (std::scanf("%llu %u %llu %d %d %d %d", &seed, &stream, &j, &T, &F, &L, &D) != 7) return 2;
+            GenP g;
+            const long long npos = T - L + 1;
+            g.key0 = (uint32_t)seed;
+            g.key1 = (uint32_t)(seed >> 32);
+            g.stream = stream;
+            g.npairs = (uint32_t)(npos * (npos + 1) / 2);
+            g.L = L;
+            g.frange = (uint32_t)F << 8;
+            g.dmax = D;
+            g.dspan = 2u * (uint32_t)D + 1u;
+            const Trk t = draw_track(g, j);
+            int32_t a, b;
+            draw_extent(g, j, a, b);
+            if (a != t.t0 || b != t.t2) return 3;
+            std::printf("%d %d %u %u %u %d\n", t.t0, t.t2, t.f0, t.f1, t.f2, t.dtau);
+        } else if (!std::strcmp(cmd, "rows")) {
+            Trk t;
+            if (std::scanf("%d %d %u %u %u", &t.t0, &t.t2, &t.f0, &t.f1, &t.f2) != 5) return 2;
+            t.dtau = 0;
+            Dda s = dda_init(t);
+            const int N = t.t2 - t.t0 + 1;
+            for (int k = 0; k < N; ++k) {
+                std::printf(k ? " %d" : "%d", s.row);
+                dda_step(s);
+            }
+            std::printf("\n");
+        } else if (!std::strcmp(cmd, "rot")) {
+            unsigned ph;
+            float pr, pi;
+            if (std::scanf("%u %f %f", &ph, &pr, &pi) != 3) return 2;
+            std::printf("%.9e\n", (double)rot_re(ph, pr, pi));
+        } else if (!std::strcmp(cmd, "key")) {
+            float z;
+            unsigned j;
+            if (std::scanf("%f %u", &z, &j) != 2) return 2;
+            std::printf("%016llx\n", (unsigned long long)key_encode(z, j));
+        } else {
+            return 1;
+        }
+        std::fflush(stdout);
+    }
+    return 0;
+}

@@ -1,0 +1,70 @@
+"""The C ABI: libstt.so loads and exports every function include/stt.h declares.
+
+No compute calls here (no GPU needed); only the host-side key helpers run.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import math
+import os
+import re
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADERS = [os.path.join(ROOT, "include", h) for h in sorted(os.listdir(os.path.join(ROOT, "include")))
+           if h.endswith(".h")]
+LIB = os.path.join(ROOT, "paper_1401_8060_amd", "libstt.so")
+
+
+def declared_functions():
+    names = []
+    for h in HEADERS:
+        text = open(h).read()
+        text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+        for m in re.finditer(r"^\s*(?:const\s+)?[A-Za-z_][A-Za-z0-9_]*\s*\*?\s*(stt_[a-z0-9_]+)\s*\(", text, re.M):
+            names.append(m.group(1))
+    return sorted(set(names))
+
+
+@pytest.fixture(scope="module")
+def libstt():
+    if not os.path.exists(LIB):
+        import paper_1401_8060_amd.build as b
+        b.build()
+    return C.CDLL(LIB)
+
+
+def test_header_declares_the_entry_points():
+    names = declared_functions()
+    for required in ["stt_make_tracks", "stt_score", "stt_argmax", "stt_create", "stt_destroy"]:
+        assert required in names
+
+
+def test_every_declared_symbol_is_exported(libstt):
+    missing = [n for n in declared_functions() if not hasattr(libstt, n)]
+    assert not missing, missing
+
+
+def test_host_key_helpers(libstt):
+    libstt.stt_key_encode.argtypes = [C.c_float, C.c_uint32]
+    libstt.stt_key_encode.restype = C.c_uint64
+    libstt.stt_key_decode.argtypes = [C.c_uint64, C.POINTER(C.c_float), C.POINTER(C.c_uint32)]
+    libstt.stt_key_decode.restype = None
+    for z, j in [(8.25, 12345), (-3.0, 0), (0.0, 2 ** 32 - 1), (math.inf, 7)]:
+        k = libstt.stt_key_encode(z, j)
+        zz, jj = C.c_float(), C.c_uint32()
+        libstt.stt_key_decode(k, C.byref(zz), C.byref(jj))
+        assert zz.value == z and jj.value == j
+    assert libstt.stt_key_encode(2.0, 5) > libstt.stt_key_encode(2.0, 6) > libstt.stt_key_encode(1.0, 0)
+
+
+def test_strerror_and_create_without_device(libstt):
+    libstt.stt_strerror.restype = C.c_char_p
+    assert libstt.stt_strerror(0) == b"ok"
+    assert libstt.stt_strerror(-2) == b"size out of supported range"
+    # creating a context on a device that does not exist reports a HIP error
+    libstt.stt_create.argtypes = [C.c_int, C.c_void_p, C.POINTER(C.c_void_p)]
+    h = C.c_void_p()
+    assert libstt.stt_create(4096, None, C.byref(h)) == -4
+    assert libstt.stt_create(0, None, None) == -1
