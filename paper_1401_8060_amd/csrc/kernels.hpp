@@ -28,6 +28,10 @@ struct MapP {
 };
 
 constexpr int kMaxDt = 2895;  // Dt * Dt * 256 < 2^31
+// FP32 partial sums are flushed into the FP64 total after every column c with
+// c % kFlush == kFlush - 1: a fixed grid of absolute columns, so a template's
+// arithmetic does not depend on which workgroup or scorer handles it.
+constexpr int kFlush = 16;
 constexpr int kWG = 256;      // threads per workgroup of the scorers
 
 __device__ __forceinline__ bool track_ok(const Trk &t, const MapP &m)
@@ -110,7 +114,7 @@ __global__ __launch_bounds__(kWG) void k_score_direct(MapP m, GenP g, const Trk 
                 const float2 y = Yc[s.row];
                 const float w = 1.0f / Sc[s.row];
                 part += rot_re(pa + (uint32_t)s.row * pb, y.x * w, y.y * w);
-                if ((k & 15) == 15) { acc += part; part = 0.0f; }
+                if (((t.t0 + k) & (kFlush - 1)) == kFlush - 1) { acc += part; part = 0.0f; }
                 dda_step(s);
                 Yc += m.ld;
                 Sc += m.ld;
@@ -312,13 +316,17 @@ __global__ __launch_bounds__(kWG) void k_score_slab(MapP m, GenP g, const Trk *t
                     dda_step(st[q]);
                 }
             }
-        }
+            if ((c & (kFlush - 1)) == kFlush - 1) {  // wave-uniform
 #pragma unroll
-        for (int q = 0; q < TPT; ++q) {
-            acc[q] += part[q];
-            part[q] = 0.0f;
+                for (int q = 0; q < TPT; ++q) {
+                    acc[q] += part[q];
+                    part[q] = 0.0f;
+                }
+            }
         }
     }
+#pragma unroll
+    for (int q = 0; q < TPT; ++q) acc[q] += part[q];
 
     uint64_t key = 0;
 #pragma unroll

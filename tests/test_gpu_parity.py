@@ -83,6 +83,9 @@ def test_config1_plain_map_full(orc, stt, ctx):
         zk, jk = stt.key_decode(key)
         assert_argmax(jk, z_orc)
         assert zk == np.float32(z[jk])
+    res = list(_score_both(ctx, stt, m, gen=_gen(stt), n=n).values())
+    # both scorers walk each template in the same order with the same partial-sum grid
+    assert np.array_equal(res[0][0], res[1][0]) and res[0][1] == res[1][1]
 
 
 def test_norm_n_is_mean(orc, stt, ctx):
@@ -208,8 +211,8 @@ def test_argmax_entry_point(stt, ctx):
     import torch
     _say("argmax")
     z = np.random.default_rng(4).standard_normal(1_000_003).astype(np.float32)
-    z[[5, 77, 999_999]] = np.float32(np.nan)
     z[[1000, 2000]] = z.max() + 1
+    z[[5, 77, 999_999]] = np.float32(np.nan)
     key = ctx.argmax(torch.from_numpy(z).cuda(), first=10)
     zk, jk = stt.key_decode(key_to_host(key))
     assert jk == 1010 and zk == z[1000]
