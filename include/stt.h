@@ -120,8 +120,13 @@ stt_status stt_kernel_ms_total(stt_ctx *ctx, int32_t which, double *total_ms, in
 /* Scorer selection, for tests and tuning: path 0 = automatic, 1 = direct
  * gathers from global memory, 2 = LDS time slabs (STT_EUNSUPPORTED when one
  * column of the map does not fit lds_bytes). lds_bytes (0 = keep) is the slab
- * budget per workgroup, in [1024, 163840]; default 81920 (two per CU). */
+ * budget per workgroup, in [1024, 163840]; default 163840. */
 stt_status stt_set_path(stt_ctx *ctx, int32_t path, int32_t lds_bytes);
+
+/* Shape of the LDS-slab scorer: wg lanes per workgroup and tpt templates per
+ * lane; STT_EUNSUPPORTED for a shape not compiled in (256x4, 512x4, 1024x4,
+ * 512x2, 1024x2, 256x8, 512x8). Default 1024x4. */
+stt_status stt_set_slab_shape(stt_ctx *ctx, int32_t wg, int32_t tpt);
 
 /* Template generation (Sec. III: each template from six random numbers plus
  * a random delay, before Eq. 8). Writes out_dev[i] = track j = first + i for

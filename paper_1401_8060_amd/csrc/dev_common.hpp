@@ -131,6 +131,36 @@ STT_HD void floor_divmod(int64_t a, uint32_t q, int32_t &quo, uint32_t &rem)
     rem = (uint32_t)r;
 }
 
+// State at an arbitrary integer k0 (k0 < 0 "rewinds" before the first column).
+// The recurrence is exact for every integer k, so stepping from k0 reaches the
+// exact rows at k = 0..Dt; rows at k < 0 or k > Dt are meaningless (and may
+// leave [0, F)), which callers mask. row and dq are kept modulo 2^32 (the true
+// values at negative k may not fit 32 bits), which is exact for the valid k.
+STT_HD Dda dda_init_at(const Trk &t, int32_t k0)
+{
+    Dda s;
+    const int64_t Dt = t.t2 - t.t0;
+    const uint32_t Q = (uint32_t)(Dt * Dt) << 8;
+    s.Q = Q;
+    const int64_t A = Dt * Dt * (int64_t)t.f0;
+    const int64_t C = (int64_t)t.f0 - 2 * (int64_t)t.f1 + (int64_t)t.f2;
+    const int64_t B = 2 * Dt * ((int64_t)t.f1 - (int64_t)t.f0);
+    const int64_t k = k0;
+    const int64_t num = A + B * k + C * k * k;
+    const int64_t del = B + C * (2 * k + 1);
+    int64_t q = num / (int64_t)Q, r = num - q * (int64_t)Q;
+    if (r < 0) { r += Q; --q; }
+    s.row = (int32_t)(uint32_t)(uint64_t)q;
+    s.rem = (uint32_t)r;
+    q = del / (int64_t)Q;
+    r = del - q * (int64_t)Q;
+    if (r < 0) { r += Q; --q; }
+    s.dq = (int32_t)(uint32_t)(uint64_t)q;
+    s.dr = (uint32_t)r;
+    floor_divmod(2 * C, Q, s.ddq, s.ddr);
+    return s;
+}
+
 STT_HD Dda dda_init(const Trk &t)
 {
     Dda s;
@@ -151,11 +181,11 @@ STT_HD void dda_step(Dda &s)
     uint32_t r = s.rem + s.dr;
     const bool c1 = r >= s.Q;
     s.rem = c1 ? r - s.Q : r;
-    s.row += s.dq + (c1 ? 1 : 0);
+    s.row = (int32_t)((uint32_t)s.row + (uint32_t)s.dq + (c1 ? 1u : 0u));  // modulo 2^32
     uint32_t d = s.dr + s.ddr;
     const bool c2 = d >= s.Q;
     s.dr = c2 ? d - s.Q : d;
-    s.dq += s.ddq + (c2 ? 1 : 0);
+    s.dq = (int32_t)((uint32_t)s.dq + (uint32_t)s.ddq + (c2 ? 1u : 0u));
 }
 
 // ----------------------------------------------------------------------------

@@ -235,46 +235,47 @@ __global__ __launch_bounds__(256) void k_bin_scatter(MapP m, GenP g, const Trk *
 }
 
 // ---------------------------------------------------------------- time-slab scorer
-// One workgroup = 256 lanes x TPT templates taken consecutively from the
-// binned order, so they start and end in nearly the same columns. The
-// workgroup sweeps its column range in slabs of S columns: all lanes stage a
-// slab (F rows x S columns of p = Y/sigma, 8 B per pixel) into LDS with
-// coalesced loads, then each lane walks its templates one column at a time,
-// gathering its pixel from LDS, applying the exact phase and accumulating.
-// Per-template partial sums are FP32 within a slab and FP64 across slabs.
+// One workgroup = WG lanes x TPT templates taken consecutively from the binned
+// order; wave w owns the 64*TPT consecutive entries starting at w*64*TPT, so a
+// wave's templates start and end in nearly the same columns. The workgroup
+// sweeps the union of its waves' column ranges in slabs of S columns: all lanes
+// stage a slab (F rows x S columns of p = Y/sigma, 8 B per pixel) into LDS with
+// coalesced loads, then each wave walks its own column range through the slab.
+// Every template's DDA is started at its wave's first column (rewound when the
+// template starts later), so all lanes step together: no divergent branches in
+// the inner loop, the pixels outside a template are masked by a select and
+// their LDS address clamped into the column. Per-template partial sums are FP32
+// between flush columns and FP64 across them.
 
-template <int TPT, bool EXPL>
-__global__ __launch_bounds__(kWG) void k_score_slab(MapP m, GenP g, const Trk *tr, const uint32_t *order,
-                                                    uint64_t first, int64_t n, int S, int32_t norm, float *snr,
-                                                    uint64_t *best)
+template <int WG, int TPT, bool EXPL>
+__global__ __launch_bounds__(WG) void k_score_slab(MapP m, GenP g, const Trk *tr, const uint32_t *order,
+                                                   uint64_t first, int64_t n, int S, int32_t norm, float *snr,
+                                                   uint64_t *best)
 {
     extern __shared__ float2 slab[];
     __shared__ int blo, bhi;
     if (threadIdx.x == 0) { blo = 0x7fffffff; bhi = -1; }
 
+    const int lane = threadIdx.x & 63;
+    const int64_t wbase = (int64_t)blockIdx.x * (WG * TPT) + (int64_t)(threadIdx.x >> 6) * (64 * TPT);
+    Trk tk[TPT];
     int32_t t0[TPT];
     uint32_t span[TPT], pa[TPT], pb[TPT], idx[TPT];
     bool ok[TPT], live[TPT];
-    Dda st[TPT];
-    float part[TPT];
-    double acc[TPT];
     int lo = 0x7fffffff, hi = -1;
-    const int64_t base = (int64_t)blockIdx.x * (kWG * TPT);
 #pragma unroll
     for (int q = 0; q < TPT; ++q) {
-        const int64_t e = base + q * kWG + threadIdx.x;
+        const int64_t e = wbase + q * 64 + lane;
         live[q] = e < n;
         idx[q] = live[q] ? order[e] : 0u;
-        Trk t = EXPL ? tr[live[q] ? idx[q] : 0] : draw_track(g, first + idx[q]);
+        Trk t = EXPL ? tr[idx[q]] : draw_track(g, first + idx[q]);
         ok[q] = live[q] && (!EXPL || track_ok(t, m));
         if (!ok[q]) t = Trk{0, 1, 0u, 0u, 0u, 0};  // never active: (c - t0) > span below
-        st[q] = dda_init(t);
+        tk[q] = t;
         t0[q] = ok[q] ? t.t0 : 0x7fffffff;
         span[q] = ok[q] ? (uint32_t)(t.t2 - t.t0) : 0u;
         pa[q] = phase_a(m.fq4_lo, t.dtau);
         pb[q] = phase_b(m.dfq4, t.dtau);
-        part[q] = 0.0f;
-        acc[q] = 0.0;
         if (ok[q]) {
             lo = min(lo, t.t0);
             hi = max(hi, t.t2);
@@ -282,26 +283,45 @@ __global__ __launch_bounds__(kWG) void k_score_slab(MapP m, GenP g, const Trk *t
     }
     lo = wave_min_i32(lo);
     hi = wave_max_i32(hi);
+    Dda st[TPT];
+    float part[TPT];
+    double acc[TPT];
+    const int start = lo == 0x7fffffff ? 0 : lo;
+#pragma unroll
+    for (int q = 0; q < TPT; ++q) {
+        st[q] = dda_init_at(tk[q], start - tk[q].t0);
+        part[q] = 0.0f;
+        acc[q] = 0.0;
+    }
     __syncthreads();
-    if ((threadIdx.x & 63) == 0) {
+    if (lane == 0) {
         atomicMin(&blo, lo);
         atomicMax(&bhi, hi);
     }
     __syncthreads();
     const int c_first = blo, c_last = bhi;
     const int F = m.F;
+    const int rmax = F - 1;
+    // staging walk: element e = tid + i*WG of the slab is (column e / F, row e % F)
+    const int dcol = WG / F, drow = WG % F;
+    const int col0 = threadIdx.x / F, row0 = threadIdx.x % F;
 
     for (int c0 = c_first; c0 <= c_last; c0 += S) {
         const int ncol = min(S, c_last - c0 + 1);
         __syncthreads();  // the previous slab has been consumed
-        for (int col = 0; col < ncol; ++col) {
-            const float2 *Yc = m.Y + (int64_t)(c0 + col) * m.ld;
-            const float *Sc = m.sig + (int64_t)(c0 + col) * m.ld;
-            float2 *dst = slab + col * F;
-            for (int r = threadIdx.x; r < F; r += kWG) {
-                const float2 y = Yc[r];
-                const float w = 1.0f / Sc[r];
-                dst[r] = make_float2(y.x * w, y.y * w);
+        {
+            int col = col0, r = row0;
+            const float2 *Yb = m.Y + (int64_t)c0 * m.ld;
+            const float *Sb = m.sig + (int64_t)c0 * m.ld;
+#pragma unroll 4
+            for (int e = threadIdx.x; e < ncol * F; e += WG) {
+                const int64_t off = (int64_t)col * m.ld + r;
+                const float2 y = Yb[off];
+                const float w = 1.0f / Sb[off];
+                slab[col * F + r] = make_float2(y.x * w, y.y * w);
+                r += drow;
+                col += dcol;
+                if (r >= F) { r -= F; ++col; }
             }
         }
         __syncthreads();
@@ -310,11 +330,11 @@ __global__ __launch_bounds__(kWG) void k_score_slab(MapP m, GenP g, const Trk *t
             const float2 *col = slab + (c - c0) * F;
 #pragma unroll
             for (int q = 0; q < TPT; ++q) {
-                if ((uint32_t)c - (uint32_t)t0[q] <= span[q]) {
-                    const float2 p = col[st[q].row];
-                    part[q] += rot_re(pa[q] + (uint32_t)st[q].row * pb[q], p.x, p.y);
-                    dda_step(st[q]);
-                }
+                const bool act = (uint32_t)c - (uint32_t)t0[q] <= span[q];
+                const float2 p = col[min(max(st[q].row, 0), rmax)];
+                const float v = rot_re(pa[q] + (uint32_t)st[q].row * pb[q], p.x, p.y);
+                part[q] += act ? v : 0.0f;
+                dda_step(st[q]);
             }
             if ((c & (kFlush - 1)) == kFlush - 1) {  // wave-uniform
 #pragma unroll
@@ -325,14 +345,12 @@ __global__ __launch_bounds__(kWG) void k_score_slab(MapP m, GenP g, const Trk *t
             }
         }
     }
-#pragma unroll
-    for (int q = 0; q < TPT; ++q) acc[q] += part[q];
 
     uint64_t key = 0;
 #pragma unroll
     for (int q = 0; q < TPT; ++q) {
         if (!live[q]) continue;
-        const float z = ok[q] ? finish(acc[q], (int32_t)span[q] + 1, norm) : __builtin_nanf("");
+        const float z = ok[q] ? finish(acc[q] + part[q], (int32_t)span[q] + 1, norm) : __builtin_nanf("");
         if (snr) snr[idx[q]] = z;
         const uint64_t k = key_encode(z, (uint32_t)(first + idx[q]));
         key = k > key ? k : key;

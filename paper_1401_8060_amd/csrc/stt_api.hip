@@ -22,7 +22,9 @@ struct stt_ctx {
     void *scratch = nullptr;
     size_t scratch_bytes = 0;
     int path = 0;  // 0 auto, 1 direct, 2 slab
-    int lds_bytes = 80 * 1024;  // slab budget per workgroup (two workgroups per CU)
+    int lds_bytes = 160 * 1024;  // slab budget per workgroup
+    int slab_wg = 1024;          // slab scorer shape: lanes per workgroup
+    int slab_tpt = 4;            //                    templates per lane
     // Timing: every call takes six events from a pool (start/end of the scoring
     // kernel, of the binning kernels and of the whole call); queries sum them.
     bool timing = false;
@@ -168,6 +170,47 @@ int bucket_shift(int T)
     return wb;
 }
 
+template <int WG, int TPT, bool EXPL>
+stt_status launch_slab_t(stt_ctx *c, const MapP &m, const GenP &g, const Trk *tr, const uint32_t *order,
+                         int64_t first, int64_t n, int S, size_t shm, int32_t norm, float *snr, uint64_t *best)
+{
+    auto kern = k_score_slab<WG, TPT, EXPL>;
+    if (shm > 64 * 1024)
+        STT_HIP(c, hipFuncSetAttribute((const void *)kern, hipFuncAttributeMaxDynamicSharedMemorySize, (int)shm));
+    const unsigned grid = (unsigned)((n + WG * TPT - 1) / (WG * TPT));
+    hipLaunchKernelGGL(kern, dim3(grid), dim3(WG), shm, c->stream, m, g, tr, order, (uint64_t)first, n, S, norm, snr,
+                       best);
+    STT_HIP(c, hipGetLastError());
+    return STT_OK;
+}
+
+// The (workgroup size, templates per lane) shapes compiled into the library.
+template <bool EXPL>
+stt_status launch_slab(stt_ctx *c, int wg, int tpt, const MapP &m, const GenP &g, const Trk *tr,
+                       const uint32_t *order, int64_t first, int64_t n, int S, size_t shm, int32_t norm, float *snr,
+                       uint64_t *best)
+{
+#define STT_SLAB_CASE(W, P)                                                                            \
+    if (wg == W && tpt == P) return launch_slab_t<W, P, EXPL>(c, m, g, tr, order, first, n, S, shm, norm, snr, best);
+    STT_SLAB_CASE(256, 4)
+    STT_SLAB_CASE(512, 4)
+    STT_SLAB_CASE(1024, 4)
+    STT_SLAB_CASE(512, 2)
+    STT_SLAB_CASE(1024, 2)
+    STT_SLAB_CASE(256, 8)
+    STT_SLAB_CASE(512, 8)
+#undef STT_SLAB_CASE
+    return fail(c, STT_EUNSUPPORTED, "no slab scorer compiled for workgroup %d x %d templates", wg, tpt);
+}
+
+bool slab_shape_ok(int wg, int tpt)
+{
+    static const int shapes[][2] = {{256, 4}, {512, 4}, {1024, 4}, {512, 2}, {1024, 2}, {256, 8}, {512, 8}};
+    for (const auto &s : shapes)
+        if (s[0] == wg && s[1] == tpt) return true;
+    return false;
+}
+
 template <bool EXPL>
 stt_status score_impl(stt_ctx *c, const stt_map *map, const GenP &g, const Trk *tr, int64_t first, int64_t n,
                       int32_t norm, float *snr, uint64_t *best)
@@ -215,17 +258,11 @@ stt_status score_impl(stt_ctx *c, const stt_map *map, const GenP &g, const Trk *
         STT_HIP(c, hipGetLastError());
         ev_record(c, 3);
         c->used[1] = true;
-        constexpr int TPT = 4;
-        const unsigned grid = (unsigned)((n + kWG * TPT - 1) / (kWG * TPT));
         const int S = std::min(slab_cols, m.T);
         const size_t shm = sizeof(float2) * (size_t)S * m.F;
-        if (shm > 64 * 1024)
-            STT_HIP(c, hipFuncSetAttribute((const void *)k_score_slab<TPT, EXPL>,
-                                           hipFuncAttributeMaxDynamicSharedMemorySize, (int)shm));
         ev_record(c, 0);
-        hipLaunchKernelGGL((k_score_slab<TPT, EXPL>), dim3(grid), dim3(kWG), shm, c->stream, m, g, tr,
-                           (const uint32_t *)order, (uint64_t)first, n, S, norm, snr, best);
-        STT_HIP(c, hipGetLastError());
+        s = launch_slab<EXPL>(c, c->slab_wg, c->slab_tpt, m, g, tr, order, first, n, S, shm, norm, snr, best);
+        if (s != STT_OK) return s;
         ev_record(c, 1);
         c->used[0] = true;
     }
@@ -351,6 +388,15 @@ stt_status stt_set_path(stt_ctx *c, int32_t path, int32_t lds_bytes)
         return fail(c, STT_ERANGE, "lds_bytes=%d outside [1024, 163840]", lds_bytes);
     c->path = path;
     if (lds_bytes) c->lds_bytes = lds_bytes;
+    return STT_OK;
+}
+
+stt_status stt_set_slab_shape(stt_ctx *c, int32_t wg, int32_t tpt)
+{
+    if (!c) return STT_EINVAL;
+    if (!slab_shape_ok(wg, tpt)) return fail(c, STT_EUNSUPPORTED, "no slab scorer for %d x %d", wg, tpt);
+    c->slab_wg = wg;
+    c->slab_tpt = tpt;
     return STT_OK;
 }
 

@@ -72,6 +72,24 @@ def test_dda_rows_bit_exact(orc, devmath):
         assert got == want, c
 
 
+def test_rewound_dda_reaches_exact_rows(orc, devmath):
+    """Starting the DDA up to a whole map before the template (as the slab scorer
+    does for the first column of a wave) still gives the exact rows."""
+    sel = np.random.default_rng(8)
+    cases = []
+    for _ in range(2000):
+        F = int(sel.choice([1, 7, 1000, 32767]))
+        Dt = int(sel.choice([1, 2, 5, 64, 999, 2895]))
+        k0 = -int(sel.choice([0, 1, 15, 63, 500, 2895]))
+        f = sel.integers(0, F * 256, size=3)
+        cases.append((0, Dt, int(f[0]), int(f[1]), int(f[2]), k0, F))
+    out = devmath([f"rowsat {a} {b} {c} {d} {e} {k}" for (a, b, c, d, e, k, F) in cases])
+    for c, line in zip(cases, out):
+        got = [int(x) for x in line.split()]
+        want = orc.rows(np.array(c[:5] + (0,), dtype=orc.TRACK_DTYPE), c[6]).tolist()
+        assert got == want, c
+
+
 def test_phase_rotation_accuracy(devmath):
     sel = np.random.default_rng(3)
     ph = sel.integers(0, 2 ** 32, 20000).tolist() + [0, 2 ** 30, 2 ** 31, 3 * 2 ** 30, 2 ** 32 - 1,

@@ -110,10 +110,33 @@ def test_slab_boundaries_and_ragged_tail(orc, stt, ctx, lds):
     z_orc = orc.score_gen(orc.Map(Y, s), 4, 2, 10, D10MS, first, n)
     ctx.set_path(stt.PATH_SLAB, lds)
     snr, key = ctx.score(m, gen=_gen(stt, 4, 2), first=first, n=n)
-    ctx.set_path(stt.PATH_AUTO, 80 * 1024)
+    ctx.set_path(stt.PATH_AUTO, 160 * 1024)
     assert_close(snr.cpu().numpy(), z_orc, what="slab")
     zk, jk = stt.key_decode(key_to_host(key))
     assert_argmax(jk - first, z_orc)
+
+
+SHAPES = [(256, 4), (512, 4), (1024, 4), (512, 2), (1024, 2), (256, 8), (512, 8)]
+
+
+@pytest.mark.parametrize("wg,tpt", SHAPES)
+def test_every_slab_shape(orc, stt, ctx, wg, tpt):
+    """Each compiled (workgroup, templates per lane) shape of the slab scorer, on a map whose
+    width leaves a ragged staging walk (F=333) and a call that ends in a partial workgroup."""
+    _say("shape", wg, tpt)
+    T, F, n, first = 257, 333, 9000, 77
+    Y, s = synth.noise_map(T, F, seed=90, sigma=("loguniform", 0.5, 2.0))
+    m = stt.Map(*to_dev(Y, s))
+    z_orc = orc.score_gen(orc.Map(Y, s), 21, 4, 10, D10MS, first, n)
+    ctx.set_path(stt.PATH_SLAB)
+    ctx.set_slab_shape(wg, tpt)
+    try:
+        snr, key = ctx.score(m, gen=_gen(stt, 21, 4), first=first, n=n)
+    finally:
+        ctx.set_slab_shape(1024, 4)
+        ctx.set_path(stt.PATH_AUTO)
+    assert_close(snr.cpu().numpy(), z_orc, what=f"shape {wg}x{tpt}")
+    assert_argmax(stt.key_decode(key_to_host(key))[1] - first, z_orc)
 
 
 def test_explicit_tracks_and_invalid_ones(orc, stt, ctx):
