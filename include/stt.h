@@ -124,9 +124,14 @@ stt_status stt_kernel_ms_total(stt_ctx *ctx, int32_t which, double *total_ms, in
 stt_status stt_set_path(stt_ctx *ctx, int32_t path, int32_t lds_bytes);
 
 /* Shape of the LDS-slab scorer: wg lanes per workgroup and tpt templates per
- * lane; STT_EUNSUPPORTED for a shape not compiled in (256x4, 512x4, 1024x4,
- * 512x2, 1024x2, 256x8, 512x8). Default 1024x4. */
+ * lane; STT_EUNSUPPORTED for a shape not compiled in (1024x4, 512x4, 256x4,
+ * 1024x2, 512x2). Default 1024x4. */
 stt_status stt_set_slab_shape(stt_ctx *ctx, int32_t wg, int32_t tpt);
+
+/* Phase-factor evaluation: hw = 1 (default) the hardware sine/cosine
+ * instructions (argument in turns; measured on gfx950 at most 1.3e-7 from the
+ * true values over a full turn); hw = 0 a polynomial accurate to 1.5e-7. */
+stt_status stt_set_trig(stt_ctx *ctx, int32_t hw);
 
 /* Template generation (Sec. III: each template from six random numbers plus
  * a random delay, before Eq. 8). Writes out_dev[i] = track j = first + i for

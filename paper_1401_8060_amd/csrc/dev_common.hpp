@@ -188,6 +188,44 @@ STT_HD void dda_step(Dda &s)
     s.dq = (int32_t)((uint32_t)s.dq + (uint32_t)s.ddq + (c2 ? 1u : 0u));
 }
 
+// The same walk in FP64, for the scorers' inner loops. With num'(k) =
+// num(k) + 1/2 (an integer plus a half, |num'| < 2^52, so exact in FP64) the
+// two adds per step are exact, and row = trunc(num' * (1/Q)) is the exact
+// floor for every valid k: num/Q is at least 1/Q away from the next integer
+// above and 1/(2Q) >= 2^-32 exceeds the product's error of at most 2^-37
+// (relative 2^-52 on a value below 2^15). Rows of invalid k (k < 0 or k > Dt)
+// are meaningless and must be masked by the caller.
+struct DdaF {
+    double num;   // num(k) + 1/2
+    double del;   // num(k+1) - num(k)
+    double dd;    // 2C
+    double invq;  // 1/Q rounded to nearest
+};
+
+STT_HD DdaF ddaf_init_at(const Trk &t, int32_t k0)
+{
+    DdaF s;
+    const int64_t Dt = t.t2 - t.t0;
+    const int64_t Q = (Dt * Dt) << 8;
+    const int64_t A = Dt * Dt * (int64_t)t.f0;
+    const int64_t C = (int64_t)t.f0 - 2 * (int64_t)t.f1 + (int64_t)t.f2;
+    const int64_t B = 2 * Dt * ((int64_t)t.f1 - (int64_t)t.f0);
+    const int64_t k = k0;
+    s.num = (double)(A + B * k + C * k * k) + 0.5;
+    s.del = (double)(B + C * (2 * k + 1));
+    s.dd = (double)(2 * C);
+    s.invq = 1.0 / (double)Q;
+    return s;
+}
+
+STT_HD int32_t ddaf_row(const DdaF &s) { return (int32_t)(s.num * s.invq); }
+
+STT_HD void ddaf_step(DdaF &s)
+{
+    s.num += s.del;
+    s.del += s.dd;
+}
+
 // ----------------------------------------------------------------------------
 // Phase factor of Eq. 8. f dtau = (fq4/16 Hz)(dtau 2^-28 s) = fq4*dtau 2^-32
 // turns, so the phase is the 32-bit wrap of fq4*dtau: exact. Per track,

@@ -76,6 +76,29 @@ __device__ __forceinline__ float finish(double S, int32_t N, int32_t norm)
     return (float)(norm == 1 ? S / (double)N : S / sqrt((double)N));
 }
 
+// Phase of row r for a template: pa + r*pb (mod 2^32), with the multiply split
+// into 24-bit pieces (r < 2^24 for every valid row) so that it maps onto the
+// full-rate 24-bit multiplies: r*pb = r*(pb mod 2^24) + (r*(pb >> 24)) << 24.
+__device__ __forceinline__ uint32_t phase_of(uint32_t pa, uint32_t pbl, uint32_t pbh, int32_t row)
+{
+    const uint32_t r = (uint32_t)row;
+    return (__umul24(r, pbl) + pa) + ((uint32_t)__umul24(r, pbh) << 24);
+}
+
+// Re[exp(2 pi i ph/2^32) p]. HW = false: the polynomial of rot_re (about
+// 1.5e-7 absolute). HW = true: the hardware sine and cosine, which take their
+// argument in turns; measured on gfx950 over 2^22 phases spanning a turn:
+// at most 1.25e-7 absolute error, rms 3.5e-8, no bias.
+template <bool HW>
+__device__ __forceinline__ float rot(uint32_t ph, float pr, float pim)
+{
+    if (HW) {
+        const float x = (float)(int32_t)ph * 2.3283064365386963e-10f;  // turns in [-1/2, 1/2)
+        return fmaf(__builtin_amdgcn_cosf(x), pr, -__builtin_amdgcn_sinf(x) * pim);
+    }
+    return rot_re(ph, pr, pim);
+}
+
 // A fill kernel rather than a memset node, so that captured graphs replay it faithfully.
 __global__ __launch_bounds__(256) void k_fill_u32(uint32_t *p, int64_t n, uint32_t v)
 {
@@ -93,7 +116,7 @@ __global__ __launch_bounds__(256) void k_make_tracks(GenP g, uint64_t first, int
 
 // ---------------------------------------------------------------- direct scorer
 
-template <bool EXPL>
+template <bool EXPL, bool HW>
 __global__ __launch_bounds__(kWG) void k_score_direct(MapP m, GenP g, const Trk *tr, uint64_t first, int64_t n,
                                                       int32_t norm, float *snr, uint64_t *best)
 {
@@ -103,19 +126,21 @@ __global__ __launch_bounds__(kWG) void k_score_direct(MapP m, GenP g, const Trk 
         const Trk t = EXPL ? tr[i] : draw_track(g, first + (uint64_t)i);
         float z = __builtin_nanf("");
         if (!EXPL || track_ok(t, m)) {
-            Dda s = dda_init(t);
+            DdaF s = ddaf_init_at(t, 0);
             const uint32_t pa = phase_a(m.fq4_lo, t.dtau), pb = phase_b(m.dfq4, t.dtau);
+            const uint32_t pbl = pb & 0xFFFFFFu, pbh = pb >> 24;
             const int32_t N = t.t2 - t.t0 + 1;
             const float2 *Yc = m.Y + (int64_t)t.t0 * m.ld;
             const float *Sc = m.sig + (int64_t)t.t0 * m.ld;
             double acc = 0.0;
             float part = 0.0f;
             for (int32_t k = 0; k < N; ++k) {
-                const float2 y = Yc[s.row];
-                const float w = 1.0f / Sc[s.row];
-                part += rot_re(pa + (uint32_t)s.row * pb, y.x * w, y.y * w);
+                const int32_t row = ddaf_row(s);
+                const float2 y = Yc[row];
+                const float w = 1.0f / Sc[row];
+                part += rot<HW>(phase_of(pa, pbl, pbh, row), y.x * w, y.y * w);
                 if (((t.t0 + k) & (kFlush - 1)) == kFlush - 1) { acc += part; part = 0.0f; }
-                dda_step(s);
+                ddaf_step(s);
                 Yc += m.ld;
                 Sc += m.ld;
             }
@@ -247,7 +272,37 @@ __global__ __launch_bounds__(256) void k_bin_scatter(MapP m, GenP g, const Trk *
 // their LDS address clamped into the column. Per-template partial sums are FP32
 // between flush columns and FP64 across them.
 
-template <int WG, int TPT, bool EXPL>
+// Walk columns ca..cb of the current slab (column c0 at slab[0]) for the TPT
+// templates of this lane. MASK = false is the wave's core, where every
+// template of the wave covers every column: no select and no clamp.
+template <int TPT, bool MASK, bool HW>
+__device__ __forceinline__ void walk(int ca, int cb, int c0, const float2 *slab, int F, const int32_t (&t0)[TPT],
+                                     const uint32_t (&span)[TPT], const uint32_t (&pa)[TPT],
+                                     const uint32_t (&pbl)[TPT], const uint32_t (&pbh)[TPT], DdaF (&st)[TPT],
+                                     float (&part)[TPT], double (&acc)[TPT])
+{
+    for (int c = ca; c <= cb; ++c) {
+        const float2 *col = slab + (c - c0) * F;
+#pragma unroll
+        for (int q = 0; q < TPT; ++q) {
+            const int32_t row = ddaf_row(st[q]);
+            const bool act = !MASK || (uint32_t)c - (uint32_t)t0[q] <= span[q];
+            const float2 p = col[act ? row : 0];
+            const float v = rot<HW>(phase_of(pa[q], pbl[q], pbh[q], row), p.x, p.y);
+            part[q] += act ? v : 0.0f;
+            ddaf_step(st[q]);
+        }
+        if ((c & (kFlush - 1)) == kFlush - 1) {  // wave-uniform
+#pragma unroll
+            for (int q = 0; q < TPT; ++q) {
+                acc[q] += part[q];
+                part[q] = 0.0f;
+            }
+        }
+    }
+}
+
+template <int WG, int TPT, bool EXPL, bool HW>
 __global__ __launch_bounds__(WG) void k_score_slab(MapP m, GenP g, const Trk *tr, const uint32_t *order,
                                                    uint64_t first, int64_t n, int S, int32_t norm, float *snr,
                                                    uint64_t *best)
@@ -260,9 +315,10 @@ __global__ __launch_bounds__(WG) void k_score_slab(MapP m, GenP g, const Trk *tr
     const int64_t wbase = (int64_t)blockIdx.x * (WG * TPT) + (int64_t)(threadIdx.x >> 6) * (64 * TPT);
     Trk tk[TPT];
     int32_t t0[TPT];
-    uint32_t span[TPT], pa[TPT], pb[TPT], idx[TPT];
+    uint32_t span[TPT], pa[TPT], pbl[TPT], pbh[TPT], idx[TPT];
     bool ok[TPT], live[TPT];
-    int lo = 0x7fffffff, hi = -1;
+    int lo = 0x7fffffff, hi = -1;        // union of this wave's templates
+    int clo = -1, chi = 0x7fffffff;      // intersection (the core)
 #pragma unroll
     for (int q = 0; q < TPT; ++q) {
         const int64_t e = wbase + q * 64 + lane;
@@ -275,21 +331,34 @@ __global__ __launch_bounds__(WG) void k_score_slab(MapP m, GenP g, const Trk *tr
         t0[q] = ok[q] ? t.t0 : 0x7fffffff;
         span[q] = ok[q] ? (uint32_t)(t.t2 - t.t0) : 0u;
         pa[q] = phase_a(m.fq4_lo, t.dtau);
-        pb[q] = phase_b(m.dfq4, t.dtau);
+        const uint32_t pb = phase_b(m.dfq4, t.dtau);
+        pbl[q] = pb & 0xFFFFFFu;
+        pbh[q] = pb >> 24;
         if (ok[q]) {
             lo = min(lo, t.t0);
             hi = max(hi, t.t2);
+            clo = max(clo, t.t0);
+            chi = min(chi, t.t2);
+        } else {
+            clo = 0x7fffffff;  // a lane without a template: no unmasked core for this wave
+            chi = -1;
         }
     }
     lo = wave_min_i32(lo);
     hi = wave_max_i32(hi);
-    Dda st[TPT];
+    clo = wave_max_i32(clo);
+    chi = wave_min_i32(chi);
+    if (clo > chi) {  // empty core: everything goes through the masked walk
+        clo = hi + 1;
+        chi = hi;
+    }
+    DdaF st[TPT];
     float part[TPT];
     double acc[TPT];
     const int start = lo == 0x7fffffff ? 0 : lo;
 #pragma unroll
     for (int q = 0; q < TPT; ++q) {
-        st[q] = dda_init_at(tk[q], start - tk[q].t0);
+        st[q] = ddaf_init_at(tk[q], start - tk[q].t0);
         part[q] = 0.0f;
         acc[q] = 0.0;
     }
@@ -301,7 +370,6 @@ __global__ __launch_bounds__(WG) void k_score_slab(MapP m, GenP g, const Trk *tr
     __syncthreads();
     const int c_first = blo, c_last = bhi;
     const int F = m.F;
-    const int rmax = F - 1;
     // staging walk: element e = tid + i*WG of the slab is (column e / F, row e % F)
     const int dcol = WG / F, drow = WG % F;
     const int col0 = threadIdx.x / F, row0 = threadIdx.x % F;
@@ -326,24 +394,9 @@ __global__ __launch_bounds__(WG) void k_score_slab(MapP m, GenP g, const Trk *tr
         }
         __syncthreads();
         const int ca = max(c0, lo), cb = min(c0 + ncol - 1, hi);  // this wave's columns in the slab
-        for (int c = ca; c <= cb; ++c) {
-            const float2 *col = slab + (c - c0) * F;
-#pragma unroll
-            for (int q = 0; q < TPT; ++q) {
-                const bool act = (uint32_t)c - (uint32_t)t0[q] <= span[q];
-                const float2 p = col[min(max(st[q].row, 0), rmax)];
-                const float v = rot_re(pa[q] + (uint32_t)st[q].row * pb[q], p.x, p.y);
-                part[q] += act ? v : 0.0f;
-                dda_step(st[q]);
-            }
-            if ((c & (kFlush - 1)) == kFlush - 1) {  // wave-uniform
-#pragma unroll
-                for (int q = 0; q < TPT; ++q) {
-                    acc[q] += part[q];
-                    part[q] = 0.0f;
-                }
-            }
-        }
+        walk<TPT, true, HW>(ca, min(cb, clo - 1), c0, slab, F, t0, span, pa, pbl, pbh, st, part, acc);
+        walk<TPT, false, HW>(max(ca, clo), min(cb, chi), c0, slab, F, t0, span, pa, pbl, pbh, st, part, acc);
+        walk<TPT, true, HW>(max(ca, chi + 1), cb, c0, slab, F, t0, span, pa, pbl, pbh, st, part, acc);
     }
 
     uint64_t key = 0;

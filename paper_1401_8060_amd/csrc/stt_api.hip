@@ -25,6 +25,7 @@ struct stt_ctx {
     int lds_bytes = 160 * 1024;  // slab budget per workgroup
     int slab_wg = 1024;          // slab scorer shape: lanes per workgroup
     int slab_tpt = 4;            //                    templates per lane
+    bool hw_trig = true;         // hardware sine/cosine (measured max error 1.3e-7) or the polynomial
     // Timing: every call takes six events from a pool (start/end of the scoring
     // kernel, of the binning kernels and of the whole call); queries sum them.
     bool timing = false;
@@ -170,11 +171,11 @@ int bucket_shift(int T)
     return wb;
 }
 
-template <int WG, int TPT, bool EXPL>
+template <int WG, int TPT, bool EXPL, bool HW>
 stt_status launch_slab_t(stt_ctx *c, const MapP &m, const GenP &g, const Trk *tr, const uint32_t *order,
                          int64_t first, int64_t n, int S, size_t shm, int32_t norm, float *snr, uint64_t *best)
 {
-    auto kern = k_score_slab<WG, TPT, EXPL>;
+    auto kern = k_score_slab<WG, TPT, EXPL, HW>;
     if (shm > 64 * 1024)
         STT_HIP(c, hipFuncSetAttribute((const void *)kern, hipFuncAttributeMaxDynamicSharedMemorySize, (int)shm));
     const unsigned grid = (unsigned)((n + WG * TPT - 1) / (WG * TPT));
@@ -185,28 +186,37 @@ stt_status launch_slab_t(stt_ctx *c, const MapP &m, const GenP &g, const Trk *tr
 }
 
 // The (workgroup size, templates per lane) shapes compiled into the library.
+static const int kShapes[][2] = {{1024, 4}, {512, 4}, {256, 4}, {1024, 2}, {512, 2}};
+
+template <bool EXPL, bool HW>
+stt_status launch_slab_h(stt_ctx *c, int wg, int tpt, const MapP &m, const GenP &g, const Trk *tr,
+                         const uint32_t *order, int64_t first, int64_t n, int S, size_t shm, int32_t norm, float *snr,
+                         uint64_t *best)
+{
+#define STT_SLAB_CASE(W, P)                                                                                 \
+    if (wg == W && tpt == P)                                                                                \
+        return launch_slab_t<W, P, EXPL, HW>(c, m, g, tr, order, first, n, S, shm, norm, snr, best);
+    STT_SLAB_CASE(1024, 4)
+    STT_SLAB_CASE(512, 4)
+    STT_SLAB_CASE(256, 4)
+    STT_SLAB_CASE(1024, 2)
+    STT_SLAB_CASE(512, 2)
+#undef STT_SLAB_CASE
+    return fail(c, STT_EUNSUPPORTED, "no slab scorer compiled for workgroup %d x %d templates", wg, tpt);
+}
+
 template <bool EXPL>
 stt_status launch_slab(stt_ctx *c, int wg, int tpt, const MapP &m, const GenP &g, const Trk *tr,
                        const uint32_t *order, int64_t first, int64_t n, int S, size_t shm, int32_t norm, float *snr,
                        uint64_t *best)
 {
-#define STT_SLAB_CASE(W, P)                                                                            \
-    if (wg == W && tpt == P) return launch_slab_t<W, P, EXPL>(c, m, g, tr, order, first, n, S, shm, norm, snr, best);
-    STT_SLAB_CASE(256, 4)
-    STT_SLAB_CASE(512, 4)
-    STT_SLAB_CASE(1024, 4)
-    STT_SLAB_CASE(512, 2)
-    STT_SLAB_CASE(1024, 2)
-    STT_SLAB_CASE(256, 8)
-    STT_SLAB_CASE(512, 8)
-#undef STT_SLAB_CASE
-    return fail(c, STT_EUNSUPPORTED, "no slab scorer compiled for workgroup %d x %d templates", wg, tpt);
+    if (c->hw_trig) return launch_slab_h<EXPL, true>(c, wg, tpt, m, g, tr, order, first, n, S, shm, norm, snr, best);
+    return launch_slab_h<EXPL, false>(c, wg, tpt, m, g, tr, order, first, n, S, shm, norm, snr, best);
 }
 
 bool slab_shape_ok(int wg, int tpt)
 {
-    static const int shapes[][2] = {{256, 4}, {512, 4}, {1024, 4}, {512, 2}, {1024, 2}, {256, 8}, {512, 8}};
-    for (const auto &s : shapes)
+    for (const auto &s : kShapes)
         if (s[0] == wg && s[1] == tpt) return true;
     return false;
 }
@@ -232,8 +242,12 @@ stt_status score_impl(stt_ctx *c, const stt_map *map, const GenP &g, const Trk *
     if (!slab) {
         ev_record(c, 0);
         const unsigned grid = (unsigned)((n + kWG - 1) / kWG);
-        hipLaunchKernelGGL(k_score_direct<EXPL>, dim3(grid), dim3(kWG), 0, c->stream, m, g, tr, (uint64_t)first, n,
-                           norm, snr, best);
+        if (c->hw_trig)
+            hipLaunchKernelGGL((k_score_direct<EXPL, true>), dim3(grid), dim3(kWG), 0, c->stream, m, g, tr,
+                               (uint64_t)first, n, norm, snr, best);
+        else
+            hipLaunchKernelGGL((k_score_direct<EXPL, false>), dim3(grid), dim3(kWG), 0, c->stream, m, g, tr,
+                               (uint64_t)first, n, norm, snr, best);
         STT_HIP(c, hipGetLastError());
         ev_record(c, 1);
         c->used[0] = true;
@@ -397,6 +411,13 @@ stt_status stt_set_slab_shape(stt_ctx *c, int32_t wg, int32_t tpt)
     if (!slab_shape_ok(wg, tpt)) return fail(c, STT_EUNSUPPORTED, "no slab scorer for %d x %d", wg, tpt);
     c->slab_wg = wg;
     c->slab_tpt = tpt;
+    return STT_OK;
+}
+
+stt_status stt_set_trig(stt_ctx *c, int32_t hw)
+{
+    if (!c || hw < 0 || hw > 1) return STT_EINVAL;
+    c->hw_trig = hw == 1;
     return STT_OK;
 }
 

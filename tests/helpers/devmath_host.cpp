@@ -5,6 +5,7 @@
 //   draw  seed stream j T F L D        -> t0 t2 f0 f1 f2 dtau
 //   rows  t0 t2 f0 f1 f2               -> N rows (DDA walk)
 //   rowsat t0 t2 f0 f1 f2 k0           -> N rows, DDA started at k0 <= 0 and stepped to 0
+//   rowsf t0 t2 f0 f1 f2 k0            -> N rows of the FP64 walk started at k0 <= 0
 //   rot   ph pr pi                     -> Re[exp(2 pi i ph/2^32)(pr + i pi)] as %.9e
 //   key   z j                          -> 64-bit key (hex)
 #include <cstdio>
@@ -61,6 +62,19 @@ int main()
             for (int k = 0; k < N; ++k) {
                 std::printf(k ? " %d" : "%d", s.row);
                 dda_step(s);
+            }
+            std::printf("\n");
+        } else if (!std::strcmp(cmd, "rowsf")) {  // FP64 walk from k0 <= 0
+            Trk t;
+            int k0;
+            if (std::scanf("%d %d %u %u %u %d", &t.t0, &t.t2, &t.f0, &t.f1, &t.f2, &k0) != 6) return 2;
+            t.dtau = 0;
+            DdaF s = ddaf_init_at(t, k0);
+            for (int k = k0; k < 0; ++k) ddaf_step(s);
+            const int N = t.t2 - t.t0 + 1;
+            for (int k = 0; k < N; ++k) {
+                std::printf(k ? " %d" : "%d", ddaf_row(s));
+                ddaf_step(s);
             }
             std::printf("\n");
         } else if (!std::strcmp(cmd, "rot")) {

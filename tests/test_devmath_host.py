@@ -90,6 +90,46 @@ def test_rewound_dda_reaches_exact_rows(orc, devmath):
         assert got == want, c
 
 
+@pytest.mark.parametrize("cmd", ["rowsat", "rowsf"])
+def test_rewound_walks_exhaustive_short_tracks(orc, devmath, cmd):
+    """Every control-frequency triple on a 1/32-row grid of a 3-row band, every
+    length up to 6 and rewinds of 0..3 columns: both walks equal the oracle's rows."""
+    F = 3
+    grid = list(range(0, F * 256, 8)) + [F * 256 - 1]
+    cases = []
+    for Dt in range(1, 7):
+        for f0 in grid[::3]:
+            for f1 in grid[::5]:
+                for f2 in grid[::7]:
+                    cases.append((0, Dt, f0, f1, f2, -(Dt % 4)))
+    out = devmath([f"{cmd} {a} {b} {c} {d} {e} {k}" for (a, b, c, d, e, k) in cases])
+    for c, line in zip(cases, out):
+        want = orc.rows(np.array(c[:5] + (0,), dtype=orc.TRACK_DTYPE), F).tolist()
+        assert [int(x) for x in line.split()] == want, c
+
+
+def test_fp64_walk_bit_exact_random(orc, devmath):
+    sel = np.random.default_rng(11)
+    cases = []
+    for _ in range(3000):
+        F = int(sel.choice([1, 2, 7, 1000, 2000, 32767]))
+        Dt = int(sel.choice([1, 2, 5, 64, 999, 1999, 2895]))
+        k0 = -int(sel.choice([0, 1, 15, 63, 500, 2895]))
+        f = sel.integers(0, F * 256, size=3)
+        cases.append((0, Dt, int(f[0]), int(f[1]), int(f[2]), k0, F))
+    for F in (1, 1000, 32767):
+        hi = F * 256 - 1
+        for Dt in (1, 2, 2895):
+            for f in [(0, 0, 0), (hi, hi, hi), (0, hi, 0), (hi, 0, hi), (0, hi, hi), (hi, 0, 0), (0, 0, hi)]:
+                for k0 in (0, -2895):
+                    cases.append((0, Dt, *f, k0, F))
+    out = devmath([f"rowsf {a} {b} {c} {d} {e} {k}" for (a, b, c, d, e, k, F) in cases])
+    for c, line in zip(cases, out):
+        got = [int(x) for x in line.split()]
+        want = orc.rows(np.array(c[:5] + (0,), dtype=orc.TRACK_DTYPE), c[6]).tolist()
+        assert got == want, c
+
+
 def test_phase_rotation_accuracy(devmath):
     sel = np.random.default_rng(3)
     ph = sel.integers(0, 2 ** 32, 20000).tolist() + [0, 2 ** 30, 2 ** 31, 3 * 2 ** 30, 2 ** 32 - 1,

@@ -116,7 +116,7 @@ def test_slab_boundaries_and_ragged_tail(orc, stt, ctx, lds):
     assert_argmax(jk - first, z_orc)
 
 
-SHAPES = [(256, 4), (512, 4), (1024, 4), (512, 2), (1024, 2), (256, 8), (512, 8)]
+SHAPES = [(1024, 4), (512, 4), (256, 4), (1024, 2), (512, 2)]
 
 
 @pytest.mark.parametrize("wg,tpt", SHAPES)
@@ -345,7 +345,7 @@ def test_argument_errors_write_nothing(stt, ctx):
     with pytest.raises(stt.SttError) as e:
         ctx.make_tracks(stt.Gen(), 3000, 10, 0, 4)
     assert e.value.status == stt.ERANGE
-    wide = stt.Map(*to_dev(*synth.noise_map(4, 20000, seed=1)))
+    wide = stt.Map(*to_dev(*synth.noise_map(4, 21000, seed=1)))  # 168 KB per column
     ctx.set_path(stt.PATH_SLAB)
     with pytest.raises(stt.SttError) as e:
         ctx.score(wide, gen=stt.Gen(min_len=2), n=10, snr=None, best_key=key)
