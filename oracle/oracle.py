@@ -74,10 +74,15 @@ def lib():
 
 
 def _bind_ext(L):
-    """Bind the extension entry points when present (top-K, FP16 emulation, bilinear)."""
-    if hasattr(L, "orc_topk"):
-        L.orc_topk.argtypes = [C.c_void_p, C.c_int64, C.c_int32, C.c_void_p]
-        L.orc_topk.restype = C.c_int
+    """Bind the extension entry points (top-K, bilinear smooth SNR, refinement)."""
+    L.orc_topk.argtypes = [C.c_void_p, C.c_int64, C.c_int32, C.c_void_p]
+    L.orc_topk.restype = C.c_int
+    L.orc_smooth.argtypes = [C.POINTER(_Map), C.c_void_p, C.c_int32, C.c_void_p]
+    L.orc_smooth.restype = C.c_double
+    L.orc_refine.argtypes = [C.POINTER(_Map), C.c_void_p, C.c_int32, C.c_int32, C.c_int32, C.c_double, C.c_void_p]
+    L.orc_refine.restype = C.c_double
+    L.orc_theta_to_track.argtypes = [C.c_void_p, C.c_int32, C.c_int32, C.c_int32, C.c_int32, C.POINTER(_Track)]
+    L.orc_theta_to_track.restype = None
 
 
 # --------------------------------------------------------------------------- primitives
@@ -195,3 +200,59 @@ def score_list(m: Map, tracks: np.ndarray, norm: int = NORM_SQRT_N) -> np.ndarra
 def argmax(z: np.ndarray) -> int:
     z = np.ascontiguousarray(np.asarray(z, dtype=np.float64))
     return int(lib().orc_argmax(z.ctypes.data, z.size))
+
+
+# --------------------------------------------------------------------------- extensions
+
+def topk(z: np.ndarray, K: int) -> np.ndarray:
+    """Indices of the K best scores (score descending, index ascending; NaN lowest)."""
+    z = np.ascontiguousarray(np.asarray(z, dtype=np.float64))
+    idx = np.zeros(max(K, 1), dtype=np.int64)
+    if lib().orc_topk(z.ctypes.data, z.size, K, idx.ctypes.data) != 0:
+        raise ValueError("bad K")
+    return idx[:K]
+
+
+def smooth(m: Map, theta, K: int, grad: bool = True):
+    """Bilinear smooth SNR of theta = (tau0, tau2, phi0, phi1, phi2, dtau_ms); returns (z, grad[6])."""
+    th = np.ascontiguousarray(np.asarray(theta, dtype=np.float64).reshape(6))
+    g = np.zeros(6, dtype=np.float64)
+    z = lib().orc_smooth(C.byref(m.c), th.ctypes.data, K, g.ctypes.data if grad else None)
+    return float(z), g
+
+
+def refine(m: Map, theta, K: int, steps: int, L: int, dtau_max_ms: float, sched=(1.0, 0.02, 0.5, 0.01)):
+    """Projected ascent on the smooth SNR; returns (best theta, its smooth SNR)."""
+    th = np.ascontiguousarray(np.asarray(theta, dtype=np.float64).reshape(6)).copy()
+    sc = np.ascontiguousarray(np.asarray(sched, dtype=np.float64))
+    z = lib().orc_refine(C.byref(m.c), th.ctypes.data, K, steps, L, dtau_max_ms, sc.ctypes.data)
+    return th, float(z)
+
+
+def theta_to_track(theta, T: int, F: int, L: int, dtau_max: int) -> np.ndarray:
+    th = np.ascontiguousarray(np.asarray(theta, dtype=np.float64).reshape(6))
+    t = _Track()
+    lib().orc_theta_to_track(th.ctypes.data, T, F, L, dtau_max, C.byref(t))
+    out = np.zeros((), dtype=TRACK_DTYPE)
+    for name in TRACK_DTYPE.names:
+        out[name] = getattr(t, name)
+    return out
+
+
+def quantize_p16(Y: np.ndarray, sigma: np.ndarray):
+    """FP16 storage of the complex SNR p = Y/sigma with a per-map power-of-two scale.
+
+    p is formed in FP32 (correctly rounded division), the exponent e makes the
+    largest |component| of p * 2^-e at most 2^15, each component is rounded to
+    binary16 (round to nearest even, numpy's conversion). Returns (stored
+    complex float16 pairs as a [T][F][2] float16 array, e, dequantised p as
+    complex128).
+    """
+    pr = (Y.real.astype(np.float32) / sigma.astype(np.float32)).astype(np.float32)
+    pi = (Y.imag.astype(np.float32) / sigma.astype(np.float32)).astype(np.float32)
+    amax = float(max(np.abs(pr).max(initial=0.0), np.abs(pi).max(initial=0.0)))
+    e = (int(np.ceil(np.log2(amax))) - 15) if amax > 0 else 0
+    sc = np.float32(2.0 ** -e)
+    q = np.stack([(pr * sc).astype(np.float16), (pi * sc).astype(np.float16)], axis=-1)
+    deq = (q[..., 0].astype(np.float64) + 1j * q[..., 1].astype(np.float64)) * 2.0 ** e
+    return q, e, deq
