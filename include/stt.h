@@ -60,7 +60,8 @@ typedef int32_t stt_status;
 #define STT_NORM_N 1
 
 #define STT_C64F32 0 /* Y: complex64 (re, im float32 interleaved); sigma: float32 */
-#define STT_C16F16 1 /* Y: FP16 (re, im) pairs scaled by 2^-scale_exp; sigma slot: FP16 1/sigma */
+#define STT_P16 1    /* Y: the complex SNR p = Y/sigma as FP16 (re, im) pairs, p = stored * 2^scale_exp;
+                        sigma: NULL (see stt_map_pack_p16) */
 
 #define STT_FBITS 8        /* fractional bits of control frequencies */
 #define STT_MAX_T 2896     /* largest map duration (columns) */
@@ -83,10 +84,10 @@ typedef struct {
 typedef struct {
     int32_t T, F;         /* columns, rows */
     int64_t ld;           /* elements between columns, ld >= F */
-    int32_t dtype;        /* STT_C64F32 or STT_C16F16 */
-    int32_t scale_exp;    /* STT_C16F16 only: Y = stored * 2^scale_exp */
-    const void *Y;        /* device: [T][ld] complex */
-    const void *sigma;    /* device: [T][ld] sigma (C64F32) or 1/sigma (C16F16) */
+    int32_t dtype;        /* STT_C64F32 or STT_P16 */
+    int32_t scale_exp;    /* STT_P16 only: p = stored * 2^scale_exp */
+    const void *Y;        /* device: [T][ld] complex (complex64, or FP16 pairs for STT_P16) */
+    const void *sigma;    /* device: [T][ld] float32 sigma (STT_C64F32); NULL for STT_P16 */
     int32_t fq4_lo;       /* frequency of row 0 in 1/16 Hz (1600 = 100 Hz) */
     int32_t dfq4;         /* row spacing in 1/16 Hz (16 = 1 Hz) */
 } stt_map;
@@ -159,6 +160,33 @@ stt_status stt_score(stt_ctx *ctx, const stt_map *map, const stt_gen *gen, const
  * the best key over snr_dev[0..n), the index of element i being first + i. */
 stt_status stt_argmax(stt_ctx *ctx, const float *snr_dev, int64_t n, int64_t first,
                       uint64_t *best_key_dev);
+
+/* FP16 storage of a map (a precision addition; the paper states no
+ * precision). Packs an STT_C64F32 map into out_dev, [T][out_ld] FP16 pairs
+ * (4 bytes per pixel, caller-owned, out_ld >= F): p = Y/sigma is formed in
+ * FP32 with a correctly rounded division, scaled by 2^-e and rounded to
+ * binary16 to nearest even, where e = ceil(log2(max |Re p|, |Im p|)) - 15
+ * keeps every value below 2^15. Writes e to *scale_exp (host). Synchronises
+ * the stream (the exponent is read back); STT_EINVAL if the map holds a
+ * non-finite value. The packed map is used as stt_map{dtype = STT_P16,
+ * Y = out_dev, sigma = NULL, scale_exp = e, ld = out_ld}. */
+stt_status stt_map_pack_p16(stt_ctx *ctx, const stt_map *map, void *out_dev, int64_t out_ld, int32_t *scale_exp);
+
+/* The K best scores of snr_dev[0..n) (Sec. V's follow-up of the loudest
+ * candidates), ordered by score descending then index ascending; NaN ranks
+ * lowest. Element i has index first + i. Writes idx_dev[0..K) (int64) and/or
+ * val_dev[0..K) (float; either may be NULL, not both). Device-resident: a
+ * radix select over the 64-bit (score, ~index) keys, no host round trip.
+ * Requires 0 <= K <= min(n, 8192). */
+stt_status stt_topk(stt_ctx *ctx, const float *snr_dev, int64_t n, int64_t first, int32_t K, int64_t *idx_dev,
+                    float *val_dev);
+
+/* FP64 re-score of K tracks (Eq. 8) from an FP32 (STT_C64F32) map: z_dev[i]
+ * (double) for track j = idx_dev[i], drawn from `gen` (tracks_dev == NULL) or
+ * read at tracks_dev[j - first]. Rows, phases and sums are computed exactly /
+ * in FP64; an invalid track (or j < first) gives NaN. */
+stt_status stt_rescore_f64(stt_ctx *ctx, const stt_map *map, const stt_gen *gen, const stt_track *tracks_dev,
+                           int64_t first, const int64_t *idx_dev, int32_t K, int32_t norm, double *z_dev);
 
 /* Host helpers for the key format (no device work). */
 uint64_t stt_key_encode(float z, uint32_t j);

@@ -15,17 +15,37 @@
 // then one 64-bit atomic max per wave, so results do not depend on scheduling.
 #pragma once
 
+#include <hip/hip_fp16.h>
+
 #include "dev_common.hpp"
 
 namespace stt {
 
 struct MapP {
-    const float2 *Y;   // [T][ld] complex64
-    const float *sig;  // [T][ld]
+    const float2 *Y;   // [T][ld] complex64 (FP32 map) -- or __half2 p (FP16 map)
+    const float *sig;  // [T][ld] sigma (FP32 map only)
     int32_t T, F;
     int64_t ld;
     int32_t fq4_lo, dfq4;
+    float scale;       // FP16 map: p = stored * scale (a power of two)
 };
+
+// Map element formats of the scorers.
+enum : int { kMapF32 = 0, kMapP16 = 1 };
+
+// The complex SNR p = Y/sigma of pixel element e (Eq. 7 with the appendix's rho = Y/sigma).
+template <int MAPT>
+__device__ __forceinline__ float2 load_p(const MapP &m, int64_t e)
+{
+    if (MAPT == kMapP16) {
+        const __half2 h = reinterpret_cast<const __half2 *>(m.Y)[e];
+        const float2 f = __half22float2(h);
+        return make_float2(f.x * m.scale, f.y * m.scale);
+    }
+    const float2 y = m.Y[e];
+    const float w = 1.0f / m.sig[e];
+    return make_float2(y.x * w, y.y * w);
+}
 
 constexpr int kMaxDt = 2895;  // Dt * Dt * 256 < 2^31
 // FP32 partial sums are flushed into the FP64 total after every column c with
@@ -116,7 +136,7 @@ __global__ __launch_bounds__(256) void k_make_tracks(GenP g, uint64_t first, int
 
 // ---------------------------------------------------------------- direct scorer
 
-template <bool EXPL, bool HW>
+template <bool EXPL, bool HW, int MAPT>
 __global__ __launch_bounds__(kWG) void k_score_direct(MapP m, GenP g, const Trk *tr, uint64_t first, int64_t n,
                                                       int32_t norm, float *snr, uint64_t *best)
 {
@@ -130,19 +150,16 @@ __global__ __launch_bounds__(kWG) void k_score_direct(MapP m, GenP g, const Trk 
             const uint32_t pa = phase_a(m.fq4_lo, t.dtau), pb = phase_b(m.dfq4, t.dtau);
             const uint32_t pbl = pb & 0xFFFFFFu, pbh = pb >> 24;
             const int32_t N = t.t2 - t.t0 + 1;
-            const float2 *Yc = m.Y + (int64_t)t.t0 * m.ld;
-            const float *Sc = m.sig + (int64_t)t.t0 * m.ld;
+            int64_t base = (int64_t)t.t0 * m.ld;
             double acc = 0.0;
             float part = 0.0f;
             for (int32_t k = 0; k < N; ++k) {
                 const int32_t row = ddaf_row(s);
-                const float2 y = Yc[row];
-                const float w = 1.0f / Sc[row];
-                part += rot<HW>(phase_of(pa, pbl, pbh, row), y.x * w, y.y * w);
+                const float2 p = load_p<MAPT>(m, base + row);
+                part += rot<HW>(phase_of(pa, pbl, pbh, row), p.x, p.y);
                 if (((t.t0 + k) & (kFlush - 1)) == kFlush - 1) { acc += part; part = 0.0f; }
                 ddaf_step(s);
-                Yc += m.ld;
-                Sc += m.ld;
+                base += m.ld;
             }
             z = finish(acc + part, N, norm);
         }
@@ -302,7 +319,7 @@ __device__ __forceinline__ void walk(int ca, int cb, int c0, const float2 *slab,
     }
 }
 
-template <int WG, int TPT, bool EXPL, bool HW>
+template <int WG, int TPT, bool EXPL, bool HW, int MAPT>
 __global__ __launch_bounds__(WG) void k_score_slab(MapP m, GenP g, const Trk *tr, const uint32_t *order,
                                                    uint64_t first, int64_t n, int S, int32_t norm, float *snr,
                                                    uint64_t *best)
@@ -379,14 +396,10 @@ __global__ __launch_bounds__(WG) void k_score_slab(MapP m, GenP g, const Trk *tr
         __syncthreads();  // the previous slab has been consumed
         {
             int col = col0, r = row0;
-            const float2 *Yb = m.Y + (int64_t)c0 * m.ld;
-            const float *Sb = m.sig + (int64_t)c0 * m.ld;
+            const int64_t base = (int64_t)c0 * m.ld;
 #pragma unroll 4
             for (int e = threadIdx.x; e < ncol * F; e += WG) {
-                const int64_t off = (int64_t)col * m.ld + r;
-                const float2 y = Yb[off];
-                const float w = 1.0f / Sb[off];
-                slab[col * F + r] = make_float2(y.x * w, y.y * w);
+                slab[col * F + r] = load_p<MAPT>(m, base + (int64_t)col * m.ld + r);
                 r += drow;
                 col += dcol;
                 if (r >= F) { r -= F; ++col; }
@@ -409,6 +422,183 @@ __global__ __launch_bounds__(WG) void k_score_slab(MapP m, GenP g, const Trk *tr
         key = k > key ? k : key;
     }
     merge_key(best, key);
+}
+
+// ---------------------------------------------------------------- FP16 map packing
+// p = Y/sigma in FP32 (correctly rounded division), then p * 2^-e rounded to
+// binary16 (round to nearest even). k_absmax finds max |component| first.
+
+__global__ __launch_bounds__(256) void k_absmax_p(MapP m, uint32_t *amax_bits)
+{
+    float mx = 0.0f;
+    const int64_t n = (int64_t)m.T * m.F;
+    for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < n; i += (int64_t)gridDim.x * 256) {
+        const int64_t t = i / m.F, r = i - t * m.F;
+        const int64_t e = t * m.ld + r;
+        const float2 y = m.Y[e];
+        const float sg = m.sig[e];
+        mx = fmaxf(mx, fmaxf(fabsf(y.x / sg), fabsf(y.y / sg)));
+    }
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) mx = fmaxf(mx, __shfl_xor(mx, off));
+    if ((threadIdx.x & 63) == 0) atomicMax(amax_bits, __float_as_uint(mx));  // non-negative floats order as integers
+}
+
+__global__ __launch_bounds__(256) void k_pack_p16(MapP m, float inv_scale, __half2 *out, int64_t out_ld)
+{
+    const int64_t n = (int64_t)m.T * m.F;
+    for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < n; i += (int64_t)gridDim.x * 256) {
+        const int64_t t = i / m.F, r = i - t * m.F;
+        const int64_t e = t * m.ld + r;
+        const float2 y = m.Y[e];
+        const float sg = m.sig[e];
+        out[t * out_ld + r] = __halves2half2(__float2half_rn((y.x / sg) * inv_scale),
+                                             __float2half_rn((y.y / sg) * inv_scale));
+    }
+}
+
+// ---------------------------------------------------------------- top-K
+// Radix select over the 64-bit keys (score bits, ~index) -- all distinct, so
+// the K-th largest key is a threshold that admits exactly K elements. Eight
+// passes of 8 bits, each a histogram of the keys that share the digits fixed
+// so far, with the choice of the next digit made on the device; then the K
+// keys at or above the threshold are gathered and sorted in one workgroup.
+
+struct TopkState {
+    uint64_t prefix;     // digits fixed so far
+    uint64_t mask;       // which bits of prefix are fixed
+    uint32_t remaining;  // how many of the K still lie in the undecided bucket
+    uint32_t count;      // gather cursor
+    uint32_t hist[256];
+};
+
+__global__ __launch_bounds__(256) void k_topk_init(TopkState *st, uint32_t K)
+{
+    if (threadIdx.x == 0) {
+        st->prefix = 0;
+        st->mask = 0;
+        st->remaining = K;
+        st->count = 0;
+    }
+    st->hist[threadIdx.x] = 0;
+}
+
+__global__ __launch_bounds__(256) void k_topk_hist(const float *z, int64_t n, uint64_t first, TopkState *st, int shift)
+{
+    __shared__ uint32_t h[256];
+    h[threadIdx.x] = 0;
+    __syncthreads();
+    const uint64_t prefix = st->prefix, mask = st->mask;
+    for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < n; i += (int64_t)gridDim.x * 256) {
+        const uint64_t k = key_encode(z[i], (uint32_t)(first + (uint64_t)i));
+        if ((k & mask) == prefix) atomicAdd(&h[(k >> shift) & 255u], 1u);
+    }
+    __syncthreads();
+    if (h[threadIdx.x]) atomicAdd(&st->hist[threadIdx.x], h[threadIdx.x]);
+}
+
+// One workgroup: choose the digit holding the remaining-th largest key, then clear the histogram.
+__global__ __launch_bounds__(256) void k_topk_pick(TopkState *st, int shift)
+{
+    __shared__ uint32_t h[256];
+    h[threadIdx.x] = st->hist[threadIdx.x];
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        uint32_t need = st->remaining, above = 0;
+        int d = 255;
+        for (; d > 0; --d) {
+            if (above + h[d] >= need) break;
+            above += h[d];
+        }
+        st->prefix |= (uint64_t)d << shift;
+        st->mask |= (uint64_t)0xFF << shift;
+        st->remaining = need - above;
+    }
+    st->hist[threadIdx.x] = 0;
+}
+
+__global__ __launch_bounds__(256) void k_topk_gather(const float *z, int64_t n, uint64_t first, TopkState *st,
+                                                     uint64_t *cand)
+{
+    const uint64_t thr = st->prefix;
+    for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < n; i += (int64_t)gridDim.x * 256) {
+        const uint64_t k = key_encode(z[i], (uint32_t)(first + (uint64_t)i));
+        if (k >= thr) cand[atomicAdd(&st->count, 1u)] = k;
+    }
+}
+
+// Sort the K gathered keys descending (bitonic, in LDS) and write (index, score).
+__global__ __launch_bounds__(1024) void k_topk_sort(const uint64_t *cand, int K, int P, int64_t *idx, float *val)
+{
+    extern __shared__ uint64_t kk[];  // P = power of two >= K
+    for (int i = threadIdx.x; i < P; i += 1024) kk[i] = i < K ? cand[i] : 0;
+    __syncthreads();
+    for (int size = 2; size <= P; size <<= 1) {
+        for (int stride = size >> 1; stride > 0; stride >>= 1) {
+            for (int i = threadIdx.x; i < P; i += 1024) {
+                const int j = i ^ stride;
+                if (j > i) {
+                    const bool desc = (i & size) == 0;
+                    const uint64_t a = kk[i], b = kk[j];
+                    if (desc ? a < b : a > b) { kk[i] = b; kk[j] = a; }
+                }
+            }
+            __syncthreads();
+        }
+    }
+    for (int i = threadIdx.x; i < K; i += 1024) {
+        const uint64_t k = kk[i];
+        const uint32_t o = (uint32_t)(k >> 32);
+        const uint32_t b = (o & 0x80000000u) ? (o & 0x7FFFFFFFu) : ~o;
+        if (idx) idx[i] = (int64_t)(0xFFFFFFFFu - (uint32_t)k);
+        if (val) val[i] = __uint_as_float(b);
+    }
+}
+
+// ---------------------------------------------------------------- FP64 re-score
+// One wave per template: lanes stride over its columns; each pixel's row is
+// the exact floor of Eq. 6 by 64-bit integer division, the phase the exact
+// 2^-32-turn integer, the term and the sum in FP64 (fixed-order wave
+// reduction, so the result is deterministic).
+
+template <bool EXPL>
+__global__ __launch_bounds__(256) void k_rescore_f64(MapP m, GenP g, const Trk *tr, uint64_t first,
+                                                     const int64_t *idx, int32_t K, int32_t norm, double *out)
+{
+    const int w = (int)(((int64_t)blockIdx.x * 256 + threadIdx.x) >> 6);
+    const int lane = threadIdx.x & 63;
+    if (w >= K) return;
+    const int64_t j = idx[w];
+    Trk t;
+    bool ok = j >= (int64_t)first;
+    if (EXPL) {
+        t = tr[ok ? j - (int64_t)first : 0];
+        ok = ok && track_ok(t, m);
+    } else {
+        t = draw_track(g, (uint64_t)j);
+    }
+    double s = 0.0;
+    int32_t N = 1;
+    if (ok) {
+        const int64_t Dt = t.t2 - t.t0;
+        N = (int32_t)Dt + 1;
+        const uint64_t Q = (uint64_t)(Dt * Dt) << 8;
+        for (int64_t k = lane; k <= Dt; k += 64) {
+            const uint64_t a = (uint64_t)(Dt - k), b = (uint64_t)k;
+            const uint64_t num = a * a * t.f0 + 2 * a * b * t.f1 + b * b * t.f2;
+            const int64_t row = (int64_t)(num / Q);
+            const int64_t e = (t.t0 + k) * m.ld + row;
+            const double sg = m.sig[e];
+            const double pr = (double)m.Y[e].x / sg, pim = (double)m.Y[e].y / sg;
+            const uint32_t ph = (uint32_t)((int64_t)(m.fq4_lo + row * m.dfq4) * (int64_t)t.dtau);
+            double sn, cs;
+            sincos(6.283185307179586 * ((double)(int32_t)ph * 2.3283064365386963e-10), &sn, &cs);
+            s += cs * pr - sn * pim;
+        }
+    }
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) s += __shfl_xor(s, off);
+    if (lane == 0) out[w] = ok ? (norm == 1 ? s / N : s / sqrt((double)N)) : __builtin_nan("");
 }
 
 }  // namespace stt

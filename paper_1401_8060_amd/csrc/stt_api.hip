@@ -21,6 +21,8 @@ struct stt_ctx {
     std::string err;
     void *scratch = nullptr;
     size_t scratch_bytes = 0;
+    void *aux = nullptr;  // top-K state and candidates
+    size_t aux_bytes = 0;
     int path = 0;  // 0 auto, 1 direct, 2 slab
     int lds_bytes = 160 * 1024;  // slab budget per workgroup
     int slab_wg = 1024;          // slab scorer shape: lanes per workgroup
@@ -81,14 +83,37 @@ stt_status ensure_scratch(stt_ctx *c, size_t bytes)
     return STT_OK;
 }
 
+stt_status ensure_aux(stt_ctx *c, size_t bytes)
+{
+    if (bytes <= c->aux_bytes) return STT_OK;
+    if (c->aux) {
+        hipError_t e = hipStreamSynchronize(c->stream);
+        if (e != hipSuccess) return fail(c, STT_EHIP, "hipStreamSynchronize: %s", hipGetErrorString(e));
+        (void)hipFree(c->aux);
+        c->aux = nullptr;
+        c->aux_bytes = 0;
+    }
+    if (hipMalloc(&c->aux, bytes) != hipSuccess) {
+        (void)hipGetLastError();
+        c->aux = nullptr;
+        return fail(c, STT_ENOMEM, "cannot allocate %zu bytes", bytes);
+    }
+    c->aux_bytes = bytes;
+    return STT_OK;
+}
+
 stt_status check_map(stt_ctx *c, const stt_map *m)
 {
     if (!m) return fail(c, STT_EINVAL, "map is NULL");
-    if (m->dtype != STT_C64F32) return fail(c, STT_EUNSUPPORTED, "map dtype %d not supported here", m->dtype);
+    if (m->dtype != STT_C64F32 && m->dtype != STT_P16)
+        return fail(c, STT_EINVAL, "map dtype %d unknown", m->dtype);
+    if (m->dtype == STT_P16 && m->sigma) return fail(c, STT_EINVAL, "an FP16 map has no sigma array (pass NULL)");
+    if (m->dtype == STT_P16 && (m->scale_exp < -126 || m->scale_exp > 127))
+        return fail(c, STT_ERANGE, "scale_exp=%d outside [-126, 127]", m->scale_exp);
     if (m->T < 2 || m->T > STT_MAX_T) return fail(c, STT_ERANGE, "T=%d outside [2, %d]", m->T, STT_MAX_T);
     if (m->F < 1 || m->F > STT_MAX_F) return fail(c, STT_ERANGE, "F=%d outside [1, %d]", m->F, STT_MAX_F);
     if (m->ld < m->F) return fail(c, STT_EINVAL, "ld=%lld < F=%d", (long long)m->ld, m->F);
-    if (!m->Y || !m->sigma) return fail(c, STT_EINVAL, "map Y or sigma is NULL");
+    if (!m->Y || (m->dtype == STT_C64F32 && !m->sigma)) return fail(c, STT_EINVAL, "map Y or sigma is NULL");
     const int64_t fmax = std::llabs((int64_t)m->fq4_lo) + (int64_t)(m->F - 1) * std::llabs((int64_t)m->dfq4);
     if (fmax >= ((int64_t)1 << 31)) return fail(c, STT_ERANGE, "row frequencies overflow 32 bits");
     return STT_OK;
@@ -131,6 +156,7 @@ MapP to_mapp(const stt_map *m)
     p.ld = m->ld;
     p.fq4_lo = m->fq4_lo;
     p.dfq4 = m->dfq4;
+    p.scale = m->dtype == STT_P16 ? std::ldexp(1.0f, m->scale_exp) : 1.0f;
     return p;
 }
 
@@ -171,11 +197,11 @@ int bucket_shift(int T)
     return wb;
 }
 
-template <int WG, int TPT, bool EXPL, bool HW>
+template <int WG, int TPT, bool EXPL, bool HW, int MAPT>
 stt_status launch_slab_t(stt_ctx *c, const MapP &m, const GenP &g, const Trk *tr, const uint32_t *order,
                          int64_t first, int64_t n, int S, size_t shm, int32_t norm, float *snr, uint64_t *best)
 {
-    auto kern = k_score_slab<WG, TPT, EXPL, HW>;
+    auto kern = k_score_slab<WG, TPT, EXPL, HW, MAPT>;
     if (shm > 64 * 1024)
         STT_HIP(c, hipFuncSetAttribute((const void *)kern, hipFuncAttributeMaxDynamicSharedMemorySize, (int)shm));
     const unsigned grid = (unsigned)((n + WG * TPT - 1) / (WG * TPT));
@@ -188,14 +214,14 @@ stt_status launch_slab_t(stt_ctx *c, const MapP &m, const GenP &g, const Trk *tr
 // The (workgroup size, templates per lane) shapes compiled into the library.
 static const int kShapes[][2] = {{1024, 4}, {512, 4}, {256, 4}, {1024, 2}, {512, 2}};
 
-template <bool EXPL, bool HW>
+template <bool EXPL, bool HW, int MAPT>
 stt_status launch_slab_h(stt_ctx *c, int wg, int tpt, const MapP &m, const GenP &g, const Trk *tr,
                          const uint32_t *order, int64_t first, int64_t n, int S, size_t shm, int32_t norm, float *snr,
                          uint64_t *best)
 {
 #define STT_SLAB_CASE(W, P)                                                                                 \
     if (wg == W && tpt == P)                                                                                \
-        return launch_slab_t<W, P, EXPL, HW>(c, m, g, tr, order, first, n, S, shm, norm, snr, best);
+        return launch_slab_t<W, P, EXPL, HW, MAPT>(c, m, g, tr, order, first, n, S, shm, norm, snr, best);
     STT_SLAB_CASE(1024, 4)
     STT_SLAB_CASE(512, 4)
     STT_SLAB_CASE(256, 4)
@@ -205,13 +231,23 @@ stt_status launch_slab_h(stt_ctx *c, int wg, int tpt, const MapP &m, const GenP 
     return fail(c, STT_EUNSUPPORTED, "no slab scorer compiled for workgroup %d x %d templates", wg, tpt);
 }
 
-template <bool EXPL>
+template <bool EXPL, int MAPT>
 stt_status launch_slab(stt_ctx *c, int wg, int tpt, const MapP &m, const GenP &g, const Trk *tr,
                        const uint32_t *order, int64_t first, int64_t n, int S, size_t shm, int32_t norm, float *snr,
                        uint64_t *best)
 {
-    if (c->hw_trig) return launch_slab_h<EXPL, true>(c, wg, tpt, m, g, tr, order, first, n, S, shm, norm, snr, best);
-    return launch_slab_h<EXPL, false>(c, wg, tpt, m, g, tr, order, first, n, S, shm, norm, snr, best);
+    if (c->hw_trig)
+        return launch_slab_h<EXPL, true, MAPT>(c, wg, tpt, m, g, tr, order, first, n, S, shm, norm, snr, best);
+    return launch_slab_h<EXPL, false, MAPT>(c, wg, tpt, m, g, tr, order, first, n, S, shm, norm, snr, best);
+}
+
+template <bool EXPL, bool HW, int MAPT>
+void launch_direct(stt_ctx *c, const MapP &m, const GenP &g, const Trk *tr, int64_t first, int64_t n, int32_t norm,
+                   float *snr, uint64_t *best)
+{
+    const unsigned grid = (unsigned)((n + kWG - 1) / kWG);
+    hipLaunchKernelGGL((k_score_direct<EXPL, HW, MAPT>), dim3(grid), dim3(kWG), 0, c->stream, m, g, tr,
+                       (uint64_t)first, n, norm, snr, best);
 }
 
 bool slab_shape_ok(int wg, int tpt)
@@ -221,7 +257,7 @@ bool slab_shape_ok(int wg, int tpt)
     return false;
 }
 
-template <bool EXPL>
+template <bool EXPL, int MAPT>
 stt_status score_impl(stt_ctx *c, const stt_map *map, const GenP &g, const Trk *tr, int64_t first, int64_t n,
                       int32_t norm, float *snr, uint64_t *best)
 {
@@ -241,13 +277,10 @@ stt_status score_impl(stt_ctx *c, const stt_map *map, const GenP &g, const Trk *
     ev_record(c, 4);
     if (!slab) {
         ev_record(c, 0);
-        const unsigned grid = (unsigned)((n + kWG - 1) / kWG);
         if (c->hw_trig)
-            hipLaunchKernelGGL((k_score_direct<EXPL, true>), dim3(grid), dim3(kWG), 0, c->stream, m, g, tr,
-                               (uint64_t)first, n, norm, snr, best);
+            launch_direct<EXPL, true, MAPT>(c, m, g, tr, first, n, norm, snr, best);
         else
-            hipLaunchKernelGGL((k_score_direct<EXPL, false>), dim3(grid), dim3(kWG), 0, c->stream, m, g, tr,
-                               (uint64_t)first, n, norm, snr, best);
+            launch_direct<EXPL, false, MAPT>(c, m, g, tr, first, n, norm, snr, best);
         STT_HIP(c, hipGetLastError());
         ev_record(c, 1);
         c->used[0] = true;
@@ -275,7 +308,7 @@ stt_status score_impl(stt_ctx *c, const stt_map *map, const GenP &g, const Trk *
         const int S = std::min(slab_cols, m.T);
         const size_t shm = sizeof(float2) * (size_t)S * m.F;
         ev_record(c, 0);
-        s = launch_slab<EXPL>(c, c->slab_wg, c->slab_tpt, m, g, tr, order, first, n, S, shm, norm, snr, best);
+        s = launch_slab<EXPL, MAPT>(c, c->slab_wg, c->slab_tpt, m, g, tr, order, first, n, S, shm, norm, snr, best);
         if (s != STT_OK) return s;
         ev_record(c, 1);
         c->used[0] = true;
@@ -325,6 +358,7 @@ stt_status stt_destroy(stt_ctx *c)
     (void)hipSetDevice(c->device);
     (void)hipStreamSynchronize(c->stream);
     if (c->scratch) (void)hipFree(c->scratch);
+    if (c->aux) (void)hipFree(c->aux);
     for (auto &e : c->pool) (void)hipEventDestroy(e);
     delete c;
     return STT_OK;
@@ -452,9 +486,12 @@ stt_status stt_score(stt_ctx *c, const stt_map *map, const stt_gen *gen, const s
     }
     if (n == 0) return STT_OK;
     STT_HIP(c, hipSetDevice(c->device));
+    const bool p16 = map->dtype == STT_P16;
     if (tracks_dev)
-        return score_impl<true>(c, map, g, (const Trk *)tracks_dev, first, n, norm, snr_dev, best_key_dev);
-    return score_impl<false>(c, map, g, nullptr, first, n, norm, snr_dev, best_key_dev);
+        return p16 ? score_impl<true, kMapP16>(c, map, g, (const Trk *)tracks_dev, first, n, norm, snr_dev, best_key_dev)
+                   : score_impl<true, kMapF32>(c, map, g, (const Trk *)tracks_dev, first, n, norm, snr_dev, best_key_dev);
+    return p16 ? score_impl<false, kMapP16>(c, map, g, nullptr, first, n, norm, snr_dev, best_key_dev)
+               : score_impl<false, kMapF32>(c, map, g, nullptr, first, n, norm, snr_dev, best_key_dev);
 }
 
 stt_status stt_argmax(stt_ctx *c, const float *snr_dev, int64_t n, int64_t first, uint64_t *best_key_dev)
@@ -468,6 +505,93 @@ stt_status stt_argmax(stt_ctx *c, const float *snr_dev, int64_t n, int64_t first
     const int64_t blocks = std::min<int64_t>((n + 255) / 256, 4096);
     hipLaunchKernelGGL(k_argmax, dim3((unsigned)blocks), dim3(256), 0, c->stream, snr_dev, n, (uint64_t)first,
                        best_key_dev);
+    STT_HIP(c, hipGetLastError());
+    return STT_OK;
+}
+
+stt_status stt_map_pack_p16(stt_ctx *c, const stt_map *map, void *out_dev, int64_t out_ld, int32_t *scale_exp)
+{
+    if (!c) return STT_EINVAL;
+    stt_status s = check_map(c, map);
+    if (s != STT_OK) return s;
+    if (map->dtype != STT_C64F32) return fail(c, STT_EINVAL, "stt_map_pack_p16 packs an FP32 (Y, sigma) map");
+    if (!out_dev || !scale_exp) return fail(c, STT_EINVAL, "out_dev and scale_exp must be non-NULL");
+    if (out_ld < map->F) return fail(c, STT_EINVAL, "out_ld=%lld < F=%d", (long long)out_ld, map->F);
+    STT_HIP(c, hipSetDevice(c->device));
+    if ((s = ensure_aux(c, sizeof(TopkState))) != STT_OK) return s;
+    uint32_t *amax = (uint32_t *)c->aux;
+    const MapP m = to_mapp(map);
+    const int64_t n = (int64_t)map->T * map->F;
+    const unsigned grid = (unsigned)std::min<int64_t>((n + 255) / 256, 2048);
+    hipLaunchKernelGGL(k_fill_u32, dim3(1), dim3(256), 0, c->stream, amax, (int64_t)1, 0u);
+    hipLaunchKernelGGL(k_absmax_p, dim3(grid), dim3(256), 0, c->stream, m, amax);
+    STT_HIP(c, hipGetLastError());
+    uint32_t bits = 0;
+    STT_HIP(c, hipMemcpyAsync(&bits, amax, sizeof bits, hipMemcpyDeviceToHost, c->stream));
+    STT_HIP(c, hipStreamSynchronize(c->stream));
+    float amaxf;
+    std::memcpy(&amaxf, &bits, sizeof amaxf);
+    if (!std::isfinite(amaxf)) return fail(c, STT_EINVAL, "map holds a non-finite Y/sigma");
+    const int e = amaxf > 0.0f ? (int)std::ceil(std::log2((double)amaxf)) - 15 : 0;
+    hipLaunchKernelGGL(k_pack_p16, dim3(grid), dim3(256), 0, c->stream, m, std::ldexp(1.0f, -e), (__half2 *)out_dev,
+                       out_ld);
+    STT_HIP(c, hipGetLastError());
+    *scale_exp = e;
+    return STT_OK;
+}
+
+stt_status stt_topk(stt_ctx *c, const float *snr_dev, int64_t n, int64_t first, int32_t K, int64_t *idx_dev,
+                    float *val_dev)
+{
+    if (!c) return STT_EINVAL;
+    stt_status s = check_range(c, first, n);
+    if (s != STT_OK) return s;
+    if (K < 0 || K > n || K > 8192) return fail(c, STT_ERANGE, "K=%d must be in [0, min(n, 8192)]", K);
+    if (K == 0) return STT_OK;
+    if (!snr_dev || (!idx_dev && !val_dev)) return fail(c, STT_EINVAL, "snr_dev and an output must be non-NULL");
+    STT_HIP(c, hipSetDevice(c->device));
+    const size_t st_bytes = (sizeof(TopkState) + 255) & ~(size_t)255;
+    if ((s = ensure_aux(c, st_bytes + sizeof(uint64_t) * (size_t)K)) != STT_OK) return s;
+    TopkState *st = (TopkState *)c->aux;
+    uint64_t *cand = (uint64_t *)((char *)c->aux + st_bytes);
+    const unsigned grid = (unsigned)std::min<int64_t>((n + 255) / 256, 2048);
+    hipLaunchKernelGGL(k_topk_init, dim3(1), dim3(256), 0, c->stream, st, (uint32_t)K);
+    for (int shift = 56; shift >= 0; shift -= 8) {
+        hipLaunchKernelGGL(k_topk_hist, dim3(grid), dim3(256), 0, c->stream, snr_dev, n, (uint64_t)first, st, shift);
+        hipLaunchKernelGGL(k_topk_pick, dim3(1), dim3(256), 0, c->stream, st, shift);
+    }
+    hipLaunchKernelGGL(k_topk_gather, dim3(grid), dim3(256), 0, c->stream, snr_dev, n, (uint64_t)first, st, cand);
+    int P = 1;
+    while (P < K) P <<= 1;
+    hipLaunchKernelGGL(k_topk_sort, dim3(1), dim3(1024), sizeof(uint64_t) * P, c->stream, (const uint64_t *)cand, K,
+                       P, idx_dev, val_dev);
+    STT_HIP(c, hipGetLastError());
+    return STT_OK;
+}
+
+stt_status stt_rescore_f64(stt_ctx *c, const stt_map *map, const stt_gen *gen, const stt_track *tracks_dev,
+                           int64_t first, const int64_t *idx_dev, int32_t K, int32_t norm, double *z_dev)
+{
+    if (!c) return STT_EINVAL;
+    stt_status s = check_map(c, map);
+    if (s != STT_OK) return s;
+    if (map->dtype != STT_C64F32) return fail(c, STT_EINVAL, "the FP64 re-score reads an FP32 (Y, sigma) map");
+    if (norm != STT_NORM_SQRT_N && norm != STT_NORM_N) return fail(c, STT_EINVAL, "norm=%d", norm);
+    if (K < 0) return fail(c, STT_EINVAL, "K=%d", K);
+    if (first < 0) return fail(c, STT_EINVAL, "first=%lld", (long long)first);
+    GenP g{};
+    if (!tracks_dev && (s = make_genp(c, gen, map->T, map->F, g)) != STT_OK) return s;
+    if (K == 0) return STT_OK;
+    if (!idx_dev || !z_dev) return fail(c, STT_EINVAL, "idx_dev and z_dev must be non-NULL");
+    STT_HIP(c, hipSetDevice(c->device));
+    const MapP m = to_mapp(map);
+    const unsigned grid = (unsigned)(((int64_t)K * 64 + 255) / 256);
+    if (tracks_dev)
+        hipLaunchKernelGGL(k_rescore_f64<true>, dim3(grid), dim3(256), 0, c->stream, m, g, (const Trk *)tracks_dev,
+                           (uint64_t)first, idx_dev, K, norm, z_dev);
+    else
+        hipLaunchKernelGGL(k_rescore_f64<false>, dim3(grid), dim3(256), 0, c->stream, m, g, (const Trk *)nullptr,
+                           (uint64_t)first, idx_dev, K, norm, z_dev);
     STT_HIP(c, hipGetLastError());
     return STT_OK;
 }

@@ -18,7 +18,7 @@ LIB_PATH = os.path.join(_PKG, "libstt.so")
 
 OK, EINVAL, ERANGE, ENOMEM, EHIP, EUNSUPPORTED = 0, -1, -2, -3, -4, -5
 NORM_SQRT_N, NORM_N = 0, 1
-C64F32, C16F16 = 0, 1
+C64F32, C16 = 0, 1  # map element formats: (complex64 Y, float32 sigma) / FP16 p
 FBITS = 8
 MAX_T, MAX_F = 2896, 32767
 DTAU_UNIT_S = 2.0 ** -28
@@ -139,6 +139,26 @@ class Map:
 
     def c(self) -> _Map:
         return _Map(self.T, self.F, self.ld, C64F32, 0, self.Y.data_ptr(), self.sigma.data_ptr(),
+                    self.fq4_lo, self.dfq4)
+
+
+class P16Map:
+    """An FP16 map of the complex SNR p = Y/sigma: data [T][ld][2] float16, p = data * 2^scale_exp."""
+
+    def __init__(self, data: torch.Tensor, scale_exp: int, fq4_lo: int = 1600, dfq4: int = 16):
+        if data.dtype != torch.float16 or data.dim() != 3 or data.shape[2] != 2 or not data.is_cuda:
+            raise ValueError("data must be a [T][F][2] float16 tensor on the GPU")
+        if data.stride(2) != 1 or data.stride(1) != 2:
+            raise ValueError("pairs must be contiguous and frequency-contiguous")
+        self.data = data
+        self.T, self.F = data.shape[0], data.shape[1]
+        self.ld = data.stride(0) // 2
+        self.scale_exp = int(scale_exp)
+        self.fq4_lo, self.dfq4 = fq4_lo, dfq4
+        self.Y = data  # device placement for allocations
+
+    def c(self) -> _Map:
+        return _Map(self.T, self.F, self.ld, C16, self.scale_exp, self.data.data_ptr(), None,
                     self.fq4_lo, self.dfq4)
 
 
@@ -268,6 +288,38 @@ class Context:
                                     C.c_void_p(snr.data_ptr()) if snr is not None else None,
                                     C.c_void_p(best_key.data_ptr())))
         return snr, best_key
+
+    def pack_p16(self, m: Map) -> P16Map:
+        """FP16 copy of the map's complex SNR p = Y/sigma with a per-map 2^e scale (synchronises)."""
+        out = torch.empty((m.T, m.F, 2), dtype=torch.float16, device=m.Y.device)
+        e = C.c_int32()
+        mc = m.c()
+        self._chk(self._L.stt_map_pack_p16(self.h, C.byref(mc), C.c_void_p(out.data_ptr()), m.F, C.byref(e)))
+        return P16Map(out, e.value, m.fq4_lo, m.dfq4)
+
+    def topk(self, snr: torch.Tensor, K: int, first: int = 0, n: int | None = None):
+        """(int64 indices, float32 scores) of the K best of snr[0..n), best first."""
+        if snr.dtype != torch.float32 or not snr.is_contiguous():
+            raise ValueError("snr must be a contiguous float32 tensor")
+        n = snr.numel() if n is None else n
+        idx = torch.empty(K, dtype=torch.int64, device=snr.device)
+        val = torch.empty(K, dtype=torch.float32, device=snr.device)
+        self._chk(self._L.stt_topk(self.h, C.c_void_p(snr.data_ptr()), n, first, K, C.c_void_p(idx.data_ptr()),
+                                   C.c_void_p(val.data_ptr())))
+        return idx, val
+
+    def rescore_f64(self, m: Map, idx: torch.Tensor, gen: Gen | None = None, tracks: torch.Tensor | None = None,
+                    first: int = 0, norm: int = NORM_SQRT_N) -> torch.Tensor:
+        """FP64 scores of tracks idx (drawn from gen, or tracks[idx - first]) on the FP32 map."""
+        if idx.dtype != torch.int64 or not idx.is_contiguous():
+            raise ValueError("idx must be a contiguous int64 tensor")
+        out = torch.empty(idx.numel(), dtype=torch.float64, device=idx.device)
+        mc = m.c()
+        g = gen.c() if gen is not None else None
+        self._chk(self._L.stt_rescore_f64(self.h, C.byref(mc), C.byref(g) if g is not None else None,
+                                          C.c_void_p(tracks.data_ptr()) if tracks is not None else None, first,
+                                          C.c_void_p(idx.data_ptr()), idx.numel(), norm, C.c_void_p(out.data_ptr())))
+        return out
 
     def argmax(self, snr: torch.Tensor, first: int = 0, best_key: torch.Tensor | None = None) -> torch.Tensor:
         if snr.dtype != torch.float32 or not snr.is_contiguous():

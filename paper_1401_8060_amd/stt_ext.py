@@ -1,6 +1,20 @@
-"""Bindings of the extension entry points of libstt (filled in as they are exported)."""
+"""Bindings of the extension entry points of libstt: FP16 maps, top-K, FP64 re-score."""
 from __future__ import annotations
+
+import ctypes as C
 
 
 def bind(L) -> None:
-    return None
+    vp, i32, i64 = C.c_void_p, C.c_int32, C.c_int64
+    sigs = {
+        "stt_map_pack_p16": ([vp, vp, vp, i64, C.POINTER(i32)], i32),
+        "stt_topk": ([vp, vp, i64, i64, i32, vp, vp], i32),
+        "stt_rescore_f64": ([vp, vp, vp, vp, i64, vp, i32, i32, vp], i32),
+    }
+    for name, (args, res) in sigs.items():
+        fn = getattr(L, name)
+        fn.argtypes = args
+        fn.restype = res
+
+
+EXPORTED = ["stt_map_pack_p16", "stt_topk", "stt_rescore_f64"]

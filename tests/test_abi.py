@@ -37,7 +37,8 @@ def libstt():
 
 def test_header_declares_the_entry_points():
     names = declared_functions()
-    for required in ["stt_make_tracks", "stt_score", "stt_argmax", "stt_create", "stt_destroy"]:
+    for required in ["stt_make_tracks", "stt_score", "stt_argmax", "stt_create", "stt_destroy", "stt_topk",
+                     "stt_rescore_f64", "stt_map_pack_p16"]:
         assert required in names
 
 
