@@ -183,10 +183,12 @@ stt_status stt_topk(stt_ctx *ctx, const float *snr_dev, int64_t n, int64_t first
 
 /* FP64 re-score of K tracks (Eq. 8) from an FP32 (STT_C64F32) map: z_dev[i]
  * (double) for track j = idx_dev[i], drawn from `gen` (tracks_dev == NULL) or
- * read at tracks_dev[j - first]. Rows, phases and sums are computed exactly /
- * in FP64; an invalid track (or j < first) gives NaN. */
+ * read at tracks_dev[j - first] from a list of n_tracks. Rows and phases are
+ * exact integers, terms and sums FP64; an invalid track, or j outside the
+ * list (or outside [0, 2^32) for drawn tracks), gives NaN. */
 stt_status stt_rescore_f64(stt_ctx *ctx, const stt_map *map, const stt_gen *gen, const stt_track *tracks_dev,
-                           int64_t first, const int64_t *idx_dev, int32_t K, int32_t norm, double *z_dev);
+                           int64_t n_tracks, int64_t first, const int64_t *idx_dev, int32_t K, int32_t norm,
+                           double *z_dev);
 
 /* Host helpers for the key format (no device work). */
 uint64_t stt_key_encode(float z, uint32_t j);

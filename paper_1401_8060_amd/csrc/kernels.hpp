@@ -518,12 +518,15 @@ __global__ __launch_bounds__(256) void k_topk_pick(TopkState *st, int shift)
 }
 
 __global__ __launch_bounds__(256) void k_topk_gather(const float *z, int64_t n, uint64_t first, TopkState *st,
-                                                     uint64_t *cand)
+                                                     uint64_t *cand, uint32_t K)
 {
     const uint64_t thr = st->prefix;
     for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < n; i += (int64_t)gridDim.x * 256) {
         const uint64_t k = key_encode(z[i], (uint32_t)(first + (uint64_t)i));
-        if (k >= thr) cand[atomicAdd(&st->count, 1u)] = k;
+        if (k >= thr) {
+            const uint32_t pos = atomicAdd(&st->count, 1u);
+            if (pos < K) cand[pos] = k;  // exactly K keys pass (all keys are distinct); the bound is a guard
+        }
     }
 }
 
@@ -562,7 +565,7 @@ __global__ __launch_bounds__(1024) void k_topk_sort(const uint64_t *cand, int K,
 // reduction, so the result is deterministic).
 
 template <bool EXPL>
-__global__ __launch_bounds__(256) void k_rescore_f64(MapP m, GenP g, const Trk *tr, uint64_t first,
+__global__ __launch_bounds__(256) void k_rescore_f64(MapP m, GenP g, const Trk *tr, int64_t ntr, uint64_t first,
                                                      const int64_t *idx, int32_t K, int32_t norm, double *out)
 {
     const int w = (int)(((int64_t)blockIdx.x * 256 + threadIdx.x) >> 6);
@@ -570,11 +573,13 @@ __global__ __launch_bounds__(256) void k_rescore_f64(MapP m, GenP g, const Trk *
     if (w >= K) return;
     const int64_t j = idx[w];
     Trk t;
-    bool ok = j >= (int64_t)first;
+    bool ok;
     if (EXPL) {
+        ok = j >= (int64_t)first && j - (int64_t)first < ntr;
         t = tr[ok ? j - (int64_t)first : 0];
         ok = ok && track_ok(t, m);
     } else {
+        ok = j >= 0 && j < ((int64_t)1 << 32);
         t = draw_track(g, (uint64_t)j);
     }
     double s = 0.0;

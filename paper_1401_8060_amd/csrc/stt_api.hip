@@ -560,7 +560,8 @@ stt_status stt_topk(stt_ctx *c, const float *snr_dev, int64_t n, int64_t first, 
         hipLaunchKernelGGL(k_topk_hist, dim3(grid), dim3(256), 0, c->stream, snr_dev, n, (uint64_t)first, st, shift);
         hipLaunchKernelGGL(k_topk_pick, dim3(1), dim3(256), 0, c->stream, st, shift);
     }
-    hipLaunchKernelGGL(k_topk_gather, dim3(grid), dim3(256), 0, c->stream, snr_dev, n, (uint64_t)first, st, cand);
+    hipLaunchKernelGGL(k_topk_gather, dim3(grid), dim3(256), 0, c->stream, snr_dev, n, (uint64_t)first, st, cand,
+                       (uint32_t)K);
     int P = 1;
     while (P < K) P <<= 1;
     hipLaunchKernelGGL(k_topk_sort, dim3(1), dim3(1024), sizeof(uint64_t) * P, c->stream, (const uint64_t *)cand, K,
@@ -570,7 +571,8 @@ stt_status stt_topk(stt_ctx *c, const float *snr_dev, int64_t n, int64_t first, 
 }
 
 stt_status stt_rescore_f64(stt_ctx *c, const stt_map *map, const stt_gen *gen, const stt_track *tracks_dev,
-                           int64_t first, const int64_t *idx_dev, int32_t K, int32_t norm, double *z_dev)
+                           int64_t n_tracks, int64_t first, const int64_t *idx_dev, int32_t K, int32_t norm,
+                           double *z_dev)
 {
     if (!c) return STT_EINVAL;
     stt_status s = check_map(c, map);
@@ -579,6 +581,7 @@ stt_status stt_rescore_f64(stt_ctx *c, const stt_map *map, const stt_gen *gen, c
     if (norm != STT_NORM_SQRT_N && norm != STT_NORM_N) return fail(c, STT_EINVAL, "norm=%d", norm);
     if (K < 0) return fail(c, STT_EINVAL, "K=%d", K);
     if (first < 0) return fail(c, STT_EINVAL, "first=%lld", (long long)first);
+    if (tracks_dev && n_tracks < 0) return fail(c, STT_EINVAL, "n_tracks=%lld", (long long)n_tracks);
     GenP g{};
     if (!tracks_dev && (s = make_genp(c, gen, map->T, map->F, g)) != STT_OK) return s;
     if (K == 0) return STT_OK;
@@ -588,10 +591,10 @@ stt_status stt_rescore_f64(stt_ctx *c, const stt_map *map, const stt_gen *gen, c
     const unsigned grid = (unsigned)(((int64_t)K * 64 + 255) / 256);
     if (tracks_dev)
         hipLaunchKernelGGL(k_rescore_f64<true>, dim3(grid), dim3(256), 0, c->stream, m, g, (const Trk *)tracks_dev,
-                           (uint64_t)first, idx_dev, K, norm, z_dev);
+                           n_tracks, (uint64_t)first, idx_dev, K, norm, z_dev);
     else
         hipLaunchKernelGGL(k_rescore_f64<false>, dim3(grid), dim3(256), 0, c->stream, m, g, (const Trk *)nullptr,
-                           (uint64_t)first, idx_dev, K, norm, z_dev);
+                           (int64_t)0, (uint64_t)first, idx_dev, K, norm, z_dev);
     STT_HIP(c, hipGetLastError());
     return STT_OK;
 }

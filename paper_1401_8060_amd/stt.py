@@ -317,7 +317,8 @@ class Context:
         mc = m.c()
         g = gen.c() if gen is not None else None
         self._chk(self._L.stt_rescore_f64(self.h, C.byref(mc), C.byref(g) if g is not None else None,
-                                          C.c_void_p(tracks.data_ptr()) if tracks is not None else None, first,
+                                          C.c_void_p(tracks.data_ptr()) if tracks is not None else None,
+                                          tracks.shape[0] if tracks is not None else 0, first,
                                           C.c_void_p(idx.data_ptr()), idx.numel(), norm, C.c_void_p(out.data_ptr())))
         return out
 

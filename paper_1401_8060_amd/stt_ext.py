@@ -9,7 +9,7 @@ def bind(L) -> None:
     sigs = {
         "stt_map_pack_p16": ([vp, vp, vp, i64, C.POINTER(i32)], i32),
         "stt_topk": ([vp, vp, i64, i64, i32, vp, vp], i32),
-        "stt_rescore_f64": ([vp, vp, vp, vp, i64, vp, i32, i32, vp], i32),
+        "stt_rescore_f64": ([vp, vp, vp, vp, i64, i64, vp, i32, i32, vp], i32),
     }
     for name, (args, res) in sigs.items():
         fn = getattr(L, name)
