@@ -190,6 +190,25 @@ stt_status stt_rescore_f64(stt_ctx *ctx, const stt_map *map, const stt_gen *gen,
                            int64_t n_tracks, int64_t first, const int64_t *idx_dev, int32_t K, int32_t norm,
                            double *z_dev);
 
+/* Batch of maps (the paper's n_ts time-shifted background maps, Sec. V; one
+ * recorded maximum per spectrogram). Map m (maps_host[m], host array; all of
+ * one dtype, each its own T, F, ld) is scored with n_trk_host[m] templates
+ * j = 0 .. n_trk-1 drawn from `gen` with Philox stream gen->stream + m.
+ * best_key_per_map_dev[m] is max-merged with map m's best key (indices are
+ * per map); if snr_dev_host (host array of n_maps device pointers, entries
+ * may be NULL) is given, snr_dev_host[m][j] receives the scores. All maps are
+ * binned and scored by one persistent launch whose workgroups take (map,
+ * block) items from a device queue. With graphs on (default) the whole call
+ * is captured in a HIP graph, replayed while every argument stays the same.
+ * Any change of arguments re-uploads the descriptor tables (synchronising the
+ * stream) and re-captures. Requires sum n_trk < 2^32. */
+stt_status stt_score_batch(stt_ctx *ctx, const stt_map *maps_host, int32_t n_maps, const stt_gen *gen,
+                           const int64_t *n_trk_host, int32_t norm, uint64_t *best_key_per_map_dev,
+                           float *const *snr_dev_host);
+
+/* Graph capture of batches on (1, default) or off (0: direct launches). */
+stt_status stt_set_graph(stt_ctx *ctx, int32_t on);
+
 /* Host helpers for the key format (no device work). */
 uint64_t stt_key_encode(float z, uint32_t j);
 void stt_key_decode(uint64_t key, float *z, uint32_t *j);

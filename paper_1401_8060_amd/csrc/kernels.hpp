@@ -319,17 +319,19 @@ __device__ __forceinline__ void walk(int ca, int cb, int c0, const float2 *slab,
     }
 }
 
+// One block of WG*TPT consecutive entries of `order` (block index b): the
+// whole slab sweep for those templates. slab is the dynamic LDS (S*F float2),
+// bnd two LDS ints. Callable repeatedly by a persistent workgroup.
 template <int WG, int TPT, bool EXPL, bool HW, int MAPT>
-__global__ __launch_bounds__(WG) void k_score_slab(MapP m, GenP g, const Trk *tr, const uint32_t *order,
-                                                   uint64_t first, int64_t n, int S, int32_t norm, float *snr,
-                                                   uint64_t *best)
+__device__ __forceinline__ void score_block(const MapP &m, const GenP &g, const Trk *tr, const uint32_t *order,
+                                            uint64_t first, int64_t n, int64_t b, int S, int32_t norm, float *snr,
+                                            uint64_t *best, float2 *slab, int *bnd)
 {
-    extern __shared__ float2 slab[];
-    __shared__ int blo, bhi;
-    if (threadIdx.x == 0) { blo = 0x7fffffff; bhi = -1; }
+    __syncthreads();  // LDS of a previous block is no longer read
+    if (threadIdx.x == 0) { bnd[0] = 0x7fffffff; bnd[1] = -1; }
 
     const int lane = threadIdx.x & 63;
-    const int64_t wbase = (int64_t)blockIdx.x * (WG * TPT) + (int64_t)(threadIdx.x >> 6) * (64 * TPT);
+    const int64_t wbase = b * (WG * TPT) + (int64_t)(threadIdx.x >> 6) * (64 * TPT);
     Trk tk[TPT];
     int32_t t0[TPT];
     uint32_t span[TPT], pa[TPT], pbl[TPT], pbh[TPT], idx[TPT];
@@ -381,11 +383,11 @@ __global__ __launch_bounds__(WG) void k_score_slab(MapP m, GenP g, const Trk *tr
     }
     __syncthreads();
     if (lane == 0) {
-        atomicMin(&blo, lo);
-        atomicMax(&bhi, hi);
+        atomicMin(&bnd[0], lo);
+        atomicMax(&bnd[1], hi);
     }
     __syncthreads();
-    const int c_first = blo, c_last = bhi;
+    const int c_first = bnd[0], c_last = bnd[1];
     const int F = m.F;
     // staging walk: element e = tid + i*WG of the slab is (column e / F, row e % F)
     const int dcol = WG / F, drow = WG % F;
@@ -422,6 +424,143 @@ __global__ __launch_bounds__(WG) void k_score_slab(MapP m, GenP g, const Trk *tr
         key = k > key ? k : key;
     }
     merge_key(best, key);
+}
+
+template <int WG, int TPT, bool EXPL, bool HW, int MAPT>
+__global__ __launch_bounds__(WG) void k_score_slab(MapP m, GenP g, const Trk *tr, const uint32_t *order,
+                                                   uint64_t first, int64_t n, int S, int32_t norm, float *snr,
+                                                   uint64_t *best)
+{
+    extern __shared__ float2 slab[];
+    __shared__ int bnd[2];
+    score_block<WG, TPT, EXPL, HW, MAPT>(m, g, tr, order, first, n, (int64_t)blockIdx.x, S, norm, snr, best, slab,
+                                         bnd);
+}
+
+// ---------------------------------------------------------------- batches of maps
+// A batch scores n_m generated templates on each map m (the paper's n_ts
+// time-shifted background maps, Sec. V). Map m's templates are binned within
+// the map; its blocks of WG*TPT binned templates are the work items
+// [item0[m], item0[m+1]). One persistent launch: each workgroup takes the
+// next item from an atomic queue until the queue is empty, so maps of uneven
+// length share the machine without a tail per map.
+
+struct BatchMap {
+    MapP m;
+    GenP g;
+    int64_t n;          // templates on this map
+    uint64_t order0;    // offset of this map's binned order in the shared order array
+    uint64_t bin0;      // offset of this map's bucket counters
+    int32_t wb, nbins;  // bucket shift and count of this map
+    int32_t S;          // slab columns
+    int32_t chunk0;     // first sort chunk of this map
+    float *snr;         // optional per-template output
+};
+
+__device__ __forceinline__ int find_map(const uint32_t *start, int n_maps, uint32_t item)
+{
+    int lo = 0, hi = n_maps;  // start[lo] <= item < start[hi]
+    while (hi - lo > 1) {
+        const int mid = (lo + hi) >> 1;
+        if (start[mid] <= item) lo = mid; else hi = mid;
+    }
+    return lo;
+}
+
+__global__ __launch_bounds__(256) void k_bin_count_batch(const BatchMap *maps, int n_maps, const uint32_t *chunk_start,
+                                                         uint32_t *totals)
+{
+    __shared__ uint32_t hist[kMaxBins];
+    const int mi = find_map(chunk_start, n_maps, blockIdx.x);
+    const BatchMap &d = maps[mi];
+    for (int b = threadIdx.x; b < d.nbins; b += 256) hist[b] = 0;
+    __syncthreads();
+    const int64_t base = (int64_t)(blockIdx.x - chunk_start[mi]) * kBinChunk;
+    for (int q = 0; q < kBinPerThread; ++q) {
+        const int64_t i = base + q * 256 + threadIdx.x;
+        if (i < d.n) atomicAdd(&hist[bin_of<false>(d.g, nullptr, d.m, 0, i, d.wb)], 1u);
+    }
+    __syncthreads();
+    for (int b = threadIdx.x; b < d.nbins; b += 256)
+        if (hist[b]) atomicAdd(&totals[d.bin0 + b], hist[b]);
+}
+
+// One workgroup per map: exclusive scan of its bucket totals, offset by the map's order0.
+__global__ __launch_bounds__(256) void k_bin_scan_batch(const BatchMap *maps, const uint32_t *totals, uint32_t *cursor)
+{
+    __shared__ uint32_t part[256];
+    const BatchMap &d = maps[blockIdx.x];
+    const int per = (d.nbins + 255) / 256;
+    const int lo = threadIdx.x * per, hi = min(d.nbins, lo + per);
+    uint32_t s = 0;
+    for (int b = lo; b < hi; ++b) s += totals[d.bin0 + b];
+    part[threadIdx.x] = s;
+    __syncthreads();
+    for (int off = 1; off < 256; off <<= 1) {
+        const uint32_t v = threadIdx.x >= off ? part[threadIdx.x - off] : 0;
+        __syncthreads();
+        part[threadIdx.x] += v;
+        __syncthreads();
+    }
+    uint32_t run = (uint32_t)d.order0 + part[threadIdx.x] - s;
+    for (int b = lo; b < hi; ++b) {
+        cursor[d.bin0 + b] = run;
+        run += totals[d.bin0 + b];
+    }
+}
+
+__global__ __launch_bounds__(256) void k_bin_scatter_batch(const BatchMap *maps, int n_maps, const uint32_t *chunk_start,
+                                                           uint32_t *cursor, uint32_t *order)
+{
+    __shared__ uint32_t cnt[kMaxBins];
+    const int mi = find_map(chunk_start, n_maps, blockIdx.x);
+    const BatchMap &d = maps[mi];
+    for (int b = threadIdx.x; b < d.nbins; b += 256) cnt[b] = 0;
+    __syncthreads();
+    const int64_t base = (int64_t)(blockIdx.x - chunk_start[mi]) * kBinChunk;
+    uint32_t bin[kBinPerThread], rank[kBinPerThread];
+#pragma unroll
+    for (int q = 0; q < kBinPerThread; ++q) {
+        const int64_t i = base + q * 256 + threadIdx.x;
+        bin[q] = 0;
+        rank[q] = 0;
+        if (i < d.n) {
+            bin[q] = bin_of<false>(d.g, nullptr, d.m, 0, i, d.wb);
+            rank[q] = atomicAdd(&cnt[bin[q]], 1u);
+        }
+    }
+    __syncthreads();
+    for (int b = threadIdx.x; b < d.nbins; b += 256)
+        if (cnt[b]) cnt[b] = atomicAdd(&cursor[d.bin0 + b], cnt[b]);
+    __syncthreads();
+#pragma unroll
+    for (int q = 0; q < kBinPerThread; ++q) {
+        const int64_t i = base + q * 256 + threadIdx.x;
+        if (i < d.n) order[cnt[bin[q]] + rank[q]] = (uint32_t)i;
+    }
+}
+
+template <int WG, int TPT, bool HW, int MAPT>
+__global__ __launch_bounds__(WG) void k_score_batch(const BatchMap *maps, int n_maps, const uint32_t *item_start,
+                                                    uint32_t *queue, const uint32_t *order, int32_t norm,
+                                                    uint64_t *best)
+{
+    extern __shared__ float2 slab[];
+    __shared__ int bnd[2];
+    __shared__ uint32_t item_s;
+    const uint32_t total = item_start[n_maps];
+    for (;;) {
+        __syncthreads();
+        if (threadIdx.x == 0) item_s = atomicAdd(queue, 1u);
+        __syncthreads();
+        const uint32_t item = item_s;
+        if (item >= total) break;  // every workgroup reaches this: the queue only grows
+        const int mi = find_map(item_start, n_maps, item);
+        const BatchMap d = maps[mi];
+        score_block<WG, TPT, false, HW, MAPT>(d.m, d.g, nullptr, order + d.order0, 0, d.n,
+                                              (int64_t)(item - item_start[mi]), d.S, norm, d.snr, best + mi, slab,
+                                              bnd);
+    }
 }
 
 // ---------------------------------------------------------------- FP16 map packing

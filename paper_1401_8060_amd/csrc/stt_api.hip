@@ -37,6 +37,16 @@ struct stt_ctx {
     bool used[3] = {false, false, false};
     struct Rec { size_t base; bool used[3]; };
     std::vector<Rec> recs;   // calls since the last total query
+    // Batches: descriptor tables on the device, and the captured graph of the
+    // last batch (replayed while the arguments stay the same).
+    bool use_graph = true;
+    hipStream_t cap_stream = nullptr;
+    void *bdev = nullptr;
+    size_t bdev_bytes = 0;
+    std::vector<uint8_t> bkey;
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t gexec = nullptr;
+    int n_cu = 0;
 };
 
 namespace {
@@ -359,6 +369,10 @@ stt_status stt_destroy(stt_ctx *c)
     (void)hipStreamSynchronize(c->stream);
     if (c->scratch) (void)hipFree(c->scratch);
     if (c->aux) (void)hipFree(c->aux);
+    if (c->bdev) (void)hipFree(c->bdev);
+    if (c->gexec) (void)hipGraphExecDestroy(c->gexec);
+    if (c->graph) (void)hipGraphDestroy(c->graph);
+    if (c->cap_stream) (void)hipStreamDestroy(c->cap_stream);
     for (auto &e : c->pool) (void)hipEventDestroy(e);
     delete c;
     return STT_OK;
@@ -596,6 +610,226 @@ stt_status stt_rescore_f64(stt_ctx *c, const stt_map *map, const stt_gen *gen, c
         hipLaunchKernelGGL(k_rescore_f64<false>, dim3(grid), dim3(256), 0, c->stream, m, g, (const Trk *)nullptr,
                            (int64_t)0, (uint64_t)first, idx_dev, K, norm, z_dev);
     STT_HIP(c, hipGetLastError());
+    return STT_OK;
+}
+
+// ----------------------------------------------------------------------------- batches
+
+}  // extern "C"
+
+namespace {
+
+template <int WG, int TPT, bool HW, int MAPT>
+stt_status launch_batch_t(stt_ctx *c, hipStream_t st, const BatchMap *maps, int n_maps, const uint32_t *item_start,
+                          uint32_t total_items, uint32_t *queue, const uint32_t *order, int32_t norm, uint64_t *best,
+                          size_t shm)
+{
+    auto kern = k_score_batch<WG, TPT, HW, MAPT>;
+    if (shm > 64 * 1024)
+        STT_HIP(c, hipFuncSetAttribute((const void *)kern, hipFuncAttributeMaxDynamicSharedMemorySize, (int)shm));
+    int per_cu = 0;
+    STT_HIP(c, hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kern, WG, shm));
+    if (per_cu < 1) return fail(c, STT_EUNSUPPORTED, "batch scorer %dx%d does not fit with %zu B of LDS", WG, TPT, shm);
+    const unsigned grid = (unsigned)std::min<int64_t>((int64_t)per_cu * c->n_cu, total_items);
+    if (grid == 0) return STT_OK;
+    hipLaunchKernelGGL(kern, dim3(grid), dim3(WG), shm, st, maps, n_maps, item_start, queue, order, norm, best);
+    STT_HIP(c, hipGetLastError());
+    return STT_OK;
+}
+
+template <bool HW, int MAPT>
+stt_status launch_batch_h(stt_ctx *c, hipStream_t st, const BatchMap *maps, int n_maps, const uint32_t *item_start,
+                          uint32_t total_items, uint32_t *queue, const uint32_t *order, int32_t norm, uint64_t *best,
+                          size_t shm)
+{
+#define STT_BATCH_CASE(W, P)                                                                                     \
+    if (c->slab_wg == W && c->slab_tpt == P)                                                                     \
+        return launch_batch_t<W, P, HW, MAPT>(c, st, maps, n_maps, item_start, total_items, queue, order, norm, best, \
+                                              shm);
+    STT_BATCH_CASE(1024, 4)
+    STT_BATCH_CASE(512, 4)
+    STT_BATCH_CASE(256, 4)
+    STT_BATCH_CASE(1024, 2)
+    STT_BATCH_CASE(512, 2)
+#undef STT_BATCH_CASE
+    return fail(c, STT_EUNSUPPORTED, "no batch scorer for %dx%d", c->slab_wg, c->slab_tpt);
+}
+
+template <typename T>
+void key_add(std::vector<uint8_t> &k, const T &v)
+{
+    const uint8_t *b = (const uint8_t *)&v;
+    k.insert(k.end(), b, b + sizeof(T));
+}
+
+}  // namespace
+
+extern "C" {
+
+stt_status stt_set_graph(stt_ctx *c, int32_t on)
+{
+    if (!c || on < 0 || on > 1) return STT_EINVAL;
+    c->use_graph = on == 1;
+    return STT_OK;
+}
+
+stt_status stt_score_batch(stt_ctx *c, const stt_map *maps_host, int32_t n_maps, const stt_gen *gen,
+                           const int64_t *n_trk_host, int32_t norm, uint64_t *best_key_per_map_dev,
+                           float *const *snr_dev_host)
+{
+    if (!c) return STT_EINVAL;
+    if (n_maps < 0 || n_maps > 65536) return fail(c, STT_ERANGE, "n_maps=%d outside [0, 65536]", n_maps);
+    if (n_maps == 0) return STT_OK;
+    if (!maps_host || !n_trk_host || !gen) return fail(c, STT_EINVAL, "maps, gen and n_trk must be non-NULL");
+    if (!best_key_per_map_dev) return fail(c, STT_EINVAL, "best_key_per_map_dev must be non-NULL");
+    if (norm != STT_NORM_SQRT_N && norm != STT_NORM_N) return fail(c, STT_EINVAL, "norm=%d", norm);
+    const int dtype = maps_host[0].dtype;
+    std::vector<BatchMap> bm(n_maps);
+    std::vector<uint32_t> chunk_start(n_maps + 1), item_start(n_maps + 1);
+    const int per_item = c->slab_wg * c->slab_tpt;
+    uint64_t norder = 0, nchunks = 0, nitems = 0;
+    size_t shm = 0;
+    for (int i = 0; i < n_maps; ++i) {
+        const stt_map *mp = &maps_host[i];
+        stt_status s = check_map(c, mp);
+        if (s != STT_OK) return fail(c, s, "map %d: %s", i, c->err.c_str());
+        if (mp->dtype != dtype) return fail(c, STT_EINVAL, "all maps of a batch share one dtype");
+        const int64_t n = n_trk_host[i];
+        if (n < 0 || n > ((int64_t)1 << 32)) return fail(c, STT_ERANGE, "map %d: n_trk=%lld", i, (long long)n);
+        stt_gen g = *gen;
+        g.stream = gen->stream + (uint32_t)i;
+        BatchMap &d = bm[i];
+        if ((s = make_genp(c, &g, mp->T, mp->F, d.g)) != STT_OK) return fail(c, s, "map %d: %s", i, c->err.c_str());
+        d.m = to_mapp(mp);
+        d.n = n;
+        d.order0 = norder;
+        d.bin0 = (uint64_t)i * kMaxBins;
+        d.wb = bucket_shift(mp->T);
+        const int nb = ((mp->T - 1) >> d.wb) + 1;
+        d.nbins = nb * (nb + 1) / 2;
+        d.S = std::min(std::min<int>(64, (c->lds_bytes - 256) / (8 * mp->F)), mp->T);
+        if (d.S < 1) return fail(c, STT_EUNSUPPORTED, "map %d: F=%d too wide for the LDS slab", i, mp->F);
+        shm = std::max(shm, sizeof(float2) * (size_t)d.S * mp->F);
+        d.snr = snr_dev_host ? snr_dev_host[i] : nullptr;
+        chunk_start[i] = (uint32_t)nchunks;
+        item_start[i] = (uint32_t)nitems;
+        d.chunk0 = (int32_t)nchunks;
+        norder += (uint64_t)n;
+        nchunks += (uint64_t)((n + kBinChunk - 1) / kBinChunk);
+        nitems += (uint64_t)((n + per_item - 1) / per_item);
+        if (norder >= ((uint64_t)1 << 32) || nitems >= ((uint64_t)1 << 31))
+            return fail(c, STT_ERANGE, "a batch holds fewer than 2^32 templates");
+    }
+    chunk_start[n_maps] = (uint32_t)nchunks;
+    item_start[n_maps] = (uint32_t)nitems;
+    STT_HIP(c, hipSetDevice(c->device));
+    if (!c->n_cu) STT_HIP(c, hipDeviceGetAttribute(&c->n_cu, hipDeviceAttributeMultiprocessorCount, c->device));
+
+    // scratch: [totals | cursor | queue | order]
+    const size_t nb_all = (size_t)n_maps * kMaxBins;
+    const size_t need = sizeof(uint32_t) * (2 * nb_all + 64 + norder);
+    stt_status s = ensure_scratch(c, need);
+    if (s != STT_OK) return s;
+    uint32_t *totals = (uint32_t *)c->scratch;
+    uint32_t *cursor = totals + nb_all;
+    uint32_t *queue = cursor + nb_all;
+    uint32_t *order = queue + 64;
+
+    // the argument key: a repeat of the last batch replays its graph
+    std::vector<uint8_t> key;
+    key_add(key, n_maps);
+    key_add(key, norm);
+    key_add(key, best_key_per_map_dev);
+    key_add(key, c->scratch);
+    key_add(key, c->slab_wg);
+    key_add(key, c->slab_tpt);
+    key_add(key, c->lds_bytes);
+    key_add(key, c->hw_trig);
+    for (const auto &d : bm) key_add(key, d);
+    const bool same = c->use_graph && c->gexec && key == c->bkey;
+
+    if (!same) {
+        // descriptor tables to the device (synchronous: they must outlive the call)
+        const size_t tbl = sizeof(BatchMap) * n_maps + sizeof(uint32_t) * 2 * (n_maps + 1);
+        if (tbl > c->bdev_bytes) {
+            STT_HIP(c, hipStreamSynchronize(c->stream));
+            if (c->bdev) (void)hipFree(c->bdev);
+            c->bdev = nullptr;
+            c->bdev_bytes = 0;
+            if (hipMalloc(&c->bdev, tbl) != hipSuccess) {
+                (void)hipGetLastError();
+                return fail(c, STT_ENOMEM, "cannot allocate %zu bytes of batch tables", tbl);
+            }
+            c->bdev_bytes = tbl;
+        }
+        STT_HIP(c, hipStreamSynchronize(c->stream));  // the previous batch may still read the tables
+        BatchMap *dmaps = (BatchMap *)c->bdev;
+        uint32_t *dchunk = (uint32_t *)(dmaps + n_maps);
+        uint32_t *ditem = dchunk + (n_maps + 1);
+        STT_HIP(c, hipMemcpy(dmaps, bm.data(), sizeof(BatchMap) * n_maps, hipMemcpyHostToDevice));
+        STT_HIP(c, hipMemcpy(dchunk, chunk_start.data(), sizeof(uint32_t) * (n_maps + 1), hipMemcpyHostToDevice));
+        STT_HIP(c, hipMemcpy(ditem, item_start.data(), sizeof(uint32_t) * (n_maps + 1), hipMemcpyHostToDevice));
+        if (c->gexec) { (void)hipGraphExecDestroy(c->gexec); c->gexec = nullptr; }
+        if (c->graph) { (void)hipGraphDestroy(c->graph); c->graph = nullptr; }
+        c->bkey.clear();
+
+        auto enqueue = [&](hipStream_t st) -> stt_status {
+            hipLaunchKernelGGL(k_fill_u32, dim3((unsigned)((nb_all + 64 + 255) / 256)), dim3(256), 0, st, totals,
+                               (int64_t)(nb_all), 0u);
+            hipLaunchKernelGGL(k_fill_u32, dim3(1), dim3(256), 0, st, queue, (int64_t)1, 0u);
+            if (nchunks) {
+                hipLaunchKernelGGL(k_bin_count_batch, dim3((unsigned)nchunks), dim3(256), 0, st,
+                                   (const BatchMap *)dmaps, n_maps, (const uint32_t *)dchunk, totals);
+                hipLaunchKernelGGL(k_bin_scan_batch, dim3(n_maps), dim3(256), 0, st, (const BatchMap *)dmaps,
+                                   (const uint32_t *)totals, cursor);
+                hipLaunchKernelGGL(k_bin_scatter_batch, dim3((unsigned)nchunks), dim3(256), 0, st,
+                                   (const BatchMap *)dmaps, n_maps, (const uint32_t *)dchunk, cursor, order);
+            }
+            STT_HIP(c, hipGetLastError());
+            if (dtype == STT_P16)
+                return c->hw_trig ? launch_batch_h<true, kMapP16>(c, st, dmaps, n_maps, ditem, (uint32_t)nitems, queue,
+                                                                  order, norm, best_key_per_map_dev, shm)
+                                  : launch_batch_h<false, kMapP16>(c, st, dmaps, n_maps, ditem, (uint32_t)nitems,
+                                                                   queue, order, norm, best_key_per_map_dev, shm);
+            return c->hw_trig ? launch_batch_h<true, kMapF32>(c, st, dmaps, n_maps, ditem, (uint32_t)nitems, queue,
+                                                              order, norm, best_key_per_map_dev, shm)
+                              : launch_batch_h<false, kMapF32>(c, st, dmaps, n_maps, ditem, (uint32_t)nitems, queue,
+                                                               order, norm, best_key_per_map_dev, shm);
+        };
+
+        if (!c->use_graph) {
+            if ((s = ev_begin(c)) != STT_OK) return s;
+            ev_record(c, 4);
+            ev_record(c, 0);
+            s = enqueue(c->stream);
+            ev_record(c, 1);
+            ev_record(c, 5);
+            c->used[0] = c->used[2] = true;
+            ev_end(c);
+            return s;
+        }
+        if (!c->cap_stream) STT_HIP(c, hipStreamCreateWithFlags(&c->cap_stream, hipStreamNonBlocking));
+        STT_HIP(c, hipStreamBeginCapture(c->cap_stream, hipStreamCaptureModeRelaxed));
+        s = enqueue(c->cap_stream);
+        hipGraph_t g = nullptr;
+        const hipError_t e = hipStreamEndCapture(c->cap_stream, &g);
+        if (s != STT_OK) {
+            if (g) (void)hipGraphDestroy(g);
+            return s;
+        }
+        if (e != hipSuccess) return fail(c, STT_EHIP, "hipStreamEndCapture: %s", hipGetErrorString(e));
+        c->graph = g;
+        STT_HIP(c, hipGraphInstantiate(&c->gexec, c->graph, nullptr, nullptr, 0));
+        c->bkey = key;
+    }
+    if ((s = ev_begin(c)) != STT_OK) return s;
+    ev_record(c, 4);
+    ev_record(c, 0);
+    STT_HIP(c, hipGraphLaunch(c->gexec, c->stream));
+    ev_record(c, 1);
+    ev_record(c, 5);
+    c->used[0] = c->used[2] = true;
+    ev_end(c);
     return STT_OK;
 }
 

@@ -322,6 +322,39 @@ class Context:
                                           C.c_void_p(idx.data_ptr()), idx.numel(), norm, C.c_void_p(out.data_ptr())))
         return out
 
+    def set_graph(self, on: bool):
+        self._chk(self._L.stt_set_graph(self.h, 1 if on else 0))
+
+    def score_batch(self, maps, gen: Gen, n_trk, norm: int = NORM_SQRT_N, best_keys: torch.Tensor | None = None,
+                    snr=None) -> torch.Tensor:
+        """Score n_trk[m] templates on each map m (Philox stream gen.stream + m) in one launch.
+
+        Returns the [n_maps] int64 best-key tensor (max-merged into ``best_keys`` when given).
+        ``snr`` is None or a list of per-map float32 tensors (entries may be None).
+        """
+        nm = len(maps)
+        if len(n_trk) != nm:
+            raise ValueError("one template count per map")
+        dev = maps[0].Y.device if nm else torch.device("cuda")
+        if best_keys is None:
+            best_keys = torch.zeros(nm, dtype=torch.int64, device=dev)
+        if best_keys.dtype != torch.int64 or best_keys.numel() < nm or not best_keys.is_contiguous():
+            raise ValueError("best_keys must be a contiguous int64 tensor with one entry per map")
+        arr = (_Map * max(nm, 1))(*[m.c() for m in maps])
+        ns = (C.c_int64 * max(nm, 1))(*[int(x) for x in n_trk])
+        ptrs = None
+        if snr is not None:
+            if len(snr) != nm:
+                raise ValueError("one snr entry per map")
+            for t, n in zip(snr, n_trk):
+                if t is not None and (t.dtype != torch.float32 or t.numel() < n or not t.is_contiguous()):
+                    raise ValueError("snr tensors must be contiguous float32 with n_trk elements")
+            ptrs = (C.c_void_p * max(nm, 1))(*[t.data_ptr() if t is not None else None for t in snr])
+        g = gen.c()
+        self._chk(self._L.stt_score_batch(self.h, arr, nm, C.byref(g), ns, norm, C.c_void_p(best_keys.data_ptr()),
+                                          ptrs))
+        return best_keys
+
     def argmax(self, snr: torch.Tensor, first: int = 0, best_key: torch.Tensor | None = None) -> torch.Tensor:
         if snr.dtype != torch.float32 or not snr.is_contiguous():
             raise ValueError("snr must be a contiguous float32 tensor")

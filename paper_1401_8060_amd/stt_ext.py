@@ -10,6 +10,8 @@ def bind(L) -> None:
         "stt_map_pack_p16": ([vp, vp, vp, i64, C.POINTER(i32)], i32),
         "stt_topk": ([vp, vp, i64, i64, i32, vp, vp], i32),
         "stt_rescore_f64": ([vp, vp, vp, vp, i64, i64, vp, i32, i32, vp], i32),
+        "stt_score_batch": ([vp, vp, i32, vp, vp, i32, vp, vp], i32),
+        "stt_set_graph": ([vp, i32], i32),
     }
     for name, (args, res) in sigs.items():
         fn = getattr(L, name)
@@ -17,4 +19,4 @@ def bind(L) -> None:
         fn.restype = res
 
 
-EXPORTED = ["stt_map_pack_p16", "stt_topk", "stt_rescore_f64"]
+EXPORTED = ["stt_map_pack_p16", "stt_topk", "stt_rescore_f64", "stt_score_batch", "stt_set_graph"]

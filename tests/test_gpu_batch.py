@@ -1,0 +1,143 @@
+"""GPU parity of the batching addition: many maps of uneven duration scored in one
+persistent launch (optionally captured in a HIP graph), per-map maximum and argmax."""
+from __future__ import annotations
+
+import sys
+
+import numpy as np
+import pytest
+
+import synth
+from tests.parity_util import assert_argmax, assert_close, key_to_host, to_dev
+
+pytestmark = pytest.mark.gpu
+D10MS = 2684355
+
+
+@pytest.fixture(scope="module")
+def stt():
+    import paper_1401_8060_amd.stt as stt
+    return stt
+
+
+@pytest.fixture(scope="module")
+def ctx(stt):
+    c = stt.Context(0)
+    yield c
+    c.close()
+
+
+def _say(*a):
+    print(*a, flush=True, file=sys.stderr)
+
+
+def _maps(Ts, F, seed):
+    out = []
+    for k, T in enumerate(Ts):
+        Y, s = synth.noise_map(T, F, seed=seed, sigma=("loguniform", 0.5, 2.0), stream=k)
+        out.append((Y, s))
+    return out
+
+
+def _per_map(ctx, stt, maps, g, ns):
+    import torch
+    keys, snrs = [], []
+    for k, (m, n) in enumerate(zip(maps, ns)):
+        gk = stt.Gen(seed=g.seed, stream=g.stream + k, min_len=g.min_len, dtau_max=g.dtau_max)
+        snr, key = ctx.score(m, gen=gk, n=n) if n else (torch.empty(0, device="cuda"), torch.zeros(1, dtype=torch.int64, device="cuda"))
+        keys.append(key_to_host(key))
+        snrs.append(snr.cpu().numpy())
+    return keys, snrs
+
+
+@pytest.mark.parametrize("graph", [False, True])
+def test_batch_equals_per_map_calls(stt, ctx, graph):
+    import torch
+    _say("batch vs per-map, graph", graph)
+    Ts = [60, 900, 333, 10, 1500, 257, 700]
+    ns = [5000, 40000, 0, 777, 60001, 4096, 12345]
+    F = 300
+    host = _maps(Ts, F, seed=31)
+    maps = [stt.Map(*to_dev(Y, s)) for Y, s in host]
+    g = stt.Gen(seed=9, stream=100, min_len=10, dtau_max=D10MS)
+    ctx.set_graph(graph)
+    snr = [torch.empty(max(n, 1), dtype=torch.float32, device="cuda") for n in ns]
+    keys = ctx.score_batch(maps, g, ns, snr=snr)
+    want_keys, want_snr = _per_map(ctx, stt, maps, g, ns)
+    got = keys.cpu().numpy().view(np.uint64).tolist()
+    assert got == want_keys
+    for k, n in enumerate(ns):
+        assert np.array_equal(snr[k][:n].cpu().numpy(), want_snr[k])
+    ctx.set_graph(True)
+
+
+def test_batch_against_oracle(orc, stt, ctx):
+    _say("batch vs oracle")
+    Ts = [40, 120, 75]
+    ns = [3000, 6000, 4500]
+    F = 64
+    host = _maps(Ts, F, seed=32)
+    maps = [stt.Map(*to_dev(Y, s)) for Y, s in host]
+    g = stt.Gen(seed=5, stream=0, min_len=10, dtau_max=D10MS)
+    import torch
+    snr = [torch.empty(n, dtype=torch.float32, device="cuda") for n in ns]
+    keys = ctx.score_batch(maps, g, ns, snr=snr).cpu().numpy().view(np.uint64)
+    for k, ((Y, s), n) in enumerate(zip(host, ns)):
+        z_orc = orc.score_gen(orc.Map(Y, s), 5, k, 10, D10MS, 0, n)
+        assert_close(snr[k].cpu().numpy(), z_orc, what=f"map {k}")
+        assert_argmax(stt.key_decode(int(keys[k]))[1], z_orc)
+
+
+def test_graph_replays_match_eager(stt, ctx):
+    """Replays of the captured batch, with eager work in between, each equal to the eager result."""
+    import torch
+    _say("graph replays")
+    Ts = [500, 800, 650]
+    ns = [100_000, 150_000, 80_000]
+    host = _maps(Ts, 400, seed=33)
+    maps = [stt.Map(*to_dev(Y, s)) for Y, s in host]
+    g = stt.Gen(seed=2, stream=0, min_len=10, dtau_max=D10MS)
+    ctx.set_graph(False)
+    eager = ctx.score_batch(maps, g, ns).clone()
+    ctx.set_graph(True)
+    keys = torch.zeros(3, dtype=torch.int64, device="cuda")
+    for rep in range(4):
+        keys.zero_()
+        ctx.score_batch(maps, g, ns, best_keys=keys)
+        # unrelated eager work and a synchronisation between replays
+        ctx.score(maps[0], gen=g, n=5000)
+        torch.cuda.synchronize()
+        assert torch.equal(keys, eager), rep
+    # a changed argument is re-captured, not replayed stale
+    ns2 = [100_000, 150_001, 80_000]
+    ctx.set_graph(False)
+    eager2 = ctx.score_batch(maps, g, ns2).clone()
+    ctx.set_graph(True)
+    assert torch.equal(ctx.score_batch(maps, g, ns2), eager2)
+    assert torch.equal(ctx.score_batch(maps, g, ns), eager)
+
+
+def test_fp16_batch_equals_per_map(stt, ctx):
+    _say("fp16 batch")
+    Ts = [300, 1000, 450]
+    ns = [20000, 50000, 30000]
+    host = _maps(Ts, 500, seed=34)
+    maps = [ctx.pack_p16(stt.Map(*to_dev(Y, s))) for Y, s in host]
+    g = stt.Gen(seed=3, stream=7, min_len=10, dtau_max=D10MS)
+    keys = ctx.score_batch(maps, g, ns).cpu().numpy().view(np.uint64).tolist()
+    want, _ = _per_map(ctx, stt, maps, g, ns)
+    assert keys == want
+
+
+def test_batch_argument_errors(stt, ctx):
+    _say("batch errors")
+    Y, s = synth.noise_map(50, 20, seed=1)
+    m = stt.Map(*to_dev(Y, s))
+    with pytest.raises(stt.SttError):
+        ctx.score_batch([m, m], stt.Gen(min_len=60), [10, 10])
+    with pytest.raises(ValueError):
+        ctx.score_batch([m, m], stt.Gen(), [10])
+    pm = ctx.pack_p16(m)
+    with pytest.raises(stt.SttError) as e:
+        ctx.score_batch([m, pm], stt.Gen(), [10, 10])
+    assert e.value.status == stt.EINVAL
