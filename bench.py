@@ -1,12 +1,14 @@
 #!/usr/bin/env python3
 """Throughput of the template search on one MI355X.
 
-A step is one pass of the whole hot path on the search-scale map: generate 10^7
-random quadratic-Bezier templates (Philox), bin them by time extent, score
-every one on a T=1000 x F=1000 complex64 map (log-uniform sigma, one injected
-track at SNR 8) with the random-phase-factor statistic, write the per-track
-SNRs and reduce to the max/argmax key. The map is resident in HBM before the
-timed region. Prints one JSON line.
+Default workload (the one the headline metric is quoted on): a step is one
+pass of the whole hot path on the search-scale map -- generate 10^7 random
+quadratic-Bezier templates (Philox), bin them by time extent, score every one
+on a T=1000 x F=1000 complex64 map (log-uniform sigma, one injected track at
+SNR 8) with the random-phase-factor statistic, write the per-track SNRs and
+reduce to the max/argmax key. The map is resident in HBM before the timed
+region. Other workloads (--workload) measure the batched, FP16 and small
+configurations; each prints one JSON line of the same form.
 """
 from __future__ import annotations
 
@@ -22,16 +24,27 @@ sys.path.insert(0, ROOT)
 
 METRIC = "Bézier tracks scored/sec per MI355X (track-pixels/s, % gather roofline)"
 HBM_PEAK_GBS = 8000.0
-BYTES_PER_PIXEL = 12  # complex64 Y + float32 sigma: the pixel record one gather reads
+BYTES_F32 = 12  # complex64 Y + float32 sigma: the pixel record one template pixel reads
+BYTES_P16 = 4   # FP16 (re, im) of p = Y/sigma
 
 WORKLOADS = {
     # search-scale plain map: T=1000 x F=1000, 1 s x 1 Hz pixels from 100 Hz, 10^7 tracks, FP32
-    "search_1000x1000_1e7": dict(T=1000, F=1000, n=10_000_000, seed=2, L=10, dtau_s=0.01,
-                                 sigma=("loguniform", 0.5, 2.0), inject=True),
+    "search_1000x1000_1e7": dict(kind="single", T=1000, F=1000, n=10_000_000, seed=2, L=10, dtau_s=0.01,
+                                 sigma=("loguniform", 0.5, 2.0), inject=(200, 799, 250.5, 600.25, 450.75)),
     # the paper's Table III shape (151 Hz x 250 s at 1 s x 1 Hz with 50% overlap -> 500 columns),
     # t_min 35 s of ADI 1 at the 0.5 s column stride -> 70 columns, 2 x 10^7 templates
-    "paper_table3_151x500_2e7": dict(T=500, F=151, n=20_000_000, seed=3, L=70, dtau_s=0.01,
-                                     sigma=("loguniform", 0.5, 2.0), inject=False),
+    "paper_table3_151x500_2e7": dict(kind="single", T=500, F=151, n=20_000_000, seed=3, L=70, dtau_s=0.01,
+                                     sigma=("loguniform", 0.5, 2.0), inject=None),
+    # small plain map: T=100 x F=128, sigma = 1, 10^4 tracks, Philox seed 1 (latency-bound)
+    "plain_100x128_1e4": dict(kind="single", T=100, F=128, n=10_000, seed=1, L=10, dtau_s=0.01, sigma="unit",
+                              inject=None),
+    # batched background: 256 maps, T uniform on [500, 2000], F=1000, 10^6 tracks per map, one graph launch
+    "batch_256maps_1e6": dict(kind="batch", n_maps=256, T_lo=500, T_hi=2000, F=1000, n=1_000_000, seed=3, L=10,
+                              dtau_s=0.01, sigma=("loguniform", 0.5, 2.0)),
+    # precision: T=2000 x F=2000 stored in FP16, 10^8 tracks, top-1024 re-scored in FP64
+    "precision_2000x2000_1e8": dict(kind="precision", T=2000, F=2000, n=100_000_000, seed=4, L=10, dtau_s=0.01,
+                                    sigma=("loguniform", 0.5, 2.0), K=1024,
+                                    inject=(150, 1799, 500.5, 1500.25, 900.75)),
 }
 
 
@@ -39,15 +52,26 @@ def log(*a):
     print(*a, file=sys.stderr, flush=True)
 
 
-def make_map(w):
-    import numpy as np
+def make_map(w, stream=0, T=None):
     import synth
-    Y, s = synth.noise_map(w["T"], w["F"], seed=1000 + w["seed"], sigma=w["sigma"])
-    if w["inject"]:
-        cols, rows = synth.bezier_rows_float(200, 799, 250.5, 600.25, 450.75)
+    T = T or w["T"]
+    Y, s = synth.noise_map(T, w["F"], seed=1000 + w["seed"], sigma=w["sigma"], stream=stream)
+    if w.get("inject"):
+        cols, rows = synth.bezier_rows_float(*w["inject"])
         dt0 = int(round(0.003 / 2.0 ** -28))
         synth.add_pixels(Y, s, cols, rows, 8.0 / math.sqrt(cols.size), -((100.0 + rows) * dt0 * 2.0 ** -28))
     return Y, s, synth.map_sha256(Y, s)
+
+
+def count_px(ctx, g, T, F, n):
+    """Exact track-pixel count of templates 0..n-1 (outside any timed region)."""
+    px, chunk = 0, 1 << 24
+    for a in range(0, n, chunk):
+        b = min(n, a + chunk)
+        tr = ctx.make_tracks(g, T, F, a, b - a)
+        px += int((tr[:, 1] - tr[:, 0] + 1).sum().item())
+        del tr
+    return px
 
 
 def cpu_baseline(w, Y, s, dtau_max, budget_s=12.0):
@@ -66,72 +90,10 @@ def cpu_baseline(w, Y, s, dtau_max, budget_s=12.0):
                 sample=f"first {n} of the {w['n']} tracks of the same map and seed, one thread, {dt:.1f} s")
 
 
-def main():
-    ap = argparse.ArgumentParser()
-    ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=20)
-    ap.add_argument("--warmup", type=int, default=3)
-    ap.add_argument("--workload", default="search_1000x1000_1e7", choices=sorted(WORKLOADS))
-    ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--no-snr", action="store_true", help="reduce to the argmax only (no per-track output)")
-    args = ap.parse_args()
-    if args.gpus != 1:
-        print(f"bench.py runs on one GPU only (asked for {args.gpus}); the search shards by track range "
-              "or by map with no communication but a max, which this build leaves out.", file=sys.stderr)
-        sys.exit(2)
-
-    import numpy as np
-    import torch
-    import paper_1401_8060_amd.stt as stt
-
-    w = WORKLOADS[args.workload]
-    dtau_max = stt.dtau_units(w["dtau_s"])
-    log(f"bench: building map {w['T']}x{w['F']}")
-    Y, s, sha = make_map(w)
-    dev = torch.device("cuda:0")
-    m = stt.Map(torch.from_numpy(Y).to(dev), torch.from_numpy(s).to(dev))
-    ctx = stt.Context(0)
-    g = stt.Gen(seed=w["seed"], stream=0, min_len=w["L"], dtau_max=dtau_max)
-    n = w["n"]
-
-    # exact number of track-pixels of this workload (outside the timed region)
-    px = 0
-    chunk = 1 << 24
-    for a in range(0, n, chunk):
-        b = min(n, a + chunk)
-        tr = ctx.make_tracks(g, w["T"], w["F"], a, b - a)
-        px += int((tr[:, 1] - tr[:, 0] + 1).sum().item())
-        del tr
-    ctx.reserve(n)
-    snr = None if args.no_snr else torch.empty(n, dtype=torch.float32, device=dev)
-    key = torch.zeros(1, dtype=torch.int64, device=dev)
-
-    log(f"bench: {n} tracks, {px} track-pixels; warmup {args.warmup}")
-    for _ in range(args.warmup):
-        key.zero_()
-        ctx.score(m, gen=g, n=n, snr=snr, best_key=key)
-    torch.cuda.synchronize()
-    ctx.set_timing(True)
-    log(f"bench: timing {args.steps} steps")
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    for _ in range(args.steps):
-        key.zero_()
-        ctx.score(m, gen=g, n=n, snr=snr, best_key=key)
-    torch.cuda.synchronize()
-    t1 = time.perf_counter()
-    score_ms, cnt = ctx.kernel_ms_total(stt.STAGE_SCORE)
-    ctx.set_timing(False)
-    ms_step = (t1 - t0) * 1e3 / args.steps
-    score_avg_ms = score_ms / max(cnt, 1)
-    zk, jk = stt.decode_best(key)
-    log(f"bench: {ms_step:.3f} ms/step, scoring kernel {score_avg_ms:.3f} ms avg over {cnt}; best z={zk:.4f} j={jk}")
-
-    tracks_per_s = n / (ms_step * 1e-3)
-    achieved = px * BYTES_PER_PIXEL / (score_avg_ms * 1e-3) / 1e9
-    out = {
+def base_record(args, workload, w, n_tracks, ms_step, px, dtype):
+    return {
         "metric": METRIC,
-        "value": tracks_per_s,
+        "value": n_tracks / (ms_step * 1e-3),
         "unit": "tracks/s",
         "n_gpus": 1,
         "steps": args.steps,
@@ -140,23 +102,197 @@ def main():
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": "f32",
+        "dtype": dtype,
         "data": "synthetic",
-        "config": {"workload": args.workload, "T": w["T"], "F": w["F"], "n_tracks": n, "min_len": w["L"],
-                   "dtau_max_s": w["dtau_s"], "sigma": list(w["sigma"]), "injection": w["inject"],
-                   "per_track_snr": snr is not None, "map_sha256": sha[:16]},
+        "config": {"workload": workload},
         "track_px_per_s": px / (ms_step * 1e-3),
         "track_px": px,
-        "best": {"z": zk, "j": jk},
-        "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": achieved / HBM_PEAK_GBS, "traffic": None,
-                     "kernel": "k_score_slab", "kernel_ms": score_avg_ms,
-                     "bytes_per_track_px": BYTES_PER_PIXEL},
     }
+
+
+def roofline(kernel, kernel_ms, px, bpp):
+    achieved = px * bpp / (kernel_ms * 1e-3) / 1e9
+    return {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+            "frac": achieved / HBM_PEAK_GBS, "traffic": None, "kernel": kernel, "kernel_ms": kernel_ms,
+            "bytes_per_track_px": bpp}
+
+
+def timed(args, fn, torch):
+    for _ in range(args.warmup):
+        fn()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        fn()
+    torch.cuda.synchronize()
+    return (time.perf_counter() - t0) * 1e3 / args.steps
+
+
+def run_single(args, name, w):
+    import torch
+    import paper_1401_8060_amd.stt as stt
+    dtau_max = stt.dtau_units(w["dtau_s"])
+    log(f"bench: building map {w['T']}x{w['F']}")
+    Y, s, sha = make_map(w)
+    dev = torch.device("cuda:0")
+    m = stt.Map(torch.from_numpy(Y).to(dev), torch.from_numpy(s).to(dev))
+    ctx = stt.Context(0)
+    g = stt.Gen(seed=w["seed"], stream=0, min_len=w["L"], dtau_max=dtau_max)
+    n = w["n"]
+    px = count_px(ctx, g, w["T"], w["F"], n)
+    ctx.reserve(n)
+    snr = None if args.no_snr else torch.empty(n, dtype=torch.float32, device=dev)
+    key = torch.zeros(1, dtype=torch.int64, device=dev)
+
+    def step():
+        key.zero_()
+        ctx.score(m, gen=g, n=n, snr=snr, best_key=key)
+
+    log(f"bench: {n} tracks, {px} track-pixels; warmup {args.warmup}, timing {args.steps} steps")
+    for _ in range(args.warmup):
+        step()
+    torch.cuda.synchronize()
+    ctx.set_timing(True)
+    ms_step = timed(argparse.Namespace(warmup=0, steps=args.steps), step, torch)
+    score_ms, cnt = ctx.kernel_ms_total(stt.STAGE_SCORE)
+    ctx.set_timing(False)
+    kern_ms = score_ms / max(cnt, 1)
+    zk, jk = stt.decode_best(key)
+    log(f"bench: {ms_step:.3f} ms/step, scoring kernel {kern_ms:.3f} ms avg over {cnt}; best z={zk:.4f} j={jk}")
+    out = base_record(args, name, w, n, ms_step, px, "f32")
+    out["config"].update({"T": w["T"], "F": w["F"], "n_tracks": n, "min_len": w["L"], "dtau_max_s": w["dtau_s"],
+                          "sigma": list(w["sigma"]) if w["sigma"] != "unit" else "unit",
+                          "injection": w["inject"] is not None, "per_track_snr": snr is not None, "map_sha256": sha[:16]})
+    out["best"] = {"z": zk, "j": jk}
+    out["roofline"] = roofline("k_score_slab" if n >= 4096 else "k_score_direct", kern_ms, px, BYTES_F32)
     if not args.no_cpu_baseline:
         log("bench: timing the CPU oracle on a sample")
         out["cpu_baseline"] = cpu_baseline(w, Y, s, dtau_max)
     ctx.close()
+    return out
+
+
+def run_batch(args, name, w):
+    import numpy as np
+    import torch
+    import synth
+    import paper_1401_8060_amd.stt as stt
+    dtau_max = stt.dtau_units(w["dtau_s"])
+    u = synth.uniform01(w["seed"], 99, w["n_maps"])
+    Ts = (w["T_lo"] + np.floor(u * (w["T_hi"] - w["T_lo"] + 1))).astype(int).tolist()
+    dev = torch.device("cuda:0")
+    ctx = stt.Context(0)
+    log(f"bench: building {w['n_maps']} maps, T in [{min(Ts)}, {max(Ts)}], F={w['F']}")
+    maps = []
+    for k, T in enumerate(Ts):
+        Y, s, _ = make_map(w, stream=k, T=T)
+        maps.append(stt.Map(torch.from_numpy(Y).to(dev), torch.from_numpy(s).to(dev)))
+        del Y, s
+    g = stt.Gen(seed=w["seed"], stream=0, min_len=w["L"], dtau_max=dtau_max)
+    ns = [w["n"]] * len(maps)
+    px = sum(count_px(ctx, stt.Gen(seed=g.seed, stream=k, min_len=g.min_len, dtau_max=g.dtau_max), T, w["F"], w["n"])
+             for k, T in enumerate(Ts))
+    med = maps[int(np.argsort(Ts)[len(Ts) // 2])]
+    choice = ctx.autotune(med, g, w["n"])
+    log(f"bench: autotuned slab shape {choice[0]}x{choice[1]}, LDS {choice[2]} B")
+    fp16 = args.map_dtype == "p16"
+    smaps = [ctx.pack_p16(m) for m in maps] if fp16 else maps
+    keys = torch.zeros(len(maps), dtype=torch.int64, device=dev)
+
+    def step():
+        keys.zero_()
+        ctx.score_batch(smaps, g, ns, best_keys=keys)
+
+    log(f"bench: {len(maps)} maps x {w['n']} tracks, {px} track-pixels")
+    ms_step = timed(args, step, torch)
+    # kernel breakdown from direct (uncaptured) launches of the same batch
+    ctx.set_graph(False)
+    ctx.set_timing(True)
+    for _ in range(3):
+        step()
+    score_ms, cnt = ctx.kernel_ms_total(stt.STAGE_SCORE)
+    ctx.set_timing(False)
+    ctx.set_graph(True)
+    kern_ms = score_ms / max(cnt, 1)
+    log(f"bench: {ms_step:.3f} ms/step (graph replay), batch scoring kernel {kern_ms:.3f} ms")
+    out = base_record(args, name, w, len(maps) * w["n"], ms_step, px, "f16" if fp16 else "f32")
+    out["config"].update({"n_maps": len(maps), "T_range": [w["T_lo"], w["T_hi"]], "F": w["F"],
+                          "tracks_per_map": w["n"], "map_dtype": args.map_dtype, "graph": True,
+                          "slab_shape": list(choice)})
+    out["roofline"] = roofline("k_score_batch", kern_ms, px, BYTES_P16 if fp16 else BYTES_F32)
+    if fp16:
+        # error of FP16 storage against plain FP32 scoring of the same maps, on two maps in full
+        errs = []
+        for k in (0, len(maps) // 2):
+            gk = stt.Gen(seed=g.seed, stream=k, min_len=g.min_len, dtau_max=g.dtau_max)
+            z32 = ctx.score(maps[k], gen=gk, n=w["n"])[0].double()
+            z16 = ctx.score(smaps[k], gen=gk, n=w["n"])[0].double()
+            errs.append((z16 - z32).abs())
+        e = torch.cat(errs)
+        out["fp16_vs_fp32"] = {"max_abs_dz": e.max().item(), "mean_abs_dz": e.mean().item(),
+                               "sample": "all tracks of maps 0 and n_maps/2"}
+    ctx.close()
+    return out
+
+
+def run_precision(args, name, w):
+    import torch
+    import paper_1401_8060_amd.stt as stt
+    dtau_max = stt.dtau_units(w["dtau_s"])
+    log(f"bench: building map {w['T']}x{w['F']}")
+    Y, s, sha = make_map(w)
+    dev = torch.device("cuda:0")
+    m = stt.Map(torch.from_numpy(Y).to(dev), torch.from_numpy(s).to(dev))
+    ctx = stt.Context(0)
+    pm = ctx.pack_p16(m)
+    g = stt.Gen(seed=w["seed"], stream=0, min_len=w["L"], dtau_max=dtau_max)
+    n, K = w["n"], w["K"]
+    px = count_px(ctx, g, w["T"], w["F"], n)
+    ctx.reserve(n)
+    snr = torch.empty(n, dtype=torch.float32, device=dev)
+    res = {}
+
+    def step():
+        ctx.score(pm, gen=g, n=n, snr=snr)
+        idx, val = ctx.topk(snr, K)
+        res["idx"], res["val"] = idx, val
+        res["z64"] = ctx.rescore_f64(m, idx, gen=g)
+
+    ctx.set_timing(True)
+    ms_step = timed(args, step, torch)
+    score_ms, cnt = ctx.kernel_ms_total(stt.STAGE_SCORE)
+    ctx.set_timing(False)
+    kern_ms = score_ms / max(cnt, 1)
+    err = (res["val"].double() - res["z64"]).abs()
+    best = int(torch.argmax(res["z64"]).item())
+    log(f"bench: {ms_step:.3f} ms/step, FP16 scoring kernel {kern_ms:.3f} ms; top-{K} |dz| max {err.max().item():.2e}")
+    out = base_record(args, name, w, n, ms_step, px, "f16")
+    out["config"].update({"T": w["T"], "F": w["F"], "n_tracks": n, "map_dtype": "p16", "scale_exp": pm.scale_exp,
+                          "top_k": K, "rescore": "f64", "map_sha256": sha[:16]})
+    out["roofline"] = roofline("k_score_slab", kern_ms, px, BYTES_P16)
+    out["topk_fp16_vs_fp64"] = {"max_abs_dz": err.max().item(), "mean_abs_dz": err.mean().item()}
+    out["best"] = {"z64": res["z64"][best].item(), "j": int(res["idx"][best].item())}
+    ctx.close()
+    return out
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--workload", default="search_1000x1000_1e7", choices=sorted(WORKLOADS))
+    ap.add_argument("--map-dtype", default="f32", choices=["f32", "p16"], help="batch workload map storage")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-snr", action="store_true", help="reduce to the argmax only (no per-track output)")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py runs on one GPU only (asked for {args.gpus}); the search shards by template range "
+              "or by map with no communication but a max, which this build leaves out.", file=sys.stderr)
+        sys.exit(2)
+    w = WORKLOADS[args.workload]
+    runner = {"single": run_single, "batch": run_batch, "precision": run_precision}[w["kind"]]
+    out = runner(args, args.workload, w)
     print(json.dumps(out), flush=True)
 
 

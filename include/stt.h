@@ -209,6 +209,17 @@ stt_status stt_score_batch(stt_ctx *ctx, const stt_map *maps_host, int32_t n_map
 /* Graph capture of batches on (1, default) or off (0: direct launches). */
 stt_status stt_set_graph(stt_ctx *ctx, int32_t on);
 
+/* Autotuner of the slab scorer: times every compiled workgroup shape with LDS
+ * slab budgets of 160, 112, 80 and 48 KB on `n` templates from `gen` on this
+ * map (one warm-up and three timed calls each, HIP events, kernel time only),
+ * applies the fastest to the context (stt_set_slab_shape, stt_set_path's
+ * lds_bytes) and writes it as choice_out[3] = {wg, tpt, lds_bytes} (host,
+ * may be NULL). With cache_path (a JSON file, may be NULL) the choice is
+ * looked up first under a key of (GPU architecture, F, dtype, power-of-two
+ * buckets of T and n, trig mode) and stored after a search. Synchronises. */
+stt_status stt_autotune(stt_ctx *ctx, const stt_map *map, const stt_gen *gen, int64_t n, const char *cache_path,
+                        int32_t *choice_out);
+
 /* Host helpers for the key format (no device work). */
 uint64_t stt_key_encode(float z, uint32_t j);
 void stt_key_decode(uint64_t key, float *z, uint32_t *j);

@@ -15,6 +15,11 @@
 
 using namespace stt;
 
+struct Rec {
+    size_t base;  // first of the call's six events in the pool
+    bool used[3];
+};
+
 struct stt_ctx {
     int device = 0;
     hipStream_t stream = nullptr;
@@ -35,7 +40,6 @@ struct stt_ctx {
     size_t next = 0;         // first free event of the pool
     size_t last = 0;         // first event of the last call
     bool used[3] = {false, false, false};
-    struct Rec { size_t base; bool used[3]; };
     std::vector<Rec> recs;   // calls since the last total query
     // Batches: descriptor tables on the device, and the captured graph of the
     // last batch (replayed while the arguments stay the same).
@@ -193,7 +197,7 @@ void ev_record(stt_ctx *c, int i)
 void ev_end(stt_ctx *c)
 {
     if (!c->timing) return;
-    stt_ctx::Rec r;
+    Rec r;
     r.base = c->last;
     for (int i = 0; i < 3; ++i) r.used[i] = c->used[i];
     c->recs.push_back(r);
@@ -774,6 +778,8 @@ stt_status stt_score_batch(stt_ctx *c, const stt_map *maps_host, int32_t n_maps,
         c->bkey.clear();
 
         auto enqueue = [&](hipStream_t st) -> stt_status {
+            const bool timed = st == c->stream;  // events only outside graph capture
+            if (timed) ev_record(c, 2);
             hipLaunchKernelGGL(k_fill_u32, dim3((unsigned)((nb_all + 64 + 255) / 256)), dim3(256), 0, st, totals,
                                (int64_t)(nb_all), 0u);
             hipLaunchKernelGGL(k_fill_u32, dim3(1), dim3(256), 0, st, queue, (int64_t)1, 0u);
@@ -786,25 +792,32 @@ stt_status stt_score_batch(stt_ctx *c, const stt_map *maps_host, int32_t n_maps,
                                    (const BatchMap *)dmaps, n_maps, (const uint32_t *)dchunk, cursor, order);
             }
             STT_HIP(c, hipGetLastError());
+            if (timed) {
+                ev_record(c, 3);
+                ev_record(c, 0);
+                c->used[0] = c->used[1] = true;
+            }
+            stt_status r;
             if (dtype == STT_P16)
-                return c->hw_trig ? launch_batch_h<true, kMapP16>(c, st, dmaps, n_maps, ditem, (uint32_t)nitems, queue,
+                r = c->hw_trig ? launch_batch_h<true, kMapP16>(c, st, dmaps, n_maps, ditem, (uint32_t)nitems, queue,
                                                                   order, norm, best_key_per_map_dev, shm)
                                   : launch_batch_h<false, kMapP16>(c, st, dmaps, n_maps, ditem, (uint32_t)nitems,
                                                                    queue, order, norm, best_key_per_map_dev, shm);
-            return c->hw_trig ? launch_batch_h<true, kMapF32>(c, st, dmaps, n_maps, ditem, (uint32_t)nitems, queue,
-                                                              order, norm, best_key_per_map_dev, shm)
-                              : launch_batch_h<false, kMapF32>(c, st, dmaps, n_maps, ditem, (uint32_t)nitems, queue,
-                                                               order, norm, best_key_per_map_dev, shm);
+            else
+                r = c->hw_trig ? launch_batch_h<true, kMapF32>(c, st, dmaps, n_maps, ditem, (uint32_t)nitems, queue,
+                                                               order, norm, best_key_per_map_dev, shm)
+                               : launch_batch_h<false, kMapF32>(c, st, dmaps, n_maps, ditem, (uint32_t)nitems, queue,
+                                                                order, norm, best_key_per_map_dev, shm);
+            if (timed) ev_record(c, 1);
+            return r;
         };
 
         if (!c->use_graph) {
             if ((s = ev_begin(c)) != STT_OK) return s;
             ev_record(c, 4);
-            ev_record(c, 0);
             s = enqueue(c->stream);
-            ev_record(c, 1);
             ev_record(c, 5);
-            c->used[0] = c->used[2] = true;
+            c->used[2] = true;
             ev_end(c);
             return s;
         }
@@ -824,12 +837,156 @@ stt_status stt_score_batch(stt_ctx *c, const stt_map *maps_host, int32_t n_maps,
     }
     if ((s = ev_begin(c)) != STT_OK) return s;
     ev_record(c, 4);
-    ev_record(c, 0);
     STT_HIP(c, hipGraphLaunch(c->gexec, c->stream));
-    ev_record(c, 1);
     ev_record(c, 5);
-    c->used[0] = c->used[2] = true;
+    c->used[2] = true;  // a replayed graph is timed as a whole
     ev_end(c);
+    return STT_OK;
+}
+
+// ----------------------------------------------------------------------------- autotuning
+
+namespace {
+
+struct TuneChoice {
+    int wg, tpt, lds;
+    double ms;
+};
+
+std::string tune_key(const stt_ctx *c, const stt_map *m, int64_t n)
+{
+    hipDeviceProp_t prop;
+    std::string arch = "gpu";
+    if (hipGetDeviceProperties(&prop, c->device) == hipSuccess) arch = prop.gcnArchName;
+    const std::string a = arch.substr(0, arch.find(':'));
+    // maps of similar duration (power-of-two bucket) and call size share a choice
+    int tb = 0;
+    while ((1 << (tb + 1)) <= m->T) ++tb;
+    int nb = 0;
+    while (((int64_t)1 << (nb + 1)) <= n) ++nb;
+    char buf[160];
+    snprintf(buf, sizeof buf, "%s/F=%d/dtype=%d/T=2^%d/n=2^%d/trig=%d", a.c_str(), m->F, m->dtype, tb, nb,
+             c->hw_trig ? 1 : 0);
+    return buf;
+}
+
+// The cache file holds one line per key:  "<key>": {"wg": W, "tpt": P, "lds": B, "ms": T}
+bool cache_lookup(const char *path, const std::string &key, TuneChoice &out)
+{
+    if (!path) return false;
+    FILE *f = fopen(path, "r");
+    if (!f) return false;
+    char line[512];
+    bool found = false;
+    const std::string pat = "\"" + key + "\":";
+    while (fgets(line, sizeof line, f)) {
+        const char *p = strstr(line, pat.c_str());
+        if (!p) continue;
+        TuneChoice t;
+        if (sscanf(p + pat.size(), " {\"wg\": %d, \"tpt\": %d, \"lds\": %d, \"ms\": %lf}", &t.wg, &t.tpt, &t.lds,
+                   &t.ms) == 4) {
+            out = t;
+            found = true;
+        }
+    }
+    fclose(f);
+    return found;
+}
+
+void cache_store(const char *path, const std::string &key, const TuneChoice &t)
+{
+    if (!path) return;
+    std::vector<std::string> lines;
+    if (FILE *f = fopen(path, "r")) {
+        char line[512];
+        const std::string pat = "\"" + key + "\":";
+        while (fgets(line, sizeof line, f)) {
+            std::string l(line);
+            while (!l.empty() && (l.back() == '\n' || l.back() == ',')) l.pop_back();
+            if (l.empty() || l == "{" || l == "}" || l.find(pat) != std::string::npos) continue;
+            lines.push_back(l);
+        }
+        fclose(f);
+    }
+    char buf[512];
+    snprintf(buf, sizeof buf, "  \"%s\": {\"wg\": %d, \"tpt\": %d, \"lds\": %d, \"ms\": %.6f}", key.c_str(), t.wg,
+             t.tpt, t.lds, t.ms);
+    lines.push_back(buf);
+    const std::string tmp = std::string(path) + ".tmp";
+    if (FILE *f = fopen(tmp.c_str(), "w")) {
+        fprintf(f, "{\n");
+        for (size_t i = 0; i < lines.size(); ++i) fprintf(f, "%s%s\n", lines[i].c_str(), i + 1 < lines.size() ? "," : "");
+        fprintf(f, "}\n");
+        fclose(f);
+        rename(tmp.c_str(), path);
+    }
+}
+
+}  // namespace
+
+stt_status stt_autotune(stt_ctx *c, const stt_map *map, const stt_gen *gen, int64_t n, const char *cache_path,
+                        int32_t *choice_out)
+{
+    if (!c) return STT_EINVAL;
+    stt_status s = check_map(c, map);
+    if (s != STT_OK) return s;
+    if (n < 1 || n > ((int64_t)1 << 32)) return fail(c, STT_ERANGE, "n=%lld", (long long)n);
+    GenP gp;
+    if ((s = make_genp(c, gen, map->T, map->F, gp)) != STT_OK) return s;
+    const std::string key = tune_key(c, map, n);
+    TuneChoice best{0, 0, 0, 1e30};
+    if (!cache_lookup(cache_path, key, best)) {
+        const int old_path = c->path, old_wg = c->slab_wg, old_tpt = c->slab_tpt, old_lds = c->lds_bytes;
+        const bool old_timing = c->timing;
+        std::vector<Rec> saved;
+        saved.swap(c->recs);
+        const size_t saved_next = c->next;
+        c->timing = true;
+        c->recs.clear();
+        c->next = saved_next;  // tuning events come after any the caller has not read yet
+        static const int ldss[] = {160 * 1024, 112 * 1024, 80 * 1024, 48 * 1024};
+        for (const auto &sh : kShapes)
+            for (int lds : ldss) {
+                if ((lds - 256) / (8 * map->F) < 1) continue;
+                c->path = 2;
+                c->slab_wg = sh[0];
+                c->slab_tpt = sh[1];
+                c->lds_bytes = lds;
+                double tot = 0;
+                int cnt = 0;
+                for (int rep = 0; rep < 4 && s == STT_OK; ++rep) {
+                    s = stt_score(c, map, gen, nullptr, 0, n, STT_NORM_SQRT_N, nullptr, nullptr);
+                    if (s != STT_OK) break;
+                    float ms = 0;
+                    if ((s = stt_kernel_ms(c, 0, &ms)) != STT_OK) break;
+                    if (rep > 0) { tot += ms; ++cnt; }  // the first run warms up
+                }
+                c->recs.clear();
+                c->next = saved_next;
+                if (s != STT_OK) break;
+                if (cnt && tot / cnt < best.ms) best = TuneChoice{sh[0], sh[1], lds, tot / cnt};
+            }
+        c->path = old_path;
+        c->slab_wg = old_wg;
+        c->slab_tpt = old_tpt;
+        c->lds_bytes = old_lds;
+        c->timing = old_timing;
+        c->recs.swap(saved);
+        c->next = saved_next;
+        if (s != STT_OK) return s;
+        if (best.wg == 0) return fail(c, STT_EUNSUPPORTED, "no slab configuration fits F=%d", map->F);
+        cache_store(cache_path, key, best);
+    }
+    if (!slab_shape_ok(best.wg, best.tpt) || best.lds < 1024 || best.lds > 160 * 1024)
+        return fail(c, STT_EINVAL, "cache entry for %s is not a valid configuration", key.c_str());
+    c->slab_wg = best.wg;
+    c->slab_tpt = best.tpt;
+    c->lds_bytes = best.lds;
+    if (choice_out) {
+        choice_out[0] = best.wg;
+        choice_out[1] = best.tpt;
+        choice_out[2] = best.lds;
+    }
     return STT_OK;
 }
 

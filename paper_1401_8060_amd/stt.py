@@ -322,6 +322,15 @@ class Context:
                                           C.c_void_p(idx.data_ptr()), idx.numel(), norm, C.c_void_p(out.data_ptr())))
         return out
 
+    def autotune(self, m, gen: Gen, n: int, cache_path: str | None = None) -> tuple[int, int, int]:
+        """Pick (and apply) the fastest slab shape and LDS budget for this map and call size."""
+        out = (C.c_int32 * 3)()
+        mc = m.c()
+        g = gen.c()
+        self._chk(self._L.stt_autotune(self.h, C.byref(mc), C.byref(g), n,
+                                       cache_path.encode() if cache_path else None, out))
+        return out[0], out[1], out[2]
+
     def set_graph(self, on: bool):
         self._chk(self._L.stt_set_graph(self.h, 1 if on else 0))
 

@@ -12,6 +12,7 @@ def bind(L) -> None:
         "stt_rescore_f64": ([vp, vp, vp, vp, i64, i64, vp, i32, i32, vp], i32),
         "stt_score_batch": ([vp, vp, i32, vp, vp, i32, vp, vp], i32),
         "stt_set_graph": ([vp, i32], i32),
+        "stt_autotune": ([vp, vp, vp, i64, C.c_char_p, vp], i32),
     }
     for name, (args, res) in sigs.items():
         fn = getattr(L, name)
@@ -19,4 +20,4 @@ def bind(L) -> None:
         fn.restype = res
 
 
-EXPORTED = ["stt_map_pack_p16", "stt_topk", "stt_rescore_f64", "stt_score_batch", "stt_set_graph"]
+EXPORTED = ["stt_map_pack_p16", "stt_topk", "stt_rescore_f64", "stt_score_batch", "stt_set_graph", "stt_autotune"]

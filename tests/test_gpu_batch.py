@@ -141,3 +141,24 @@ def test_batch_argument_errors(stt, ctx):
     with pytest.raises(stt.SttError) as e:
         ctx.score_batch([m, pm], stt.Gen(), [10, 10])
     assert e.value.status == stt.EINVAL
+
+
+def test_autotune_applies_and_caches(stt, ctx, tmp_path):
+    _say("autotune")
+    Y, s = synth.noise_map(400, 250, seed=35, sigma=("loguniform", 0.5, 2.0))
+    m = stt.Map(*to_dev(Y, s))
+    g = stt.Gen(seed=1, min_len=10, dtau_max=D10MS)
+    cache = str(tmp_path / "tune.json")
+    choice = ctx.autotune(m, g, 200_000, cache)
+    assert choice[0] in (256, 512, 1024) and choice[1] in (2, 4) and 1024 <= choice[2] <= 160 * 1024
+    text = open(cache).read()
+    assert f'"wg": {choice[0]}' in text and "F=250" in text
+    # a second call finds the entry (same choice), and results stay those of the oracle-checked scorer
+    assert ctx.autotune(m, g, 200_000, cache) == choice
+    z_tuned, k_tuned = ctx.score(m, gen=g, n=50_000)
+    ctx.set_slab_shape(1024, 4)
+    ctx.set_path(0, 160 * 1024)
+    z_def, k_def = ctx.score(m, gen=g, n=50_000)
+    assert key_to_host(k_tuned) == key_to_host(k_def)
+    import torch
+    assert torch.equal(z_tuned, z_def)
