@@ -220,6 +220,48 @@ stt_status stt_set_graph(stt_ctx *ctx, int32_t on);
 stt_status stt_autotune(stt_ctx *ctx, const stt_map *map, const stt_gen *gen, int64_t n, const char *cache_path,
                         int32_t *choice_out);
 
+/* ---- differentiation (an addition; the paper scores only pixel sets) ----
+ * theta_dev: [n][6] float32 per template, (tau0, tau2, phi0, phi1, phi2,
+ * dtau_ms): start and end time in columns, control frequencies in rows
+ * (continuous), delay in milliseconds. K_dev: [n] int32 sample counts (K = the
+ * seed template's N). The smooth statistic z~ interpolates
+ * G(t, r) = Re[exp(2 pi i f(r) dtau) p(t, r)] (the Eq. 8 term) bilinearly at
+ * K points along the Eq. 6 curve, u = clamp(t, 0, T-1), v = clamp(f - 1/2,
+ * 0, F-1), and divides the sum by sqrt(K); a clamped coordinate has zero
+ * derivative. Requires F >= 2. */
+
+/* Templates j = idx_dev[i] (device int64) drawn as by stt_make_tracks. */
+stt_status stt_tracks_at(stt_ctx *ctx, const stt_gen *gen, int32_t T, int32_t F, const int64_t *idx_dev, int64_t n,
+                         stt_track *out_dev);
+
+/* theta and K of plain templates: (t0, t2, f0/256, f1/256, f2/256, dtau 2^-28 s in ms), K = N. */
+stt_status stt_tracks_to_theta(stt_ctx *ctx, const stt_track *tracks_dev, int64_t n, float *theta_dev,
+                               int32_t *K_dev);
+
+/* Forward: z_dev[i] = z~(theta_i). */
+stt_status stt_smooth(stt_ctx *ctx, const stt_map *map, const float *theta_dev, const int32_t *K_dev, int32_t n,
+                      float *z_dev);
+
+/* Forward and hand-written backward: z_dev[i] = z~(theta_i) and grad_dev[i][q] = dz~/dtheta_q. */
+stt_status stt_grad(stt_ctx *ctx, const stt_map *map, const float *theta_dev, const int32_t *K_dev, int32_t n,
+                    float *z_dev, float *grad_dev);
+
+/* Projected gradient ascent of z~ for every template (Sec. V's deeper
+ * follow-up of the loudest candidates, here as a local refinement): `steps`
+ * iterations; the five positions move by eta_px along g/|g|, the delay by
+ * eta_ms along sign(g), eta falling linearly over the steps from sched_host =
+ * {px0, px1, ms0, ms1} (host; NULL = {1, 0.02, 0.5, 0.01}); after each step
+ * theta is projected onto 0 <= tau <= T-1, tau2 - tau0 >= min_len - 1,
+ * 0 <= phi < F, |dtau| <= dtau_max (2^-28 s units). On return theta_dev holds
+ * each template's best iterate (the projected start included) and
+ * z_smooth_dev its z~. If plain_dev is given the best iterates are rounded to
+ * plain templates (times half up and widened to min_len, frequencies
+ * floor(256 phi) inside the band, delay to the nearest unit); if also
+ * z_plain_dev, those are scored with the plain statistic (norm). */
+stt_status stt_refine(stt_ctx *ctx, const stt_map *map, int32_t min_len, int32_t dtau_max, float *theta_dev,
+                      const int32_t *K_dev, int32_t n, int32_t steps, const float *sched_host, float *z_smooth_dev,
+                      stt_track *plain_dev, float *z_plain_dev, int32_t norm);
+
 /* Host helpers for the key format (no device work). */
 uint64_t stt_key_encode(float z, uint32_t j);
 void stt_key_decode(uint64_t key, float *z, uint32_t *j);

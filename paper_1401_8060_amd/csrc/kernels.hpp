@@ -745,4 +745,210 @@ __global__ __launch_bounds__(256) void k_rescore_f64(MapP m, GenP g, const Trk *
     if (lane == 0) out[w] = ok ? (norm == 1 ? s / N : s / sqrt((double)N)) : __builtin_nan("");
 }
 
+// ---------------------------------------------------------------- smooth SNR and its gradient
+// theta = (tau0, tau2, phi0, phi1, phi2, dtau_ms) per template, K samples
+// xi_k = k/(K-1); sample (u, v) = (clamp(t_k, 0, T-1), clamp(f_k - 1/2, 0, F-1)),
+// bilinear interpolation of G(t, r) = Re[exp(2 pi i f(r) dtau) p(t, r)] and
+// of its dtau-derivative; z~ = K^-1/2 sum. One wave per template, lanes over
+// samples; sums in FP64, reduced in a fixed order (deterministic).
+
+template <int MAPT>
+__device__ __forceinline__ void smooth_node(const MapP &m, int64_t t, int64_t r, double dtau_s, float &g, float &gd)
+{
+    const float2 p = load_p<MAPT>(m, t * m.ld + r);
+    const double f_hz = (double)(m.fq4_lo + r * m.dfq4) * 0.0625;
+    double turns = f_hz * dtau_s;
+    turns -= floor(turns);
+    const float x = (float)turns;
+    const float c = __builtin_amdgcn_cosf(x), s = __builtin_amdgcn_sinf(x);
+    g = c * p.x - s * p.y;
+    gd = -6.283185307179586f * (float)f_hz * (s * p.x + c * p.y);
+}
+
+template <int MAPT>
+__global__ __launch_bounds__(256) void k_smooth_grad(MapP m, const float *theta, const int32_t *Ks, int32_t n,
+                                                     float *z_out, float *grad_out)
+{
+    const int w = (int)(((int64_t)blockIdx.x * 256 + threadIdx.x) >> 6);
+    const int lane = threadIdx.x & 63;
+    if (w >= n) return;
+    const float *th = theta + (int64_t)w * 6;
+    const double tau0 = th[0], tau2 = th[1], ph0 = th[2], ph1 = th[3], ph2 = th[4];
+    const double dtau_s = (double)th[5] * 1e-3;
+    const int K = Ks[w];
+    double z = 0, g0 = 0, g1 = 0, g2 = 0, g3 = 0, g4 = 0, g5 = 0;
+    for (int k = lane; k < K; k += 64) {
+        const double xi = K > 1 ? (double)k / (double)(K - 1) : 0.0;
+        const double b0 = (1 - xi) * (1 - xi), b1 = 2 * xi * (1 - xi), b2 = xi * xi;
+        const double u0 = tau0 + xi * (tau2 - tau0), v0 = b0 * ph0 + b1 * ph1 + b2 * ph2 - 0.5;
+        // clamp into the map (fmax/fmin also send a NaN coordinate to the lower edge)
+        const double u = fmin(fmax(u0, 0.0), (double)(m.T - 1)), v = fmin(fmax(v0, 0.0), (double)(m.F - 1));
+        const bool ut = u0 >= 0.0 && u0 <= (double)(m.T - 1), vt = v0 >= 0.0 && v0 <= (double)(m.F - 1);
+        int64_t i = (int64_t)floor(u), r = (int64_t)floor(v);
+        if (i > m.T - 2) i = m.T - 2;
+        if (r > m.F - 2) r = m.F - 2;
+        const double a = u - (double)i, b = v - (double)r;
+        float G00, G10, G01, G11, D00, D10, D01, D11;
+        smooth_node<MAPT>(m, i, r, dtau_s, G00, D00);
+        smooth_node<MAPT>(m, i + 1, r, dtau_s, G10, D10);
+        smooth_node<MAPT>(m, i, r + 1, dtau_s, G01, D01);
+        smooth_node<MAPT>(m, i + 1, r + 1, dtau_s, G11, D11);
+        z += (1 - a) * (1 - b) * G00 + a * (1 - b) * G10 + (1 - a) * b * G01 + a * b * G11;
+        const double du = ut ? (1 - b) * (G10 - G00) + b * (G11 - G01) : 0.0;
+        const double dv = vt ? (1 - a) * (G01 - G00) + a * (G11 - G10) : 0.0;
+        g0 += (1 - xi) * du;
+        g1 += xi * du;
+        g2 += b0 * dv;
+        g3 += b1 * dv;
+        g4 += b2 * dv;
+        g5 += ((1 - a) * (1 - b) * D00 + a * (1 - b) * D10 + (1 - a) * b * D01 + a * b * D11) * 1e-3;
+    }
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) {
+        z += __shfl_xor(z, off);
+        g0 += __shfl_xor(g0, off);
+        g1 += __shfl_xor(g1, off);
+        g2 += __shfl_xor(g2, off);
+        g3 += __shfl_xor(g3, off);
+        g4 += __shfl_xor(g4, off);
+        g5 += __shfl_xor(g5, off);
+    }
+    if (lane == 0) {
+        const double sc = K > 0 ? 1.0 / sqrt((double)K) : 0.0;
+        z_out[w] = (float)(z * sc);
+        if (grad_out) {
+            float *go = grad_out + (int64_t)w * 6;
+            go[0] = (float)(g0 * sc);
+            go[1] = (float)(g1 * sc);
+            go[2] = (float)(g2 * sc);
+            go[3] = (float)(g3 * sc);
+            go[4] = (float)(g4 * sc);
+            go[5] = (float)(g5 * sc);
+        }
+    }
+}
+
+// ---------------------------------------------------------------- refinement helpers
+
+__global__ __launch_bounds__(256) void k_tracks_at(GenP g, const int64_t *idx, int64_t n, Trk *out)
+{
+    const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    if (i < n) out[i] = draw_track(g, (uint64_t)idx[i]);
+}
+
+// A plain template's parameters as a smooth-SNR point: times as columns,
+// control frequencies in rows, delay in ms; K = its pixel count.
+__global__ __launch_bounds__(256) void k_track_to_theta(const Trk *tr, int64_t n, float *theta, int32_t *Ks)
+{
+    const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    if (i >= n) return;
+    const Trk t = tr[i];
+    float *th = theta + i * 6;
+    th[0] = (float)t.t0;
+    th[1] = (float)t.t2;
+    th[2] = (float)t.f0 * (1.0f / 256.0f);
+    th[3] = (float)t.f1 * (1.0f / 256.0f);
+    th[4] = (float)t.f2 * (1.0f / 256.0f);
+    th[5] = (float)((double)t.dtau * (1e3 / 268435456.0));
+    Ks[i] = t.t2 - t.t0 + 1;
+}
+
+struct RefineP {
+    int32_t T, F, L;
+    double dmax_ms;
+    double px0, px1, ms0, ms1;
+    int32_t steps;
+};
+
+__device__ __forceinline__ void project_theta(double *th, const RefineP &p)
+{
+    double a = th[0], b = th[1];
+    if (b - a < p.L - 1) {
+        const double mid = 0.5 * (a + b);
+        a = mid - 0.5 * (p.L - 1);
+        b = mid + 0.5 * (p.L - 1);
+    }
+    if (a < 0) { b -= a; a = 0; }
+    if (b > p.T - 1) { a -= b - (p.T - 1); b = p.T - 1; }
+    if (a < 0) a = 0;
+    th[0] = a;
+    th[1] = b;
+    const double fhi = (double)p.F - 1.0 / 512.0;
+    for (int q = 2; q < 5; ++q) th[q] = fmin(fhi, fmax(0.0, th[q]));
+    th[5] = fmin(p.dmax_ms, fmax(-p.dmax_ms, th[5]));
+}
+
+__global__ __launch_bounds__(256) void k_refine_project(float *theta, int32_t n, RefineP p)
+{
+    const int i = blockIdx.x * 256 + threadIdx.x;
+    if (i >= n) return;
+    double th[6];
+    for (int q = 0; q < 6; ++q) th[q] = theta[(int64_t)i * 6 + q];
+    project_theta(th, p);
+    for (int q = 0; q < 6; ++q) theta[(int64_t)i * 6 + q] = (float)th[q];
+}
+
+// Keep the iterate if it beats the best so far (s < 0: initialise the best), then
+// take step s (unless s == steps): normalised ascent and projection.
+__global__ __launch_bounds__(256) void k_refine_step(float *theta, const float *z, const float *grad, float *best_theta,
+                                                     float *best_z, int32_t n, int32_t s, RefineP p)
+{
+    const int i = blockIdx.x * 256 + threadIdx.x;
+    if (i >= n) return;
+    float *th = theta + (int64_t)i * 6;
+    if (s < 0 || z[i] > best_z[i]) {
+        best_z[i] = z[i];
+        for (int q = 0; q < 6; ++q) best_theta[(int64_t)i * 6 + q] = th[q];
+    }
+    if (s < 0 || s >= p.steps) return;
+    const double w = p.steps > 1 ? (double)s / (double)(p.steps - 1) : 0.0;
+    const double epx = p.px0 + w * (p.px1 - p.px0), ems = p.ms0 + w * (p.ms1 - p.ms0);
+    const float *g = grad + (int64_t)i * 6;
+    double t[6];
+    for (int q = 0; q < 6; ++q) t[q] = th[q];
+    double n2 = 0;
+    for (int q = 0; q < 5; ++q) n2 += (double)g[q] * g[q];
+    if (n2 > 0) {
+        const double inv = 1.0 / sqrt(n2);
+        for (int q = 0; q < 5; ++q) t[q] += epx * g[q] * inv;
+    }
+    if (g[5] > 0) t[5] += ems;
+    else if (g[5] < 0) t[5] -= ems;
+    project_theta(t, p);
+    for (int q = 0; q < 6; ++q) th[q] = (float)t[q];
+}
+
+// Back to a plain template (times half up, widened to L pixels; frequencies
+// floor(256 phi) inside the band; delay to the nearest 2^-28 s, clipped).
+__global__ __launch_bounds__(256) void k_theta_to_track(const float *theta, int64_t n, int32_t T, int32_t F, int32_t L,
+                                                        int32_t dtau_max, Trk *out)
+{
+    const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    if (i >= n) return;
+    const float *th = theta + i * 6;
+    // rounded and clamped in FP64 before converting, so any input stays inside the map
+    int32_t t0 = (int32_t)fmin(fmax(floor((double)th[0] + 0.5), 0.0), (double)(T - 1));
+    int32_t t2 = (int32_t)fmin(fmax(floor((double)th[1] + 0.5), 0.0), (double)(T - 1));
+    if (t2 - t0 < L - 1) {
+        t2 = t0 + L - 1;
+        if (t2 > T - 1) { t0 -= t2 - (T - 1); t2 = T - 1; }
+    }
+    Trk t;
+    t.t0 = t0;
+    t.t2 = t2;
+    uint32_t f[3];
+    for (int q = 0; q < 3; ++q) {
+        double v = floor((double)th[2 + q] * 256.0);
+        v = fmin(fmax(v, 0.0), (double)F * 256 - 1);
+        f[q] = (uint32_t)v;
+    }
+    t.f0 = f[0];
+    t.f1 = f[1];
+    t.f2 = f[2];
+    double d = floor((double)th[5] * 1e-3 * 268435456.0 + 0.5);
+    d = fmin(fmax(d, -(double)dtau_max), (double)dtau_max);
+    t.dtau = (int32_t)d;
+    out[i] = t;
+}
+
 }  // namespace stt

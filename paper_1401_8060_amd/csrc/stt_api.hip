@@ -28,6 +28,8 @@ struct stt_ctx {
     size_t scratch_bytes = 0;
     void *aux = nullptr;  // top-K state and candidates
     size_t aux_bytes = 0;
+    void *rbuf = nullptr;  // refinement state
+    size_t rbuf_bytes = 0;
     int path = 0;  // 0 auto, 1 direct, 2 slab
     int lds_bytes = 160 * 1024;  // slab budget per workgroup
     int slab_wg = 1024;          // slab scorer shape: lanes per workgroup
@@ -373,6 +375,7 @@ stt_status stt_destroy(stt_ctx *c)
     (void)hipStreamSynchronize(c->stream);
     if (c->scratch) (void)hipFree(c->scratch);
     if (c->aux) (void)hipFree(c->aux);
+    if (c->rbuf) (void)hipFree(c->rbuf);
     if (c->bdev) (void)hipFree(c->bdev);
     if (c->gexec) (void)hipGraphExecDestroy(c->gexec);
     if (c->graph) (void)hipGraphDestroy(c->graph);
@@ -844,7 +847,160 @@ stt_status stt_score_batch(stt_ctx *c, const stt_map *maps_host, int32_t n_maps,
     return STT_OK;
 }
 
+// ----------------------------------------------------------------------------- differentiation
+
+stt_status stt_tracks_at(stt_ctx *c, const stt_gen *gen, int32_t T, int32_t F, const int64_t *idx_dev, int64_t n,
+                         stt_track *out_dev)
+{
+    if (!c) return STT_EINVAL;
+    GenP g;
+    stt_status s = make_genp(c, gen, T, F, g);
+    if (s != STT_OK) return s;
+    if (n < 0) return fail(c, STT_EINVAL, "n=%lld", (long long)n);
+    if (n == 0) return STT_OK;
+    if (!idx_dev || !out_dev) return fail(c, STT_EINVAL, "idx_dev and out_dev must be non-NULL");
+    STT_HIP(c, hipSetDevice(c->device));
+    hipLaunchKernelGGL(k_tracks_at, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, c->stream, g, idx_dev, n,
+                       (Trk *)out_dev);
+    STT_HIP(c, hipGetLastError());
+    return STT_OK;
+}
+
+stt_status stt_tracks_to_theta(stt_ctx *c, const stt_track *tracks_dev, int64_t n, float *theta_dev, int32_t *K_dev)
+{
+    if (!c) return STT_EINVAL;
+    if (n < 0) return fail(c, STT_EINVAL, "n=%lld", (long long)n);
+    if (n == 0) return STT_OK;
+    if (!tracks_dev || !theta_dev || !K_dev) return fail(c, STT_EINVAL, "NULL buffer");
+    STT_HIP(c, hipSetDevice(c->device));
+    hipLaunchKernelGGL(k_track_to_theta, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, c->stream,
+                       (const Trk *)tracks_dev, n, theta_dev, K_dev);
+    STT_HIP(c, hipGetLastError());
+    return STT_OK;
+}
+
+}  // extern "C"
+
+namespace {
+
+stt_status smooth_launch(stt_ctx *c, const stt_map *map, const float *theta, const int32_t *K, int32_t n, float *z,
+                         float *grad, hipStream_t st)
+{
+    const MapP m = to_mapp(map);
+    const unsigned grid = (unsigned)(((int64_t)n * 64 + 255) / 256);
+    if (map->dtype == STT_P16)
+        hipLaunchKernelGGL(k_smooth_grad<kMapP16>, dim3(grid), dim3(256), 0, st, m, theta, K, n, z, grad);
+    else
+        hipLaunchKernelGGL(k_smooth_grad<kMapF32>, dim3(grid), dim3(256), 0, st, m, theta, K, n, z, grad);
+    STT_HIP(c, hipGetLastError());
+    return STT_OK;
+}
+
+stt_status check_smooth(stt_ctx *c, const stt_map *map, const float *theta, const int32_t *K, int32_t n, float *z)
+{
+    stt_status s = check_map(c, map);
+    if (s != STT_OK) return s;
+    if (map->F < 2) return fail(c, STT_ERANGE, "the smooth statistic needs F >= 2");
+    if (n < 0) return fail(c, STT_EINVAL, "n=%d", n);
+    if (n > 0 && (!theta || !K || !z)) return fail(c, STT_EINVAL, "NULL buffer");
+    return STT_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+stt_status stt_smooth(stt_ctx *c, const stt_map *map, const float *theta_dev, const int32_t *K_dev, int32_t n,
+                      float *z_dev)
+{
+    if (!c) return STT_EINVAL;
+    stt_status s = check_smooth(c, map, theta_dev, K_dev, n, z_dev);
+    if (s != STT_OK || n == 0) return s;
+    STT_HIP(c, hipSetDevice(c->device));
+    return smooth_launch(c, map, theta_dev, K_dev, n, z_dev, nullptr, c->stream);
+}
+
+stt_status stt_grad(stt_ctx *c, const stt_map *map, const float *theta_dev, const int32_t *K_dev, int32_t n,
+                    float *z_dev, float *grad_dev)
+{
+    if (!c) return STT_EINVAL;
+    stt_status s = check_smooth(c, map, theta_dev, K_dev, n, z_dev);
+    if (s != STT_OK || n == 0) return s;
+    if (!grad_dev) return fail(c, STT_EINVAL, "grad_dev is NULL");
+    STT_HIP(c, hipSetDevice(c->device));
+    return smooth_launch(c, map, theta_dev, K_dev, n, z_dev, grad_dev, c->stream);
+}
+
+stt_status stt_refine(stt_ctx *c, const stt_map *map, int32_t min_len, int32_t dtau_max, float *theta_dev,
+                      const int32_t *K_dev, int32_t n, int32_t steps, const float *sched_host, float *z_smooth_dev,
+                      stt_track *plain_dev, float *z_plain_dev, int32_t norm)
+{
+    if (!c) return STT_EINVAL;
+    stt_status s = check_smooth(c, map, theta_dev, K_dev, n, z_smooth_dev);
+    if (s != STT_OK) return s;
+    if (steps < 0 || steps > 100000) return fail(c, STT_ERANGE, "steps=%d", steps);
+    if (min_len < 2 || min_len > map->T) return fail(c, STT_ERANGE, "min_len=%d outside [2, T]", min_len);
+    if (dtau_max < 0 || dtau_max >= (1 << 30)) return fail(c, STT_ERANGE, "dtau_max=%d", dtau_max);
+    if (norm != STT_NORM_SQRT_N && norm != STT_NORM_N) return fail(c, STT_EINVAL, "norm=%d", norm);
+    if (z_plain_dev && !plain_dev) return fail(c, STT_EINVAL, "z_plain_dev needs plain_dev");
+    if (n == 0) return STT_OK;
+    STT_HIP(c, hipSetDevice(c->device));
+    RefineP p;
+    p.T = map->T;
+    p.F = map->F;
+    p.L = min_len;
+    p.dmax_ms = (double)dtau_max * (1e3 / 268435456.0);
+    p.px0 = sched_host ? sched_host[0] : 1.0;
+    p.px1 = sched_host ? sched_host[1] : 0.02;
+    p.ms0 = sched_host ? sched_host[2] : 0.5;
+    p.ms1 = sched_host ? sched_host[3] : 0.01;
+    p.steps = steps;
+    // state: current theta [n][6], gradient [n][6], current z [n]
+    const size_t need = sizeof(float) * (size_t)n * 13;
+    if (need > c->rbuf_bytes) {
+        STT_HIP(c, hipStreamSynchronize(c->stream));
+        if (c->rbuf) (void)hipFree(c->rbuf);
+        c->rbuf = nullptr;
+        c->rbuf_bytes = 0;
+        if (hipMalloc(&c->rbuf, need) != hipSuccess) {
+            (void)hipGetLastError();
+            return fail(c, STT_ENOMEM, "cannot allocate %zu bytes of refinement state", need);
+        }
+        c->rbuf_bytes = need;
+    }
+    float *cur = (float *)c->rbuf, *grad = cur + (size_t)n * 6, *z = grad + (size_t)n * 6;
+    const unsigned g1 = (unsigned)((n + 255) / 256);
+    STT_HIP(c, hipMemcpyAsync(cur, theta_dev, sizeof(float) * 6 * (size_t)n, hipMemcpyDeviceToDevice, c->stream));
+    hipLaunchKernelGGL(k_refine_project, dim3(g1), dim3(256), 0, c->stream, cur, n, p);
+    if ((s = smooth_launch(c, map, cur, K_dev, n, z, grad, c->stream)) != STT_OK) return s;
+    hipLaunchKernelGGL(k_refine_step, dim3(g1), dim3(256), 0, c->stream, cur, (const float *)z, (const float *)grad,
+                       theta_dev, z_smooth_dev, n, -1, p);
+    for (int32_t it = 0; it < steps; ++it) {
+        hipLaunchKernelGGL(k_refine_step, dim3(g1), dim3(256), 0, c->stream, cur, (const float *)z,
+                           (const float *)grad, theta_dev, z_smooth_dev, n, it, p);
+        if ((s = smooth_launch(c, map, cur, K_dev, n, z, grad, c->stream)) != STT_OK) return s;
+    }
+    hipLaunchKernelGGL(k_refine_step, dim3(g1), dim3(256), 0, c->stream, cur, (const float *)z, (const float *)grad,
+                       theta_dev, z_smooth_dev, n, steps, p);
+    STT_HIP(c, hipGetLastError());
+    if (plain_dev) {
+        hipLaunchKernelGGL(k_theta_to_track, dim3(g1), dim3(256), 0, c->stream, (const float *)theta_dev, (int64_t)n,
+                           map->T, map->F, min_len, dtau_max, (Trk *)plain_dev);
+        STT_HIP(c, hipGetLastError());
+        if (z_plain_dev) {
+            const int old = c->path;
+            c->path = 1;  // a short explicit list: direct gathers
+            s = stt_score(c, map, nullptr, plain_dev, 0, n, norm, z_plain_dev, nullptr);
+            c->path = old;
+            if (s != STT_OK) return s;
+        }
+    }
+    return STT_OK;
+}
+
 // ----------------------------------------------------------------------------- autotuning
+
+}  // extern "C"
 
 namespace {
 
@@ -923,6 +1079,8 @@ void cache_store(const char *path, const std::string &key, const TuneChoice &t)
 }
 
 }  // namespace
+
+extern "C" {
 
 stt_status stt_autotune(stt_ctx *c, const stt_map *map, const stt_gen *gen, int64_t n, const char *cache_path,
                         int32_t *choice_out)

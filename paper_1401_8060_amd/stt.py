@@ -331,6 +331,69 @@ class Context:
                                        cache_path.encode() if cache_path else None, out))
         return out[0], out[1], out[2]
 
+    # -- differentiation
+    def tracks_at(self, gen: Gen, T: int, F: int, idx: torch.Tensor) -> torch.Tensor:
+        """Templates at the given indices (int64 tensor), as an [n][6] int32 tensor."""
+        if idx.dtype != torch.int64 or not idx.is_contiguous():
+            raise ValueError("idx must be a contiguous int64 tensor")
+        out = tracks_tensor(idx.numel(), device=idx.device)
+        g = gen.c()
+        self._chk(self._L.stt_tracks_at(self.h, C.byref(g), T, F, C.c_void_p(idx.data_ptr()), idx.numel(),
+                                        C.c_void_p(out.data_ptr())))
+        return out
+
+    def tracks_to_theta(self, tracks: torch.Tensor):
+        """(theta [n][6] float32, K [n] int32) of plain templates."""
+        n = tracks.shape[0]
+        theta = torch.empty((n, 6), dtype=torch.float32, device=tracks.device)
+        K = torch.empty(n, dtype=torch.int32, device=tracks.device)
+        self._chk(self._L.stt_tracks_to_theta(self.h, C.c_void_p(tracks.data_ptr()), n, C.c_void_p(theta.data_ptr()),
+                                              C.c_void_p(K.data_ptr())))
+        return theta, K
+
+    @staticmethod
+    def _theta_ok(theta, K):
+        if theta.dtype != torch.float32 or theta.dim() != 2 or theta.shape[1] != 6 or not theta.is_contiguous():
+            raise ValueError("theta must be a contiguous [n][6] float32 tensor")
+        if K.dtype != torch.int32 or K.numel() != theta.shape[0] or not K.is_contiguous():
+            raise ValueError("K must be a contiguous int32 tensor with one entry per template")
+
+    def smooth(self, m, theta: torch.Tensor, K: torch.Tensor) -> torch.Tensor:
+        self._theta_ok(theta, K)
+        z = torch.empty(theta.shape[0], dtype=torch.float32, device=theta.device)
+        mc = m.c()
+        self._chk(self._L.stt_smooth(self.h, C.byref(mc), C.c_void_p(theta.data_ptr()), C.c_void_p(K.data_ptr()),
+                                     theta.shape[0], C.c_void_p(z.data_ptr())))
+        return z
+
+    def grad(self, m, theta: torch.Tensor, K: torch.Tensor):
+        """(z~ [n], dz~/dtheta [n][6]) from the hand-written backward kernel."""
+        self._theta_ok(theta, K)
+        n = theta.shape[0]
+        z = torch.empty(n, dtype=torch.float32, device=theta.device)
+        g = torch.empty((n, 6), dtype=torch.float32, device=theta.device)
+        mc = m.c()
+        self._chk(self._L.stt_grad(self.h, C.byref(mc), C.c_void_p(theta.data_ptr()), C.c_void_p(K.data_ptr()), n,
+                                   C.c_void_p(z.data_ptr()), C.c_void_p(g.data_ptr())))
+        return z, g
+
+    def refine(self, m, theta: torch.Tensor, K: torch.Tensor, min_len: int, dtau_max: int, steps: int = 50,
+               sched=(1.0, 0.02, 0.5, 0.01), norm: int = NORM_SQRT_N, plain: bool = True):
+        """Projected ascent of z~ from theta (copied). Returns (best theta, its z~, plain templates, their z)."""
+        self._theta_ok(theta, K)
+        n = theta.shape[0]
+        th = theta.clone()
+        zs = torch.empty(n, dtype=torch.float32, device=theta.device)
+        tr = tracks_tensor(n, device=theta.device) if plain else None
+        zp = torch.empty(n, dtype=torch.float32, device=theta.device) if plain else None
+        sc = (C.c_float * 4)(*sched)
+        mc = m.c()
+        self._chk(self._L.stt_refine(self.h, C.byref(mc), min_len, dtau_max, C.c_void_p(th.data_ptr()),
+                                     C.c_void_p(K.data_ptr()), n, steps, sc, C.c_void_p(zs.data_ptr()),
+                                     C.c_void_p(tr.data_ptr()) if plain else None,
+                                     C.c_void_p(zp.data_ptr()) if plain else None, norm))
+        return th, zs, tr, zp
+
     def set_graph(self, on: bool):
         self._chk(self._L.stt_set_graph(self.h, 1 if on else 0))
 

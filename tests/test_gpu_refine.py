@@ -1,0 +1,154 @@
+"""GPU parity of the differentiation addition: the smooth statistic, its hand-written
+gradient, the autograd binding and the projected-ascent refinement."""
+from __future__ import annotations
+
+import math
+import sys
+
+import numpy as np
+import pytest
+
+import synth
+from tests.parity_util import assert_close, to_dev
+
+pytestmark = pytest.mark.gpu
+D10MS = 2684355
+
+
+@pytest.fixture(scope="module")
+def stt():
+    import paper_1401_8060_amd.stt as stt
+    return stt
+
+
+@pytest.fixture(scope="module")
+def ctx(stt):
+    c = stt.Context(0)
+    yield c
+    c.close()
+
+
+def _say(*a):
+    print(*a, flush=True, file=sys.stderr)
+
+
+def _thetas(T, F, n, seed):
+    sel = np.random.default_rng(seed)
+    K = sel.integers(10, min(T, 300), n).astype(np.int32)
+    a = sel.uniform(-5, T - 5, n)
+    th = np.stack([a, a + K + sel.uniform(-3, 30, n), *sel.uniform(-2, F + 1, (3, n)),
+                   sel.uniform(-12, 12, n)], axis=1).astype(np.float32)
+    return th, K
+
+
+def test_tracks_at_and_theta(orc, stt, ctx):
+    import torch
+    _say("tracks_at")
+    idx = np.array([0, 5, 2 ** 32 - 1, 123456789, 77], dtype=np.int64)
+    g = stt.Gen(seed=8, stream=3, min_len=10, dtau_max=D10MS)
+    tr = ctx.tracks_at(g, 900, 700, torch.from_numpy(idx).cuda()).cpu().numpy()
+    for i, j in enumerate(idx):
+        assert tuple(tr[i]) == tuple(int(x) for x in orc.draw(8, 3, int(j), 900, 700, 10, D10MS).tolist())
+    th, K = ctx.tracks_to_theta(torch.from_numpy(tr).cuda())
+    th, K = th.cpu().numpy(), K.cpu().numpy()
+    assert np.array_equal(K, tr[:, 1] - tr[:, 0] + 1)
+    assert np.array_equal(th[:, 0], tr[:, 0].astype(np.float32))
+    assert np.array_equal(th[:, 2], (tr[:, 2].astype(np.float64) / 256).astype(np.float32))
+    assert np.allclose(th[:, 5], tr[:, 5] * 2.0 ** -28 * 1e3, rtol=1e-7)
+
+
+@pytest.mark.parametrize("p16", [False, True])
+def test_smooth_and_gradient_match_oracle(orc, stt, ctx, p16):
+    import torch
+    _say("smooth/grad", p16)
+    T, F, n = 400, 250, 600
+    Y, s = synth.noise_map(T, F, seed=41, sigma=("loguniform", 0.5, 2.0))
+    m = stt.Map(*to_dev(Y, s))
+    if p16:
+        m = ctx.pack_p16(m)
+        _, _, deq = orc.quantize_p16(Y, s)
+        om = orc.Map(deq, np.ones((T, F)))
+    else:
+        om = orc.Map(Y, s)
+    th, K = _thetas(T, F, n, 3)
+    z, g = ctx.grad(m, torch.from_numpy(th).cuda(), torch.from_numpy(K).cuda())
+    z_only = ctx.smooth(m, torch.from_numpy(th).cuda(), torch.from_numpy(K).cuda())
+    assert torch.equal(z, z_only)
+    z, g = z.cpu().numpy(), g.cpu().numpy()
+    zo = np.empty(n)
+    go = np.empty((n, 6))
+    for i in range(n):
+        zo[i], go[i] = orc.smooth(om, th[i].astype(np.float64), int(K[i]))
+    assert_close(z, zo, tol=2e-5, what="smooth z")
+    err = np.abs(g - go) / np.maximum(1.0, np.abs(go))
+    assert err.max() < 2e-4, err.max()
+
+
+def test_autograd_backward_is_the_gradient_kernel(stt, ctx):
+    import torch
+    from paper_1401_8060_amd.autograd import smooth_snr
+    _say("autograd")
+    T, F, n = 200, 150, 64
+    Y, s = synth.noise_map(T, F, seed=42)
+    m = stt.Map(*to_dev(Y, s))
+    th, K = _thetas(T, F, n, 4)
+    theta = torch.from_numpy(th).cuda().requires_grad_(True)
+    Kt = torch.from_numpy(K).cuda()
+    w = torch.linspace(-1, 2, n, device="cuda")
+    z = smooth_snr(ctx, m, theta, Kt)
+    (w * z).sum().backward()
+    z2, g = ctx.grad(m, theta.detach(), Kt)
+    assert torch.equal(z.detach(), z2)
+    assert torch.allclose(theta.grad, w[:, None] * g, rtol=0, atol=0)
+
+
+def test_refine_invariants_and_plain_rescore(orc, stt, ctx):
+    import torch
+    _say("refine")
+    T, F, n, L = 300, 200, 256, 10
+    Y, s = synth.noise_map(T, F, seed=43, sigma=("loguniform", 0.5, 2.0))
+    m = stt.Map(*to_dev(Y, s))
+    om = orc.Map(Y, s)
+    g = stt.Gen(seed=6, min_len=L, dtau_max=D10MS)
+    tr0 = ctx.make_tracks(g, T, F, 0, n)
+    th0, K = ctx.tracks_to_theta(tr0)
+    z0 = ctx.smooth(m, th0, K)
+    th, zs, tr, zp = ctx.refine(m, th0, K, L, D10MS, steps=50)
+    th_h, zs_h, tr_h, zp_h = th.cpu().numpy(), zs.cpu().numpy(), tr.cpu().numpy(), zp.cpu().numpy()
+    assert (zs_h >= z0.cpu().numpy() - 1e-6).all()
+    assert (th_h[:, 0] >= 0).all() and (th_h[:, 1] <= T - 1).all() and (th_h[:, 1] - th_h[:, 0] >= L - 1 - 1e-4).all()
+    assert (th_h[:, 2:5] >= 0).all() and (th_h[:, 2:5] < F).all() and (np.abs(th_h[:, 5]) <= 10.0 + 1e-5).all()
+    # the kept iterate's z~ is the smooth statistic at the returned theta
+    zo = np.array([orc.smooth(om, th_h[i].astype(np.float64), int(K[i]))[0] for i in range(n)])
+    assert_close(zs_h, zo, tol=2e-5, what="best z~")
+    # rounding to plain templates and their plain scores, exactly as the oracle defines them
+    K_h = K.cpu().numpy()
+    for i in range(n):
+        want = orc.theta_to_track(th_h[i].astype(np.float64), T, F, L, D10MS)
+        assert tuple(tr_h[i]) == tuple(int(x) for x in want.tolist())
+    assert_close(zp_h, orc.score_list(om, tr_h.view(orc.TRACK_DTYPE).reshape(-1)), what="plain rescore")
+    gain = zs_h - z0.cpu().numpy()
+    _say(f"refine: mean z~ gain {gain.mean():.3f}, max {gain.max():.3f}")
+    assert gain.mean() > 0.1
+
+
+def test_refine_recovers_an_injection(orc, stt, ctx):
+    """Noise-free map, one injected straight track: from a start a few pixels and 1 ms off,
+    the GPU refinement ends within a pixel and 0.1 ms of it, like the oracle's."""
+    import torch
+    _say("refine injection")
+    T, F = 100, 80
+    Y = np.zeros((T, F), dtype=np.complex64)
+    s = np.ones((T, F), dtype=np.float32)
+    t0, t2, r0, r2, dt0 = 20, 79, 30.5, 50.5, 2.0
+    k = np.arange(t2 - t0 + 1)
+    rows = np.floor(r0 + (r2 - r0) * k / (t2 - t0)).astype(int)
+    synth.add_pixels(Y, s, t0 + k, rows, 1.0, -(100.0 + rows) * dt0 * 1e-3)
+    m = stt.Map(*to_dev(Y, s))
+    th0 = np.array([[t0 + 1.5, t2 - 1.0, r0 + 1.5, 0.5 * (r0 + r2) - 1.0, r2 + 1.2, dt0 + 1.0]], dtype=np.float32)
+    K = np.array([t2 - t0 + 1], dtype=np.int32)
+    th, zs, _, _ = ctx.refine(m, torch.from_numpy(th0).cuda(), torch.from_numpy(K).cuda(), 10, D10MS, steps=50)
+    th = th.cpu().numpy()[0]
+    tho, zo = orc.refine(orc.Map(Y, s), th0[0].astype(np.float64), int(K[0]), 50, 10, 10.0)
+    assert abs(th[5] - dt0) < 0.1 and np.abs(th[2:5] - [r0, 0.5 * (r0 + r2), r2]).max() < 1.0
+    assert float(zs.item()) == pytest.approx(zo, rel=0.02)
