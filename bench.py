@@ -41,6 +41,9 @@ WORKLOADS = {
     # batched background: 256 maps, T uniform on [500, 2000], F=1000, 10^6 tracks per map, one graph launch
     "batch_256maps_1e6": dict(kind="batch", n_maps=256, T_lo=500, T_hi=2000, F=1000, n=1_000_000, seed=3, L=10,
                               dtau_s=0.01, sigma=("loguniform", 0.5, 2.0)),
+    # differentiation: T=1000 x F=1000 with 8 injected tracks at SNR 5..10; top-1024 of 10^6 refined 50 steps
+    "refine_1000x1000_1e6": dict(kind="refine", T=1000, F=1000, n=1_000_000, seed=5, L=10, dtau_s=0.01,
+                                 sigma=("loguniform", 0.5, 2.0), K=1024, steps=50, n_inj=8, inject=None),
     # precision: T=2000 x F=2000 stored in FP16, 10^8 tracks, top-1024 re-scored in FP64
     "precision_2000x2000_1e8": dict(kind="precision", T=2000, F=2000, n=100_000_000, seed=4, L=10, dtau_s=0.01,
                                     sigma=("loguniform", 0.5, 2.0), K=1024,
@@ -276,6 +279,58 @@ def run_precision(args, name, w):
     return out
 
 
+def run_refine(args, name, w):
+    import numpy as np
+    import torch
+    import synth
+    import paper_1401_8060_amd.stt as stt
+    dtau_max = stt.dtau_units(w["dtau_s"])
+    T, F = w["T"], w["F"]
+    log(f"bench: building map {T}x{F} with {w['n_inj']} injections")
+    Y, s, _ = make_map(w)
+    u = synth.uniform01(w["seed"], 77, 6 * w["n_inj"]).reshape(w["n_inj"], 6)
+    inj = []
+    for i in range(w["n_inj"]):
+        t0 = int(u[i, 0] * (T - 300))
+        t2 = t0 + 100 + int(u[i, 1] * 190)
+        f = 20 + u[i, 2:5] * (F - 40)
+        dt = int(round((u[i, 5] * 2 - 1) * 0.008 / 2.0 ** -28))
+        snr = 5.0 + 5.0 * i / (w["n_inj"] - 1)
+        cols, rows = synth.bezier_rows_float(t0, t2, *f)
+        synth.add_pixels(Y, s, cols, rows, snr / math.sqrt(cols.size), -((100.0 + rows) * dt * 2.0 ** -28))
+        inj.append(dict(t0=t0, t2=t2, snr=snr))
+    dev = torch.device("cuda:0")
+    m = stt.Map(torch.from_numpy(Y).to(dev), torch.from_numpy(s).to(dev))
+    ctx = stt.Context(0)
+    g = stt.Gen(seed=w["seed"], stream=0, min_len=w["L"], dtau_max=dtau_max)
+    n, K = w["n"], w["K"]
+    px = count_px(ctx, g, T, F, n)
+    snr = torch.empty(n, dtype=torch.float32, device=dev)
+    res = {}
+
+    def step():
+        ctx.score(m, gen=g, n=n, snr=snr)
+        idx, val = ctx.topk(snr, K)
+        tr = ctx.tracks_at(g, T, F, idx)
+        th, Ks = ctx.tracks_to_theta(tr)
+        res.update(val=val, th0=th, K=Ks)
+        res["out"] = ctx.refine(m, th, Ks, w["L"], dtau_max, steps=w["steps"])
+
+    ms_step = timed(args, step, torch)
+    z_plain0 = res["val"].double()
+    z_s0 = ctx.smooth(m, res["th0"], res["K"]).double()
+    th, zs, trr, zp = res["out"]
+    log(f"bench: {ms_step:.3f} ms/step; best plain z {z_plain0.max().item():.3f} -> refined {zp.max().item():.3f}")
+    out = base_record(args, name, w, n, ms_step, px, "f32")
+    out["config"].update({"T": T, "F": F, "n_tracks": n, "top_k": K, "steps": w["steps"], "injections": inj})
+    out["refine"] = {"best_plain_z_random_search": z_plain0.max().item(),
+                     "best_plain_z_after_refine": zp.max().item(),
+                     "mean_smooth_gain": (zs.double() - z_s0).mean().item(),
+                     "improved_fraction": (zp.double() > z_plain0).double().mean().item()}
+    ctx.close()
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -285,14 +340,25 @@ def main():
     ap.add_argument("--map-dtype", default="f32", choices=["f32", "p16"], help="batch workload map storage")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-snr", action="store_true", help="reduce to the argmax only (no per-track output)")
+    ap.add_argument("--copy-probe-mb", type=int, default=0,
+                    help="after the run, copy this many MiB device-to-device (a known-size kernel for counter scaling)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for {args.gpus}); the search shards by template range "
               "or by map with no communication but a max, which this build leaves out.", file=sys.stderr)
         sys.exit(2)
     w = WORKLOADS[args.workload]
-    runner = {"single": run_single, "batch": run_batch, "precision": run_precision}[w["kind"]]
+    runner = {"single": run_single, "batch": run_batch, "precision": run_precision, "refine": run_refine}[w["kind"]]
     out = runner(args, args.workload, w)
+    if args.copy_probe_mb:
+        import torch
+        nb = args.copy_probe_mb << 20
+        src = torch.ones(nb // 4, dtype=torch.float32, device="cuda")
+        dst = torch.empty_like(src)
+        torch.cuda.synchronize()
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        out["copy_probe_bytes"] = nb
     print(json.dumps(out), flush=True)
 
 
