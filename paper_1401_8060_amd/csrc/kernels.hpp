@@ -30,8 +30,12 @@ struct MapP {
     float scale;       // FP16 map: p = stored * scale (a power of two)
 };
 
-// Map element formats of the scorers.
-enum : int { kMapF32 = 0, kMapP16 = 1 };
+// Map element formats of the scorers: the caller's (Y, sigma) FP32 map, the
+// FP16 p map, and p = Y/sigma folded into complex64 by k_fold_p (columns padded
+// to a multiple of 128 pixels so that slabs can be copied into LDS in 1 KB
+// pieces).
+enum : int { kMapF32 = 0, kMapP16 = 1, kMapPF = 2 };
+constexpr int kDmaPix = 128;  // pixels one wave moves per LDS-DMA instruction (64 lanes x 16 B)
 
 // The complex SNR p = Y/sigma of pixel element e (Eq. 7 with the appendix's rho = Y/sigma).
 template <int MAPT>
@@ -42,9 +46,22 @@ __device__ __forceinline__ float2 load_p(const MapP &m, int64_t e)
         const float2 f = __half22float2(h);
         return make_float2(f.x * m.scale, f.y * m.scale);
     }
+    if (MAPT == kMapPF) return m.Y[e];
     const float2 y = m.Y[e];
     const float w = 1.0f / m.sig[e];
     return make_float2(y.x * w, y.y * w);
+}
+
+// p = Y/sigma of every pixel into a complex64 map with column stride ld_out
+// (pixels F..ld_out-1 of a column are zero). The same expression as load_p's,
+// so scores do not depend on whether the map was folded first.
+__global__ __launch_bounds__(256) void k_fold_p(MapP m, float2 *out, int64_t ld_out)
+{
+    const int64_t n = (int64_t)m.T * ld_out;
+    for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < n; i += (int64_t)gridDim.x * 256) {
+        const int64_t t = i / ld_out, r = i - t * ld_out;
+        out[i] = r < m.F ? load_p<kMapF32>(m, t * m.ld + r) : make_float2(0.0f, 0.0f);
+    }
 }
 
 constexpr int kMaxDt = 2895;  // Dt * Dt * 256 < 2^31
@@ -293,13 +310,13 @@ __global__ __launch_bounds__(256) void k_bin_scatter(MapP m, GenP g, const Trk *
 // templates of this lane. MASK = false is the wave's core, where every
 // template of the wave covers every column: no select and no clamp.
 template <int TPT, bool MASK, bool HW>
-__device__ __forceinline__ void walk(int ca, int cb, int c0, const float2 *slab, int F, const int32_t (&t0)[TPT],
+__device__ __forceinline__ void walk(int ca, int cb, int c0, const float2 *slab, int ldc, const int32_t (&t0)[TPT],
                                      const uint32_t (&span)[TPT], const uint32_t (&pa)[TPT],
                                      const uint32_t (&pbl)[TPT], const uint32_t (&pbh)[TPT], DdaF (&st)[TPT],
                                      float (&part)[TPT], double (&acc)[TPT])
 {
     for (int c = ca; c <= cb; ++c) {
-        const float2 *col = slab + (c - c0) * F;
+        const float2 *col = slab + (c - c0) * ldc;
 #pragma unroll
         for (int q = 0; q < TPT; ++q) {
             const int32_t row = ddaf_row(st[q]);
@@ -322,6 +339,9 @@ __device__ __forceinline__ void walk(int ca, int cb, int c0, const float2 *slab,
 // One block of WG*TPT consecutive entries of `order` (block index b): the
 // whole slab sweep for those templates. slab is the dynamic LDS (S*F float2),
 // bnd two LDS ints. Callable repeatedly by a persistent workgroup.
+// MAPT == kMapPF stages with LDS DMA into two slab buffers (double buffering:
+// slab k+1 streams in while slab k is walked); the other formats stage through
+// registers into one buffer, converting on the way.
 template <int WG, int TPT, bool EXPL, bool HW, int MAPT>
 __device__ __forceinline__ void score_block(const MapP &m, const GenP &g, const Trk *tr, const uint32_t *order,
                                             uint64_t first, int64_t n, int64_t b, int S, int32_t norm, float *snr,
@@ -389,29 +409,59 @@ __device__ __forceinline__ void score_block(const MapP &m, const GenP &g, const 
     __syncthreads();
     const int c_first = bnd[0], c_last = bnd[1];
     const int F = m.F;
-    // staging walk: element e = tid + i*WG of the slab is (column e / F, row e % F)
-    const int dcol = WG / F, drow = WG % F;
-    const int col0 = threadIdx.x / F, row0 = threadIdx.x % F;
 
-    for (int c0 = c_first; c0 <= c_last; c0 += S) {
-        const int ncol = min(S, c_last - c0 + 1);
-        __syncthreads();  // the previous slab has been consumed
-        {
-            int col = col0, r = row0;
-            const int64_t base = (int64_t)c0 * m.ld;
-#pragma unroll 4
-            for (int e = threadIdx.x; e < ncol * F; e += WG) {
-                slab[col * F + r] = load_p<MAPT>(m, base + (int64_t)col * m.ld + r);
-                r += drow;
-                col += dcol;
-                if (r >= F) { r -= F; ++col; }
+    if (MAPT == kMapPF) {
+        // m.ld is a multiple of kDmaPix; a column is m.ld / kDmaPix pieces of 1 KB
+        const int ldc = (int)m.ld, per_col = ldc / kDmaPix;
+        const int wave = threadIdx.x >> 6;
+        auto issue = [&](int c0, int bsel) {
+            const int nchunk = min(S, c_last - c0 + 1) * per_col;
+            float2 *dst = slab + (size_t)bsel * S * ldc;
+            for (int ch = wave; ch < nchunk; ch += WG / 64) {
+                const int col = ch / per_col, off = (ch - col * per_col) * kDmaPix;
+                const float2 *src = m.Y + (int64_t)(c0 + col) * ldc + off + lane * 2;
+                __builtin_amdgcn_global_load_lds((const void *)src,
+                                                 (__attribute__((address_space(3))) void *)(dst + col * ldc + off), 16,
+                                                 0, 0);
             }
+        };
+        if (c_first <= c_last) issue(c_first, 0);
+        int k = 0;
+        for (int c0 = c_first; c0 <= c_last; c0 += S, ++k) {
+            __builtin_amdgcn_s_waitcnt(0);  // this wave's copies of slab k have landed
+            __syncthreads();                // so have everyone's, and slab k-1 is no longer read
+            if (c0 + S <= c_last) issue(c0 + S, (k + 1) & 1);
+            const float2 *cur = slab + (size_t)(k & 1) * S * ldc;
+            const int ncol = min(S, c_last - c0 + 1);
+            const int ca = max(c0, lo), cb = min(c0 + ncol - 1, hi);  // this wave's columns in the slab
+            walk<TPT, true, HW>(ca, min(cb, clo - 1), c0, cur, ldc, t0, span, pa, pbl, pbh, st, part, acc);
+            walk<TPT, false, HW>(max(ca, clo), min(cb, chi), c0, cur, ldc, t0, span, pa, pbl, pbh, st, part, acc);
+            walk<TPT, true, HW>(max(ca, chi + 1), cb, c0, cur, ldc, t0, span, pa, pbl, pbh, st, part, acc);
         }
-        __syncthreads();
-        const int ca = max(c0, lo), cb = min(c0 + ncol - 1, hi);  // this wave's columns in the slab
-        walk<TPT, true, HW>(ca, min(cb, clo - 1), c0, slab, F, t0, span, pa, pbl, pbh, st, part, acc);
-        walk<TPT, false, HW>(max(ca, clo), min(cb, chi), c0, slab, F, t0, span, pa, pbl, pbh, st, part, acc);
-        walk<TPT, true, HW>(max(ca, chi + 1), cb, c0, slab, F, t0, span, pa, pbl, pbh, st, part, acc);
+    } else {
+        // staging walk: element e = tid + i*WG of the slab is (column e / F, row e % F)
+        const int dcol = WG / F, drow = WG % F;
+        const int col0 = threadIdx.x / F, row0 = threadIdx.x % F;
+        for (int c0 = c_first; c0 <= c_last; c0 += S) {
+            const int ncol = min(S, c_last - c0 + 1);
+            __syncthreads();  // the previous slab has been consumed
+            {
+                int col = col0, r = row0;
+                const int64_t base = (int64_t)c0 * m.ld;
+#pragma unroll 4
+                for (int e = threadIdx.x; e < ncol * F; e += WG) {
+                    slab[col * F + r] = load_p<MAPT>(m, base + (int64_t)col * m.ld + r);
+                    r += drow;
+                    col += dcol;
+                    if (r >= F) { r -= F; ++col; }
+                }
+            }
+            __syncthreads();
+            const int ca = max(c0, lo), cb = min(c0 + ncol - 1, hi);  // this wave's columns in the slab
+            walk<TPT, true, HW>(ca, min(cb, clo - 1), c0, slab, F, t0, span, pa, pbl, pbh, st, part, acc);
+            walk<TPT, false, HW>(max(ca, clo), min(cb, chi), c0, slab, F, t0, span, pa, pbl, pbh, st, part, acc);
+            walk<TPT, true, HW>(max(ca, chi + 1), cb, c0, slab, F, t0, span, pa, pbl, pbh, st, part, acc);
+        }
     }
 
     uint64_t key = 0;

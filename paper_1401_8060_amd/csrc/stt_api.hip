@@ -30,6 +30,9 @@ struct stt_ctx {
     size_t aux_bytes = 0;
     void *rbuf = nullptr;  // refinement state
     size_t rbuf_bytes = 0;
+    void *pbuf = nullptr;  // folded p = Y/sigma maps for LDS-DMA staging
+    size_t pbuf_bytes = 0;
+    bool dma = true;       // fold + double-buffered LDS-DMA staging where a column fits
     int path = 0;  // 0 auto, 1 direct, 2 slab
     int lds_bytes = 160 * 1024;  // slab budget per workgroup
     int slab_wg = 1024;          // slab scorer shape: lanes per workgroup
@@ -117,6 +120,28 @@ stt_status ensure_aux(stt_ctx *c, size_t bytes)
     c->aux_bytes = bytes;
     return STT_OK;
 }
+
+stt_status ensure_pbuf(stt_ctx *c, size_t bytes)
+{
+    if (bytes <= c->pbuf_bytes) return STT_OK;
+    if (c->pbuf) {
+        hipError_t e = hipStreamSynchronize(c->stream);
+        if (e != hipSuccess) return fail(c, STT_EHIP, "hipStreamSynchronize: %s", hipGetErrorString(e));
+        (void)hipFree(c->pbuf);
+        c->pbuf = nullptr;
+        c->pbuf_bytes = 0;
+    }
+    if (hipMalloc(&c->pbuf, bytes) != hipSuccess) {
+        (void)hipGetLastError();
+        return fail(c, STT_ENOMEM, "cannot allocate %zu bytes for the folded map", bytes);
+    }
+    c->pbuf_bytes = bytes;
+    return STT_OK;
+}
+
+// Column stride of a folded map and the slab depth that two buffers of it allow.
+int64_t fold_ld(int F) { return ((int64_t)F + kDmaPix - 1) / kDmaPix * kDmaPix; }
+int dma_slab_cols(const stt_ctx *c, int64_t ldc) { return (int)std::min<int64_t>(64, (c->lds_bytes - 256) / (16 * ldc)); }
 
 stt_status check_map(stt_ctx *c, const stt_map *m)
 {
@@ -321,10 +346,29 @@ stt_status score_impl(stt_ctx *c, const stt_map *map, const GenP &g, const Trk *
         STT_HIP(c, hipGetLastError());
         ev_record(c, 3);
         c->used[1] = true;
-        const int S = std::min(slab_cols, m.T);
-        const size_t shm = sizeof(float2) * (size_t)S * m.F;
-        ev_record(c, 0);
-        s = launch_slab<EXPL, MAPT>(c, c->slab_wg, c->slab_tpt, m, g, tr, order, first, n, S, shm, norm, snr, best);
+        const int64_t ldc = fold_ld(m.F);
+        if (MAPT == kMapF32 && c->dma && dma_slab_cols(c, ldc) >= 1) {
+            // fold p = Y/sigma once, then stream slabs into LDS with double-buffered DMA
+            const size_t pb = sizeof(float2) * (size_t)m.T * (size_t)ldc;
+            if ((s = ensure_pbuf(c, pb)) != STT_OK) return s;
+            const unsigned fg = (unsigned)std::min<int64_t>(((int64_t)m.T * ldc + 255) / 256, 4096);
+            hipLaunchKernelGGL(k_fold_p, dim3(fg), dim3(256), 0, c->stream, m, (float2 *)c->pbuf, ldc);
+            MapP mf = m;
+            mf.Y = (const float2 *)c->pbuf;
+            mf.sig = nullptr;
+            mf.ld = ldc;
+            const int S = std::min(dma_slab_cols(c, ldc), m.T);
+            const size_t shm = 2 * sizeof(float2) * (size_t)S * ldc;
+            ev_record(c, 0);
+            s = launch_slab<EXPL, kMapPF>(c, c->slab_wg, c->slab_tpt, mf, g, tr, order, first, n, S, shm, norm, snr,
+                                          best);
+        } else {
+            const int S = std::min(slab_cols, m.T);
+            const size_t shm = sizeof(float2) * (size_t)S * m.F;
+            ev_record(c, 0);
+            s = launch_slab<EXPL, MAPT>(c, c->slab_wg, c->slab_tpt, m, g, tr, order, first, n, S, shm, norm, snr,
+                                        best);
+        }
         if (s != STT_OK) return s;
         ev_record(c, 1);
         c->used[0] = true;
@@ -376,6 +420,7 @@ stt_status stt_destroy(stt_ctx *c)
     if (c->scratch) (void)hipFree(c->scratch);
     if (c->aux) (void)hipFree(c->aux);
     if (c->rbuf) (void)hipFree(c->rbuf);
+    if (c->pbuf) (void)hipFree(c->pbuf);
     if (c->bdev) (void)hipFree(c->bdev);
     if (c->gexec) (void)hipGraphExecDestroy(c->gexec);
     if (c->graph) (void)hipGraphDestroy(c->graph);
@@ -466,6 +511,13 @@ stt_status stt_set_slab_shape(stt_ctx *c, int32_t wg, int32_t tpt)
     if (!slab_shape_ok(wg, tpt)) return fail(c, STT_EUNSUPPORTED, "no slab scorer for %d x %d", wg, tpt);
     c->slab_wg = wg;
     c->slab_tpt = tpt;
+    return STT_OK;
+}
+
+stt_status stt_set_staging(stt_ctx *c, int32_t dma)
+{
+    if (!c || dma < 0 || dma > 1) return STT_EINVAL;
+    c->dma = dma == 1;
     return STT_OK;
 }
 
@@ -696,6 +748,9 @@ stt_status stt_score_batch(stt_ctx *c, const stt_map *maps_host, int32_t n_maps,
     const int per_item = c->slab_wg * c->slab_tpt;
     uint64_t norder = 0, nchunks = 0, nitems = 0;
     size_t shm = 0;
+    bool fold_ok = c->dma && dtype == STT_C64F32;  // every map's column fits two DMA slabs
+    uint64_t fold_px = 0;
+    std::vector<uint64_t> fold_off(n_maps, 0);
     for (int i = 0; i < n_maps; ++i) {
         const stt_map *mp = &maps_host[i];
         stt_status s = check_map(c, mp);
@@ -717,6 +772,12 @@ stt_status stt_score_batch(stt_ctx *c, const stt_map *maps_host, int32_t n_maps,
         d.S = std::min(std::min<int>(64, (c->lds_bytes - 256) / (8 * mp->F)), mp->T);
         if (d.S < 1) return fail(c, STT_EUNSUPPORTED, "map %d: F=%d too wide for the LDS slab", i, mp->F);
         shm = std::max(shm, sizeof(float2) * (size_t)d.S * mp->F);
+        if (mp->dtype == STT_C64F32) {
+            const int64_t ldc = fold_ld(mp->F);
+            fold_ok = fold_ok && dma_slab_cols(c, ldc) >= 1;
+            fold_off[i] = fold_px;
+            fold_px += (uint64_t)mp->T * (uint64_t)ldc;
+        }
         d.snr = snr_dev_host ? snr_dev_host[i] : nullptr;
         chunk_start[i] = (uint32_t)nchunks;
         item_start[i] = (uint32_t)nitems;
@@ -730,6 +791,22 @@ stt_status stt_score_batch(stt_ctx *c, const stt_map *maps_host, int32_t n_maps,
     chunk_start[n_maps] = (uint32_t)nchunks;
     item_start[n_maps] = (uint32_t)nitems;
     STT_HIP(c, hipSetDevice(c->device));
+    std::vector<MapP> orig(n_maps);
+    for (int i = 0; i < n_maps; ++i) orig[i] = bm[i].m;
+    if (fold_ok) {
+        stt_status sf = ensure_pbuf(c, sizeof(float2) * (size_t)fold_px);
+        if (sf != STT_OK) return sf;
+        shm = 0;
+        for (int i = 0; i < n_maps; ++i) {
+            BatchMap &d = bm[i];
+            const int64_t ldc = fold_ld(d.m.F);
+            d.m.Y = (const float2 *)c->pbuf + fold_off[i];
+            d.m.sig = nullptr;
+            d.m.ld = ldc;
+            d.S = std::min(dma_slab_cols(c, ldc), d.m.T);
+            shm = std::max(shm, 2 * sizeof(float2) * (size_t)d.S * (size_t)ldc);
+        }
+    }
     if (!c->n_cu) STT_HIP(c, hipDeviceGetAttribute(&c->n_cu, hipDeviceAttributeMultiprocessorCount, c->device));
 
     // scratch: [totals | cursor | queue | order]
@@ -752,7 +829,10 @@ stt_status stt_score_batch(stt_ctx *c, const stt_map *maps_host, int32_t n_maps,
     key_add(key, c->slab_tpt);
     key_add(key, c->lds_bytes);
     key_add(key, c->hw_trig);
+    key_add(key, fold_ok);
+    key_add(key, c->pbuf);
     for (const auto &d : bm) key_add(key, d);
+    for (const auto &o : orig) key_add(key, o);
     const bool same = c->use_graph && c->gexec && key == c->bkey;
 
     if (!same) {
@@ -783,6 +863,12 @@ stt_status stt_score_batch(stt_ctx *c, const stt_map *maps_host, int32_t n_maps,
         auto enqueue = [&](hipStream_t st) -> stt_status {
             const bool timed = st == c->stream;  // events only outside graph capture
             if (timed) ev_record(c, 2);
+            if (fold_ok)
+                for (int i = 0; i < n_maps; ++i) {
+                    const int64_t ldc = bm[i].m.ld;
+                    const unsigned fg = (unsigned)std::min<int64_t>(((int64_t)orig[i].T * ldc + 255) / 256, 4096);
+                    hipLaunchKernelGGL(k_fold_p, dim3(fg), dim3(256), 0, st, orig[i], (float2 *)bm[i].m.Y, ldc);
+                }
             hipLaunchKernelGGL(k_fill_u32, dim3((unsigned)((nb_all + 64 + 255) / 256)), dim3(256), 0, st, totals,
                                (int64_t)(nb_all), 0u);
             hipLaunchKernelGGL(k_fill_u32, dim3(1), dim3(256), 0, st, queue, (int64_t)1, 0u);
@@ -801,7 +887,12 @@ stt_status stt_score_batch(stt_ctx *c, const stt_map *maps_host, int32_t n_maps,
                 c->used[0] = c->used[1] = true;
             }
             stt_status r;
-            if (dtype == STT_P16)
+            if (fold_ok)
+                r = c->hw_trig ? launch_batch_h<true, kMapPF>(c, st, dmaps, n_maps, ditem, (uint32_t)nitems, queue,
+                                                              order, norm, best_key_per_map_dev, shm)
+                               : launch_batch_h<false, kMapPF>(c, st, dmaps, n_maps, ditem, (uint32_t)nitems, queue,
+                                                               order, norm, best_key_per_map_dev, shm);
+            else if (dtype == STT_P16)
                 r = c->hw_trig ? launch_batch_h<true, kMapP16>(c, st, dmaps, n_maps, ditem, (uint32_t)nitems, queue,
                                                                   order, norm, best_key_per_map_dev, shm)
                                   : launch_batch_h<false, kMapP16>(c, st, dmaps, n_maps, ditem, (uint32_t)nitems,

@@ -74,6 +74,7 @@ def lib():
             "stt_set_path": ([vp, i32, i32], i32),
             "stt_set_slab_shape": ([vp, i32, i32], i32),
             "stt_set_trig": ([vp, i32], i32),
+            "stt_set_staging": ([vp, i32], i32),
             "stt_make_tracks": ([vp, C.POINTER(_Gen), i32, i32, i64, i64, vp], i32),
             "stt_score": ([vp, C.POINTER(_Map), C.POINTER(_Gen), vp, i64, i64, i32, vp, vp], i32),
             "stt_argmax": ([vp, vp, i64, i64, vp], i32),
@@ -97,7 +98,7 @@ def _bind_ext(L):
 
 EXPORTED = [
     "stt_create", "stt_destroy", "stt_set_stream", "stt_sync", "stt_strerror", "stt_last_error",
-    "stt_reserve", "stt_set_timing", "stt_kernel_ms", "stt_kernel_ms_total", "stt_set_path", "stt_set_slab_shape", "stt_set_trig", "stt_make_tracks", "stt_score",
+    "stt_reserve", "stt_set_timing", "stt_kernel_ms", "stt_kernel_ms_total", "stt_set_path", "stt_set_slab_shape", "stt_set_trig", "stt_set_staging", "stt_make_tracks", "stt_score",
     "stt_argmax", "stt_key_encode", "stt_key_decode",
 ]
 
@@ -238,6 +239,9 @@ class Context:
 
     def set_slab_shape(self, wg: int, tpt: int):
         self._chk(self._L.stt_set_slab_shape(self.h, wg, tpt))
+
+    def set_staging(self, dma: bool):
+        self._chk(self._L.stt_set_staging(self.h, 1 if dma else 0))
 
     def set_trig(self, hw: bool):
         self._chk(self._L.stt_set_trig(self.h, 1 if hw else 0))

@@ -353,3 +353,34 @@ def test_argument_errors_write_nothing(stt, ctx):
     ctx.set_path(stt.PATH_AUTO)
     torch.cuda.synchronize()
     assert key_to_host(key) == 0
+
+
+@pytest.mark.parametrize("F", [1000, 1024, 77, 4000])
+def test_dma_and_register_staging_identical(orc, stt, ctx, F):
+    """The folded-map LDS-DMA staging and the register staging give bit-identical scores
+    (same p = Y/sigma bits, same walk); checked on one map against the oracle too."""
+    import torch
+    _say("staging", F)
+    T, n = 260, 30_000
+    Y, s = synth.noise_map(T, F, seed=F, sigma=("loguniform", 0.5, 2.0))
+    m = stt.Map(*to_dev(Y, s))
+    g = _gen(stt, 12, 1)
+    ctx.set_path(stt.PATH_SLAB)
+    res = []
+    for dma in (True, False):
+        ctx.set_staging(dma)
+        res.append(ctx.score(m, gen=g, n=n))
+    ctx.set_staging(True)
+    ctx.set_path(stt.PATH_AUTO)
+    assert torch.equal(res[0][0], res[1][0]) and key_to_host(res[0][1]) == key_to_host(res[1][1])
+    if F == 1000:
+        z_orc = orc.score_gen(orc.Map(Y, s), 12, 1, 10, D10MS, 0, n)
+        assert_close(res[0][0].cpu().numpy(), z_orc, what="dma staging")
+    # batches: folded maps of several widths against register-staged ones
+    maps = [m, stt.Map(*to_dev(*synth.noise_map(150, F, seed=F + 1)))]
+    keys = []
+    for dma in (True, False):
+        ctx.set_staging(dma)
+        keys.append(ctx.score_batch(maps, g, [20_000, 9_999]).clone())
+    ctx.set_staging(True)
+    assert torch.equal(keys[0], keys[1])
