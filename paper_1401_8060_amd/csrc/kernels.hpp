@@ -136,6 +136,47 @@ __device__ __forceinline__ float rot(uint32_t ph, float pr, float pim)
     return rot_re(ph, pr, pim);
 }
 
+// Phase constants of one template. HW path: fa + row*fb turns in FP64, exact
+// (fa, fb are 32-bit integers over 2^32; row*fb has at most 47 significant
+// bits and the sum at most 48, below FP64's 53), reduced by fract and rounded
+// once to FP32 for the hardware sine/cosine (which take turns). Polynomial
+// path: the 32-bit integer phase of rot_re.
+struct PhaseK {
+    double fa, fb;           // HW
+    uint32_t pa, pbl, pbh;   // polynomial
+};
+
+__device__ __forceinline__ PhaseK phase_k(const MapP &m, int32_t dtau)
+{
+    PhaseK k;
+    const uint32_t pa = phase_a(m.fq4_lo, dtau), pb = phase_b(m.dfq4, dtau);
+    k.fa = (double)pa * 2.3283064365386963e-10;
+    k.fb = (double)pb * 2.3283064365386963e-10;
+    k.pa = pa;
+    k.pbl = pb & 0xFFFFFFu;
+    k.pbh = pb >> 24;
+    return k;
+}
+
+// Row of the FP64 walk and the template's Eq. 8 term at that row for pixel value p.
+template <bool HW>
+__device__ __forceinline__ int32_t pixel_row(const DdaF &st, double &rd)
+{
+    rd = trunc(st.num * st.invq);
+    return (int32_t)rd;
+}
+
+template <bool HW>
+__device__ __forceinline__ float pixel_term(const PhaseK &k, double rd, int32_t row, float2 p)
+{
+    if constexpr (HW) {
+        const float x = (float)__builtin_amdgcn_fract(fma(rd, k.fb, k.fa));
+        return fmaf(__builtin_amdgcn_cosf(x), p.x, -__builtin_amdgcn_sinf(x) * p.y);
+    } else {
+        return rot_re(phase_of(k.pa, k.pbl, k.pbh, row), p.x, p.y);
+    }
+}
+
 // A fill kernel rather than a memset node, so that captured graphs replay it faithfully.
 __global__ __launch_bounds__(256) void k_fill_u32(uint32_t *p, int64_t n, uint32_t v)
 {
@@ -164,16 +205,16 @@ __global__ __launch_bounds__(kWG) void k_score_direct(MapP m, GenP g, const Trk 
         float z = __builtin_nanf("");
         if (!EXPL || track_ok(t, m)) {
             DdaF s = ddaf_init_at(t, 0);
-            const uint32_t pa = phase_a(m.fq4_lo, t.dtau), pb = phase_b(m.dfq4, t.dtau);
-            const uint32_t pbl = pb & 0xFFFFFFu, pbh = pb >> 24;
+            const PhaseK pk = phase_k(m, t.dtau);
             const int32_t N = t.t2 - t.t0 + 1;
             int64_t base = (int64_t)t.t0 * m.ld;
             double acc = 0.0;
             float part = 0.0f;
             for (int32_t k = 0; k < N; ++k) {
-                const int32_t row = ddaf_row(s);
+                double rd;
+                const int32_t row = pixel_row<HW>(s, rd);
                 const float2 p = load_p<MAPT>(m, base + row);
-                part += rot<HW>(phase_of(pa, pbl, pbh, row), p.x, p.y);
+                part += pixel_term<HW>(pk, rd, row, p);
                 if (((t.t0 + k) & (kFlush - 1)) == kFlush - 1) { acc += part; part = 0.0f; }
                 ddaf_step(s);
                 base += m.ld;
@@ -311,18 +352,18 @@ __global__ __launch_bounds__(256) void k_bin_scatter(MapP m, GenP g, const Trk *
 // template of the wave covers every column: no select and no clamp.
 template <int TPT, bool MASK, bool HW>
 __device__ __forceinline__ void walk(int ca, int cb, int c0, const float2 *slab, int ldc, const int32_t (&t0)[TPT],
-                                     const uint32_t (&span)[TPT], const uint32_t (&pa)[TPT],
-                                     const uint32_t (&pbl)[TPT], const uint32_t (&pbh)[TPT], DdaF (&st)[TPT],
+                                     const uint32_t (&span)[TPT], const PhaseK (&pk)[TPT], DdaF (&st)[TPT],
                                      float (&part)[TPT], double (&acc)[TPT])
 {
     for (int c = ca; c <= cb; ++c) {
         const float2 *col = slab + (c - c0) * ldc;
 #pragma unroll
         for (int q = 0; q < TPT; ++q) {
-            const int32_t row = ddaf_row(st[q]);
+            double rd;
+            const int32_t row = pixel_row<HW>(st[q], rd);
             const bool act = !MASK || (uint32_t)c - (uint32_t)t0[q] <= span[q];
             const float2 p = col[act ? row : 0];
-            const float v = rot<HW>(phase_of(pa[q], pbl[q], pbh[q], row), p.x, p.y);
+            const float v = pixel_term<HW>(pk[q], rd, row, p);
             part[q] += act ? v : 0.0f;
             ddaf_step(st[q]);
         }
@@ -354,7 +395,8 @@ __device__ __forceinline__ void score_block(const MapP &m, const GenP &g, const 
     const int64_t wbase = b * (WG * TPT) + (int64_t)(threadIdx.x >> 6) * (64 * TPT);
     Trk tk[TPT];
     int32_t t0[TPT];
-    uint32_t span[TPT], pa[TPT], pbl[TPT], pbh[TPT], idx[TPT];
+    uint32_t span[TPT], idx[TPT];
+    PhaseK pk[TPT];
     bool ok[TPT], live[TPT];
     int lo = 0x7fffffff, hi = -1;        // union of this wave's templates
     int clo = -1, chi = 0x7fffffff;      // intersection (the core)
@@ -369,10 +411,7 @@ __device__ __forceinline__ void score_block(const MapP &m, const GenP &g, const 
         tk[q] = t;
         t0[q] = ok[q] ? t.t0 : 0x7fffffff;
         span[q] = ok[q] ? (uint32_t)(t.t2 - t.t0) : 0u;
-        pa[q] = phase_a(m.fq4_lo, t.dtau);
-        const uint32_t pb = phase_b(m.dfq4, t.dtau);
-        pbl[q] = pb & 0xFFFFFFu;
-        pbh[q] = pb >> 24;
+        pk[q] = phase_k(m, t.dtau);
         if (ok[q]) {
             lo = min(lo, t.t0);
             hi = max(hi, t.t2);
@@ -434,9 +473,9 @@ __device__ __forceinline__ void score_block(const MapP &m, const GenP &g, const 
             const float2 *cur = slab + (size_t)(k & 1) * S * ldc;
             const int ncol = min(S, c_last - c0 + 1);
             const int ca = max(c0, lo), cb = min(c0 + ncol - 1, hi);  // this wave's columns in the slab
-            walk<TPT, true, HW>(ca, min(cb, clo - 1), c0, cur, ldc, t0, span, pa, pbl, pbh, st, part, acc);
-            walk<TPT, false, HW>(max(ca, clo), min(cb, chi), c0, cur, ldc, t0, span, pa, pbl, pbh, st, part, acc);
-            walk<TPT, true, HW>(max(ca, chi + 1), cb, c0, cur, ldc, t0, span, pa, pbl, pbh, st, part, acc);
+            walk<TPT, true, HW>(ca, min(cb, clo - 1), c0, cur, ldc, t0, span, pk, st, part, acc);
+            walk<TPT, false, HW>(max(ca, clo), min(cb, chi), c0, cur, ldc, t0, span, pk, st, part, acc);
+            walk<TPT, true, HW>(max(ca, chi + 1), cb, c0, cur, ldc, t0, span, pk, st, part, acc);
         }
     } else {
         // staging walk: element e = tid + i*WG of the slab is (column e / F, row e % F)
@@ -458,9 +497,9 @@ __device__ __forceinline__ void score_block(const MapP &m, const GenP &g, const 
             }
             __syncthreads();
             const int ca = max(c0, lo), cb = min(c0 + ncol - 1, hi);  // this wave's columns in the slab
-            walk<TPT, true, HW>(ca, min(cb, clo - 1), c0, slab, F, t0, span, pa, pbl, pbh, st, part, acc);
-            walk<TPT, false, HW>(max(ca, clo), min(cb, chi), c0, slab, F, t0, span, pa, pbl, pbh, st, part, acc);
-            walk<TPT, true, HW>(max(ca, chi + 1), cb, c0, slab, F, t0, span, pa, pbl, pbh, st, part, acc);
+            walk<TPT, true, HW>(ca, min(cb, clo - 1), c0, slab, F, t0, span, pk, st, part, acc);
+            walk<TPT, false, HW>(max(ca, clo), min(cb, chi), c0, slab, F, t0, span, pk, st, part, acc);
+            walk<TPT, true, HW>(max(ca, chi + 1), cb, c0, slab, F, t0, span, pk, st, part, acc);
         }
     }
 

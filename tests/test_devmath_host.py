@@ -144,6 +144,21 @@ def test_phase_rotation_accuracy(devmath):
     assert err.max() < 5e-7
 
 
+def test_fp64_phase_is_exact(devmath):
+    """The scorers' FP64 phase fract(fa + row*fb) (fa, fb = integers / 2^32) equals the
+    32-bit integer phase (fq4_lo + row*dfq4)*dtau mod 2^32 exactly, for any row < 2^15."""
+    sel = np.random.default_rng(21)
+    lines = []
+    for _ in range(20000):
+        fq4 = int(sel.integers(0, 2 ** 20))
+        dfq = int(sel.integers(1, 2 ** 8))
+        dtau = int(sel.integers(-(2 ** 30) + 1, 2 ** 30))
+        row = int(sel.integers(0, 2 ** 15))
+        lines.append(f"ph64 {fq4} {dfq} {dtau} {row}")
+    lines += ["ph64 1600 16 2684355 32766", "ph64 1048575 255 -1073741823 32767", "ph64 0 1 0 0"]
+    assert all(x == "1" for x in devmath(lines))
+
+
 def test_key_order_and_special_values(devmath):
     zs = [-math.inf, -3.5, -1e-30, -0.0, 0.0, 1e-30, 2.0, 2.0, math.inf, math.nan]
     js = [5, 4, 3, 2, 1, 9, 7, 6, 0, 8]
