@@ -245,7 +245,7 @@ __global__ __launch_bounds__(256) void k_argmax(const float *z, int64_t n, uint6
 
 constexpr int kBinPerThread = 32;                 // templates per thread in the sort passes
 constexpr int kBinChunk = 256 * kBinPerThread;    // templates per workgroup
-constexpr int kMaxBins = 64 * 65 / 2;             // at most 64 buckets per axis
+constexpr int kMaxBins = 128 * 129 / 2;           // at most 128 buckets per axis
 
 template <bool EXPL>
 __device__ __forceinline__ uint32_t bin_of(const GenP &g, const Trk *tr, const MapP &m, uint64_t first, int64_t i,

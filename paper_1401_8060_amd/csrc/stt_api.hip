@@ -230,11 +230,18 @@ void ev_end(stt_ctx *c)
     c->recs.push_back(r);
 }
 
-// Bucket shift so that at most 64 buckets cover T columns.
-int bucket_shift(int T)
+// Bucket width 2^wb of the time-extent sort: the narrowest that keeps at most
+// 128 buckets per axis and, on average, at least one wave's worth (256) of
+// templates per (start, end) bucket -- narrow buckets make a wave's templates
+// start and end together, so more of its columns need no mask.
+int bucket_shift(int T, int64_t n)
 {
     int wb = 0;
-    while (((T - 1) >> wb) + 1 > 64) ++wb;
+    for (;; ++wb) {
+        const int64_t nb = ((T - 1) >> wb) + 1;
+        if (nb > 128) continue;
+        if (nb <= 1 || n / (nb * (nb + 1) / 2) >= 256) break;
+    }
     return wb;
 }
 
@@ -326,7 +333,7 @@ stt_status score_impl(stt_ctx *c, const stt_map *map, const GenP &g, const Trk *
         ev_record(c, 1);
         c->used[0] = true;
     } else {
-        const int wb = bucket_shift(m.T);
+        const int wb = bucket_shift(m.T, n);
         const int nb = ((m.T - 1) >> wb) + 1;
         const int nbins = nb * (nb + 1) / 2;
         const size_t need = sizeof(uint32_t) * (2 * (size_t)kMaxBins + (size_t)n);
@@ -766,7 +773,7 @@ stt_status stt_score_batch(stt_ctx *c, const stt_map *maps_host, int32_t n_maps,
         d.n = n;
         d.order0 = norder;
         d.bin0 = (uint64_t)i * kMaxBins;
-        d.wb = bucket_shift(mp->T);
+        d.wb = bucket_shift(mp->T, n);
         const int nb = ((mp->T - 1) >> d.wb) + 1;
         d.nbins = nb * (nb + 1) / 2;
         d.S = std::min(std::min<int>(64, (c->lds_bytes - 256) / (8 * mp->F)), mp->T);
