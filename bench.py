@@ -144,6 +144,9 @@ def run_single(args, name, w):
     n = w["n"]
     px = count_px(ctx, g, w["T"], w["F"], n)
     ctx.reserve(n)
+    choice = ctx.autotune(m, g, n) if n >= 4096 else None  # slab shape and LDS budget (setup, untimed)
+    if choice:
+        log(f"bench: autotuned slab shape {choice[0]}x{choice[1]}, LDS {choice[2]} B")
     snr = None if args.no_snr else torch.empty(n, dtype=torch.float32, device=dev)
     key = torch.zeros(1, dtype=torch.int64, device=dev)
 
@@ -165,7 +168,8 @@ def run_single(args, name, w):
     out = base_record(args, name, w, n, ms_step, px, "f32")
     out["config"].update({"T": w["T"], "F": w["F"], "n_tracks": n, "min_len": w["L"], "dtau_max_s": w["dtau_s"],
                           "sigma": list(w["sigma"]) if w["sigma"] != "unit" else "unit",
-                          "injection": w["inject"] is not None, "per_track_snr": snr is not None, "map_sha256": sha[:16]})
+                          "injection": w["inject"] is not None, "per_track_snr": snr is not None, "map_sha256": sha[:16],
+                          "slab_shape": list(choice) if choice else None})
     out["best"] = {"z": zk, "j": jk}
     out["roofline"] = roofline("k_score_slab" if n >= 4096 else "k_score_direct", kern_ms, px, BYTES_F32)
     if not args.no_cpu_baseline:
