@@ -129,11 +129,12 @@ stt_status stt_set_path(stt_ctx *ctx, int32_t path, int32_t lds_bytes);
  * 1024x2, 512x2). Default 1024x4. */
 stt_status stt_set_slab_shape(stt_ctx *ctx, int32_t wg, int32_t tpt);
 
-/* Slab staging for FP32 maps: dma = 1 (default) folds p = Y/sigma into a
- * context-owned complex64 copy of the map (columns padded to 128 pixels) and
- * streams slabs into two LDS buffers with direct global-to-LDS copies,
- * overlapping the next slab with the current one; dma = 0 stages through
- * registers into one buffer, dividing on the way. Scores are identical. */
+/* Slab staging: dma = 1 (default) folds p (Y/sigma of an FP32 map, or the
+ * exact FP32 values of an FP16 map) into a context-owned complex64 copy of the
+ * map (columns padded to 128 pixels) and streams slabs into two LDS buffers
+ * with direct global-to-LDS copies, overlapping the next slab with the
+ * current one; dma = 0 stages through registers into one buffer, converting
+ * on the way. Scores are identical. */
 stt_status stt_set_staging(stt_ctx *ctx, int32_t dma);
 
 /* Phase-factor evaluation: hw = 1 (default) the hardware sine/cosine

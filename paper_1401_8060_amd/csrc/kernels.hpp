@@ -52,15 +52,17 @@ __device__ __forceinline__ float2 load_p(const MapP &m, int64_t e)
     return make_float2(y.x * w, y.y * w);
 }
 
-// p = Y/sigma of every pixel into a complex64 map with column stride ld_out
-// (pixels F..ld_out-1 of a column are zero). The same expression as load_p's,
-// so scores do not depend on whether the map was folded first.
+// p of every pixel into a complex64 map with column stride ld_out (pixels
+// F..ld_out-1 of a column are zero): Y/sigma of an FP32 map, or the exact FP32
+// value of an FP16 map's entry. The same expression as load_p's, so scores do
+// not depend on whether the map was folded first.
+template <int MAPT>
 __global__ __launch_bounds__(256) void k_fold_p(MapP m, float2 *out, int64_t ld_out)
 {
     const int64_t n = (int64_t)m.T * ld_out;
     for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < n; i += (int64_t)gridDim.x * 256) {
         const int64_t t = i / ld_out, r = i - t * ld_out;
-        out[i] = r < m.F ? load_p<kMapF32>(m, t * m.ld + r) : make_float2(0.0f, 0.0f);
+        out[i] = r < m.F ? load_p<MAPT>(m, t * m.ld + r) : make_float2(0.0f, 0.0f);
     }
 }
 

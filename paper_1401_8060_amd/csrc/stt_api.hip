@@ -354,12 +354,13 @@ stt_status score_impl(stt_ctx *c, const stt_map *map, const GenP &g, const Trk *
         ev_record(c, 3);
         c->used[1] = true;
         const int64_t ldc = fold_ld(m.F);
-        if (MAPT == kMapF32 && c->dma && dma_slab_cols(c, ldc) >= 1) {
-            // fold p = Y/sigma once, then stream slabs into LDS with double-buffered DMA
+        if (c->dma && dma_slab_cols(c, ldc) >= 1) {
+            // fold p (Y/sigma, or the FP16 entries' exact FP32 values) once, then stream slabs
+            // into LDS with double-buffered DMA
             const size_t pb = sizeof(float2) * (size_t)m.T * (size_t)ldc;
             if ((s = ensure_pbuf(c, pb)) != STT_OK) return s;
             const unsigned fg = (unsigned)std::min<int64_t>(((int64_t)m.T * ldc + 255) / 256, 4096);
-            hipLaunchKernelGGL(k_fold_p, dim3(fg), dim3(256), 0, c->stream, m, (float2 *)c->pbuf, ldc);
+            hipLaunchKernelGGL(k_fold_p<MAPT>, dim3(fg), dim3(256), 0, c->stream, m, (float2 *)c->pbuf, ldc);
             MapP mf = m;
             mf.Y = (const float2 *)c->pbuf;
             mf.sig = nullptr;
@@ -755,7 +756,7 @@ stt_status stt_score_batch(stt_ctx *c, const stt_map *maps_host, int32_t n_maps,
     const int per_item = c->slab_wg * c->slab_tpt;
     uint64_t norder = 0, nchunks = 0, nitems = 0;
     size_t shm = 0;
-    bool fold_ok = c->dma && dtype == STT_C64F32;  // every map's column fits two DMA slabs
+    bool fold_ok = c->dma;  // every map's column fits two DMA slabs
     uint64_t fold_px = 0;
     std::vector<uint64_t> fold_off(n_maps, 0);
     for (int i = 0; i < n_maps; ++i) {
@@ -779,7 +780,7 @@ stt_status stt_score_batch(stt_ctx *c, const stt_map *maps_host, int32_t n_maps,
         d.S = std::min(std::min<int>(64, (c->lds_bytes - 256) / (8 * mp->F)), mp->T);
         if (d.S < 1) return fail(c, STT_EUNSUPPORTED, "map %d: F=%d too wide for the LDS slab", i, mp->F);
         shm = std::max(shm, sizeof(float2) * (size_t)d.S * mp->F);
-        if (mp->dtype == STT_C64F32) {
+        {
             const int64_t ldc = fold_ld(mp->F);
             fold_ok = fold_ok && dma_slab_cols(c, ldc) >= 1;
             fold_off[i] = fold_px;
@@ -874,7 +875,12 @@ stt_status stt_score_batch(stt_ctx *c, const stt_map *maps_host, int32_t n_maps,
                 for (int i = 0; i < n_maps; ++i) {
                     const int64_t ldc = bm[i].m.ld;
                     const unsigned fg = (unsigned)std::min<int64_t>(((int64_t)orig[i].T * ldc + 255) / 256, 4096);
-                    hipLaunchKernelGGL(k_fold_p, dim3(fg), dim3(256), 0, st, orig[i], (float2 *)bm[i].m.Y, ldc);
+                    if (dtype == STT_P16)
+                        hipLaunchKernelGGL(k_fold_p<kMapP16>, dim3(fg), dim3(256), 0, st, orig[i], (float2 *)bm[i].m.Y,
+                                           ldc);
+                    else
+                        hipLaunchKernelGGL(k_fold_p<kMapF32>, dim3(fg), dim3(256), 0, st, orig[i], (float2 *)bm[i].m.Y,
+                                           ldc);
                 }
             hipLaunchKernelGGL(k_fill_u32, dim3((unsigned)((nb_all + 64 + 255) / 256)), dim3(256), 0, st, totals,
                                (int64_t)(nb_all), 0u);

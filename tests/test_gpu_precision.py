@@ -50,8 +50,8 @@ def test_pack_p16_bit_exact(orc, stt, ctx):
     assert np.array_equal(got.view(np.uint16), q.view(np.uint16))
 
 
-@pytest.mark.parametrize("path", [1, 2])
-def test_p16_scores_match_oracle_on_the_stored_map(orc, stt, ctx, path):
+@pytest.mark.parametrize("path,dma", [(1, True), (2, True), (2, False)])
+def test_p16_scores_match_oracle_on_the_stored_map(orc, stt, ctx, path, dma):
     """Same FP16 inputs on both sides: the GPU's FP32 accumulation vs the oracle's FP64."""
     _say("p16 scores", path)
     T, F, n = 400, 300, 20_000
@@ -61,7 +61,9 @@ def test_p16_scores_match_oracle_on_the_stored_map(orc, stt, ctx, path):
     z_orc = orc.score_gen(om, 7, 0, 10, D10MS, 0, n)
     pm = ctx.pack_p16(stt.Map(*to_dev(Y, s)))
     ctx.set_path(path)
+    ctx.set_staging(dma)
     snr, key = ctx.score(pm, gen=stt.Gen(seed=7, min_len=10, dtau_max=D10MS), n=n)
+    ctx.set_staging(True)
     ctx.set_path(0)
     assert_close(snr.cpu().numpy(), z_orc, what=f"p16 path {path}")
     assert_argmax(stt.key_decode(key_to_host(key))[1], z_orc)
