@@ -24,6 +24,8 @@ sys.path.insert(0, ROOT)
 
 METRIC = "Bézier tracks scored/sec per MI355X (track-pixels/s, % gather roofline)"
 HBM_PEAK_GBS = 8000.0
+TUNE_CACHE = os.path.join(ROOT, "paper_1401_8060_amd", "tuning", "gfx950.json")
+KERNEL_SOURCES = [os.path.join(ROOT, "paper_1401_8060_amd", "csrc", f) for f in ("kernels.hpp", "dev_common.hpp")]
 BYTES_F32 = 12  # complex64 Y + float32 sigma: the pixel record one template pixel reads
 BYTES_P16 = 4   # FP16 (re, im) of p = Y/sigma
 
@@ -113,10 +115,37 @@ def base_record(args, workload, w, n_tracks, ms_step, px, dtype):
     }
 
 
-def roofline(kernel, kernel_ms, px, bpp):
+def kernel_source_hash():
+    import hashlib
+    h = hashlib.sha256()
+    for f in KERNEL_SOURCES:
+        with open(f, "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()
+
+
+def measured_traffic(workload, shape):
+    """HBM-side bytes per launch from the committed counter summary of this workload, if it was
+    taken on the current kernel sources and the same slab shape; otherwise None."""
+    path = os.path.join(ROOT, "profiles", f"traffic_{workload}.txt")
+    if not os.path.exists(path):
+        return None
+    kv = {}
+    for line in open(path):
+        if ":" in line and not line.startswith("#"):
+            k, v = line.split(":", 1)
+            kv[k.strip()] = v.strip()
+    if kv.get("kernel_source_sha256") != kernel_source_hash():
+        return None
+    if shape is not None and kv.get("slab_shape") != "x".join(str(x) for x in shape):
+        return None
+    return float(kv["traffic_bytes_per_launch"])
+
+
+def roofline(kernel, kernel_ms, px, bpp, traffic=None):
     achieved = px * bpp / (kernel_ms * 1e-3) / 1e9
     return {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-            "frac": achieved / HBM_PEAK_GBS, "traffic": None, "kernel": kernel, "kernel_ms": kernel_ms,
+            "frac": achieved / HBM_PEAK_GBS, "traffic": traffic, "kernel": kernel, "kernel_ms": kernel_ms,
             "bytes_per_track_px": bpp}
 
 
@@ -144,7 +173,8 @@ def run_single(args, name, w):
     n = w["n"]
     px = count_px(ctx, g, w["T"], w["F"], n)
     ctx.reserve(n)
-    choice = ctx.autotune(m, g, n) if n >= 4096 else None  # slab shape and LDS budget (setup, untimed)
+    # slab shape and LDS budget from the tuning cache (searched and stored when missing; untimed setup)
+    choice = ctx.autotune(m, g, n, args.tune_cache) if n >= 4096 else None
     if choice:
         log(f"bench: autotuned slab shape {choice[0]}x{choice[1]}, LDS {choice[2]} B")
     snr = None if args.no_snr else torch.empty(n, dtype=torch.float32, device=dev)
@@ -171,7 +201,8 @@ def run_single(args, name, w):
                           "injection": w["inject"] is not None, "per_track_snr": snr is not None, "map_sha256": sha[:16],
                           "slab_shape": list(choice) if choice else None})
     out["best"] = {"z": zk, "j": jk}
-    out["roofline"] = roofline("k_score_slab" if n >= 4096 else "k_score_direct", kern_ms, px, BYTES_F32)
+    out["roofline"] = roofline("k_score_slab" if n >= 4096 else "k_score_direct", kern_ms, px, BYTES_F32,
+                               measured_traffic(name, choice))
     if not args.no_cpu_baseline:
         log("bench: timing the CPU oracle on a sample")
         out["cpu_baseline"] = cpu_baseline(w, Y, s, dtau_max)
@@ -200,7 +231,7 @@ def run_batch(args, name, w):
     px = sum(count_px(ctx, stt.Gen(seed=g.seed, stream=k, min_len=g.min_len, dtau_max=g.dtau_max), T, w["F"], w["n"])
              for k, T in enumerate(Ts))
     med = maps[int(np.argsort(Ts)[len(Ts) // 2])]
-    choice = ctx.autotune(med, g, w["n"])
+    choice = ctx.autotune(med, g, w["n"], args.tune_cache)
     log(f"bench: autotuned slab shape {choice[0]}x{choice[1]}, LDS {choice[2]} B")
     fp16 = args.map_dtype == "p16"
     smaps = [ctx.pack_p16(m) for m in maps] if fp16 else maps
@@ -226,7 +257,8 @@ def run_batch(args, name, w):
     out["config"].update({"n_maps": len(maps), "T_range": [w["T_lo"], w["T_hi"]], "F": w["F"],
                           "tracks_per_map": w["n"], "map_dtype": args.map_dtype, "graph": True,
                           "slab_shape": list(choice)})
-    out["roofline"] = roofline("k_score_batch", kern_ms, px, BYTES_P16 if fp16 else BYTES_F32)
+    out["roofline"] = roofline("k_score_batch", kern_ms, px, BYTES_P16 if fp16 else BYTES_F32,
+                               measured_traffic(name + ("_p16" if fp16 else ""), choice))
     if fp16:
         # error of FP16 storage against plain FP32 scoring of the same maps, on two maps in full
         errs = []
@@ -256,6 +288,8 @@ def run_precision(args, name, w):
     n, K = w["n"], w["K"]
     px = count_px(ctx, g, w["T"], w["F"], n)
     ctx.reserve(n)
+    choice = ctx.autotune(pm, g, n, args.tune_cache)
+    log(f"bench: autotuned slab shape {choice[0]}x{choice[1]}, LDS {choice[2]} B")
     snr = torch.empty(n, dtype=torch.float32, device=dev)
     res = {}
 
@@ -275,8 +309,8 @@ def run_precision(args, name, w):
     log(f"bench: {ms_step:.3f} ms/step, FP16 scoring kernel {kern_ms:.3f} ms; top-{K} |dz| max {err.max().item():.2e}")
     out = base_record(args, name, w, n, ms_step, px, "f16")
     out["config"].update({"T": w["T"], "F": w["F"], "n_tracks": n, "map_dtype": "p16", "scale_exp": pm.scale_exp,
-                          "top_k": K, "rescore": "f64", "map_sha256": sha[:16]})
-    out["roofline"] = roofline("k_score_slab", kern_ms, px, BYTES_P16)
+                          "top_k": K, "rescore": "f64", "map_sha256": sha[:16], "slab_shape": list(choice)})
+    out["roofline"] = roofline("k_score_slab", kern_ms, px, BYTES_P16, measured_traffic(name, choice))
     out["topk_fp16_vs_fp64"] = {"max_abs_dz": err.max().item(), "mean_abs_dz": err.mean().item()}
     out["best"] = {"z64": res["z64"][best].item(), "j": int(res["idx"][best].item())}
     ctx.close()
@@ -309,6 +343,8 @@ def run_refine(args, name, w):
     g = stt.Gen(seed=w["seed"], stream=0, min_len=w["L"], dtau_max=dtau_max)
     n, K = w["n"], w["K"]
     px = count_px(ctx, g, T, F, n)
+    choice = ctx.autotune(m, g, n, args.tune_cache)
+    log(f"bench: autotuned slab shape {choice[0]}x{choice[1]}, LDS {choice[2]} B")
     snr = torch.empty(n, dtype=torch.float32, device=dev)
     res = {}
 
@@ -344,12 +380,14 @@ def main():
     ap.add_argument("--map-dtype", default="f32", choices=["f32", "p16"], help="batch workload map storage")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-snr", action="store_true", help="reduce to the argmax only (no per-track output)")
+    ap.add_argument("--tune-cache", default=TUNE_CACHE,
+                    help="autotuner cache (JSON); a missing entry is searched on the GPU and stored")
     ap.add_argument("--copy-probe-mb", type=int, default=0,
                     help="after the run, copy this many MiB device-to-device (a known-size kernel for counter scaling)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for {args.gpus}); the search shards by template range "
-              "or by map with no communication but a max, which this build leaves out.", file=sys.stderr)
+              "or by map with no communication but a max, which is not implemented here.", file=sys.stderr)
         sys.exit(2)
     w = WORKLOADS[args.workload]
     runner = {"single": run_single, "batch": run_batch, "precision": run_precision, "refine": run_refine}[w["kind"]]
