@@ -188,15 +188,18 @@ STT_HD void dda_step(Dda &s)
     s.dq = (int32_t)((uint32_t)s.dq + (uint32_t)s.ddq + (c2 ? 1u : 0u));
 }
 
-// The same walk in FP64, for the scorers' inner loops. With num'(k) =
-// num(k) + 1/2 (an integer plus a half, |num'| < 2^52, so exact in FP64) the
-// two adds per step are exact, and row = trunc(num' * (1/Q)) is the exact
-// floor for every valid k: num/Q is at least 1/Q away from the next integer
-// above and 1/(2Q) >= 2^-32 exceeds the product's error of at most 2^-37
-// (relative 2^-52 on a value below 2^15). Rows of invalid k (k < 0 or k > Dt)
-// are meaningless and must be masked by the caller.
+// The same walk in FP64, for the scorers' inner loops. It carries the
+// centred numerator c(k) = num(k) - Q/2 + 1/2 (Q = 256 Dt^2 is even, so c is
+// an integer plus a half, |c| < 2^52: exact in FP64, and the two adds per step
+// are exact). Write num = a*Q + b with 0 <= b < Q < 2^31: c/Q = a - 1/2 +
+// (b + 1/2)/Q lies inside (a - 1/2, a + 1/2), at least 1/(2Q) > 2^-32 from
+// either end, while the product with the rounded 1/Q is off by at most 2^-37
+// (relative 2^-52 on a value below 2^15). So one FMA, fma(c, 1/Q, 3*2^51),
+// rounds to exactly 3*2^51 + a, an integer on the unit grid of [2^52, 2^53)
+// whose low 32 bits are the row a = floor(num/Q). Rows of invalid k (k < 0 or
+// k > Dt) are meaningless and must be masked by the caller.
 struct DdaF {
-    double num;   // num(k) + 1/2
+    double num;   // c(k) = num(k) - Q/2 + 1/2
     double del;   // num(k+1) - num(k)
     double dd;    // 2C
     double invq;  // 1/Q rounded to nearest
@@ -211,14 +214,20 @@ STT_HD DdaF ddaf_init_at(const Trk &t, int32_t k0)
     const int64_t C = (int64_t)t.f0 - 2 * (int64_t)t.f1 + (int64_t)t.f2;
     const int64_t B = 2 * Dt * ((int64_t)t.f1 - (int64_t)t.f0);
     const int64_t k = k0;
-    s.num = (double)(A + B * k + C * k * k) + 0.5;
+    s.num = (double)(A + B * k + C * k * k - (Q >> 1)) + 0.5;
     s.del = (double)(B + C * (2 * k + 1));
     s.dd = (double)(2 * C);
     s.invq = 1.0 / (double)Q;
     return s;
 }
 
-STT_HD int32_t ddaf_row(const DdaF &s) { return (int32_t)(s.num * s.invq); }
+STT_HD int32_t ddaf_row(const DdaF &s)
+{
+    const double y = fma(s.num, s.invq, 6755399441055744.0);  // 3 * 2^51
+    uint64_t u;
+    __builtin_memcpy(&u, &y, sizeof u);
+    return (int32_t)(uint32_t)u;
+}
 
 STT_HD void ddaf_step(DdaF &s)
 {
@@ -233,6 +242,13 @@ STT_HD void ddaf_step(DdaF &s)
 // ----------------------------------------------------------------------------
 STT_HD uint32_t phase_a(int32_t fq4_lo, int32_t dtau) { return (uint32_t)fq4_lo * (uint32_t)dtau; }
 STT_HD uint32_t phase_b(int32_t dfq4, int32_t dtau) { return (uint32_t)dfq4 * (uint32_t)dtau; }
+
+// The phase of row `row` as FP32 turns in [-1/2, 1/2]: the exact 32-bit phase,
+// read as signed and rounded once (at most 2^-26 turn off).
+STT_HD float phase_turns(uint32_t pa, uint32_t pb, int32_t row)
+{
+    return (float)(int32_t)(pa + (uint32_t)row * pb) * 2.3283064365386963e-10f;
+}
 
 // Re[exp(2 pi i ph/2^32) (pr + i pi)]. The half-turn bit h = [ph in [1/4,3/4)
 // turn] is split off exactly in integers, leaving |angle| <= pi/2 where the

@@ -115,67 +115,32 @@ __device__ __forceinline__ float finish(double S, int32_t N, int32_t norm)
     return (float)(norm == 1 ? S / (double)N : S / sqrt((double)N));
 }
 
-// Phase of row r for a template: pa + r*pb (mod 2^32), with the multiply split
-// into 24-bit pieces (r < 2^24 for every valid row) so that it maps onto the
-// full-rate 24-bit multiplies: r*pb = r*(pb mod 2^24) + (r*(pb >> 24)) << 24.
-__device__ __forceinline__ uint32_t phase_of(uint32_t pa, uint32_t pbl, uint32_t pbh, int32_t row)
-{
-    const uint32_t r = (uint32_t)row;
-    return (__umul24(r, pbl) + pa) + ((uint32_t)__umul24(r, pbh) << 24);
-}
-
-// Re[exp(2 pi i ph/2^32) p]. HW = false: the polynomial of rot_re (about
-// 1.5e-7 absolute). HW = true: the hardware sine and cosine, which take their
-// argument in turns; measured on gfx950 over 2^22 phases spanning a turn:
-// at most 1.25e-7 absolute error, rms 3.5e-8, no bias.
-template <bool HW>
-__device__ __forceinline__ float rot(uint32_t ph, float pr, float pim)
-{
-    if (HW) {
-        const float x = (float)(int32_t)ph * 2.3283064365386963e-10f;  // turns in [-1/2, 1/2)
-        return fmaf(__builtin_amdgcn_cosf(x), pr, -__builtin_amdgcn_sinf(x) * pim);
-    }
-    return rot_re(ph, pr, pim);
-}
-
-// Phase constants of one template. HW path: fa + row*fb turns in FP64, exact
-// (fa, fb are 32-bit integers over 2^32; row*fb has at most 47 significant
-// bits and the sum at most 48, below FP64's 53), reduced by fract and rounded
-// once to FP32 for the hardware sine/cosine (which take turns). Polynomial
-// path: the 32-bit integer phase of rot_re.
+// Phase constants of one template: its Eq. 8 phase at row r is pa + r*pb in
+// units of 2^-32 turn, exact with 32-bit wrap-around.
 struct PhaseK {
-    double fa, fb;           // HW
-    uint32_t pa, pbl, pbh;   // polynomial
+    uint32_t pa, pb;
 };
 
 __device__ __forceinline__ PhaseK phase_k(const MapP &m, int32_t dtau)
 {
-    PhaseK k;
-    const uint32_t pa = phase_a(m.fq4_lo, dtau), pb = phase_b(m.dfq4, dtau);
-    k.fa = (double)pa * 2.3283064365386963e-10;
-    k.fb = (double)pb * 2.3283064365386963e-10;
-    k.pa = pa;
-    k.pbl = pb & 0xFFFFFFu;
-    k.pbh = pb >> 24;
-    return k;
+    return PhaseK{phase_a(m.fq4_lo, dtau), phase_b(m.dfq4, dtau)};
 }
 
-// Row of the FP64 walk and the template's Eq. 8 term at that row for pixel value p.
+// part + Re[exp(2 pi i phase(row)) p], the template's Eq. 8 term at this row.
+// HW: the exact 32-bit phase rounded once to FP32 turns (phase_turns) feeds
+// the hardware sine and cosine, which take turns; measured on gfx950 over 2^22
+// phases spanning a turn: at most 1.25e-7 absolute error, rms 3.5e-8, no bias.
+// The two products are added to the running sum by fused multiply-adds.
+// HW = false: the polynomial of rot_re (about 1.5e-7 absolute).
 template <bool HW>
-__device__ __forceinline__ int32_t pixel_row(const DdaF &st, double &rd)
-{
-    rd = trunc(st.num * st.invq);
-    return (int32_t)rd;
-}
-
-template <bool HW>
-__device__ __forceinline__ float pixel_term(const PhaseK &k, double rd, int32_t row, float2 p)
+__device__ __forceinline__ float add_term(float part, const PhaseK &k, int32_t row, float2 p)
 {
     if constexpr (HW) {
-        const float x = (float)__builtin_amdgcn_fract(fma(rd, k.fb, k.fa));
-        return fmaf(__builtin_amdgcn_cosf(x), p.x, -__builtin_amdgcn_sinf(x) * p.y);
+        const float x = phase_turns(k.pa, k.pb, row);
+        part = fmaf(__builtin_amdgcn_cosf(x), p.x, part);
+        return fmaf(-__builtin_amdgcn_sinf(x), p.y, part);
     } else {
-        return rot_re(phase_of(k.pa, k.pbl, k.pbh, row), p.x, p.y);
+        return part + rot_re(k.pa + (uint32_t)row * k.pb, p.x, p.y);
     }
 }
 
@@ -213,10 +178,9 @@ __global__ __launch_bounds__(kWG) void k_score_direct(MapP m, GenP g, const Trk 
             double acc = 0.0;
             float part = 0.0f;
             for (int32_t k = 0; k < N; ++k) {
-                double rd;
-                const int32_t row = pixel_row<HW>(s, rd);
+                const int32_t row = ddaf_row(s);
                 const float2 p = load_p<MAPT>(m, base + row);
-                part += pixel_term<HW>(pk, rd, row, p);
+                part = add_term<HW>(part, pk, row, p);
                 if (((t.t0 + k) & (kFlush - 1)) == kFlush - 1) { acc += part; part = 0.0f; }
                 ddaf_step(s);
                 base += m.ld;
@@ -357,19 +321,25 @@ __device__ __forceinline__ void walk(int ca, int cb, int c0, const float2 *slab,
                                      const uint32_t (&span)[TPT], const PhaseK (&pk)[TPT], DdaF (&st)[TPT],
                                      float (&part)[TPT], double (&acc)[TPT])
 {
-    for (int c = ca; c <= cb; ++c) {
-        const float2 *col = slab + (c - c0) * ldc;
+    // segments end at the flush columns (c = 15 mod 16), so the inner loop has no flush test
+    for (int c = ca; c <= cb;) {
+        const int ce = min(cb, c | (kFlush - 1));
+        for (; c <= ce; ++c) {
+            const float2 *col = slab + (c - c0) * ldc;
 #pragma unroll
-        for (int q = 0; q < TPT; ++q) {
-            double rd;
-            const int32_t row = pixel_row<HW>(st[q], rd);
-            const bool act = !MASK || (uint32_t)c - (uint32_t)t0[q] <= span[q];
-            const float2 p = col[act ? row : 0];
-            const float v = pixel_term<HW>(pk[q], rd, row, p);
-            part[q] += act ? v : 0.0f;
-            ddaf_step(st[q]);
+            for (int q = 0; q < TPT; ++q) {
+                const int32_t row = ddaf_row(st[q]);
+                if (MASK) {
+                    const bool act = (uint32_t)c - (uint32_t)t0[q] <= span[q];
+                    const float v = add_term<HW>(part[q], pk[q], row, col[act ? row : 0]);
+                    part[q] = act ? v : part[q];
+                } else {
+                    part[q] = add_term<HW>(part[q], pk[q], row, col[row]);
+                }
+                ddaf_step(st[q]);
+            }
         }
-        if ((c & (kFlush - 1)) == kFlush - 1) {  // wave-uniform
+        if ((ce & (kFlush - 1)) == kFlush - 1) {  // wave-uniform
 #pragma unroll
             for (int q = 0; q < TPT; ++q) {
                 acc[q] += part[q];
@@ -452,19 +422,19 @@ __device__ __forceinline__ void score_block(const MapP &m, const GenP &g, const 
     const int F = m.F;
 
     if (MAPT == kMapPF) {
-        // m.ld is a multiple of kDmaPix; a column is m.ld / kDmaPix pieces of 1 KB
+        // m.ld is a multiple of kDmaPix and the columns are contiguous, so the
+        // slab of columns c0.. is one run of pieces of kDmaPix pixels (1 KB),
+        // piece ch at pixel offset ch * kDmaPix in the map and in the buffer.
         const int ldc = (int)m.ld, per_col = ldc / kDmaPix;
         const int wave = threadIdx.x >> 6;
         auto issue = [&](int c0, int bsel) {
             const int nchunk = min(S, c_last - c0 + 1) * per_col;
+            const float2 *src = m.Y + (int64_t)c0 * ldc + lane * 2;
             float2 *dst = slab + (size_t)bsel * S * ldc;
-            for (int ch = wave; ch < nchunk; ch += WG / 64) {
-                const int col = ch / per_col, off = (ch - col * per_col) * kDmaPix;
-                const float2 *src = m.Y + (int64_t)(c0 + col) * ldc + off + lane * 2;
-                __builtin_amdgcn_global_load_lds((const void *)src,
-                                                 (__attribute__((address_space(3))) void *)(dst + col * ldc + off), 16,
+            for (int ch = wave; ch < nchunk; ch += WG / 64)
+                __builtin_amdgcn_global_load_lds((const void *)(src + ch * kDmaPix),
+                                                 (__attribute__((address_space(3))) void *)(dst + ch * kDmaPix), 16,
                                                  0, 0);
-            }
         };
         if (c_first <= c_last) issue(c_first, 0);
         int k = 0;

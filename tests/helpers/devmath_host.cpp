@@ -7,7 +7,7 @@
 //   rowsat t0 t2 f0 f1 f2 k0           -> N rows, DDA started at k0 <= 0 and stepped to 0
 //   rowsf t0 t2 f0 f1 f2 k0            -> N rows of the FP64 walk started at k0 <= 0
 //   rot   ph pr pi                     -> Re[exp(2 pi i ph/2^32)(pr + i pi)] as %.9e
-//   ph64  fq4_lo dfq4 dtau row         -> 1 if the FP64 phase fract(fa + row fb) is the exact integer phase
+//   phx   fq4_lo dfq4 dtau row         -> the scorers' phase argument (FP32 turns in [-1/2, 1/2])
 //   key   z j                          -> 64-bit key (hex)
 #include <cmath>
 #include <cstdio>
@@ -84,15 +84,10 @@ int main()
             float pr, pi;
             if (std::scanf("%u %f %f", &ph, &pr, &pi) != 3) return 2;
             std::printf("%.9e\n", (double)rot_re(ph, pr, pi));
-        } else if (!std::strcmp(cmd, "ph64")) {  // FP64 phase of the scorers vs the 32-bit integer phase
+        } else if (!std::strcmp(cmd, "phx")) {  // the scorers' FP32 phase argument, in turns
             int fq4_lo, dfq4, dtau, row;
             if (std::scanf("%d %d %d %d", &fq4_lo, &dfq4, &dtau, &row) != 4) return 2;
-            const uint32_t pa = phase_a(fq4_lo, dtau), pb = phase_b(dfq4, dtau);
-            const double fa = (double)pa * 2.3283064365386963e-10, fb = (double)pb * 2.3283064365386963e-10;
-            const double y = fma((double)row, fb, fa);
-            const double fr = y - floor(y);
-            const uint32_t exact = pa + (uint32_t)row * pb;
-            std::printf("%d\n", fr * 4294967296.0 == (double)exact ? 1 : 0);
+            std::printf("%.9e\n", (double)phase_turns(phase_a(fq4_lo, dtau), phase_b(dfq4, dtau), row));
         } else if (!std::strcmp(cmd, "key")) {
             float z;
             unsigned j;

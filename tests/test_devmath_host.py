@@ -13,6 +13,8 @@ import shutil
 import struct
 import subprocess
 
+from fractions import Fraction
+
 import numpy as np
 import pytest
 
@@ -144,19 +146,23 @@ def test_phase_rotation_accuracy(devmath):
     assert err.max() < 5e-7
 
 
-def test_fp64_phase_is_exact(devmath):
-    """The scorers' FP64 phase fract(fa + row*fb) (fa, fb = integers / 2^32) equals the
-    32-bit integer phase (fq4_lo + row*dfq4)*dtau mod 2^32 exactly, for any row < 2^15."""
+def test_phase_argument(devmath):
+    """The scorers' sine/cosine argument is the Eq. 8 phase f*dtau in turns, f = (fq4_lo + row*dfq4)/16 Hz
+    and dtau in 2^-28 s, reduced to [-1/2, 1/2] and rounded once to FP32: within 2^-26 turn of the exact
+    value (mod 1), checked against rational arithmetic."""
     sel = np.random.default_rng(21)
-    lines = []
+    cases = []
     for _ in range(20000):
-        fq4 = int(sel.integers(0, 2 ** 20))
-        dfq = int(sel.integers(1, 2 ** 8))
-        dtau = int(sel.integers(-(2 ** 30) + 1, 2 ** 30))
-        row = int(sel.integers(0, 2 ** 15))
-        lines.append(f"ph64 {fq4} {dfq} {dtau} {row}")
-    lines += ["ph64 1600 16 2684355 32766", "ph64 1048575 255 -1073741823 32767", "ph64 0 1 0 0"]
-    assert all(x == "1" for x in devmath(lines))
+        cases.append((int(sel.integers(0, 2 ** 20)), int(sel.integers(1, 2 ** 8)),
+                      int(sel.integers(-(2 ** 30) + 1, 2 ** 30)), int(sel.integers(0, 2 ** 15))))
+    cases += [(1600, 16, 2684355, 32766), (1048575, 255, -1073741823, 32767), (0, 1, 0, 0), (1600, 16, 1 << 27, 1)]
+    got = devmath([f"phx {a} {b} {c} {d}" for a, b, c, d in cases])
+    for (fq4, dfq, dtau, row), g in zip(cases, got):
+        exact = Fraction((fq4 + row * dfq) * dtau, 2 ** 32)  # (fq4/16 Hz)(dtau 2^-28 s) turns
+        err = (Fraction(float(np.float32(g))) - exact) % 1  # the printed FP32 value, read back exactly
+        err = min(err, 1 - err)
+        assert err <= Fraction(1, 2 ** 26), (fq4, dfq, dtau, row, g)
+        assert -0.5 <= float(g) <= 0.5
 
 
 def test_key_order_and_special_values(devmath):
