@@ -10,9 +10,11 @@
 //                   into LDS and every lane gathers its templates' pixels there
 //   k_score_direct  one lane per template, pixels gathered straight from the
 //                   map in global memory (small calls, very wide maps)
+//   k_reduce_keys   max of the slab scorer's per-workgroup best keys
 //   k_argmax        max/argmax of an existing score array
-// Reductions use the packed 64-bit key (score bits, ~index): wave shuffles,
-// then one 64-bit atomic max per wave, so results do not depend on scheduling.
+// Reductions use the packed 64-bit key (score bits, ~index), so results do not
+// depend on scheduling: wave shuffles, then across the workgroup through LDS
+// (slab scorers) or one 64-bit atomic max per wave (small kernels).
 #pragma once
 
 #include <hip/hip_fp16.h>
@@ -90,18 +92,20 @@ __device__ __forceinline__ uint64_t wave_max_u64(uint64_t v)
     return v;
 }
 
+// Wave-wide min/max, returned as a wave-uniform (scalar) value so that loop
+// bounds and addresses derived from it stay off the vector ALU.
 __device__ __forceinline__ int wave_min_i32(int v)
 {
 #pragma unroll
     for (int off = 32; off > 0; off >>= 1) v = min(v, __shfl_xor(v, off));
-    return v;
+    return __builtin_amdgcn_readfirstlane(v);
 }
 
 __device__ __forceinline__ int wave_max_i32(int v)
 {
 #pragma unroll
     for (int off = 32; off > 0; off >>= 1) v = max(v, __shfl_xor(v, off));
-    return v;
+    return __builtin_amdgcn_readfirstlane(v);
 }
 
 __device__ __forceinline__ void merge_key(uint64_t *best, uint64_t key)
@@ -356,9 +360,9 @@ __device__ __forceinline__ void walk(int ca, int cb, int c0, const float2 *slab,
 // slab k+1 streams in while slab k is walked); the other formats stage through
 // registers into one buffer, converting on the way.
 template <int WG, int TPT, bool EXPL, bool HW, int MAPT>
-__device__ __forceinline__ void score_block(const MapP &m, const GenP &g, const Trk *tr, const uint32_t *order,
-                                            uint64_t first, int64_t n, int64_t b, int S, int32_t norm, float *snr,
-                                            uint64_t *best, float2 *slab, int *bnd)
+__device__ __forceinline__ uint64_t score_block(const MapP &m, const GenP &g, const Trk *tr, const uint32_t *order,
+                                                uint64_t first, int64_t n, int64_t b, int S, int32_t norm, float *snr,
+                                                float2 *slab, int *bnd, uint64_t *kred)
 {
     __syncthreads();  // LDS of a previous block is no longer read
     if (threadIdx.x == 0) { bnd[0] = 0x7fffffff; bnd[1] = -1; }
@@ -418,7 +422,7 @@ __device__ __forceinline__ void score_block(const MapP &m, const GenP &g, const 
         atomicMax(&bnd[1], hi);
     }
     __syncthreads();
-    const int c_first = bnd[0], c_last = bnd[1];
+    const int c_first = __builtin_amdgcn_readfirstlane(bnd[0]), c_last = __builtin_amdgcn_readfirstlane(bnd[1]);
     const int F = m.F;
 
     if (MAPT == kMapPF) {
@@ -426,7 +430,7 @@ __device__ __forceinline__ void score_block(const MapP &m, const GenP &g, const 
         // slab of columns c0.. is one run of pieces of kDmaPix pixels (1 KB),
         // piece ch at pixel offset ch * kDmaPix in the map and in the buffer.
         const int ldc = (int)m.ld, per_col = ldc / kDmaPix;
-        const int wave = threadIdx.x >> 6;
+        const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
         auto issue = [&](int c0, int bsel) {
             const int nchunk = min(S, c_last - c0 + 1) * per_col;
             const float2 *src = m.Y + (int64_t)c0 * ldc + lane * 2;
@@ -484,18 +488,44 @@ __device__ __forceinline__ void score_block(const MapP &m, const GenP &g, const 
         const uint64_t k = key_encode(z, (uint32_t)(first + idx[q]));
         key = k > key ? k : key;
     }
-    merge_key(best, key);
+    // the block's best key: waves by shuffles, then across waves through LDS
+    key = wave_max_u64(key);
+    if (lane == 0) kred[threadIdx.x >> 6] = key;
+    __syncthreads();
+    if (threadIdx.x == 0)
+        for (int w = 1; w < WG / 64; ++w) key = kred[w] > key ? kred[w] : key;
+    return key;  // valid in thread 0
 }
 
+// One block of binned templates per workgroup. Each workgroup stores its best
+// key in its own slot of wg_keys (no atomics: many same-address atomics from
+// every wave serialise across the chip); k_reduce_keys folds the slots.
 template <int WG, int TPT, bool EXPL, bool HW, int MAPT>
 __global__ __launch_bounds__(WG) void k_score_slab(MapP m, GenP g, const Trk *tr, const uint32_t *order,
                                                    uint64_t first, int64_t n, int S, int32_t norm, float *snr,
-                                                   uint64_t *best)
+                                                   uint64_t *wg_keys)
 {
     extern __shared__ float2 slab[];
     __shared__ int bnd[2];
-    score_block<WG, TPT, EXPL, HW, MAPT>(m, g, tr, order, first, n, (int64_t)blockIdx.x, S, norm, snr, best, slab,
-                                         bnd);
+    __shared__ uint64_t kred[WG / 64];
+    const uint64_t key = score_block<WG, TPT, EXPL, HW, MAPT>(m, g, tr, order, first, n, (int64_t)blockIdx.x, S,
+                                                              norm, snr, slab, bnd, kred);
+    if (threadIdx.x == 0) wg_keys[blockIdx.x] = key;
+}
+
+// Max of n keys into *best (max-merged with what it holds), in one workgroup.
+__global__ __launch_bounds__(1024) void k_reduce_keys(const uint64_t *keys, int64_t n, uint64_t *best)
+{
+    __shared__ uint64_t kred[16];
+    uint64_t key = 0;
+    for (int64_t i = threadIdx.x; i < n; i += 1024) key = keys[i] > key ? keys[i] : key;
+    key = wave_max_u64(key);
+    if ((threadIdx.x & 63) == 0) kred[threadIdx.x >> 6] = key;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        for (int w = 1; w < 16; ++w) key = kred[w] > key ? kred[w] : key;
+        if (key) atomicMax((unsigned long long *)best, (unsigned long long)key);
+    }
 }
 
 // ---------------------------------------------------------------- batches of maps
@@ -608,6 +638,7 @@ __global__ __launch_bounds__(WG) void k_score_batch(const BatchMap *maps, int n_
 {
     extern __shared__ float2 slab[];
     __shared__ int bnd[2];
+    __shared__ uint64_t kred[WG / 64];
     __shared__ uint32_t item_s;
     const uint32_t total = item_start[n_maps];
     for (;;) {
@@ -618,9 +649,11 @@ __global__ __launch_bounds__(WG) void k_score_batch(const BatchMap *maps, int n_
         if (item >= total) break;  // every workgroup reaches this: the queue only grows
         const int mi = find_map(item_start, n_maps, item);
         const BatchMap d = maps[mi];
-        score_block<WG, TPT, false, HW, MAPT>(d.m, d.g, nullptr, order + d.order0, 0, d.n,
-                                              (int64_t)(item - item_start[mi]), d.S, norm, d.snr, best + mi, slab,
-                                              bnd);
+        const uint64_t key = score_block<WG, TPT, false, HW, MAPT>(d.m, d.g, nullptr, order + d.order0, 0, d.n,
+                                                                   (int64_t)(item - item_start[mi]), d.S, norm,
+                                                                   d.snr, slab, bnd, kred);
+        // one atomic per item, spread over the maps' keys
+        if (threadIdx.x == 0 && key) atomicMax((unsigned long long *)(best + mi), (unsigned long long)key);
     }
 }
 

@@ -247,14 +247,14 @@ int bucket_shift(int T, int64_t n)
 
 template <int WG, int TPT, bool EXPL, bool HW, int MAPT>
 stt_status launch_slab_t(stt_ctx *c, const MapP &m, const GenP &g, const Trk *tr, const uint32_t *order,
-                         int64_t first, int64_t n, int S, size_t shm, int32_t norm, float *snr, uint64_t *best)
+                         int64_t first, int64_t n, int S, size_t shm, int32_t norm, float *snr, uint64_t *wg_keys)
 {
     auto kern = k_score_slab<WG, TPT, EXPL, HW, MAPT>;
     if (shm > 64 * 1024)
         STT_HIP(c, hipFuncSetAttribute((const void *)kern, hipFuncAttributeMaxDynamicSharedMemorySize, (int)shm));
     const unsigned grid = (unsigned)((n + WG * TPT - 1) / (WG * TPT));
     hipLaunchKernelGGL(kern, dim3(grid), dim3(WG), shm, c->stream, m, g, tr, order, (uint64_t)first, n, S, norm, snr,
-                       best);
+                       wg_keys);
     STT_HIP(c, hipGetLastError());
     return STT_OK;
 }
@@ -265,11 +265,11 @@ static const int kShapes[][2] = {{1024, 4}, {512, 4}, {256, 4}, {1024, 2}, {512,
 template <bool EXPL, bool HW, int MAPT>
 stt_status launch_slab_h(stt_ctx *c, int wg, int tpt, const MapP &m, const GenP &g, const Trk *tr,
                          const uint32_t *order, int64_t first, int64_t n, int S, size_t shm, int32_t norm, float *snr,
-                         uint64_t *best)
+                         uint64_t *wg_keys)
 {
 #define STT_SLAB_CASE(W, P)                                                                                 \
     if (wg == W && tpt == P)                                                                                \
-        return launch_slab_t<W, P, EXPL, HW, MAPT>(c, m, g, tr, order, first, n, S, shm, norm, snr, best);
+        return launch_slab_t<W, P, EXPL, HW, MAPT>(c, m, g, tr, order, first, n, S, shm, norm, snr, wg_keys);
     STT_SLAB_CASE(1024, 4)
     STT_SLAB_CASE(512, 4)
     STT_SLAB_CASE(256, 4)
@@ -282,11 +282,11 @@ stt_status launch_slab_h(stt_ctx *c, int wg, int tpt, const MapP &m, const GenP 
 template <bool EXPL, int MAPT>
 stt_status launch_slab(stt_ctx *c, int wg, int tpt, const MapP &m, const GenP &g, const Trk *tr,
                        const uint32_t *order, int64_t first, int64_t n, int S, size_t shm, int32_t norm, float *snr,
-                       uint64_t *best)
+                       uint64_t *wg_keys)
 {
     if (c->hw_trig)
-        return launch_slab_h<EXPL, true, MAPT>(c, wg, tpt, m, g, tr, order, first, n, S, shm, norm, snr, best);
-    return launch_slab_h<EXPL, false, MAPT>(c, wg, tpt, m, g, tr, order, first, n, S, shm, norm, snr, best);
+        return launch_slab_h<EXPL, true, MAPT>(c, wg, tpt, m, g, tr, order, first, n, S, shm, norm, snr, wg_keys);
+    return launch_slab_h<EXPL, false, MAPT>(c, wg, tpt, m, g, tr, order, first, n, S, shm, norm, snr, wg_keys);
 }
 
 template <bool EXPL, bool HW, int MAPT>
@@ -296,6 +296,15 @@ void launch_direct(stt_ctx *c, const MapP &m, const GenP &g, const Trk *tr, int6
     const unsigned grid = (unsigned)((n + kWG - 1) / kWG);
     hipLaunchKernelGGL((k_score_direct<EXPL, HW, MAPT>), dim3(grid), dim3(kWG), 0, c->stream, m, g, tr,
                        (uint64_t)first, n, norm, snr, best);
+}
+
+// Scratch of a scoring call of n templates: bucket totals and cursors, the
+// binned order (padded to an even count), then one best-key slot per scorer
+// workgroup (each takes at least 1024 templates, whatever the shape).
+size_t score_scratch_bytes(int64_t n)
+{
+    const size_t n_order = ((size_t)n + 1) & ~(size_t)1;
+    return sizeof(uint32_t) * (2 * (size_t)kMaxBins + n_order) + sizeof(uint64_t) * (size_t)((n + 1023) / 1024);
 }
 
 bool slab_shape_ok(int wg, int tpt)
@@ -336,12 +345,13 @@ stt_status score_impl(stt_ctx *c, const stt_map *map, const GenP &g, const Trk *
         const int wb = bucket_shift(m.T, n);
         const int nb = ((m.T - 1) >> wb) + 1;
         const int nbins = nb * (nb + 1) / 2;
-        const size_t need = sizeof(uint32_t) * (2 * (size_t)kMaxBins + (size_t)n);
-        stt_status s = ensure_scratch(c, need);
+        const size_t n_order = ((size_t)n + 1) & ~(size_t)1;  // keeps the key slots 8-byte aligned
+        stt_status s = ensure_scratch(c, score_scratch_bytes(n));
         if (s != STT_OK) return s;
         uint32_t *totals = (uint32_t *)c->scratch;
         uint32_t *cursor = totals + kMaxBins;
         uint32_t *order = cursor + kMaxBins;
+        uint64_t *wg_keys = (uint64_t *)(order + n_order);
         const unsigned bgrid = (unsigned)((n + kBinChunk - 1) / kBinChunk);
         ev_record(c, 2);
         hipLaunchKernelGGL(k_fill_u32, dim3((nbins + 255) / 256), dim3(256), 0, c->stream, totals, nbins, 0u);
@@ -369,17 +379,22 @@ stt_status score_impl(stt_ctx *c, const stt_map *map, const GenP &g, const Trk *
             const size_t shm = 2 * sizeof(float2) * (size_t)S * ldc;
             ev_record(c, 0);
             s = launch_slab<EXPL, kMapPF>(c, c->slab_wg, c->slab_tpt, mf, g, tr, order, first, n, S, shm, norm, snr,
-                                          best);
+                                          wg_keys);
         } else {
             const int S = std::min(slab_cols, m.T);
             const size_t shm = sizeof(float2) * (size_t)S * m.F;
             ev_record(c, 0);
             s = launch_slab<EXPL, MAPT>(c, c->slab_wg, c->slab_tpt, m, g, tr, order, first, n, S, shm, norm, snr,
-                                        best);
+                                        wg_keys);
         }
         if (s != STT_OK) return s;
         ev_record(c, 1);
         c->used[0] = true;
+        if (best) {
+            const int64_t n_wg = (n + (int64_t)c->slab_wg * c->slab_tpt - 1) / ((int64_t)c->slab_wg * c->slab_tpt);
+            hipLaunchKernelGGL(k_reduce_keys, dim3(1), dim3(1024), 0, c->stream, (const uint64_t *)wg_keys, n_wg, best);
+            STT_HIP(c, hipGetLastError());
+        }
     }
     ev_record(c, 5);
     c->used[2] = true;
@@ -455,7 +470,7 @@ stt_status stt_sync(stt_ctx *c)
 stt_status stt_reserve(stt_ctx *c, int64_t max_tracks)
 {
     if (!c || max_tracks < 0) return fail(c, STT_EINVAL, "bad reserve request");
-    return ensure_scratch(c, sizeof(uint32_t) * (2 * (size_t)kMaxBins + (size_t)max_tracks));
+    return ensure_scratch(c, score_scratch_bytes(max_tracks));
 }
 
 stt_status stt_set_timing(stt_ctx *c, int32_t on)
