@@ -230,11 +230,10 @@ def run_batch(args, name, w):
     ns = [w["n"]] * len(maps)
     px = sum(count_px(ctx, stt.Gen(seed=g.seed, stream=k, min_len=g.min_len, dtau_max=g.dtau_max), T, w["F"], w["n"])
              for k, T in enumerate(Ts))
-    med = maps[int(np.argsort(Ts)[len(Ts) // 2])]
-    choice = ctx.autotune(med, g, w["n"], args.tune_cache)
-    log(f"bench: autotuned slab shape {choice[0]}x{choice[1]}, LDS {choice[2]} B")
     fp16 = args.map_dtype == "p16"
     smaps = [ctx.pack_p16(m) for m in maps] if fp16 else maps
+    choice = ctx.autotune_batch(smaps, g, ns, args.tune_cache)
+    log(f"bench: autotuned slab shape {choice[0]}x{choice[1]}, LDS {choice[2]} B")
     keys = torch.zeros(len(maps), dtype=torch.int64, device=dev)
 
     def step():

@@ -228,6 +228,17 @@ stt_status stt_set_graph(stt_ctx *ctx, int32_t on);
 stt_status stt_autotune(stt_ctx *ctx, const stt_map *map, const stt_gen *gen, int64_t n, const char *cache_path,
                         int32_t *choice_out);
 
+/* Autotuner of the batch scorer: the same search, timing the persistent batch
+ * launch of stt_score_batch itself on these maps (direct launches, one warm-up
+ * and two timed batches per candidate, kernel time only), since the best shape
+ * of a queue of many uneven maps differs from a single map's. Arguments as in
+ * stt_score_batch; cache key (GPU architecture, "batch", largest F, dtype,
+ * power-of-two buckets of the longest T, of n_maps and of the total template
+ * count, trig mode). Uses a temporary device buffer of n_maps keys. Applies and
+ * returns the choice as stt_autotune does. Synchronises. */
+stt_status stt_autotune_batch(stt_ctx *ctx, const stt_map *maps_host, int32_t n_maps, const stt_gen *gen,
+                              const int64_t *n_trk_host, const char *cache_path, int32_t *choice_out);
+
 /* ---- differentiation (an addition; the paper scores only pixel sets) ----
  * theta_dev: [n][6] float32 per template, (tau0, tau2, phi0, phi1, phi2,
  * dtau_ms): start and end time in columns, control frequencies in rows

@@ -7,6 +7,7 @@
 #include <cmath>
 #include <cstdio>
 #include <cstring>
+#include <functional>
 #include <string>
 #include <vector>
 
@@ -1128,21 +1129,104 @@ struct TuneChoice {
     double ms;
 };
 
-std::string tune_key(const stt_ctx *c, const stt_map *m, int64_t n)
+std::string gpu_arch(const stt_ctx *c)
 {
     hipDeviceProp_t prop;
     std::string arch = "gpu";
     if (hipGetDeviceProperties(&prop, c->device) == hipSuccess) arch = prop.gcnArchName;
-    const std::string a = arch.substr(0, arch.find(':'));
-    // maps of similar duration (power-of-two bucket) and call size share a choice
-    int tb = 0;
-    while ((1 << (tb + 1)) <= m->T) ++tb;
-    int nb = 0;
-    while (((int64_t)1 << (nb + 1)) <= n) ++nb;
+    return arch.substr(0, arch.find(':'));
+}
+
+int log2_floor(int64_t v)
+{
+    int b = 0;
+    while (((int64_t)1 << (b + 1)) <= v) ++b;
+    return b;
+}
+
+// maps of similar duration (power-of-two bucket) and call size share a choice
+std::string tune_key(const stt_ctx *c, const stt_map *m, int64_t n)
+{
     char buf[160];
-    snprintf(buf, sizeof buf, "%s/F=%d/dtype=%d/T=2^%d/n=2^%d/trig=%d", a.c_str(), m->F, m->dtype, tb, nb,
-             c->hw_trig ? 1 : 0);
+    snprintf(buf, sizeof buf, "%s/F=%d/dtype=%d/T=2^%d/n=2^%d/trig=%d", gpu_arch(c).c_str(), m->F, m->dtype,
+             log2_floor(m->T), log2_floor(n), c->hw_trig ? 1 : 0);
     return buf;
+}
+
+std::string tune_key_batch(const stt_ctx *c, int F, int dtype, int T, int n_maps, int64_t n_total)
+{
+    char buf[192];
+    snprintf(buf, sizeof buf, "%s/batch/F=%d/dtype=%d/T=2^%d/maps=2^%d/n=2^%d/trig=%d", gpu_arch(c).c_str(), F, dtype,
+             log2_floor(T), log2_floor(n_maps), log2_floor(n_total), c->hw_trig ? 1 : 0);
+    return buf;
+}
+
+// Times `call` (which must leave a timed scoring stage) for every compiled
+// shape and LDS budget that fits columns of F pixels: `reps` timed runs after
+// one warm-up, mean of the scoring kernel's HIP-event time. The context's
+// shape, budget, timing and graph settings and the caller's pending timing
+// records are restored afterwards.
+stt_status tune_search(stt_ctx *c, int F, int reps, const std::function<stt_status()> &call, TuneChoice &best)
+{
+    const int old_path = c->path, old_wg = c->slab_wg, old_tpt = c->slab_tpt, old_lds = c->lds_bytes;
+    const bool old_timing = c->timing, old_graph = c->use_graph;
+    std::vector<Rec> saved;
+    saved.swap(c->recs);
+    const size_t saved_next = c->next;
+    c->timing = true;
+    c->use_graph = false;
+    c->recs.clear();
+    c->next = saved_next;  // tuning events come after any the caller has not read yet
+    static const int ldss[] = {160 * 1024, 112 * 1024, 80 * 1024, 48 * 1024};
+    stt_status s = STT_OK;
+    for (const auto &sh : kShapes) {
+        for (int lds : ldss) {
+            if ((lds - 256) / (8 * F) < 1) continue;
+            c->path = 2;
+            c->slab_wg = sh[0];
+            c->slab_tpt = sh[1];
+            c->lds_bytes = lds;
+            double tot = 0;
+            int cnt = 0;
+            for (int rep = 0; rep <= reps && s == STT_OK; ++rep) {
+                if ((s = call()) != STT_OK) break;
+                float ms = 0;
+                if ((s = stt_kernel_ms(c, 0, &ms)) != STT_OK) break;
+                if (rep > 0) { tot += ms; ++cnt; }  // the first run warms up
+            }
+            c->recs.clear();
+            c->next = saved_next;
+            if (s != STT_OK) break;
+            if (cnt && tot / cnt < best.ms) best = TuneChoice{sh[0], sh[1], lds, tot / cnt};
+        }
+        if (s != STT_OK) break;
+    }
+    c->path = old_path;
+    c->slab_wg = old_wg;
+    c->slab_tpt = old_tpt;
+    c->lds_bytes = old_lds;
+    c->timing = old_timing;
+    c->use_graph = old_graph;
+    c->recs.swap(saved);
+    c->next = saved_next;
+    if (s != STT_OK) return s;
+    if (best.wg == 0) return fail(c, STT_EUNSUPPORTED, "no slab configuration fits F=%d", F);
+    return STT_OK;
+}
+
+stt_status apply_choice(stt_ctx *c, const std::string &key, const TuneChoice &best, int32_t *choice_out)
+{
+    if (!slab_shape_ok(best.wg, best.tpt) || best.lds < 1024 || best.lds > 160 * 1024)
+        return fail(c, STT_EINVAL, "cache entry for %s is not a valid configuration", key.c_str());
+    c->slab_wg = best.wg;
+    c->slab_tpt = best.tpt;
+    c->lds_bytes = best.lds;
+    if (choice_out) {
+        choice_out[0] = best.wg;
+        choice_out[1] = best.tpt;
+        choice_out[2] = best.lds;
+    }
+    return STT_OK;
 }
 
 // The cache file holds one line per key:  "<key>": {"wg": W, "tpt": P, "lds": B, "ms": T}
@@ -1213,58 +1297,49 @@ stt_status stt_autotune(stt_ctx *c, const stt_map *map, const stt_gen *gen, int6
     const std::string key = tune_key(c, map, n);
     TuneChoice best{0, 0, 0, 1e30};
     if (!cache_lookup(cache_path, key, best)) {
-        const int old_path = c->path, old_wg = c->slab_wg, old_tpt = c->slab_tpt, old_lds = c->lds_bytes;
-        const bool old_timing = c->timing;
-        std::vector<Rec> saved;
-        saved.swap(c->recs);
-        const size_t saved_next = c->next;
-        c->timing = true;
-        c->recs.clear();
-        c->next = saved_next;  // tuning events come after any the caller has not read yet
-        static const int ldss[] = {160 * 1024, 112 * 1024, 80 * 1024, 48 * 1024};
-        for (const auto &sh : kShapes)
-            for (int lds : ldss) {
-                if ((lds - 256) / (8 * map->F) < 1) continue;
-                c->path = 2;
-                c->slab_wg = sh[0];
-                c->slab_tpt = sh[1];
-                c->lds_bytes = lds;
-                double tot = 0;
-                int cnt = 0;
-                for (int rep = 0; rep < 4 && s == STT_OK; ++rep) {
-                    s = stt_score(c, map, gen, nullptr, 0, n, STT_NORM_SQRT_N, nullptr, nullptr);
-                    if (s != STT_OK) break;
-                    float ms = 0;
-                    if ((s = stt_kernel_ms(c, 0, &ms)) != STT_OK) break;
-                    if (rep > 0) { tot += ms; ++cnt; }  // the first run warms up
-                }
-                c->recs.clear();
-                c->next = saved_next;
-                if (s != STT_OK) break;
-                if (cnt && tot / cnt < best.ms) best = TuneChoice{sh[0], sh[1], lds, tot / cnt};
-            }
-        c->path = old_path;
-        c->slab_wg = old_wg;
-        c->slab_tpt = old_tpt;
-        c->lds_bytes = old_lds;
-        c->timing = old_timing;
-        c->recs.swap(saved);
-        c->next = saved_next;
+        s = tune_search(c, map->F, 3, [&] { return stt_score(c, map, gen, nullptr, 0, n, STT_NORM_SQRT_N, nullptr, nullptr); },
+                        best);
         if (s != STT_OK) return s;
-        if (best.wg == 0) return fail(c, STT_EUNSUPPORTED, "no slab configuration fits F=%d", map->F);
         cache_store(cache_path, key, best);
     }
-    if (!slab_shape_ok(best.wg, best.tpt) || best.lds < 1024 || best.lds > 160 * 1024)
-        return fail(c, STT_EINVAL, "cache entry for %s is not a valid configuration", key.c_str());
-    c->slab_wg = best.wg;
-    c->slab_tpt = best.tpt;
-    c->lds_bytes = best.lds;
-    if (choice_out) {
-        choice_out[0] = best.wg;
-        choice_out[1] = best.tpt;
-        choice_out[2] = best.lds;
+    return apply_choice(c, key, best, choice_out);
+}
+
+stt_status stt_autotune_batch(stt_ctx *c, const stt_map *maps_host, int32_t n_maps, const stt_gen *gen,
+                              const int64_t *n_trk_host, const char *cache_path, int32_t *choice_out)
+{
+    if (!c) return STT_EINVAL;
+    if (n_maps < 1 || n_maps > 65536) return fail(c, STT_ERANGE, "n_maps=%d outside [1, 65536]", n_maps);
+    if (!maps_host || !gen || !n_trk_host) return fail(c, STT_EINVAL, "maps, gen and n_trk must be non-NULL");
+    int Fmax = 0, Tmax = 0;
+    int64_t ntot = 0;
+    for (int i = 0; i < n_maps; ++i) {
+        stt_status s = check_map(c, &maps_host[i]);
+        if (s != STT_OK) return s;
+        if (n_trk_host[i] < 0) return fail(c, STT_ERANGE, "n_trk[%d] < 0", i);
+        Fmax = std::max(Fmax, maps_host[i].F);
+        Tmax = std::max(Tmax, maps_host[i].T);
+        ntot += n_trk_host[i];
     }
-    return STT_OK;
+    if (ntot < 1) return fail(c, STT_ERANGE, "no templates to time");
+    const std::string key = tune_key_batch(c, Fmax, maps_host[0].dtype, Tmax, n_maps, ntot);
+    TuneChoice best{0, 0, 0, 1e30};
+    if (!cache_lookup(cache_path, key, best)) {
+        void *keys = nullptr;
+        STT_HIP(c, hipSetDevice(c->device));
+        if (hipMalloc(&keys, sizeof(uint64_t) * (size_t)n_maps) != hipSuccess) {
+            (void)hipGetLastError();
+            return fail(c, STT_ENOMEM, "cannot allocate the tuner's %d keys", n_maps);
+        }
+        stt_status s = tune_search(c, Fmax, 2, [&] {
+            return stt_score_batch(c, maps_host, n_maps, gen, n_trk_host, STT_NORM_SQRT_N, (uint64_t *)keys, nullptr);
+        }, best);
+        (void)hipStreamSynchronize(c->stream);
+        (void)hipFree(keys);
+        if (s != STT_OK) return s;
+        cache_store(cache_path, key, best);
+    }
+    return apply_choice(c, key, best, choice_out);
 }
 
 uint64_t stt_key_encode(float z, uint32_t j) { return key_encode(z, j); }

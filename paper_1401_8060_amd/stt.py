@@ -335,6 +335,19 @@ class Context:
                                        cache_path.encode() if cache_path else None, out))
         return out[0], out[1], out[2]
 
+    def autotune_batch(self, maps, gen: Gen, n_trk, cache_path: str | None = None) -> tuple[int, int, int]:
+        """Pick (and apply) the fastest slab shape and LDS budget for this batch of maps (as score_batch)."""
+        nm = len(maps)
+        if nm < 1 or len(n_trk) != nm:
+            raise ValueError("one template count per map, at least one map")
+        out = (C.c_int32 * 3)()
+        arr = (_Map * nm)(*[m.c() for m in maps])
+        ns = (C.c_int64 * nm)(*[int(x) for x in n_trk])
+        g = gen.c()
+        self._chk(self._L.stt_autotune_batch(self.h, arr, nm, C.byref(g), ns,
+                                             cache_path.encode() if cache_path else None, out))
+        return out[0], out[1], out[2]
+
     # -- differentiation
     def tracks_at(self, gen: Gen, T: int, F: int, idx: torch.Tensor) -> torch.Tensor:
         """Templates at the given indices (int64 tensor), as an [n][6] int32 tensor."""

@@ -162,3 +162,27 @@ def test_autotune_applies_and_caches(stt, ctx, tmp_path):
     assert key_to_host(k_tuned) == key_to_host(k_def)
     import torch
     assert torch.equal(z_tuned, z_def)
+
+
+def test_autotune_batch_applies_and_caches(stt, ctx, tmp_path):
+    _say("autotune_batch")
+    maps = []
+    for k, T in enumerate((300, 520, 410)):
+        Y, s = synth.noise_map(T, 200, seed=60 + k, sigma=("loguniform", 0.5, 2.0))
+        maps.append(stt.Map(*to_dev(Y, s)))
+    g = stt.Gen(seed=3, min_len=10, dtau_max=D10MS)
+    ns = [30_000, 50_000, 40_000]
+    cache = str(tmp_path / "tune.json")
+    choice = ctx.autotune_batch(maps, g, ns, cache)
+    assert choice[0] in (256, 512, 1024) and choice[1] in (2, 4) and 1024 <= choice[2] <= 160 * 1024
+    text = open(cache).read()
+    assert "/batch/F=200/" in text and f'"wg": {choice[0]}' in text
+    assert ctx.autotune_batch(maps, g, ns, cache) == choice
+    # the tuned batch gives the keys of per-map scoring with the default shape
+    keys = ctx.score_batch(maps, g, ns)
+    ctx.set_slab_shape(1024, 4)
+    ctx.set_path(0, 160 * 1024)
+    for k, m in enumerate(maps):
+        gk = stt.Gen(seed=g.seed, stream=g.stream + k, min_len=g.min_len, dtau_max=g.dtau_max)
+        _, kk = ctx.score(m, gen=gk, n=ns[k])
+        assert key_to_host(kk) == int(keys[k].item()) & (2 ** 64 - 1)
