@@ -304,6 +304,21 @@ __global__ __launch_bounds__(256) void k_bin_scatter(MapP m, GenP g, const Trk *
     }
 }
 
+// One LDS-DMA copy of 16 bytes per lane: lane i's 16 bytes at src land at
+// lds_dst + 16 i (lds_dst wave-uniform). Written as inline assembly so that the
+// compiler does not tie it to the LDS reads of the other slab buffer: its
+// wait-count pass cannot tell the two buffers apart and would stall each
+// wave's first read of a slab until its prefetch of the next slab had landed.
+// The caller waits for the copies itself (a full s_waitcnt and a barrier
+// before a buffer is read). A copy the compiler does not count can only make
+// its own memory waits stricter (vector memory counters drain in order).
+__device__ __forceinline__ void lds_dma_16(const float2 *src, float2 *lds_dst)
+{
+    const uint32_t m0 = __builtin_amdgcn_readfirstlane(
+        (uint32_t)(uintptr_t)(__attribute__((address_space(3))) float2 *)lds_dst);
+    asm volatile("s_mov_b32 m0, %1\n\tglobal_load_lds_dwordx4 %0, off" : : "v"(src), "s"(m0) : "memory", "m0");
+}
+
 // ---------------------------------------------------------------- time-slab scorer
 // One workgroup = WG lanes x TPT templates taken consecutively from the binned
 // order; wave w owns the 64*TPT consecutive entries starting at w*64*TPT, so a
@@ -436,9 +451,7 @@ __device__ __forceinline__ uint64_t score_block(const MapP &m, const GenP &g, co
             const float2 *src = m.Y + (int64_t)c0 * ldc + lane * 2;
             float2 *dst = slab + (size_t)bsel * S * ldc;
             for (int ch = wave; ch < nchunk; ch += WG / 64)
-                __builtin_amdgcn_global_load_lds((const void *)(src + ch * kDmaPix),
-                                                 (__attribute__((address_space(3))) void *)(dst + ch * kDmaPix), 16,
-                                                 0, 0);
+                lds_dma_16(src + ch * kDmaPix, dst + ch * kDmaPix);
         };
         if (c_first <= c_last) issue(c_first, 0);
         int k = 0;
