@@ -118,10 +118,14 @@ stt_status stt_set_timing(stt_ctx *ctx, int32_t on);
 stt_status stt_kernel_ms(stt_ctx *ctx, int32_t which, float *ms);
 stt_status stt_kernel_ms_total(stt_ctx *ctx, int32_t which, double *total_ms, int32_t *count);
 
-/* Scorer selection, for tests and tuning: path 0 = automatic, 1 = direct
- * gathers from global memory, 2 = LDS time slabs (STT_EUNSUPPORTED when one
- * column of the map does not fit lds_bytes). lds_bytes (0 = keep) is the slab
- * budget per workgroup, in [1024, 163840]; default 163840. */
+/* Scorer selection, for tests and tuning: path 0 = automatic (LDS time slabs
+ * from 4096 templates on when a column fits; otherwise one wave per template
+ * below 65536 templates, else one lane per template), 1 = one lane per
+ * template, direct gathers from global memory, 2 = LDS time slabs
+ * (STT_EUNSUPPORTED when one column of the map does not fit lds_bytes), 3 =
+ * one wave per template, direct gathers. All paths give bit-identical scores.
+ * lds_bytes (0 = keep) is the slab budget per workgroup, in [1024, 163840];
+ * default 163840. */
 stt_status stt_set_path(stt_ctx *ctx, int32_t path, int32_t lds_bytes);
 
 /* Shape of the LDS-slab scorer: wg lanes per workgroup and tpt templates per

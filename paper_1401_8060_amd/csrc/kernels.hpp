@@ -197,6 +197,67 @@ __global__ __launch_bounds__(kWG) void k_score_direct(MapP m, GenP g, const Trk 
     merge_key(best, key);
 }
 
+// One wave per template, for calls too small to fill the chip with one lane
+// per template. The template's columns fall into flush groups of kFlush
+// aligned columns; lane l takes groups l, l + 64, ... and computes each
+// group's FP32 partial with the same operations, in the same order, as the
+// sequential walk of k_score_direct. The FP64 sum over groups then runs in
+// column order (read lane by lane), so the score is bit-identical to the other
+// scorers'. Four waves (templates) per workgroup.
+constexpr int kWaveGroups = (STT_MAX_T + kFlush - 1) / kFlush + 1;  // groups a template can touch
+constexpr int kWaveRounds = (kWaveGroups + 63) / 64;
+
+template <bool EXPL, bool HW, int MAPT>
+__global__ __launch_bounds__(256) void k_score_wave(MapP m, GenP g, const Trk *tr, uint64_t first, int64_t n,
+                                                    int32_t norm, float *snr, uint64_t *best)
+{
+    const int lane = threadIdx.x & 63;
+    const int64_t i = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);  // wave-uniform
+    uint64_t key = 0;
+    if (i < n) {
+        const Trk t = EXPL ? tr[i] : draw_track(g, first + (uint64_t)i);
+        float z = __builtin_nanf("");
+        if (!EXPL || track_ok(t, m)) {
+            const PhaseK pk = phase_k(m, t.dtau);
+            const int gfirst = t.t0 / kFlush, glast = t.t2 / kFlush;
+            float gp[kWaveRounds];
+#pragma unroll
+            for (int r = 0; r < kWaveRounds; ++r) {
+                gp[r] = 0.0f;
+                const int gi = gfirst + r * 64 + lane;
+                if (gi > glast) continue;
+                const int ca = max(t.t0, gi * kFlush), cb = min(t.t2, gi * kFlush + kFlush - 1);
+                DdaF s = ddaf_init_at(t, ca - t.t0);
+                int64_t base = (int64_t)ca * m.ld;
+                float part = 0.0f;
+                for (int c = ca; c <= cb; ++c) {
+                    const int32_t row = ddaf_row(s);
+                    part = add_term<HW>(part, pk, row, load_p<MAPT>(m, base + row));
+                    ddaf_step(s);
+                    base += m.ld;
+                }
+                gp[r] = part;
+            }
+            // The sequential walk adds each group's partial to acc, in order: at the group's flush
+            // column, or (the last group, when t2 is not a flush column) as finish(acc + part);
+            // a flushed last group leaves part = 0 for that final addition.
+            const int ng = glast - gfirst + 1;
+            double acc = 0.0;
+#pragma unroll
+            for (int r = 0; r < kWaveRounds; ++r) {
+                const int cnt = min(64, ng - r * 64);
+                for (int l = 0; l < cnt; ++l)
+                    acc += __builtin_bit_cast(float, __builtin_amdgcn_readlane(__builtin_bit_cast(int, gp[r]), l));
+            }
+            if ((t.t2 & (kFlush - 1)) == kFlush - 1) acc = acc + 0.0f;
+            z = finish(acc, t.t2 - t.t0 + 1, norm);
+        }
+        if (lane == 0 && snr) snr[i] = z;
+        key = key_encode(z, (uint32_t)(first + (uint64_t)i));
+    }
+    merge_key(best, key);
+}
+
 // ---------------------------------------------------------------- argmax of an array
 
 __global__ __launch_bounds__(256) void k_argmax(const float *z, int64_t n, uint64_t first, uint64_t *best)
@@ -872,19 +933,25 @@ __device__ __forceinline__ void smooth_node(const MapP &m, int64_t t, int64_t r,
     gd = -6.283185307179586f * (float)f_hz * (s * p.x + c * p.y);
 }
 
+// One workgroup of kSmoothWG lanes per template (lanes over the K samples):
+// the bilinear gathers miss L2, so several waves per template keep more of
+// them in flight than one wave could.
+constexpr int kSmoothWG = 256;
+
 template <int MAPT>
-__global__ __launch_bounds__(256) void k_smooth_grad(MapP m, const float *theta, const int32_t *Ks, int32_t n,
-                                                     float *z_out, float *grad_out)
+__global__ __launch_bounds__(kSmoothWG) void k_smooth_grad(MapP m, const float *theta, const int32_t *Ks, int32_t n,
+                                                           float *z_out, float *grad_out)
 {
-    const int w = (int)(((int64_t)blockIdx.x * 256 + threadIdx.x) >> 6);
+    __shared__ double red[kSmoothWG / 64][7];
+    const int w = blockIdx.x;
     const int lane = threadIdx.x & 63;
-    if (w >= n) return;
+    if (w >= n) return;  // whole workgroup
     const float *th = theta + (int64_t)w * 6;
     const double tau0 = th[0], tau2 = th[1], ph0 = th[2], ph1 = th[3], ph2 = th[4];
     const double dtau_s = (double)th[5] * 1e-3;
     const int K = Ks[w];
     double z = 0, g0 = 0, g1 = 0, g2 = 0, g3 = 0, g4 = 0, g5 = 0;
-    for (int k = lane; k < K; k += 64) {
+    for (int k = threadIdx.x; k < K; k += kSmoothWG) {
         const double xi = K > 1 ? (double)k / (double)(K - 1) : 0.0;
         const double b0 = (1 - xi) * (1 - xi), b1 = 2 * xi * (1 - xi), b2 = xi * xi;
         const double u0 = tau0 + xi * (tau2 - tau0), v0 = b0 * ph0 + b1 * ph1 + b2 * ph2 - 0.5;
@@ -921,6 +988,15 @@ __global__ __launch_bounds__(256) void k_smooth_grad(MapP m, const float *theta,
         g5 += __shfl_xor(g5, off);
     }
     if (lane == 0) {
+        double *r = red[threadIdx.x >> 6];
+        r[0] = z, r[1] = g0, r[2] = g1, r[3] = g2, r[4] = g3, r[5] = g4, r[6] = g5;
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        for (int v = 1; v < kSmoothWG / 64; ++v) {
+            z += red[v][0], g0 += red[v][1], g1 += red[v][2], g2 += red[v][3];
+            g3 += red[v][4], g4 += red[v][5], g5 += red[v][6];
+        }
         const double sc = K > 0 ? 1.0 / sqrt((double)K) : 0.0;
         z_out[w] = (float)(z * sc);
         if (grad_out) {

@@ -291,9 +291,14 @@ stt_status launch_slab(stt_ctx *c, int wg, int tpt, const MapP &m, const GenP &g
 }
 
 template <bool EXPL, bool HW, int MAPT>
-void launch_direct(stt_ctx *c, const MapP &m, const GenP &g, const Trk *tr, int64_t first, int64_t n, int32_t norm,
-                   float *snr, uint64_t *best)
+void launch_direct(stt_ctx *c, bool per_wave, const MapP &m, const GenP &g, const Trk *tr, int64_t first, int64_t n,
+                   int32_t norm, float *snr, uint64_t *best)
 {
+    if (per_wave) {
+        hipLaunchKernelGGL((k_score_wave<EXPL, HW, MAPT>), dim3((unsigned)((n + 3) / 4)), dim3(256), 0, c->stream, m,
+                           g, tr, (uint64_t)first, n, norm, snr, best);
+        return;
+    }
     const unsigned grid = (unsigned)((n + kWG - 1) / kWG);
     hipLaunchKernelGGL((k_score_direct<EXPL, HW, MAPT>), dim3(grid), dim3(kWG), 0, c->stream, m, g, tr,
                        (uint64_t)first, n, norm, snr, best);
@@ -323,8 +328,10 @@ stt_status score_impl(stt_ctx *c, const stt_map *map, const GenP &g, const Trk *
     // the slab plus the kernel's few static LDS words must fit the 160 KB of a CU
     const int slab_cols = std::min<int>(64, (c->lds_bytes - 256) / (8 * m.F));
     bool slab = slab_cols >= 1;
-    if (c->path == 1) slab = false;
+    if (c->path == 1 || c->path == 3) slab = false;
     if (c->path == 0 && n < 4096) slab = false;
+    // without slabs: one wave per template for calls too small to fill the chip lane by lane
+    const bool per_wave = c->path == 3 || (c->path == 0 && n < 65536);
     if (c->path == 2 && !slab)
         return fail(c, STT_EUNSUPPORTED, "F=%d too wide for an LDS slab of %d bytes", m.F, c->lds_bytes);
 
@@ -336,9 +343,9 @@ stt_status score_impl(stt_ctx *c, const stt_map *map, const GenP &g, const Trk *
     if (!slab) {
         ev_record(c, 0);
         if (c->hw_trig)
-            launch_direct<EXPL, true, MAPT>(c, m, g, tr, first, n, norm, snr, best);
+            launch_direct<EXPL, true, MAPT>(c, per_wave, m, g, tr, first, n, norm, snr, best);
         else
-            launch_direct<EXPL, false, MAPT>(c, m, g, tr, first, n, norm, snr, best);
+            launch_direct<EXPL, false, MAPT>(c, per_wave, m, g, tr, first, n, norm, snr, best);
         STT_HIP(c, hipGetLastError());
         ev_record(c, 1);
         c->used[0] = true;
@@ -521,7 +528,7 @@ stt_status stt_kernel_ms_total(stt_ctx *c, int32_t which, double *total_ms, int3
 // Internal knob used by tests and tuning: 0 auto, 1 direct gathers, 2 LDS slabs.
 stt_status stt_set_path(stt_ctx *c, int32_t path, int32_t lds_bytes)
 {
-    if (!c || path < 0 || path > 2) return STT_EINVAL;
+    if (!c || path < 0 || path > 3) return STT_EINVAL;
     if (lds_bytes != 0 && (lds_bytes < 1024 || lds_bytes > 160 * 1024))
         return fail(c, STT_ERANGE, "lds_bytes=%d outside [1024, 163840]", lds_bytes);
     c->path = path;
@@ -1007,11 +1014,11 @@ stt_status smooth_launch(stt_ctx *c, const stt_map *map, const float *theta, con
                          float *grad, hipStream_t st)
 {
     const MapP m = to_mapp(map);
-    const unsigned grid = (unsigned)(((int64_t)n * 64 + 255) / 256);
+    const unsigned grid = (unsigned)n;  // one workgroup per template
     if (map->dtype == STT_P16)
-        hipLaunchKernelGGL(k_smooth_grad<kMapP16>, dim3(grid), dim3(256), 0, st, m, theta, K, n, z, grad);
+        hipLaunchKernelGGL(k_smooth_grad<kMapP16>, dim3(grid), dim3(kSmoothWG), 0, st, m, theta, K, n, z, grad);
     else
-        hipLaunchKernelGGL(k_smooth_grad<kMapF32>, dim3(grid), dim3(256), 0, st, m, theta, K, n, z, grad);
+        hipLaunchKernelGGL(k_smooth_grad<kMapF32>, dim3(grid), dim3(kSmoothWG), 0, st, m, theta, K, n, z, grad);
     STT_HIP(c, hipGetLastError());
     return STT_OK;
 }
@@ -1109,7 +1116,7 @@ stt_status stt_refine(stt_ctx *c, const stt_map *map, int32_t min_len, int32_t d
         STT_HIP(c, hipGetLastError());
         if (z_plain_dev) {
             const int old = c->path;
-            c->path = 1;  // a short explicit list: direct gathers
+            c->path = 0;  // automatic: a short explicit list takes one wave per template
             s = stt_score(c, map, nullptr, plain_dev, 0, n, norm, z_plain_dev, nullptr);
             c->path = old;
             if (s != STT_OK) return s;

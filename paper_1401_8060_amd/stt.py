@@ -22,7 +22,7 @@ C64F32, C16 = 0, 1  # map element formats: (complex64 Y, float32 sigma) / FP16 p
 FBITS = 8
 MAX_T, MAX_F = 2896, 32767
 DTAU_UNIT_S = 2.0 ** -28
-PATH_AUTO, PATH_DIRECT, PATH_SLAB = 0, 1, 2
+PATH_AUTO, PATH_DIRECT, PATH_SLAB, PATH_WAVE = 0, 1, 2, 3
 STAGE_SCORE, STAGE_BIN, STAGE_CALL = 0, 1, 2
 
 

@@ -44,7 +44,7 @@ def _gen(stt, seed=1, stream=0, L=10, D=D10MS):
 
 def _score_both(ctx, stt, m, **kw):
     out = {}
-    for path in (stt.PATH_DIRECT, stt.PATH_SLAB):
+    for path in (stt.PATH_DIRECT, stt.PATH_SLAB, stt.PATH_WAVE):
         ctx.set_path(path)
         snr, key = ctx.score(m, **kw)
         out[path] = (snr.cpu().numpy().astype(np.float64), key_to_host(key))
@@ -84,8 +84,9 @@ def test_config1_plain_map_full(orc, stt, ctx):
         assert_argmax(jk, z_orc)
         assert zk == np.float32(z[jk])
     res = list(_score_both(ctx, stt, m, gen=_gen(stt), n=n).values())
-    # both scorers walk each template in the same order with the same partial-sum grid
-    assert np.array_equal(res[0][0], res[1][0]) and res[0][1] == res[1][1]
+    # every scorer walks each template in the same order with the same partial-sum grid
+    for other in res[1:]:
+        assert np.array_equal(res[0][0], other[0]) and res[0][1] == other[1]
 
 
 def test_norm_n_is_mean(orc, stt, ctx):
@@ -156,7 +157,7 @@ def test_explicit_tracks_and_invalid_ones(orc, stt, ctx):
     z_orc = orc.score_list(orc.Map(Y, s), allt)
     assert np.isnan(z_orc[-len(bad):]).all()
     dev = torch.from_numpy(allt.view(np.int32).reshape(-1, 6).copy()).cuda()
-    for path in (stt.PATH_DIRECT, stt.PATH_SLAB):
+    for path in (stt.PATH_DIRECT, stt.PATH_SLAB, stt.PATH_WAVE):
         ctx.set_path(path)
         snr, key = ctx.score(m, tracks=dev, first=100)
         assert_close(snr.cpu().numpy(), z_orc, what=f"explicit path {path}")
@@ -293,7 +294,7 @@ def test_brute_force_tiny_map(orc, stt, ctx):
     z_orc = orc.score_list(orc.Map(Y, s), tr)
     m = stt.Map(*to_dev(Y, s))
     dev = torch.from_numpy(tr.view(np.int32).reshape(-1, 6).copy()).cuda()
-    for path in (stt.PATH_DIRECT, stt.PATH_SLAB):
+    for path in (stt.PATH_DIRECT, stt.PATH_SLAB, stt.PATH_WAVE):
         ctx.set_path(path)
         snr, key = ctx.score(m, tracks=dev)
         assert_close(snr.cpu().numpy(), z_orc, what=f"brute path {path}")

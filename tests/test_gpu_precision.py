@@ -50,7 +50,7 @@ def test_pack_p16_bit_exact(orc, stt, ctx):
     assert np.array_equal(got.view(np.uint16), q.view(np.uint16))
 
 
-@pytest.mark.parametrize("path,dma", [(1, True), (2, True), (2, False)])
+@pytest.mark.parametrize("path,dma", [(1, True), (2, True), (2, False), (3, True)])
 def test_p16_scores_match_oracle_on_the_stored_map(orc, stt, ctx, path, dma):
     """Same FP16 inputs on both sides: the GPU's FP32 accumulation vs the oracle's FP64."""
     _say("p16 scores", path)
