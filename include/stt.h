@@ -280,7 +280,8 @@ stt_status stt_grad(stt_ctx *ctx, const stt_map *map, const float *theta_dev, co
  * z_smooth_dev its z~. If plain_dev is given the best iterates are rounded to
  * plain templates (times half up and widened to min_len, frequencies
  * floor(256 phi) inside the band, delay to the nearest unit); if also
- * z_plain_dev, those are scored with the plain statistic (norm). */
+ * z_plain_dev, those are scored with the plain statistic (norm). One
+ * workgroup per template runs all its steps in a single launch. */
 stt_status stt_refine(stt_ctx *ctx, const stt_map *map, int32_t min_len, int32_t dtau_max, float *theta_dev,
                       const int32_t *K_dev, int32_t n, int32_t steps, const float *sched_host, float *z_smooth_dev,
                       stt_track *plain_dev, float *z_plain_dev, int32_t norm);

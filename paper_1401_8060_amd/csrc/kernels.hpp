@@ -938,18 +938,18 @@ __device__ __forceinline__ void smooth_node(const MapP &m, int64_t t, int64_t r,
 // them in flight than one wave could.
 constexpr int kSmoothWG = 256;
 
+// The smooth statistic of one template at th[0..5] (readable by every lane)
+// and, with grad_out, its gradient; all kSmoothWG lanes of the workgroup call
+// it. Lane k sums samples k, k + kSmoothWG, ...; waves reduce by shuffles and
+// thread 0 adds the waves in order, so the result does not depend on timing.
+// Results (z, grad_out[0..5]) are valid in thread 0.
 template <int MAPT>
-__global__ __launch_bounds__(kSmoothWG) void k_smooth_grad(MapP m, const float *theta, const int32_t *Ks, int32_t n,
-                                                           float *z_out, float *grad_out)
+__device__ __forceinline__ void smooth_block(const MapP &m, const float *th, int K, double (*red)[7], float &z_out,
+                                             float *grad_out)
 {
-    __shared__ double red[kSmoothWG / 64][7];
-    const int w = blockIdx.x;
     const int lane = threadIdx.x & 63;
-    if (w >= n) return;  // whole workgroup
-    const float *th = theta + (int64_t)w * 6;
     const double tau0 = th[0], tau2 = th[1], ph0 = th[2], ph1 = th[3], ph2 = th[4];
     const double dtau_s = (double)th[5] * 1e-3;
-    const int K = Ks[w];
     double z = 0, g0 = 0, g1 = 0, g2 = 0, g3 = 0, g4 = 0, g5 = 0;
     for (int k = threadIdx.x; k < K; k += kSmoothWG) {
         const double xi = K > 1 ? (double)k / (double)(K - 1) : 0.0;
@@ -998,17 +998,28 @@ __global__ __launch_bounds__(kSmoothWG) void k_smooth_grad(MapP m, const float *
             g3 += red[v][4], g4 += red[v][5], g5 += red[v][6];
         }
         const double sc = K > 0 ? 1.0 / sqrt((double)K) : 0.0;
-        z_out[w] = (float)(z * sc);
+        z_out = (float)(z * sc);
         if (grad_out) {
-            float *go = grad_out + (int64_t)w * 6;
-            go[0] = (float)(g0 * sc);
-            go[1] = (float)(g1 * sc);
-            go[2] = (float)(g2 * sc);
-            go[3] = (float)(g3 * sc);
-            go[4] = (float)(g4 * sc);
-            go[5] = (float)(g5 * sc);
+            grad_out[0] = (float)(g0 * sc);
+            grad_out[1] = (float)(g1 * sc);
+            grad_out[2] = (float)(g2 * sc);
+            grad_out[3] = (float)(g3 * sc);
+            grad_out[4] = (float)(g4 * sc);
+            grad_out[5] = (float)(g5 * sc);
         }
     }
+}
+
+template <int MAPT>
+__global__ __launch_bounds__(kSmoothWG) void k_smooth_grad(MapP m, const float *theta, const int32_t *Ks, int32_t n,
+                                                           float *z_out, float *grad_out)
+{
+    __shared__ double red[kSmoothWG / 64][7];
+    const int w = blockIdx.x;
+    if (w >= n) return;  // whole workgroup
+    float z;
+    smooth_block<MAPT>(m, theta + (int64_t)w * 6, Ks[w], red, z, grad_out ? grad_out + (int64_t)w * 6 : nullptr);
+    if (threadIdx.x == 0) z_out[w] = z;
 }
 
 // ---------------------------------------------------------------- refinement helpers
@@ -1061,32 +1072,14 @@ __device__ __forceinline__ void project_theta(double *th, const RefineP &p)
     th[5] = fmin(p.dmax_ms, fmax(-p.dmax_ms, th[5]));
 }
 
-__global__ __launch_bounds__(256) void k_refine_project(float *theta, int32_t n, RefineP p)
+// Ascent step s of a template at th (FP32 parameters, updated in place) with
+// gradient g: the five positions move by eta_px * g / |g|, the delay by
+// eta_ms * sign(g), with the step sizes falling linearly over the steps; then
+// projection onto the feasible set.
+__device__ __forceinline__ void refine_move(float *th, const float *g, int32_t s, const RefineP &p)
 {
-    const int i = blockIdx.x * 256 + threadIdx.x;
-    if (i >= n) return;
-    double th[6];
-    for (int q = 0; q < 6; ++q) th[q] = theta[(int64_t)i * 6 + q];
-    project_theta(th, p);
-    for (int q = 0; q < 6; ++q) theta[(int64_t)i * 6 + q] = (float)th[q];
-}
-
-// Keep the iterate if it beats the best so far (s < 0: initialise the best), then
-// take step s (unless s == steps): normalised ascent and projection.
-__global__ __launch_bounds__(256) void k_refine_step(float *theta, const float *z, const float *grad, float *best_theta,
-                                                     float *best_z, int32_t n, int32_t s, RefineP p)
-{
-    const int i = blockIdx.x * 256 + threadIdx.x;
-    if (i >= n) return;
-    float *th = theta + (int64_t)i * 6;
-    if (s < 0 || z[i] > best_z[i]) {
-        best_z[i] = z[i];
-        for (int q = 0; q < 6; ++q) best_theta[(int64_t)i * 6 + q] = th[q];
-    }
-    if (s < 0 || s >= p.steps) return;
     const double w = p.steps > 1 ? (double)s / (double)(p.steps - 1) : 0.0;
     const double epx = p.px0 + w * (p.px1 - p.px0), ems = p.ms0 + w * (p.ms1 - p.ms0);
-    const float *g = grad + (int64_t)i * 6;
     double t[6];
     for (int q = 0; q < 6; ++q) t[q] = th[q];
     double n2 = 0;
@@ -1099,6 +1092,46 @@ __global__ __launch_bounds__(256) void k_refine_step(float *theta, const float *
     else if (g[5] < 0) t[5] -= ems;
     project_theta(t, p);
     for (int q = 0; q < 6; ++q) th[q] = (float)t[q];
+}
+
+// The whole refinement of one template in one workgroup: project the start,
+// then for s = 0..steps evaluate the smooth statistic and its gradient at the
+// current point, keep the point if it is the best so far (s = 0 starts the
+// best), and, while s < steps, take ascent step s. theta holds the start on
+// entry and the best point on exit; best_z receives its smooth statistic.
+template <int MAPT>
+__global__ __launch_bounds__(kSmoothWG) void k_refine(MapP m, float *theta, const int32_t *Ks, int32_t n,
+                                                      float *best_z, RefineP p)
+{
+    __shared__ double red[kSmoothWG / 64][7];
+    __shared__ float cur[6];
+    const int w = blockIdx.x;
+    if (w >= n) return;  // whole workgroup
+    float *th_io = theta + (int64_t)w * 6;
+    if (threadIdx.x == 0) {
+        double t[6];
+        for (int q = 0; q < 6; ++q) t[q] = th_io[q];
+        project_theta(t, p);
+        for (int q = 0; q < 6; ++q) cur[q] = (float)t[q];
+    }
+    __syncthreads();
+    const int K = Ks[w];
+    float best[6], bz = 0.0f, z, g[6];
+    for (int32_t s = 0; s <= p.steps; ++s) {
+        smooth_block<MAPT>(m, cur, K, red, z, g);
+        if (threadIdx.x == 0) {
+            if (s == 0 || z > bz) {
+                bz = z;
+                for (int q = 0; q < 6; ++q) best[q] = cur[q];
+            }
+            if (s < p.steps) refine_move(cur, g, s, p);
+        }
+        __syncthreads();  // the new point is visible; red may be reused
+    }
+    if (threadIdx.x == 0) {
+        for (int q = 0; q < 6; ++q) th_io[q] = best[q];
+        best_z[w] = bz;
+    }
 }
 
 // Back to a plain template (times half up, widened to L pixels; frequencies

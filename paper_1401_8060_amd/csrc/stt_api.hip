@@ -29,8 +29,6 @@ struct stt_ctx {
     size_t scratch_bytes = 0;
     void *aux = nullptr;  // top-K state and candidates
     size_t aux_bytes = 0;
-    void *rbuf = nullptr;  // refinement state
-    size_t rbuf_bytes = 0;
     void *pbuf = nullptr;  // folded p = Y/sigma maps for LDS-DMA staging
     size_t pbuf_bytes = 0;
     bool dma = true;       // fold + double-buffered LDS-DMA staging where a column fits
@@ -450,7 +448,6 @@ stt_status stt_destroy(stt_ctx *c)
     (void)hipStreamSynchronize(c->stream);
     if (c->scratch) (void)hipFree(c->scratch);
     if (c->aux) (void)hipFree(c->aux);
-    if (c->rbuf) (void)hipFree(c->rbuf);
     if (c->pbuf) (void)hipFree(c->pbuf);
     if (c->bdev) (void)hipFree(c->bdev);
     if (c->gexec) (void)hipGraphExecDestroy(c->gexec);
@@ -1082,36 +1079,17 @@ stt_status stt_refine(stt_ctx *c, const stt_map *map, int32_t min_len, int32_t d
     p.ms0 = sched_host ? sched_host[2] : 0.5;
     p.ms1 = sched_host ? sched_host[3] : 0.01;
     p.steps = steps;
-    // state: current theta [n][6], gradient [n][6], current z [n]
-    const size_t need = sizeof(float) * (size_t)n * 13;
-    if (need > c->rbuf_bytes) {
-        STT_HIP(c, hipStreamSynchronize(c->stream));
-        if (c->rbuf) (void)hipFree(c->rbuf);
-        c->rbuf = nullptr;
-        c->rbuf_bytes = 0;
-        if (hipMalloc(&c->rbuf, need) != hipSuccess) {
-            (void)hipGetLastError();
-            return fail(c, STT_ENOMEM, "cannot allocate %zu bytes of refinement state", need);
-        }
-        c->rbuf_bytes = need;
-    }
-    float *cur = (float *)c->rbuf, *grad = cur + (size_t)n * 6, *z = grad + (size_t)n * 6;
-    const unsigned g1 = (unsigned)((n + 255) / 256);
-    STT_HIP(c, hipMemcpyAsync(cur, theta_dev, sizeof(float) * 6 * (size_t)n, hipMemcpyDeviceToDevice, c->stream));
-    hipLaunchKernelGGL(k_refine_project, dim3(g1), dim3(256), 0, c->stream, cur, n, p);
-    if ((s = smooth_launch(c, map, cur, K_dev, n, z, grad, c->stream)) != STT_OK) return s;
-    hipLaunchKernelGGL(k_refine_step, dim3(g1), dim3(256), 0, c->stream, cur, (const float *)z, (const float *)grad,
-                       theta_dev, z_smooth_dev, n, -1, p);
-    for (int32_t it = 0; it < steps; ++it) {
-        hipLaunchKernelGGL(k_refine_step, dim3(g1), dim3(256), 0, c->stream, cur, (const float *)z,
-                           (const float *)grad, theta_dev, z_smooth_dev, n, it, p);
-        if ((s = smooth_launch(c, map, cur, K_dev, n, z, grad, c->stream)) != STT_OK) return s;
-    }
-    hipLaunchKernelGGL(k_refine_step, dim3(g1), dim3(256), 0, c->stream, cur, (const float *)z, (const float *)grad,
-                       theta_dev, z_smooth_dev, n, steps, p);
+    const MapP m = to_mapp(map);
+    if (map->dtype == STT_P16)
+        hipLaunchKernelGGL(k_refine<kMapP16>, dim3((unsigned)n), dim3(kSmoothWG), 0, c->stream, m, theta_dev, K_dev, n,
+                           z_smooth_dev, p);
+    else
+        hipLaunchKernelGGL(k_refine<kMapF32>, dim3((unsigned)n), dim3(kSmoothWG), 0, c->stream, m, theta_dev, K_dev, n,
+                           z_smooth_dev, p);
     STT_HIP(c, hipGetLastError());
     if (plain_dev) {
-        hipLaunchKernelGGL(k_theta_to_track, dim3(g1), dim3(256), 0, c->stream, (const float *)theta_dev, (int64_t)n,
+        hipLaunchKernelGGL(k_theta_to_track, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, c->stream,
+                           (const float *)theta_dev, (int64_t)n,
                            map->T, map->F, min_len, dtau_max, (Trk *)plain_dev);
         STT_HIP(c, hipGetLastError());
         if (z_plain_dev) {
