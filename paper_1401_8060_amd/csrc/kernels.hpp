@@ -271,12 +271,36 @@ __global__ __launch_bounds__(256) void k_argmax(const float *z, int64_t n, uint6
 }
 
 // ---------------------------------------------------------------- binning by time extent
-// Bucket of a template: b0 = t0 >> wb, b2 = t2 >> wb (b0 <= b2), numbered on
-// the triangle as b2 (b2 + 1) / 2 + b0. Invalid given templates go to bucket 0.
+// Bucket of a template: b0 = t0 >> wb, b2 = t2 >> wb (b0 <= b2), nb buckets
+// per axis. Buckets are numbered longest extent first: with e = nb - 1 -
+// (b2 - b0) (0 for the longest), bucket = e (e + 1) / 2 + b0, b0 <= e. Blocks
+// of binned templates are dispatched in that order, so the longest-running
+// blocks start first and the launch ends on short ones. Invalid given
+// templates go to bucket 0 (they are skipped when scored).
 
 constexpr int kBinPerThread = 32;                 // templates per thread in the sort passes
 constexpr int kBinChunk = 256 * kBinPerThread;    // templates per workgroup
 constexpr int kMaxBins = 128 * 129 / 2;           // at most 128 buckets per axis
+
+// Reserve this workgroup's run in every bucket: cnt[b] (its count, in LDS)
+// becomes the global start of its run, taken from cursor[b]. All of a thread's
+// atomics are issued before any result is used, so their round trips overlap.
+__device__ __forceinline__ void reserve_runs(uint32_t *cnt, int nbins, uint32_t *cursor)
+{
+    constexpr int kPer = (kMaxBins + 255) / 256;
+    uint32_t got[kPer];
+#pragma unroll
+    for (int j = 0; j < kPer; ++j) {
+        const int b = threadIdx.x + j * 256;
+        const uint32_t c = b < nbins ? cnt[b] : 0u;
+        got[j] = c ? atomicAdd(&cursor[b], c) : 0u;
+    }
+#pragma unroll
+    for (int j = 0; j < kPer; ++j) {
+        const int b = threadIdx.x + j * 256;
+        if (b < nbins) cnt[b] = got[j];  // empty buckets are never read
+    }
+}
 
 template <bool EXPL>
 __device__ __forceinline__ uint32_t bin_of(const GenP &g, const Trk *tr, const MapP &m, uint64_t first, int64_t i,
@@ -292,7 +316,8 @@ __device__ __forceinline__ uint32_t bin_of(const GenP &g, const Trk *tr, const M
         draw_extent(g, first + (uint64_t)i, t0, t2);
     }
     const uint32_t b0 = (uint32_t)t0 >> wb, b2 = (uint32_t)t2 >> wb;
-    return b2 * (b2 + 1) / 2 + b0;
+    const uint32_t e = ((uint32_t)(m.T - 1) >> wb) - (b2 - b0);
+    return e * (e + 1) / 2 + b0;
 }
 
 template <bool EXPL>
@@ -355,8 +380,7 @@ __global__ __launch_bounds__(256) void k_bin_scatter(MapP m, GenP g, const Trk *
         }
     }
     __syncthreads();
-    for (int b = threadIdx.x; b < nbins; b += 256)
-        if (cnt[b]) cnt[b] = atomicAdd(&cursor[b], cnt[b]);
+    reserve_runs(cnt, nbins, cursor);
     __syncthreads();
 #pragma unroll
     for (int q = 0; q < kBinPerThread; ++q) {
@@ -695,8 +719,7 @@ __global__ __launch_bounds__(256) void k_bin_scatter_batch(const BatchMap *maps,
         }
     }
     __syncthreads();
-    for (int b = threadIdx.x; b < d.nbins; b += 256)
-        if (cnt[b]) cnt[b] = atomicAdd(&cursor[d.bin0 + b], cnt[b]);
+    reserve_runs(cnt, d.nbins, cursor + d.bin0);
     __syncthreads();
 #pragma unroll
     for (int q = 0; q < kBinPerThread; ++q) {
