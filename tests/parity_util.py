@@ -1,7 +1,13 @@
 """Helpers shared by the GPU parity tests: maps on the device, tolerance and argmax rules."""
 from __future__ import annotations
 
+import os
+import shutil
+
 import numpy as np
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+TUNE_CACHE = os.path.join(ROOT, "paper_1401_8060_amd", "tuning", "gfx950.json")
 
 TOL = 1e-5  # |z_gpu - z_oracle| <= TOL * max(1, |z|)  (FP32 scores vs FP64)
 
@@ -36,3 +42,11 @@ def assert_argmax(j_gpu: int, z_orc: np.ndarray, j_orc: int | None = None, tol=T
 
 def key_to_host(best_key) -> int:
     return int(best_key.item()) & 0xFFFFFFFFFFFFFFFF
+
+
+def bench_tuning_copy(tmp_path) -> str:
+    """A private copy of the committed MI355X tuning cache: full-scale tests take the slab shape
+    the benchmark launches, and a cache miss (another GPU) never rewrites the committed file."""
+    dst = str(tmp_path / "tune.json")
+    shutil.copyfile(TUNE_CACHE, dst)
+    return dst

@@ -8,7 +8,7 @@ import numpy as np
 import pytest
 
 import synth
-from tests.parity_util import assert_argmax, assert_close, key_to_host, to_dev
+from tests.parity_util import assert_argmax, assert_close, bench_tuning_copy, key_to_host, to_dev
 
 pytestmark = pytest.mark.gpu
 D10MS = 2684355
@@ -186,3 +186,44 @@ def test_autotune_batch_applies_and_caches(stt, ctx, tmp_path):
         gk = stt.Gen(seed=g.seed, stream=g.stream + k, min_len=g.min_len, dtau_max=g.dtau_max)
         _, kk = ctx.score(m, gen=gk, n=ns[k])
         assert key_to_host(kk) == int(keys[k].item()) & (2 ** 64 - 1)
+
+
+def test_batch_full_scale_sampled(orc, stt, ctx, tmp_path):
+    """The benchmark's batch (256 maps, T uniform on [500, 2000], F = 1000, 10^6 templates per
+    map) in its launch configuration: tuned slab shape, graph replay. Every map's best key is
+    checked against the oracle's score of that template; three maps also return their full
+    score arrays, checked against their keys and, on a sample, against the oracle."""
+    import torch
+    n_maps, F, n, seed, L = 256, 1000, 1_000_000, 3, 10
+    u = synth.uniform01(seed, 99, n_maps)
+    Ts = (500 + np.floor(u * 1501)).astype(int).tolist()
+    host, maps = [], []
+    for k, T in enumerate(Ts):
+        Y, s = synth.noise_map(T, F, seed=1000 + seed, sigma=("loguniform", 0.5, 2.0), stream=k)
+        host.append((Y, s))
+        maps.append(stt.Map(*to_dev(Y, s)))
+    g = stt.Gen(seed=seed, stream=0, min_len=L, dtau_max=D10MS)
+    ns = [n] * n_maps
+    choice = ctx.autotune_batch(maps, g, ns, bench_tuning_copy(tmp_path))
+    _say("batch full scale, slab shape", choice)
+    full = (0, n_maps // 2, n_maps - 1)
+    snr = [torch.empty(n, dtype=torch.float32, device="cuda") if k in full else None for k in range(n_maps)]
+    ctx.set_graph(True)
+    keys = ctx.score_batch(maps, g, ns, snr=snr).cpu().numpy().view(np.uint64).tolist()
+    ctx.set_slab_shape(1024, 4)
+    ctx.set_path(0, 160 * 1024)
+    for k, key in enumerate(keys):
+        zk, jk = stt.key_decode(int(key))
+        om = orc.Map(*host[k])
+        z_o = orc.score_gen_idx(om, seed, k, L, D10MS, np.array([jk], dtype=np.uint64))
+        assert_close([zk], z_o, what=f"map {k} best key")
+        if k in full:
+            z = snr[k].cpu().numpy()
+            assert jk == int(np.argmax(z)) and zk == z[jk]
+            idx = np.concatenate([np.random.default_rng(k).choice(n, 200, replace=False),
+                                  np.argsort(z)[-10:]]).astype(np.uint64)
+            z_orc = orc.score_gen_idx(om, seed, k, L, D10MS, idx)
+            assert_close(z[idx.astype(np.int64)], z_orc, what=f"map {k} sample")
+            top = idx[-10:]  # the GPU's ten best hold its argmax; the oracle's best of them must match
+            assert_argmax(int(np.where(top == jk)[0][0]), orc.score_gen_idx(om, seed, k, L, D10MS, top))
+        del om

@@ -14,7 +14,7 @@ import numpy as np
 import pytest
 
 import synth
-from tests.parity_util import TOL, assert_argmax, assert_close, key_to_host, to_dev
+from tests.parity_util import TOL, assert_argmax, assert_close, bench_tuning_copy, key_to_host, to_dev
 
 pytestmark = pytest.mark.gpu
 
@@ -188,13 +188,17 @@ def test_config2_reduced_full_oracle(orc, stt, ctx):
     assert_argmax(stt.key_decode(key_to_host(key))[1], z_orc)
 
 
-def test_config2_full_scale_sampled(orc, stt, ctx):
-    """10^7 tracks in the benchmark's launch configuration; oracle on a sample plus the argmax."""
-    _say("config2 full")
+def test_config2_full_scale_sampled(orc, stt, ctx, tmp_path):
+    """10^7 tracks in the benchmark's launch configuration (its map, seed and tuned slab shape);
+    oracle on a sample plus the argmax."""
     n = 10_000_000
     Y, s = _config2_map()
     m = stt.Map(*to_dev(Y, s))
+    choice = ctx.autotune(m, _gen(stt, 2), n, bench_tuning_copy(tmp_path))
+    _say("config2 full, slab shape", choice)
     snr, key = ctx.score(m, gen=_gen(stt, 2), n=n)
+    ctx.set_slab_shape(1024, 4)
+    ctx.set_path(stt.PATH_AUTO, 160 * 1024)
     z = snr.cpu().numpy()
     zk, jk = stt.key_decode(key_to_host(key))
     # the key is the argmax of the score array (lowest index among equal scores)

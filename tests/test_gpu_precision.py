@@ -9,7 +9,7 @@ import numpy as np
 import pytest
 
 import synth
-from tests.parity_util import assert_argmax, assert_close, key_to_host, to_dev
+from tests.parity_util import assert_argmax, assert_close, bench_tuning_copy, key_to_host, to_dev
 
 pytestmark = pytest.mark.gpu
 D10MS = 2684355
@@ -130,7 +130,7 @@ def test_rescore_f64_matches_oracle(orc, stt, ctx):
     assert np.allclose(z[:3], want, rtol=0, atol=1e-12) and np.isnan(z[3])
 
 
-def test_precision_pipeline_full_scale(orc, stt, ctx):
+def test_precision_pipeline_full_scale(orc, stt, ctx, tmp_path):
     """T=2000 x F=2000 map stored in FP16, 10^8 tracks with FP32 accumulation, top-1024
     re-scored in FP64 from the FP32 map. Checked: sampled FP16 scores against the oracle on
     the stored map, the top-1024 against a CPU selection over the same score array, every
@@ -143,7 +143,10 @@ def test_precision_pipeline_full_scale(orc, stt, ctx):
     m = stt.Map(*to_dev(Y, s))
     pm = ctx.pack_p16(m)
     g = stt.Gen(seed=4, min_len=10, dtau_max=D10MS)
+    _say("precision pipeline, slab shape", ctx.autotune(pm, g, n, bench_tuning_copy(tmp_path)))
     snr, key = ctx.score(pm, gen=g, n=n)
+    ctx.set_slab_shape(1024, 4)
+    ctx.set_path(0, 160 * 1024)
     idx, val = ctx.topk(snr, K)
     z64 = ctx.rescore_f64(m, idx, gen=g).cpu().numpy()
     zs = snr.cpu().numpy()
