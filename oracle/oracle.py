@@ -65,6 +65,13 @@ def lib():
                                         C.c_void_p, C.c_int64, C.c_int32, C.c_void_p]
         L.orc_score_gen_idx.restype = C.c_int
         L.orc_score_list.argtypes = [C.POINTER(_Map), C.c_void_p, C.c_int64, C.c_int32, C.c_void_p]
+        L.orc_score_maxdelay_gen_idx.argtypes = [C.POINTER(_Map), C.c_uint64, C.c_uint32, C.c_int32, C.c_int32,
+                                                 C.c_void_p, C.c_int64, C.c_int32, C.c_int32, C.c_int32,
+                                                 C.c_int32, C.c_void_p, C.c_void_p]
+        L.orc_score_maxdelay_gen_idx.restype = C.c_int
+        L.orc_score_maxdelay_list.argtypes = [C.POINTER(_Map), C.c_void_p, C.c_int64, C.c_int32, C.c_int32,
+                                              C.c_int32, C.c_int32, C.c_void_p, C.c_void_p]
+        L.orc_score_maxdelay_list.restype = C.c_int
         L.orc_score_list.restype = C.c_int
         L.orc_argmax.argtypes = [C.c_void_p, C.c_int64]
         L.orc_argmax.restype = C.c_int64
@@ -195,6 +202,29 @@ def score_list(m: Map, tracks: np.ndarray, norm: int = NORM_SQRT_N) -> np.ndarra
     z = np.zeros(tracks.size, dtype=np.float64)
     lib().orc_score_list(C.byref(m.c), tracks.ctypes.data, tracks.size, norm, z.ctypes.data)
     return z
+
+
+def score_maxdelay_gen_idx(m: Map, seed: int, stream: int, L: int, D: int, idx, d0: int, step: int, n_tau: int,
+                           norm: int = NORM_SQRT_N):
+    """Delay-maximised scores of templates j = idx (geometry drawn as usual, delay replaced by
+    the grid d0 + m*step, m < n_tau): (z_max, maximising m)."""
+    idx = np.ascontiguousarray(np.asarray(idx, dtype=np.uint64))
+    z = np.zeros(idx.size, dtype=np.float64)
+    mm = np.zeros(idx.size, dtype=np.int32)
+    if lib().orc_score_maxdelay_gen_idx(C.byref(m.c), seed, stream, L, D, idx.ctypes.data, idx.size, d0, step,
+                                        n_tau, norm, z.ctypes.data, mm.ctypes.data) != 0:
+        raise ValueError("invalid parameters")
+    return z, mm
+
+
+def score_maxdelay_list(m: Map, tracks: np.ndarray, d0: int, step: int, n_tau: int, norm: int = NORM_SQRT_N):
+    tracks = np.ascontiguousarray(np.asarray(tracks, dtype=TRACK_DTYPE))
+    z = np.zeros(tracks.size, dtype=np.float64)
+    mm = np.zeros(tracks.size, dtype=np.int32)
+    if lib().orc_score_maxdelay_list(C.byref(m.c), tracks.ctypes.data, tracks.size, d0, step, n_tau, norm,
+                                     z.ctypes.data, mm.ctypes.data) != 0:
+        raise ValueError("invalid parameters")
+    return z, mm
 
 
 def argmax(z: np.ndarray) -> int:

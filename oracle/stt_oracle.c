@@ -243,6 +243,54 @@ int orc_score_list(const orc_map *m, const orc_track *tr, int64_t n, int32_t nor
 }
 
 /* ------------------------------------------------------------------------ */
+/* Delay-maximised statistic: the reading of "phase-maximised" that takes,   */
+/* per template, the maximum of Eq. 8 over a grid of delays instead of one   */
+/* drawn delay. The template's geometry (t0, t2, f0, f1, f2) is kept and its */
+/* own delay replaced by dtau_m = d0 + m * step for m = 0 .. n_tau - 1;      */
+/* z_max = max_m z(dtau_m), ties to the lowest m. An invalid template gives  */
+/* NaN and m = -1. Plain definition: score each delay with orc_score.        */
+/* ------------------------------------------------------------------------ */
+int orc_score_maxdelay(const orc_map *m, const orc_track *tr, int32_t d0, int32_t step, int32_t n_tau,
+                       int32_t norm, double *z_max, int32_t *m_max)
+{
+    double best = NAN;
+    int32_t bm = -1;
+    if (n_tau < 1) return -1;
+    for (int32_t k = 0; k < n_tau; ++k) {
+        int64_t d = (int64_t)d0 + (int64_t)k * step;
+        if (d < -(int64_t)1073741823 || d > (int64_t)1073741823) return -1;
+        orc_track t = *tr;
+        t.dtau = (int32_t)d;
+        double z = orc_score(m, &t, norm);
+        if (isnan(z)) { best = NAN; bm = -1; break; }
+        if (bm < 0 || z > best) { best = z; bm = k; }
+    }
+    *z_max = best;
+    *m_max = bm;
+    return 0;
+}
+
+int orc_score_maxdelay_gen_idx(const orc_map *m, uint64_t seed, uint32_t stream, int32_t L, int32_t D,
+                               const uint64_t *idx, int64_t n, int32_t d0, int32_t step, int32_t n_tau,
+                               int32_t norm, double *z, int32_t *mm)
+{
+    for (int64_t i = 0; i < n; ++i) {
+        orc_track tr;
+        if (orc_draw(seed, stream, idx[i], m->T, m->F, L, D, &tr) != 0) return -1;
+        if (orc_score_maxdelay(m, &tr, d0, step, n_tau, norm, &z[i], &mm[i]) != 0) return -1;
+    }
+    return 0;
+}
+
+int orc_score_maxdelay_list(const orc_map *m, const orc_track *tr, int64_t n, int32_t d0, int32_t step,
+                            int32_t n_tau, int32_t norm, double *z, int32_t *mm)
+{
+    for (int64_t i = 0; i < n; ++i)
+        if (orc_score_maxdelay(m, &tr[i], d0, step, n_tau, norm, &z[i], &mm[i]) != 0) return -1;
+    return 0;
+}
+
+/* ------------------------------------------------------------------------ */
 /* The most significant cluster (Sec. III before Eq. 5; Sec. V keeps the    */
 /* maximum per spectrogram).  Reading: ties go to the lowest index and NaN  */
 /* never wins.  Returns -1 when there is no finite-or-infinite candidate.   */
