@@ -168,6 +168,21 @@ stt_status stt_make_tracks(stt_ctx *ctx, const stt_gen *gen, int32_t T, int32_t 
 stt_status stt_score(stt_ctx *ctx, const stt_map *map, const stt_gen *gen, const stt_track *tracks_dev,
                      int64_t first, int64_t n, int32_t norm, float *snr_dev, uint64_t *best_key_dev);
 
+/* Delay-maximised scores: the reading of "phase-maximised" (Sec. III, Eq. 8)
+ * that maximises the statistic over the delay per template instead of drawing
+ * one. Track j (generated or given, as in stt_score) keeps its time extent and
+ * control frequencies; its own delay is replaced by each of the grid delays
+ * dtau_m = dtau0 + m * dtau_step (2^-28 s units), m = 0 .. n_tau - 1. For i in
+ * [0, n): snr_dev[i] = max_m z_j(dtau_m) (FP32; ties keep the lowest m) and
+ * tau_idx_dev[i] = that m; an invalid given track (or NaN map data) gives NaN
+ * and -1. Either output may be NULL (the context then keeps its own). The
+ * key of (max, j) is max-merged into *best_key_dev (may be NULL). Requires
+ * 1 <= n_tau <= 65536 and every grid delay in (-2^30, 2^30). The row walk and
+ * the pixel gathers are shared by the delays (8 per kernel launch). */
+stt_status stt_score_maxdelay(stt_ctx *ctx, const stt_map *map, const stt_gen *gen, const stt_track *tracks_dev,
+                              int64_t first, int64_t n, int32_t dtau0, int32_t dtau_step, int32_t n_tau, int32_t norm,
+                              float *snr_dev, int32_t *tau_idx_dev, uint64_t *best_key_dev);
+
 /* Max/argmax over an existing score array: *best_key_dev is max-merged with
  * the best key over snr_dev[0..n), the index of element i being first + i. */
 stt_status stt_argmax(stt_ctx *ctx, const float *snr_dev, int64_t n, int64_t first,

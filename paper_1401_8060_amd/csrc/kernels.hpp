@@ -626,6 +626,248 @@ __global__ __launch_bounds__(1024) void k_reduce_keys(const uint64_t *keys, int6
     }
 }
 
+// ---------------------------------------------------------------- delay-maximised scoring
+// The maximum of Eq. 8 over a grid of delays per template (a reading of
+// "phase-maximised"): the template keeps its geometry and its own delay is
+// replaced by dtau_m = d0 + m * step. A launch handles kMD consecutive delays
+// m0 .. m0 + cnt - 1 of the grid for every template: the row walk and the
+// pixel gather are shared, each delay has its own (wave-uniform) phase
+// constants and accumulators, on the same flush grid as the other scorers.
+// The running maximum and its index live in snr / tidx between launches.
+constexpr int kMD = 8;
+
+struct DelayGrid {
+    uint32_t pa[kMD], pb[kMD];  // phase constants of each delay (zero past cnt)
+    int32_t m0, cnt;
+};
+
+__device__ __forceinline__ DelayGrid delay_grid(const MapP &m, int32_t d0, int32_t step, int32_t m0, int32_t cnt)
+{
+    DelayGrid dg;
+    dg.m0 = m0;
+    dg.cnt = cnt;
+#pragma unroll
+    for (int k = 0; k < kMD; ++k) {
+        // in range for k < cnt (checked by the host); wrapping arithmetic for the rest
+        const int32_t d = (int32_t)((uint32_t)d0 + (uint32_t)(m0 + k) * (uint32_t)step);
+        dg.pa[k] = k < cnt ? phase_a(m.fq4_lo, d) : 0u;
+        dg.pb[k] = k < cnt ? phase_b(m.dfq4, d) : 0u;
+    }
+    return dg;
+}
+
+// The best of this launch's delays for one template, merged with the running
+// maximum of earlier launches (strictly greater wins, so ties keep the lowest
+// index). A NaN score (from NaN map data) makes the result NaN with index -1.
+__device__ __forceinline__ void merge_delays(const double (&acc)[kMD], const float (&part)[kMD], int32_t N,
+                                             int32_t norm, const DelayGrid &dg, bool ok, float &z, int32_t &mi)
+{
+    z = __builtin_nanf("");
+    mi = -1;
+    if (!ok) return;
+    bool nan = false;
+#pragma unroll
+    for (int k = 0; k < kMD; ++k) {
+        if (k >= dg.cnt) break;
+        const float v = finish(acc[k] + part[k], N, norm);
+        if (v != v) nan = true;
+        else if (mi < 0 || v > z) { z = v; mi = dg.m0 + k; }
+    }
+    if (nan) { z = __builtin_nanf(""); mi = -1; }
+}
+
+__device__ __forceinline__ void merge_running(float &z, int32_t &mi, float zp, int32_t mp, bool first_launch)
+{
+    if (first_launch) return;
+    if (zp != zp || mp < 0 || z != z) { z = __builtin_nanf(""); mi = -1; return; }
+    if (!(z > zp)) { z = zp; mi = mp; }
+}
+
+// One lane per template, direct gathers (small calls, maps too wide for LDS).
+template <bool EXPL, bool HW, int MAPT>
+__global__ __launch_bounds__(kWG) void k_score_md_direct(MapP m, GenP g, const Trk *tr, uint64_t first, int64_t n,
+                                                         int32_t norm, int32_t d0, int32_t step, int32_t m0,
+                                                         int32_t cnt, int32_t last, float *snr, int32_t *tidx,
+                                                         uint64_t *best)
+{
+    const int64_t i = (int64_t)blockIdx.x * kWG + threadIdx.x;
+    const DelayGrid dg = delay_grid(m, d0, step, m0, cnt);
+    uint64_t key = 0;
+    if (i < n) {
+        const Trk t = EXPL ? tr[i] : draw_track(g, first + (uint64_t)i);
+        const bool ok = !EXPL || track_ok(t, m);
+        double acc[kMD];
+        float part[kMD];
+#pragma unroll
+        for (int k = 0; k < kMD; ++k) { acc[k] = 0.0; part[k] = 0.0f; }
+        const int32_t N = t.t2 - t.t0 + 1;
+        if (ok) {
+            DdaF s = ddaf_init_at(t, 0);
+            int64_t base = (int64_t)t.t0 * m.ld;
+            for (int32_t k = 0; k < N; ++k) {
+                const int32_t row = ddaf_row(s);
+                const float2 p = load_p<MAPT>(m, base + row);
+#pragma unroll
+                for (int q = 0; q < kMD; ++q) part[q] = add_term<HW>(part[q], PhaseK{dg.pa[q], dg.pb[q]}, row, p);
+                if (((t.t0 + k) & (kFlush - 1)) == kFlush - 1) {
+#pragma unroll
+                    for (int q = 0; q < kMD; ++q) { acc[q] += part[q]; part[q] = 0.0f; }
+                }
+                ddaf_step(s);
+                base += m.ld;
+            }
+        }
+        float z;
+        int32_t mi;
+        merge_delays(acc, part, N, norm, dg, ok, z, mi);
+        merge_running(z, mi, m0 ? snr[i] : 0.0f, m0 ? tidx[i] : 0, m0 == 0);
+        snr[i] = z;
+        tidx[i] = mi;
+        if (last) key = key_encode(z, (uint32_t)(first + (uint64_t)i));
+    }
+    if (last) merge_key(best, key);
+}
+
+// Column walk of the delay-maximised slab scorer (as walk, with kMD delays).
+template <int TPT, bool MASK, bool HW>
+__device__ __forceinline__ void walk_md(int ca, int cb, int c0, const float2 *slab, int ldc,
+                                        const int32_t (&t0)[TPT], const uint32_t (&span)[TPT], const DelayGrid &dg,
+                                        DdaF (&st)[TPT], float (&part)[TPT][kMD], double (&acc)[TPT][kMD])
+{
+    for (int c = ca; c <= cb;) {
+        const int ce = min(cb, c | (kFlush - 1));
+        for (; c <= ce; ++c) {
+            const float2 *col = slab + (c - c0) * ldc;
+#pragma unroll
+            for (int q = 0; q < TPT; ++q) {
+                const int32_t row = ddaf_row(st[q]);
+                const bool act = !MASK || (uint32_t)c - (uint32_t)t0[q] <= span[q];
+                const float2 p = col[act ? row : 0];
+#pragma unroll
+                for (int k = 0; k < kMD; ++k) {
+                    const float v = add_term<HW>(part[q][k], PhaseK{dg.pa[k], dg.pb[k]}, row, p);
+                    part[q][k] = act ? v : part[q][k];
+                }
+                ddaf_step(st[q]);
+            }
+        }
+        if ((ce & (kFlush - 1)) == kFlush - 1) {  // wave-uniform
+#pragma unroll
+            for (int q = 0; q < TPT; ++q)
+#pragma unroll
+                for (int k = 0; k < kMD; ++k) { acc[q][k] += part[q][k]; part[q][k] = 0.0f; }
+        }
+    }
+}
+
+// Slab scorer of the delay grid: the folded map streamed into LDS by DMA as in
+// score_block, WG lanes x TPT binned templates per workgroup; on the last launch
+// each workgroup stores its best key in wg_keys[blockIdx.x].
+template <int WG, int TPT, bool EXPL, bool HW>
+__global__ __launch_bounds__(WG) void k_score_md_slab(MapP m, GenP g, const Trk *tr, const uint32_t *order,
+                                                      uint64_t first, int64_t n, int S, int32_t norm, int32_t d0,
+                                                      int32_t step, int32_t m0, int32_t cnt, int32_t last, float *snr,
+                                                      int32_t *tidx, uint64_t *wg_keys)
+{
+    extern __shared__ float2 slab[];
+    __shared__ int bnd[2];
+    __shared__ uint64_t kred[WG / 64];
+    if (threadIdx.x == 0) { bnd[0] = 0x7fffffff; bnd[1] = -1; }
+    const DelayGrid dg = delay_grid(m, d0, step, m0, cnt);
+    const int lane = threadIdx.x & 63;
+    const int64_t wbase = (int64_t)blockIdx.x * (WG * TPT) + (int64_t)(threadIdx.x >> 6) * (64 * TPT);
+    Trk tk[TPT];
+    int32_t t0[TPT];
+    uint32_t span[TPT], idx[TPT];
+    bool ok[TPT], live[TPT];
+    int lo = 0x7fffffff, hi = -1, clo = -1, chi = 0x7fffffff;
+#pragma unroll
+    for (int q = 0; q < TPT; ++q) {
+        const int64_t e = wbase + q * 64 + lane;
+        live[q] = e < n;
+        idx[q] = live[q] ? order[e] : 0u;
+        Trk t = EXPL ? tr[idx[q]] : draw_track(g, first + idx[q]);
+        ok[q] = live[q] && (!EXPL || track_ok(t, m));
+        if (!ok[q]) t = Trk{0, 1, 0u, 0u, 0u, 0};
+        tk[q] = t;
+        t0[q] = ok[q] ? t.t0 : 0x7fffffff;
+        span[q] = ok[q] ? (uint32_t)(t.t2 - t.t0) : 0u;
+        if (ok[q]) {
+            lo = min(lo, t.t0);
+            hi = max(hi, t.t2);
+            clo = max(clo, t.t0);
+            chi = min(chi, t.t2);
+        } else {
+            clo = 0x7fffffff;
+            chi = -1;
+        }
+    }
+    lo = wave_min_i32(lo);
+    hi = wave_max_i32(hi);
+    clo = wave_max_i32(clo);
+    chi = wave_min_i32(chi);
+    if (clo > chi) { clo = hi + 1; chi = hi; }
+    DdaF st[TPT];
+    float part[TPT][kMD];
+    double acc[TPT][kMD];
+    const int start = lo == 0x7fffffff ? 0 : lo;
+#pragma unroll
+    for (int q = 0; q < TPT; ++q) {
+        st[q] = ddaf_init_at(tk[q], start - tk[q].t0);
+#pragma unroll
+        for (int k = 0; k < kMD; ++k) { part[q][k] = 0.0f; acc[q][k] = 0.0; }
+    }
+    __syncthreads();
+    if (lane == 0) {
+        atomicMin(&bnd[0], lo);
+        atomicMax(&bnd[1], hi);
+    }
+    __syncthreads();
+    const int c_first = __builtin_amdgcn_readfirstlane(bnd[0]), c_last = __builtin_amdgcn_readfirstlane(bnd[1]);
+    const int ldc = (int)m.ld, per_col = ldc / kDmaPix;
+    const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    auto issue = [&](int c0, int bsel) {
+        const int nchunk = min(S, c_last - c0 + 1) * per_col;
+        const float2 *src = m.Y + (int64_t)c0 * ldc + lane * 2;
+        float2 *dst = slab + (size_t)bsel * S * ldc;
+        for (int ch = wave; ch < nchunk; ch += WG / 64) lds_dma_16(src + ch * kDmaPix, dst + ch * kDmaPix);
+    };
+    if (c_first <= c_last) issue(c_first, 0);
+    int kk = 0;
+    for (int c0 = c_first; c0 <= c_last; c0 += S, ++kk) {
+        __builtin_amdgcn_s_waitcnt(0);  // this wave's copies of slab kk have landed
+        __syncthreads();                // so have everyone's, and slab kk-1 is no longer read
+        if (c0 + S <= c_last) issue(c0 + S, (kk + 1) & 1);
+        const float2 *cur = slab + (size_t)(kk & 1) * S * ldc;
+        const int ncol = min(S, c_last - c0 + 1);
+        const int ca = max(c0, lo), cb = min(c0 + ncol - 1, hi);
+        walk_md<TPT, true, HW>(ca, min(cb, clo - 1), c0, cur, ldc, t0, span, dg, st, part, acc);
+        walk_md<TPT, false, HW>(max(ca, clo), min(cb, chi), c0, cur, ldc, t0, span, dg, st, part, acc);
+        walk_md<TPT, true, HW>(max(ca, chi + 1), cb, c0, cur, ldc, t0, span, dg, st, part, acc);
+    }
+    uint64_t key = 0;
+#pragma unroll
+    for (int q = 0; q < TPT; ++q) {
+        if (!live[q]) continue;
+        float z;
+        int32_t mi;
+        merge_delays(acc[q], part[q], (int32_t)span[q] + 1, norm, dg, ok[q], z, mi);
+        merge_running(z, mi, m0 ? snr[idx[q]] : 0.0f, m0 ? tidx[idx[q]] : 0, m0 == 0);
+        snr[idx[q]] = z;
+        tidx[idx[q]] = mi;
+        const uint64_t k = key_encode(z, (uint32_t)(first + idx[q]));
+        key = k > key ? k : key;
+    }
+    if (!last) return;  // uniform: every workgroup of a launch has the same flag
+    key = wave_max_u64(key);
+    if (lane == 0) kred[threadIdx.x >> 6] = key;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        for (int w = 1; w < WG / 64; ++w) key = kred[w] > key ? kred[w] : key;
+        wg_keys[blockIdx.x] = key;
+    }
+}
+
 // ---------------------------------------------------------------- batches of maps
 // A batch scores n_m generated templates on each map m (the paper's n_ts
 // time-shifted background maps, Sec. V). Map m's templates are binned within

@@ -31,6 +31,8 @@ struct stt_ctx {
     size_t aux_bytes = 0;
     void *pbuf = nullptr;  // folded p = Y/sigma maps for LDS-DMA staging
     size_t pbuf_bytes = 0;
+    void *mdbuf = nullptr;  // running maxima of delay-grid scoring when the caller keeps none
+    size_t mdbuf_bytes = 0;
     bool dma = true;       // fold + double-buffered LDS-DMA staging where a column fits
     int path = 0;  // 0 auto, 1 direct, 2 slab
     int lds_bytes = 160 * 1024;  // slab budget per workgroup
@@ -135,6 +137,24 @@ stt_status ensure_pbuf(stt_ctx *c, size_t bytes)
         return fail(c, STT_ENOMEM, "cannot allocate %zu bytes for the folded map", bytes);
     }
     c->pbuf_bytes = bytes;
+    return STT_OK;
+}
+
+stt_status ensure_mdbuf(stt_ctx *c, size_t bytes)
+{
+    if (bytes <= c->mdbuf_bytes) return STT_OK;
+    if (c->mdbuf) {
+        hipError_t e = hipStreamSynchronize(c->stream);
+        if (e != hipSuccess) return fail(c, STT_EHIP, "hipStreamSynchronize: %s", hipGetErrorString(e));
+        (void)hipFree(c->mdbuf);
+        c->mdbuf = nullptr;
+        c->mdbuf_bytes = 0;
+    }
+    if (hipMalloc(&c->mdbuf, bytes) != hipSuccess) {
+        (void)hipGetLastError();
+        return fail(c, STT_ENOMEM, "cannot allocate %zu bytes of delay-grid maxima", bytes);
+    }
+    c->mdbuf_bytes = bytes;
     return STT_OK;
 }
 
@@ -318,6 +338,37 @@ bool slab_shape_ok(int wg, int tpt)
     return false;
 }
 
+// Counting sort of templates first .. first+n-1 by time-extent bucket into the
+// context's scratch (timed as the binning stage): returns the binned order and
+// the per-workgroup key slots that follow it.
+template <bool EXPL>
+stt_status bin_templates(stt_ctx *c, const MapP &m, const GenP &g, const Trk *tr, int64_t first, int64_t n,
+                         uint32_t *&order, uint64_t *&wg_keys)
+{
+    const int wb = bucket_shift(m.T, n);
+    const int nb = ((m.T - 1) >> wb) + 1;
+    const int nbins = nb * (nb + 1) / 2;
+    const size_t n_order = ((size_t)n + 1) & ~(size_t)1;  // keeps the key slots 8-byte aligned
+    stt_status s = ensure_scratch(c, score_scratch_bytes(n));
+    if (s != STT_OK) return s;
+    uint32_t *totals = (uint32_t *)c->scratch;
+    uint32_t *cursor = totals + kMaxBins;
+    order = cursor + kMaxBins;
+    wg_keys = (uint64_t *)(order + n_order);
+    const unsigned bgrid = (unsigned)((n + kBinChunk - 1) / kBinChunk);
+    ev_record(c, 2);
+    hipLaunchKernelGGL(k_fill_u32, dim3((nbins + 255) / 256), dim3(256), 0, c->stream, totals, nbins, 0u);
+    hipLaunchKernelGGL(k_bin_count<EXPL>, dim3(bgrid), dim3(256), 0, c->stream, m, g, tr, (uint64_t)first, n, wb,
+                       nbins, totals);
+    hipLaunchKernelGGL(k_bin_scan, dim3(1), dim3(1024), 0, c->stream, (const uint32_t *)totals, nbins, cursor);
+    hipLaunchKernelGGL(k_bin_scatter<EXPL>, dim3(bgrid), dim3(256), 0, c->stream, m, g, tr, (uint64_t)first, n, wb,
+                       nbins, cursor, order);
+    STT_HIP(c, hipGetLastError());
+    ev_record(c, 3);
+    c->used[1] = true;
+    return STT_OK;
+}
+
 template <bool EXPL, int MAPT>
 stt_status score_impl(stt_ctx *c, const stt_map *map, const GenP &g, const Trk *tr, int64_t first, int64_t n,
                       int32_t norm, float *snr, uint64_t *best)
@@ -348,27 +399,10 @@ stt_status score_impl(stt_ctx *c, const stt_map *map, const GenP &g, const Trk *
         ev_record(c, 1);
         c->used[0] = true;
     } else {
-        const int wb = bucket_shift(m.T, n);
-        const int nb = ((m.T - 1) >> wb) + 1;
-        const int nbins = nb * (nb + 1) / 2;
-        const size_t n_order = ((size_t)n + 1) & ~(size_t)1;  // keeps the key slots 8-byte aligned
-        stt_status s = ensure_scratch(c, score_scratch_bytes(n));
+        uint32_t *order = nullptr;
+        uint64_t *wg_keys = nullptr;
+        stt_status s = bin_templates<EXPL>(c, m, g, tr, first, n, order, wg_keys);
         if (s != STT_OK) return s;
-        uint32_t *totals = (uint32_t *)c->scratch;
-        uint32_t *cursor = totals + kMaxBins;
-        uint32_t *order = cursor + kMaxBins;
-        uint64_t *wg_keys = (uint64_t *)(order + n_order);
-        const unsigned bgrid = (unsigned)((n + kBinChunk - 1) / kBinChunk);
-        ev_record(c, 2);
-        hipLaunchKernelGGL(k_fill_u32, dim3((nbins + 255) / 256), dim3(256), 0, c->stream, totals, nbins, 0u);
-        hipLaunchKernelGGL(k_bin_count<EXPL>, dim3(bgrid), dim3(256), 0, c->stream, m, g, tr, (uint64_t)first, n, wb,
-                           nbins, totals);
-        hipLaunchKernelGGL(k_bin_scan, dim3(1), dim3(1024), 0, c->stream, (const uint32_t *)totals, nbins, cursor);
-        hipLaunchKernelGGL(k_bin_scatter<EXPL>, dim3(bgrid), dim3(256), 0, c->stream, m, g, tr, (uint64_t)first, n,
-                           wb, nbins, cursor, order);
-        STT_HIP(c, hipGetLastError());
-        ev_record(c, 3);
-        c->used[1] = true;
         const int64_t ldc = fold_ld(m.F);
         if (c->dma && dma_slab_cols(c, ldc) >= 1) {
             // fold p (Y/sigma, or the FP16 entries' exact FP32 values) once, then stream slabs
@@ -399,6 +433,85 @@ stt_status score_impl(stt_ctx *c, const stt_map *map, const GenP &g, const Trk *
         if (best) {
             const int64_t n_wg = (n + (int64_t)c->slab_wg * c->slab_tpt - 1) / ((int64_t)c->slab_wg * c->slab_tpt);
             hipLaunchKernelGGL(k_reduce_keys, dim3(1), dim3(1024), 0, c->stream, (const uint64_t *)wg_keys, n_wg, best);
+            STT_HIP(c, hipGetLastError());
+        }
+    }
+    ev_record(c, 5);
+    c->used[2] = true;
+    ev_end(c);
+    return STT_OK;
+}
+
+// The delay grid in launches of kMD delays. Slabs (binned templates, folded map,
+// LDS-DMA) from 4096 templates on when two slabs of a column fit; otherwise one
+// lane per template with direct gathers. Both give bit-identical results.
+template <bool EXPL, int MAPT>
+stt_status maxdelay_impl(stt_ctx *c, const stt_map *map, const GenP &g, const Trk *tr, int64_t first, int64_t n,
+                         int32_t d0, int32_t step, int32_t n_tau, int32_t norm, float *snr, int32_t *tidx,
+                         uint64_t *best)
+{
+    constexpr int kMdWG = 512, kMdTPT = 2;
+    const MapP m = to_mapp(map);
+    const int64_t ldc = fold_ld(m.F);
+    bool slab = c->dma && dma_slab_cols(c, ldc) >= 1 && c->path != 1 && c->path != 3 && (c->path == 2 || n >= 4096);
+    if (c->path == 2 && !slab)
+        return fail(c, STT_EUNSUPPORTED, "F=%d too wide for two LDS slabs of %d bytes", m.F, c->lds_bytes);
+    stt_status s;
+    if (!snr || !tidx) {
+        if ((s = ensure_mdbuf(c, (sizeof(float) + sizeof(int32_t)) * (size_t)n)) != STT_OK) return s;
+        if (!snr) snr = (float *)c->mdbuf;
+        if (!tidx) tidx = (int32_t *)((float *)c->mdbuf + n);
+    }
+    if ((s = ev_begin(c)) != STT_OK) return s;
+    ev_record(c, 4);
+    const int n_launch = (n_tau + kMD - 1) / kMD;
+    if (!slab) {
+        ev_record(c, 0);
+        const unsigned grid = (unsigned)((n + kWG - 1) / kWG);
+        for (int l = 0; l < n_launch; ++l) {
+            const int32_t m0 = l * kMD, cnt = std::min(kMD, n_tau - m0), last = l == n_launch - 1;
+            if (c->hw_trig)
+                hipLaunchKernelGGL((k_score_md_direct<EXPL, true, MAPT>), dim3(grid), dim3(kWG), 0, c->stream, m, g,
+                                   tr, (uint64_t)first, n, norm, d0, step, m0, cnt, last, snr, tidx, best);
+            else
+                hipLaunchKernelGGL((k_score_md_direct<EXPL, false, MAPT>), dim3(grid), dim3(kWG), 0, c->stream, m,
+                                   g, tr, (uint64_t)first, n, norm, d0, step, m0, cnt, last, snr, tidx, best);
+        }
+        STT_HIP(c, hipGetLastError());
+        ev_record(c, 1);
+        c->used[0] = true;
+    } else {
+        uint32_t *order = nullptr;
+        uint64_t *wg_keys = nullptr;
+        if ((s = bin_templates<EXPL>(c, m, g, tr, first, n, order, wg_keys)) != STT_OK) return s;
+        const size_t pb = sizeof(float2) * (size_t)m.T * (size_t)ldc;
+        if ((s = ensure_pbuf(c, pb)) != STT_OK) return s;
+        const unsigned fg = (unsigned)std::min<int64_t>(((int64_t)m.T * ldc + 255) / 256, 4096);
+        hipLaunchKernelGGL(k_fold_p<MAPT>, dim3(fg), dim3(256), 0, c->stream, m, (float2 *)c->pbuf, ldc);
+        MapP mf = m;
+        mf.Y = (const float2 *)c->pbuf;
+        mf.sig = nullptr;
+        mf.ld = ldc;
+        const int S = std::min(dma_slab_cols(c, ldc), m.T);
+        const size_t shm = 2 * sizeof(float2) * (size_t)S * ldc;
+        const unsigned grid = (unsigned)((n + kMdWG * kMdTPT - 1) / (kMdWG * kMdTPT));
+        auto kh = k_score_md_slab<kMdWG, kMdTPT, EXPL, true>;
+        auto kp = k_score_md_slab<kMdWG, kMdTPT, EXPL, false>;
+        auto kern = c->hw_trig ? kh : kp;
+        if (shm > 64 * 1024)
+            STT_HIP(c, hipFuncSetAttribute((const void *)kern, hipFuncAttributeMaxDynamicSharedMemorySize, (int)shm));
+        ev_record(c, 0);
+        for (int l = 0; l < n_launch; ++l) {
+            const int32_t m0 = l * kMD, cnt = std::min(kMD, n_tau - m0), last = l == n_launch - 1;
+            hipLaunchKernelGGL(kern, dim3(grid), dim3(kMdWG), shm, c->stream, mf, g, tr, (const uint32_t *)order,
+                               (uint64_t)first, n, S, norm, d0, step, m0, cnt, last, snr, tidx, wg_keys);
+        }
+        STT_HIP(c, hipGetLastError());
+        ev_record(c, 1);
+        c->used[0] = true;
+        if (best) {
+            hipLaunchKernelGGL(k_reduce_keys, dim3(1), dim3(1024), 0, c->stream, (const uint64_t *)wg_keys,
+                               (int64_t)grid, best);
             STT_HIP(c, hipGetLastError());
         }
     }
@@ -449,6 +562,7 @@ stt_status stt_destroy(stt_ctx *c)
     if (c->scratch) (void)hipFree(c->scratch);
     if (c->aux) (void)hipFree(c->aux);
     if (c->pbuf) (void)hipFree(c->pbuf);
+    if (c->mdbuf) (void)hipFree(c->mdbuf);
     if (c->bdev) (void)hipFree(c->bdev);
     if (c->gexec) (void)hipGraphExecDestroy(c->gexec);
     if (c->graph) (void)hipGraphDestroy(c->graph);
@@ -593,6 +707,39 @@ stt_status stt_score(stt_ctx *c, const stt_map *map, const stt_gen *gen, const s
                    : score_impl<true, kMapF32>(c, map, g, (const Trk *)tracks_dev, first, n, norm, snr_dev, best_key_dev);
     return p16 ? score_impl<false, kMapP16>(c, map, g, nullptr, first, n, norm, snr_dev, best_key_dev)
                : score_impl<false, kMapF32>(c, map, g, nullptr, first, n, norm, snr_dev, best_key_dev);
+}
+
+stt_status stt_score_maxdelay(stt_ctx *c, const stt_map *map, const stt_gen *gen, const stt_track *tracks_dev,
+                              int64_t first, int64_t n, int32_t dtau0, int32_t dtau_step, int32_t n_tau, int32_t norm,
+                              float *snr_dev, int32_t *tau_idx_dev, uint64_t *best_key_dev)
+{
+    if (!c) return STT_EINVAL;
+    stt_status s = check_map(c, map);
+    if (s != STT_OK) return s;
+    if ((s = check_range(c, first, n)) != STT_OK) return s;
+    if (norm != STT_NORM_SQRT_N && norm != STT_NORM_N) return fail(c, STT_EINVAL, "norm=%d", norm);
+    if (n_tau < 1 || n_tau > 65536) return fail(c, STT_ERANGE, "n_tau=%d outside [1, 65536]", n_tau);
+    const int64_t dlast = (int64_t)dtau0 + (int64_t)(n_tau - 1) * dtau_step;
+    const int64_t dlim = ((int64_t)1 << 30) - 1;
+    if (dtau0 < -dlim || dtau0 > dlim || dlast < -dlim || dlast > dlim)
+        return fail(c, STT_ERANGE, "delay grid %d + m*%d (m < %d) leaves (-2^30, 2^30)", dtau0, dtau_step, n_tau);
+    GenP g{};
+    if (!tracks_dev) {
+        if ((s = make_genp(c, gen, map->T, map->F, g)) != STT_OK) return s;
+    }
+    if (n == 0) return STT_OK;
+    STT_HIP(c, hipSetDevice(c->device));
+    const bool p16 = map->dtype == STT_P16;
+    const Trk *tr = (const Trk *)tracks_dev;
+    if (tracks_dev)
+        return p16 ? maxdelay_impl<true, kMapP16>(c, map, g, tr, first, n, dtau0, dtau_step, n_tau, norm, snr_dev,
+                                                  tau_idx_dev, best_key_dev)
+                   : maxdelay_impl<true, kMapF32>(c, map, g, tr, first, n, dtau0, dtau_step, n_tau, norm, snr_dev,
+                                                  tau_idx_dev, best_key_dev);
+    return p16 ? maxdelay_impl<false, kMapP16>(c, map, g, nullptr, first, n, dtau0, dtau_step, n_tau, norm, snr_dev,
+                                               tau_idx_dev, best_key_dev)
+               : maxdelay_impl<false, kMapF32>(c, map, g, nullptr, first, n, dtau0, dtau_step, n_tau, norm, snr_dev,
+                                               tau_idx_dev, best_key_dev);
 }
 
 stt_status stt_argmax(stt_ctx *c, const float *snr_dev, int64_t n, int64_t first, uint64_t *best_key_dev)

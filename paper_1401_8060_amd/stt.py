@@ -293,6 +293,46 @@ class Context:
                                     C.c_void_p(best_key.data_ptr())))
         return snr, best_key
 
+    def score_maxdelay(self, m: Map, dtau0: int, dtau_step: int, n_tau: int, gen: Gen | None = None,
+                       tracks: torch.Tensor | None = None, first: int = 0, n: int | None = None,
+                       norm: int = NORM_SQRT_N, snr: torch.Tensor | bool | None = True,
+                       tau_idx: torch.Tensor | bool | None = True, best_key: torch.Tensor | None = None):
+        """Delay-maximised scores over the grid dtau0 + m*dtau_step (m < n_tau): returns
+        (snr or None, maximising delay index or None, best_key), as score() does for one delay."""
+        if tracks is not None:
+            if tracks.dtype != torch.int32 or tracks.dim() != 2 or tracks.shape[1] != 6 or not tracks.is_contiguous():
+                raise ValueError("tracks must be a contiguous [n][6] int32 tensor")
+            if n is None:
+                n = tracks.shape[0]
+            if n > tracks.shape[0]:
+                raise ValueError("n exceeds the number of given tracks")
+        if n is None:
+            raise ValueError("n is required with generated tracks")
+        dev = m.Y.device
+        if snr is True:
+            snr = torch.empty(n, dtype=torch.float32, device=dev)
+        if snr is False:
+            snr = None
+        if snr is not None and (snr.dtype != torch.float32 or snr.numel() < n or not snr.is_contiguous()):
+            raise ValueError("snr must be a contiguous float32 tensor of at least n elements")
+        if tau_idx is True:
+            tau_idx = torch.empty(n, dtype=torch.int32, device=dev)
+        if tau_idx is False:
+            tau_idx = None
+        if tau_idx is not None and (tau_idx.dtype != torch.int32 or tau_idx.numel() < n or not tau_idx.is_contiguous()):
+            raise ValueError("tau_idx must be a contiguous int32 tensor of at least n elements")
+        if best_key is None:
+            best_key = torch.zeros(1, dtype=torch.int64, device=dev)
+        mc = m.c()
+        g = gen.c() if gen is not None else None
+        self._chk(self._L.stt_score_maxdelay(self.h, C.byref(mc), C.byref(g) if g is not None else None,
+                                             C.c_void_p(tracks.data_ptr()) if tracks is not None else None,
+                                             first, n, dtau0, dtau_step, n_tau, norm,
+                                             C.c_void_p(snr.data_ptr()) if snr is not None else None,
+                                             C.c_void_p(tau_idx.data_ptr()) if tau_idx is not None else None,
+                                             C.c_void_p(best_key.data_ptr())))
+        return snr, tau_idx, best_key
+
     def pack_p16(self, m: Map) -> P16Map:
         """FP16 copy of the map's complex SNR p = Y/sigma with a per-map 2^e scale (synchronises)."""
         out = torch.empty((m.T, m.F, 2), dtype=torch.float16, device=m.Y.device)

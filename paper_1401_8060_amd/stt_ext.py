@@ -14,6 +14,7 @@ def bind(L) -> None:
         "stt_set_graph": ([vp, i32], i32),
         "stt_autotune": ([vp, vp, vp, i64, C.c_char_p, vp], i32),
         "stt_autotune_batch": ([vp, vp, i32, vp, vp, C.c_char_p, vp], i32),
+        "stt_score_maxdelay": ([vp, vp, vp, vp, i64, i64, i32, i32, i32, i32, vp, vp, vp], i32),
         "stt_tracks_at": ([vp, vp, i32, i32, vp, i64, vp], i32),
         "stt_tracks_to_theta": ([vp, vp, i64, vp, vp], i32),
         "stt_smooth": ([vp, vp, vp, vp, i32, vp], i32),
@@ -26,5 +27,5 @@ def bind(L) -> None:
         fn.restype = res
 
 
-EXPORTED = ["stt_map_pack_p16", "stt_topk", "stt_rescore_f64", "stt_score_batch", "stt_set_graph", "stt_autotune", "stt_autotune_batch",
+EXPORTED = ["stt_map_pack_p16", "stt_topk", "stt_rescore_f64", "stt_score_batch", "stt_set_graph", "stt_autotune", "stt_autotune_batch", "stt_score_maxdelay",
             "stt_tracks_at", "stt_tracks_to_theta", "stt_smooth", "stt_grad", "stt_refine"]
