@@ -55,6 +55,10 @@ WORKLOADS = {
     # differentiation: T=1000 x F=1000 with 8 injected tracks at SNR 5..10; top-1024 of 10^6 refined 50 steps
     "refine_1000x1000_1e6": dict(kind="refine", T=1000, F=1000, n=1_000_000, seed=5, L=10, dtau_s=0.01,
                                  sigma=("loguniform", 0.5, 2.0), K=1024, steps=50, n_inj=8, inject=None),
+    # delay-maximised: the search map, 10^6 templates each maximised over 16 delays spanning +-10 ms
+    "maxdelay_1000x1000_1e6x16": dict(kind="maxdelay", T=1000, F=1000, n=1_000_000, seed=2, L=10, dtau_s=0.01,
+                                      sigma=("loguniform", 0.5, 2.0), n_tau=16,
+                                      inject=(200, 799, 250.5, 600.25, 450.75)),
     # precision: T=2000 x F=2000 stored in FP16, 10^8 tracks, top-1024 re-scored in FP64
     "precision_2000x2000_1e8": dict(kind="precision", T=2000, F=2000, n=100_000_000, seed=4, L=10, dtau_s=0.01,
                                     sigma=("loguniform", 0.5, 2.0), K=1024,
@@ -333,6 +337,56 @@ def run_precision(args, name, w):
     return out
 
 
+def run_maxdelay(args, name, w):
+    import torch
+    import paper_1401_8060_amd.stt as stt
+    dtau_max = stt.dtau_units(w["dtau_s"])
+    log(f"bench: building map {w['T']}x{w['F']}")
+    Y, s, sha = make_map(w)
+    dev = torch.device("cuda:0")
+    m = stt.Map(torch.from_numpy(Y).to(dev), torch.from_numpy(s).to(dev))
+    ctx = stt.Context(0)
+    g = stt.Gen(seed=w["seed"], stream=0, min_len=w["L"], dtau_max=dtau_max)
+    n, nt = w["n"], w["n_tau"]
+    d0, step = -dtau_max, (2 * dtau_max) // (nt - 1)
+    px = count_px(ctx, g, w["T"], w["F"], n)
+    ctx.reserve(n)
+    snr = torch.empty(n, dtype=torch.float32, device=dev)
+    tidx = torch.empty(n, dtype=torch.int32, device=dev)
+    key = torch.zeros(1, dtype=torch.int64, device=dev)
+
+    def step_fn():
+        key.zero_()
+        ctx.score_maxdelay(m, d0, step, nt, gen=g, n=n, snr=snr, tau_idx=tidx, best_key=key)
+
+    for _ in range(args.warmup):
+        step_fn()
+    torch.cuda.synchronize()
+    ctx.set_timing(True)
+    ms_step = timed(argparse.Namespace(warmup=0, steps=args.steps), step_fn, torch)
+    score_ms, cnt = ctx.kernel_ms_total(stt.STAGE_SCORE)
+    ctx.set_timing(False)
+    kern_ms = score_ms / max(cnt, 1)
+    zk, jk = stt.decode_best(key)
+    mk = int(tidx[jk].item())
+    log(f"bench: {ms_step:.3f} ms/step, delay-grid scoring ({(nt + 7) // 8} launches) {kern_ms:.3f} ms; "
+        f"best z={zk:.4f} j={jk} delay index {mk} ({(d0 + mk * step) * 2.0 ** -28 * 1e3:.3f} ms)")
+    out = base_record(args, name, w, n, ms_step, px, "f32")
+    out["config"].update({"T": w["T"], "F": w["F"], "n_tracks": n, "n_tau": nt, "dtau0": d0, "dtau_step": step,
+                          "map_sha256": sha[:16]})
+    out["template_delays_per_s"] = n * nt / (ms_step * 1e-3)
+    # one template-delay pixel: phase (2), sine and cosine (2), term (3), accumulation (1); the row (4)
+    # is shared by the delays
+    flops = px * (4 + 8 * nt)
+    sec = kern_ms * 1e-3
+    out["roofline"] = {"bound": "alu", "achieved": flops / sec / 1e12, "peak": ALU_PEAK_TFLOPS, "unit": "TFLOP/s",
+                       "frac": flops / sec / 1e12 / ALU_PEAK_TFLOPS, "traffic": None, "kernel": "k_score_md_slab",
+                       "kernel_ms": kern_ms, "flops_per_track_px": 4 + 8 * nt}
+    out["best"] = {"z": zk, "j": jk, "delay_index": mk}
+    ctx.close()
+    return out
+
+
 def run_refine(args, name, w):
     import numpy as np
     import torch
@@ -406,7 +460,8 @@ def main():
               "or by map with no communication but a max, which is not implemented here.", file=sys.stderr)
         sys.exit(2)
     w = WORKLOADS[args.workload]
-    runner = {"single": run_single, "batch": run_batch, "precision": run_precision, "refine": run_refine}[w["kind"]]
+    runner = {"single": run_single, "batch": run_batch, "precision": run_precision, "refine": run_refine,
+              "maxdelay": run_maxdelay}[w["kind"]]
     out = runner(args, args.workload, w)
     if args.copy_probe_mb:
         import torch

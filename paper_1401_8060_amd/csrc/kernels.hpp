@@ -636,8 +636,14 @@ __global__ __launch_bounds__(1024) void k_reduce_keys(const uint64_t *keys, int6
 // The running maximum and its index live in snr / tidx between launches.
 constexpr int kMD = 8;
 
+// The grid is uniform, so at row r the phase of delay k of a launch is
+// phase_0(r) + k * dphase(r) (32-bit, exact): the first delay's phase factor
+// comes from the hardware sine and cosine exactly as in the plain scorer, and
+// each further one is the previous times exp(2 pi i dphase(r)), one complex
+// multiply (at most kMD - 1 = 7 in a row, a few 1e-7 relative).
 struct DelayGrid {
-    uint32_t pa[kMD], pb[kMD];  // phase constants of each delay (zero past cnt)
+    PhaseK k0;       // phase constants of the launch's first delay
+    PhaseK dk;       // phase constants of the grid step
     int32_t m0, cnt;
 };
 
@@ -646,14 +652,40 @@ __device__ __forceinline__ DelayGrid delay_grid(const MapP &m, int32_t d0, int32
     DelayGrid dg;
     dg.m0 = m0;
     dg.cnt = cnt;
-#pragma unroll
-    for (int k = 0; k < kMD; ++k) {
-        // in range for k < cnt (checked by the host); wrapping arithmetic for the rest
-        const int32_t d = (int32_t)((uint32_t)d0 + (uint32_t)(m0 + k) * (uint32_t)step);
-        dg.pa[k] = k < cnt ? phase_a(m.fq4_lo, d) : 0u;
-        dg.pb[k] = k < cnt ? phase_b(m.dfq4, d) : 0u;
-    }
+    const int32_t d = (int32_t)((uint32_t)d0 + (uint32_t)m0 * (uint32_t)step);  // in range (checked by the host)
+    dg.k0 = phase_k(m, d);
+    dg.dk = phase_k(m, step);
     return dg;
+}
+
+// Adds the template's Eq. 8 terms at `row` for all kMD delays of the launch.
+template <bool HW, bool MASK>
+__device__ __forceinline__ void add_terms_md(float (&part)[kMD], const DelayGrid &dg, int32_t row, float2 p, bool act)
+{
+    const float v0 = add_term<HW>(part[0], dg.k0, row, p);
+    part[0] = !MASK || act ? v0 : part[0];
+    float c, s, cr, sr;
+    if constexpr (HW) {
+        const float x0 = phase_turns(dg.k0.pa, dg.k0.pb, row), xr = phase_turns(dg.dk.pa, dg.dk.pb, row);
+        c = __builtin_amdgcn_cosf(x0);
+        s = __builtin_amdgcn_sinf(x0);
+        cr = __builtin_amdgcn_cosf(xr);
+        sr = __builtin_amdgcn_sinf(xr);
+    } else {
+        const uint32_t ph0 = dg.k0.pa + (uint32_t)row * dg.k0.pb, phr = dg.dk.pa + (uint32_t)row * dg.dk.pb;
+        c = rot_re(ph0, 1.0f, 0.0f);
+        s = rot_re(ph0 - 0x40000000u, 1.0f, 0.0f);  // cos(x - pi/2) = sin x
+        cr = rot_re(phr, 1.0f, 0.0f);
+        sr = rot_re(phr - 0x40000000u, 1.0f, 0.0f);
+    }
+#pragma unroll
+    for (int k = 1; k < kMD; ++k) {
+        const float cn = fmaf(c, cr, -s * sr), sn = fmaf(s, cr, c * sr);
+        c = cn;
+        s = sn;
+        const float v = fmaf(-s, p.y, fmaf(c, p.x, part[k]));
+        part[k] = !MASK || act ? v : part[k];
+    }
 }
 
 // The best of this launch's delays for one template, merged with the running
@@ -707,8 +739,7 @@ __global__ __launch_bounds__(kWG) void k_score_md_direct(MapP m, GenP g, const T
             for (int32_t k = 0; k < N; ++k) {
                 const int32_t row = ddaf_row(s);
                 const float2 p = load_p<MAPT>(m, base + row);
-#pragma unroll
-                for (int q = 0; q < kMD; ++q) part[q] = add_term<HW>(part[q], PhaseK{dg.pa[q], dg.pb[q]}, row, p);
+                add_terms_md<HW, false>(part, dg, row, p, true);
                 if (((t.t0 + k) & (kFlush - 1)) == kFlush - 1) {
 #pragma unroll
                     for (int q = 0; q < kMD; ++q) { acc[q] += part[q]; part[q] = 0.0f; }
@@ -743,11 +774,7 @@ __device__ __forceinline__ void walk_md(int ca, int cb, int c0, const float2 *sl
                 const int32_t row = ddaf_row(st[q]);
                 const bool act = !MASK || (uint32_t)c - (uint32_t)t0[q] <= span[q];
                 const float2 p = col[act ? row : 0];
-#pragma unroll
-                for (int k = 0; k < kMD; ++k) {
-                    const float v = add_term<HW>(part[q][k], PhaseK{dg.pa[k], dg.pb[k]}, row, p);
-                    part[q][k] = act ? v : part[q][k];
-                }
+                add_terms_md<HW, MASK>(part[q], dg, row, p, act);
                 ddaf_step(st[q]);
             }
         }

@@ -160,7 +160,8 @@ stt_status ensure_mdbuf(stt_ctx *c, size_t bytes)
 
 // Column stride of a folded map and the slab depth that two buffers of it allow.
 int64_t fold_ld(int F) { return ((int64_t)F + kDmaPix - 1) / kDmaPix * kDmaPix; }
-int dma_slab_cols(const stt_ctx *c, int64_t ldc) { return (int)std::min<int64_t>(64, (c->lds_bytes - 256) / (16 * ldc)); }
+int dma_slab_cols(int lds_bytes, int64_t ldc) { return (int)std::min<int64_t>(64, (lds_bytes - 256) / (16 * ldc)); }
+int dma_slab_cols(const stt_ctx *c, int64_t ldc) { return dma_slab_cols(c->lds_bytes, ldc); }
 
 stt_status check_map(stt_ctx *c, const stt_map *m)
 {
@@ -450,12 +451,15 @@ stt_status maxdelay_impl(stt_ctx *c, const stt_map *map, const GenP &g, const Tr
                          int32_t d0, int32_t step, int32_t n_tau, int32_t norm, float *snr, int32_t *tidx,
                          uint64_t *best)
 {
+    // 512 lanes x 2 templates, at most 80 KB of slabs: two workgroups per CU, the four waves per SIMD
+    // that the kernel's registers allow
     constexpr int kMdWG = 512, kMdTPT = 2;
+    const int lds = std::min(c->lds_bytes, 80 * 1024);
     const MapP m = to_mapp(map);
     const int64_t ldc = fold_ld(m.F);
-    bool slab = c->dma && dma_slab_cols(c, ldc) >= 1 && c->path != 1 && c->path != 3 && (c->path == 2 || n >= 4096);
+    bool slab = c->dma && dma_slab_cols(lds, ldc) >= 1 && c->path != 1 && c->path != 3 && (c->path == 2 || n >= 4096);
     if (c->path == 2 && !slab)
-        return fail(c, STT_EUNSUPPORTED, "F=%d too wide for two LDS slabs of %d bytes", m.F, c->lds_bytes);
+        return fail(c, STT_EUNSUPPORTED, "F=%d too wide for two LDS slabs of %d bytes", m.F, lds);
     stt_status s;
     if (!snr || !tidx) {
         if ((s = ensure_mdbuf(c, (sizeof(float) + sizeof(int32_t)) * (size_t)n)) != STT_OK) return s;
@@ -492,7 +496,7 @@ stt_status maxdelay_impl(stt_ctx *c, const stt_map *map, const GenP &g, const Tr
         mf.Y = (const float2 *)c->pbuf;
         mf.sig = nullptr;
         mf.ld = ldc;
-        const int S = std::min(dma_slab_cols(c, ldc), m.T);
+        const int S = std::min(dma_slab_cols(lds, ldc), m.T);
         const size_t shm = 2 * sizeof(float2) * (size_t)S * ldc;
         const unsigned grid = (unsigned)((n + kMdWG * kMdTPT - 1) / (kMdWG * kMdTPT));
         auto kh = k_score_md_slab<kMdWG, kMdTPT, EXPL, true>;
