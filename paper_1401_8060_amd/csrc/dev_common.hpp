@@ -243,11 +243,19 @@ STT_HD void ddaf_step(DdaF &s)
 STT_HD uint32_t phase_a(int32_t fq4_lo, int32_t dtau) { return (uint32_t)fq4_lo * (uint32_t)dtau; }
 STT_HD uint32_t phase_b(int32_t dfq4, int32_t dtau) { return (uint32_t)dfq4 * (uint32_t)dtau; }
 
-// The phase of row `row` as FP32 turns in [-1/2, 1/2]: the exact 32-bit phase,
-// read as signed and rounded once (at most 2^-26 turn off).
+// The phase of row `row` as FP32 turns in [1, 2) -- the hardware sine and
+// cosine take turns and reduce them exactly (measured on gfx950: the same
+// error on [1, 2) as on [0, 1)). The exact 32-bit phase plus half a unit of
+// the result is cut to its top 23 bits and spliced under the exponent of 1.0:
+// rounded to 23 fractional bits, at most 2^-24 turn off. One funnel shift.
 STT_HD float phase_turns(uint32_t pa, uint32_t pb, int32_t row)
 {
-    return (float)(int32_t)(pa + (uint32_t)row * pb) * 2.3283064365386963e-10f;
+    const uint32_t ph = pa + (uint32_t)row * pb + 256u;
+#if defined(__HIP_DEVICE_COMPILE__)
+    return __builtin_bit_cast(float, __builtin_amdgcn_alignbit(0x7Fu, ph, 9u));  // (0x7F:ph) >> 9
+#else
+    return __builtin_bit_cast(float, (0x7Fu << 23) | (ph >> 9));
+#endif
 }
 
 // Re[exp(2 pi i ph/2^32) (pr + i pi)]. The half-turn bit h = [ph in [1/4,3/4)

@@ -7,7 +7,7 @@
 //   rowsat t0 t2 f0 f1 f2 k0           -> N rows, DDA started at k0 <= 0 and stepped to 0
 //   rowsf t0 t2 f0 f1 f2 k0            -> N rows of the FP64 walk started at k0 <= 0
 //   rot   ph pr pi                     -> Re[exp(2 pi i ph/2^32)(pr + i pi)] as %.9e
-//   phx   fq4_lo dfq4 dtau row         -> the scorers' phase argument (FP32 turns in [-1/2, 1/2])
+//   phx   fq4_lo dfq4 dtau row         -> the scorers' phase argument (FP32 turns in [1, 2))
 //   key   z j                          -> 64-bit key (hex)
 #include <cmath>
 #include <cstdio>

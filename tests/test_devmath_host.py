@@ -148,8 +148,8 @@ def test_phase_rotation_accuracy(devmath):
 
 def test_phase_argument(devmath):
     """The scorers' sine/cosine argument is the Eq. 8 phase f*dtau in turns, f = (fq4_lo + row*dfq4)/16 Hz
-    and dtau in 2^-28 s, reduced to [-1/2, 1/2] and rounded once to FP32: within 2^-26 turn of the exact
-    value (mod 1), checked against rational arithmetic."""
+    and dtau in 2^-28 s, as an FP32 number in [1, 2) equal to the phase mod 1 rounded to 23 fractional
+    bits: within 2^-24 turn of the exact value (mod 1), checked against rational arithmetic."""
     sel = np.random.default_rng(21)
     cases = []
     for _ in range(20000):
@@ -161,8 +161,8 @@ def test_phase_argument(devmath):
         exact = Fraction((fq4 + row * dfq) * dtau, 2 ** 32)  # (fq4/16 Hz)(dtau 2^-28 s) turns
         err = (Fraction(float(np.float32(g))) - exact) % 1  # the printed FP32 value, read back exactly
         err = min(err, 1 - err)
-        assert err <= Fraction(1, 2 ** 26), (fq4, dfq, dtau, row, g)
-        assert -0.5 <= float(g) <= 0.5
+        assert err <= Fraction(1, 2 ** 24), (fq4, dfq, dtau, row, g)
+        assert 1.0 <= float(g) < 2.0
 
 
 def test_key_order_and_special_values(devmath):
