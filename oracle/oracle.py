@@ -20,6 +20,9 @@ DTAU_UNIT_S = 2.0 ** -28  # time delays are integers in units of 2^-28 s
 
 TRACK_DTYPE = np.dtype([("t0", "<i4"), ("t2", "<i4"), ("f0", "<u4"), ("f1", "<u4"),
                         ("f2", "<u4"), ("dtau", "<i4")])
+# a template with a free t_mid (integer t1 in [t0, t2])
+TRACK_TM_DTYPE = np.dtype([("t0", "<i4"), ("t1", "<i4"), ("t2", "<i4"), ("f0", "<u4"), ("f1", "<u4"),
+                           ("f2", "<u4"), ("dtau", "<i4")])
 
 
 class _Track(C.Structure):
@@ -65,6 +68,16 @@ def lib():
                                         C.c_void_p, C.c_int64, C.c_int32, C.c_void_p]
         L.orc_score_gen_idx.restype = C.c_int
         L.orc_score_list.argtypes = [C.POINTER(_Map), C.c_void_p, C.c_int64, C.c_int32, C.c_void_p]
+        L.orc_draw_tm.argtypes = [C.c_uint64, C.c_uint32, C.c_uint64, C.c_int32, C.c_int32, C.c_int32, C.c_int32,
+                                  C.c_void_p]
+        L.orc_draw_tm.restype = C.c_int
+        L.orc_rows_tm.argtypes = [C.c_void_p, C.c_int32, C.c_void_p]
+        L.orc_rows_tm.restype = C.c_int
+        L.orc_score_tm_gen_idx.argtypes = [C.POINTER(_Map), C.c_uint64, C.c_uint32, C.c_int32, C.c_int32, C.c_void_p,
+                                           C.c_int64, C.c_int32, C.c_void_p]
+        L.orc_score_tm_gen_idx.restype = C.c_int
+        L.orc_score_tm_list.argtypes = [C.POINTER(_Map), C.c_void_p, C.c_int64, C.c_int32, C.c_void_p]
+        L.orc_score_tm_list.restype = C.c_int
         L.orc_score_maxdelay_gen_idx.argtypes = [C.POINTER(_Map), C.c_uint64, C.c_uint32, C.c_int32, C.c_int32,
                                                  C.c_void_p, C.c_int64, C.c_int32, C.c_int32, C.c_int32,
                                                  C.c_int32, C.c_void_p, C.c_void_p]
@@ -201,6 +214,39 @@ def score_list(m: Map, tracks: np.ndarray, norm: int = NORM_SQRT_N) -> np.ndarra
     tracks = np.ascontiguousarray(np.asarray(tracks, dtype=TRACK_DTYPE))
     z = np.zeros(tracks.size, dtype=np.float64)
     lib().orc_score_list(C.byref(m.c), tracks.ctypes.data, tracks.size, norm, z.ctypes.data)
+    return z
+
+
+def draw_tm_many(seed: int, stream: int, first: int, n: int, T: int, F: int, L: int, D: int) -> np.ndarray:
+    """Free-t_mid templates j = first .. first+n-1 (TRACK_TM_DTYPE)."""
+    out = np.zeros(n, dtype=TRACK_TM_DTYPE)
+    for i in range(n):
+        if lib().orc_draw_tm(seed, stream, first + i, T, F, L, D, out[i:i + 1].ctypes.data) != 0:
+            raise ValueError("invalid draw parameters")
+    return out
+
+
+def rows_tm(track, F: int) -> np.ndarray:
+    t = np.ascontiguousarray(np.asarray(track, dtype=TRACK_TM_DTYPE).reshape(1))
+    rows = np.zeros(int(t["t2"][0]) - int(t["t0"][0]) + 1, dtype=np.int32)
+    if lib().orc_rows_tm(t.ctypes.data, F, rows.ctypes.data) < 0:
+        raise ValueError("invalid track")
+    return rows
+
+
+def score_tm_gen_idx(m: Map, seed: int, stream: int, L: int, D: int, idx, norm: int = NORM_SQRT_N) -> np.ndarray:
+    idx = np.ascontiguousarray(np.asarray(idx, dtype=np.uint64))
+    z = np.zeros(idx.size, dtype=np.float64)
+    if lib().orc_score_tm_gen_idx(C.byref(m.c), seed, stream, L, D, idx.ctypes.data, idx.size, norm,
+                                  z.ctypes.data) != 0:
+        raise ValueError("invalid parameters")
+    return z
+
+
+def score_tm_list(m: Map, tracks: np.ndarray, norm: int = NORM_SQRT_N) -> np.ndarray:
+    tracks = np.ascontiguousarray(np.asarray(tracks, dtype=TRACK_TM_DTYPE))
+    z = np.zeros(tracks.size, dtype=np.float64)
+    lib().orc_score_tm_list(C.byref(m.c), tracks.ctypes.data, tracks.size, norm, z.ctypes.data)
     return z
 
 

@@ -243,6 +243,127 @@ int orc_score_list(const orc_map *m, const orc_track *tr, int64_t n, int32_t nor
 }
 
 /* ------------------------------------------------------------------------ */
+/* Templates with a free t_mid (Eq. 6 with all six random numbers). The     */
+/* time coordinate is itself a quadratic Bezier, t(xi) = (1-xi)^2 t0 +      */
+/* 2 xi (1-xi) t1 + xi^2 t2 with an integer t1 in [t0, t2] (so t(xi) is     */
+/* monotone); drawn from the last unused word of the template's second      */
+/* Philox block: t1 = t0 + floor(x * (t2 - t0 + 1) / 2^32). The template    */
+/* still takes one pixel per column: at column t, xi(t) is the root in      */
+/* [0, 1] of a xi^2 + b xi + c = 0 with a = t0 - 2 t1 + t2, b = 2 (t1 - t0),  */
+/* c = t0 - t, and the row is floor(f(xi)/256) with f the frequency Bezier  */
+/* (1/256-row units). For a = 0 (t1 at the midpoint) this is the rasteriser */
+/* above. For a != 0, eliminating xi^2 with the quadratic gives             */
+/*   f(xi) / 256 = (U + V sqrt(D)) / W,  D = b^2 - 4 a c,                    */
+/*   V = a B - C b,  U = 2 a (a f0 - C c) - b V,  W = 512 a^2,               */
+/* B = 2 (f1 - f0), C = f0 - 2 f1 + f2 -- all integers -- and the floor is    */
+/* decided exactly in 128-bit integers: r <= (U + V sqrt D)/W  iff           */
+/* V sqrt(D) >= r W - U, compared by signs and then squares.                */
+/* ------------------------------------------------------------------------ */
+typedef struct {
+    int32_t t0, t1, t2;
+    uint32_t f0, f1, f2;
+    int32_t dtau;
+} orc_track_tm;
+
+int orc_draw_tm(uint64_t seed, uint32_t stream, uint64_t j, int32_t T, int32_t F, int32_t L, int32_t D,
+                orc_track_tm *tr)
+{
+    orc_track b;
+    if (orc_draw(seed, stream, j, T, F, L, D, &b) != 0) return -1;
+    uint32_t key[2] = {(uint32_t)seed, (uint32_t)(seed >> 32)};
+    uint32_t c1[4] = {(uint32_t)j, (uint32_t)(j >> 32), stream, 1u}, x1[4];
+    orc_philox4x32_10(c1, key, x1);
+    tr->t0 = b.t0;
+    tr->t2 = b.t2;
+    tr->t1 = b.t0 + (int32_t)(((uint64_t)x1[3] * (uint64_t)(b.t2 - b.t0 + 1)) >> 32);
+    tr->f0 = b.f0;
+    tr->f1 = b.f1;
+    tr->f2 = b.f2;
+    tr->dtau = b.dtau;
+    return 0;
+}
+
+/* sign of V sqrt(D) - X (D >= 0), exactly */
+static int cmp_vsqrtd(int64_t V, int64_t D, int64_t X)
+{
+    if (D == 0 || V == 0) return (X < 0) - (X > 0);
+    if (V > 0 && X <= 0) return 1;
+    if (V < 0 && X >= 0) return -1;
+    unsigned __int128 av = (unsigned __int128)(V > 0 ? V : -V), ax = (unsigned __int128)(X > 0 ? X : -X);
+    unsigned __int128 l = av * av * (unsigned __int128)D, r = ax * ax;
+    int c = (l > r) - (l < r); /* |V| sqrt D vs |X| */
+    return V > 0 ? c : -c;
+}
+
+int orc_rows_tm(const orc_track_tm *tr, int32_t F, int32_t *rows)
+{
+    int64_t Dt = (int64_t)tr->t2 - tr->t0;
+    if (Dt < 1 || tr->t1 < tr->t0 || tr->t1 > tr->t2) return -1;
+    uint64_t lim = (uint64_t)F << ORC_FBITS;
+    if (tr->f0 >= lim || tr->f1 >= lim || tr->f2 >= lim) return -1;
+    int64_t a = (int64_t)tr->t0 - 2 * (int64_t)tr->t1 + tr->t2, b = 2 * ((int64_t)tr->t1 - tr->t0);
+    if (a == 0) {
+        orc_track q = {tr->t0, tr->t2, tr->f0, tr->f1, tr->f2, tr->dtau};
+        return orc_rows(&q, F, rows);
+    }
+    int64_t f0 = tr->f0, B = 2 * ((int64_t)tr->f1 - f0), C = f0 - 2 * (int64_t)tr->f1 + (int64_t)tr->f2;
+    int64_t V = a * B - C * b, W = 512 * a * a;
+    for (int64_t k = 0; k <= Dt; ++k) {
+        int64_t c = -k; /* t0 - t */
+        int64_t D = b * b - 4 * a * c, U = 2 * a * (a * f0 - C * c) - b * V;
+        /* largest r in [0, F) with U + V sqrt(D) - r W >= 0; the value lies in [0, F) */
+        int32_t lo = 0, hi = F - 1;
+        while (lo < hi) {
+            int32_t mid = lo + (hi - lo + 1) / 2;
+            if (cmp_vsqrtd(V, D, (int64_t)mid * W - U) >= 0) lo = mid; else hi = mid - 1;
+        }
+        rows[k] = lo;
+    }
+    return (int)(Dt + 1);
+}
+
+/* Eq. 8 of a free-t_mid template (FP64, Neumaier), as orc_score */
+double orc_score_tm(const orc_map *m, const orc_track_tm *tr, int32_t norm)
+{
+    if (tr->t0 < 0 || tr->t2 >= m->T || tr->t2 <= tr->t0) return NAN;
+    int32_t N = tr->t2 - tr->t0 + 1;
+    int32_t *rows = (int32_t *)malloc(sizeof(int32_t) * (size_t)N);
+    if (orc_rows_tm(tr, m->F, rows) < 0) { free(rows); return NAN; }
+    double s = 0.0, c = 0.0;
+    for (int32_t k = 0; k < N; ++k) {
+        int64_t t = tr->t0 + k, r = rows[k];
+        int64_t e = t * m->ld + r;
+        double sg = m->sigma[e];
+        double p_re = m->Y[2 * e] / sg, p_im = m->Y[2 * e + 1] / sg;
+        double phi = 2.0 * M_PI * orc_phase_turns((int64_t)m->fq4_lo + r * m->dfq4, tr->dtau);
+        double term = cos(phi) * p_re - sin(phi) * p_im;
+        double nt = s + term;
+        if (fabs(s) >= fabs(term)) c += (s - nt) + term; else c += (term - nt) + s;
+        s = nt;
+    }
+    free(rows);
+    double S = s + c;
+    return norm == 1 ? S / (double)N : S / sqrt((double)N);
+}
+
+int orc_score_tm_gen_idx(const orc_map *m, uint64_t seed, uint32_t stream, int32_t L, int32_t D,
+                         const uint64_t *idx, int64_t n, int32_t norm, double *z)
+{
+    for (int64_t i = 0; i < n; ++i) {
+        orc_track_tm tr;
+        if (orc_draw_tm(seed, stream, idx[i], m->T, m->F, L, D, &tr) != 0) return -1;
+        z[i] = orc_score_tm(m, &tr, norm);
+    }
+    return 0;
+}
+
+int orc_score_tm_list(const orc_map *m, const orc_track_tm *tr, int64_t n, int32_t norm, double *z)
+{
+    for (int64_t i = 0; i < n; ++i) z[i] = orc_score_tm(m, &tr[i], norm);
+    return 0;
+}
+
+/* ------------------------------------------------------------------------ */
 /* Delay-maximised statistic: the reading of "phase-maximised" that takes,   */
 /* per template, the maximum of Eq. 8 over a grid of delays instead of one   */
 /* drawn delay. The template's geometry (t0, t2, f0, f1, f2) is kept and its */
