@@ -71,7 +71,16 @@ typedef struct {
     int32_t t0, t2;       /* first and last column, 0 <= t0 < t2 < T */
     uint32_t f0, f1, f2;  /* control frequencies, 1/256-row units, < F*256 */
     int32_t dtau;         /* time delay, units of 2^-28 s */
-} stt_track;              /* 24 bytes */
+} stt_track;
+
+/* A template with a free t_mid (Eq. 6 with all six random numbers): the time
+ * coordinate is a quadratic Bezier with control points t0, t1, t2 (integer
+ * columns, t0 <= t1 <= t2); other fields as stt_track. 28 bytes. */
+typedef struct {
+    int32_t t0, t1, t2;
+    uint32_t f0, f1, f2;
+    int32_t dtau;
+} stt_track_tm;              /* 24 bytes */
 
 typedef struct {
     uint64_t seed;     /* Philox4x32-10 key (low word, high word) */
@@ -179,6 +188,18 @@ stt_status stt_score(stt_ctx *ctx, const stt_map *map, const stt_gen *gen, const
  * key of (max, j) is max-merged into *best_key_dev (may be NULL). Requires
  * 1 <= n_tau <= 65536 and every grid delay in (-2^30, 2^30). The row walk and
  * the pixel gathers are shared by the delays (8 per kernel launch). */
+/* Free-t_mid templates (an addition: the paper's six random numbers, with t_mid
+ * free instead of at the midpoint). Generation as stt_make_tracks, plus
+ * t1 = t0 + floor(x * (t2 - t0 + 1) / 2^32) from the last word x of the second
+ * Philox block. Scoring as stt_score (Eq. 8, one pixel per column): at column
+ * t the row is floor(f(xi)/256), xi the root in [0, 1] of t(xi) = t, computed
+ * exactly (FP64 with an exact 128-bit integer decision near row boundaries).
+ * One wave per template. */
+stt_status stt_make_tracks_tm(stt_ctx *ctx, const stt_gen *gen, int32_t T, int32_t F, int64_t first, int64_t n,
+                              stt_track_tm *out_dev);
+stt_status stt_score_tm(stt_ctx *ctx, const stt_map *map, const stt_gen *gen, const stt_track_tm *tracks_dev,
+                        int64_t first, int64_t n, int32_t norm, float *snr_dev, uint64_t *best_key_dev);
+
 stt_status stt_score_maxdelay(stt_ctx *ctx, const stt_map *map, const stt_gen *gen, const stt_track *tracks_dev,
                               int64_t first, int64_t n, int32_t dtau0, int32_t dtau_step, int32_t n_tau, int32_t norm,
                               float *snr_dev, int32_t *tau_idx_dev, uint64_t *best_key_dev);

@@ -103,6 +103,101 @@ STT_HD Trk draw_track(const GenP &g, uint64_t j)
 }
 
 // ----------------------------------------------------------------------------
+// Templates with a free t_mid (Eq. 6 with its six random numbers): the time
+// coordinate is a quadratic Bezier too, with an integer t1 in [t0, t2] drawn
+// from the last word of the second Philox block. Other fields as draw_track.
+// ----------------------------------------------------------------------------
+struct TrkTm {
+    int32_t t0, t1, t2;
+    uint32_t f0, f1, f2;
+    int32_t dtau;
+};
+
+STT_HD TrkTm draw_track_tm(const GenP &g, uint64_t j)
+{
+    const Trk b = draw_track(g, j);
+    const u32x4 x1 = philox_block(g, j, 1);
+    TrkTm t;
+    t.t0 = b.t0;
+    t.t2 = b.t2;
+    t.t1 = b.t0 + (int32_t)mulhi32(x1.w, (uint32_t)(b.t2 - b.t0 + 1));
+    t.f0 = b.f0;
+    t.f1 = b.f1;
+    t.f2 = b.f2;
+    t.dtau = b.dtau;
+    return t;
+}
+
+// Row of a free-t_mid template at column t0 + dt. With a = t0 - 2 t1 + t2,
+// b = 2 (t1 - t0), the column's xi is the root in [0, 1] of
+// a xi^2 + b xi - dt = 0 and the row is floor(f(xi) / 256). For a != 0,
+// eliminating xi^2 gives f/256 = (U + V sqrt(D)) / W with the integers
+// D = b^2 + 4 a dt, V = a B - C b, U = U0 + U1 dt (U0 = 2 a^2 f0 - b V,
+// U1 = 2 a C), W = 512 a^2 (B = 2 (f1 - f0), C = f0 - 2 f1 + f2).
+// FP64 evaluates xi = 2 dt / (b + sqrt(D)) (no cancellation) and
+// f = f0 + xi (B + C xi), within about 2^-33 row of the truth; a value within
+// 1e-6 of an integer (end columns, perfect squares) is settled exactly by the
+// sign of V sqrt(D) - (r W - U), from signs and 128-bit squares. For a = 0 (t1
+// at the midpoint) xi = dt / Dt and the row is the plain rasteriser's.
+struct RowTm {
+    int64_t a, b, V, U0, U1, W, A0, B0, C0, Q0;  // A0..Q0: the a = 0 (linear) case
+    double fd, Bd, Cd, bd;
+    uint32_t f0;
+};
+
+STT_HD RowTm row_tm_init(const TrkTm &t)
+{
+    RowTm k;
+    const int64_t f0 = t.f0, f1 = t.f1, f2 = t.f2;
+    const int64_t B = 2 * (f1 - f0), C = f0 - 2 * f1 + f2;
+    k.a = (int64_t)t.t0 - 2 * (int64_t)t.t1 + t.t2;
+    k.b = 2 * ((int64_t)t.t1 - t.t0);
+    k.V = k.a * B - C * k.b;
+    k.U0 = 2 * k.a * k.a * f0 - k.b * k.V;
+    k.U1 = 2 * k.a * C;
+    k.W = 512 * k.a * k.a;
+    const int64_t Dt = (int64_t)t.t2 - t.t0;
+    k.A0 = Dt * Dt * f0;
+    k.B0 = 2 * Dt * (f1 - f0);
+    k.C0 = C;
+    k.Q0 = (Dt * Dt) << 8;
+    k.fd = (double)f0;
+    k.Bd = (double)B;
+    k.Cd = (double)C;
+    k.bd = (double)k.b;
+    k.f0 = t.f0;
+    return k;
+}
+
+// sign of V sqrt(D) - X for D >= 0, exactly
+STT_HD int cmp_vsqrtd(int64_t V, int64_t D, int64_t X)
+{
+    if (D == 0 || V == 0) return (X < 0) - (X > 0);
+    if (V > 0 && X <= 0) return 1;
+    if (V < 0 && X >= 0) return -1;
+    const unsigned __int128 av = (unsigned __int128)(V > 0 ? V : -V), ax = (unsigned __int128)(X > 0 ? X : -X);
+    const unsigned __int128 l = av * av * (unsigned __int128)(uint64_t)D, r = ax * ax;
+    const int c = (l > r) - (l < r);
+    return V > 0 ? c : -c;
+}
+
+STT_HD int32_t row_tm(const RowTm &k, int32_t dt)
+{
+    if (k.a == 0) {  // linear time: num(dt) / Q exactly (num < 2^48)
+        const int64_t num = k.A0 + k.B0 * dt + k.C0 * (int64_t)dt * dt;
+        return (int32_t)(num / k.Q0);
+    }
+    if (dt == 0) return (int32_t)(k.f0 >> 8);
+    const int64_t D = k.b * k.b + 4 * k.a * dt;
+    const double xi = 2.0 * (double)dt / (k.bd + sqrt((double)D));
+    const double y = fma(xi, fma(xi, k.Cd, k.Bd), k.fd) * (1.0 / 256.0);
+    const double r = floor(y);
+    if (y - r > 1e-6 && y - r < 1.0 - 1e-6) return (int32_t)r;
+    const int64_t r0 = (int64_t)floor(y + 0.5);  // the nearest integer: the floor is r0 or r0 - 1
+    return (int32_t)(cmp_vsqrtd(k.V, D, r0 * k.W - (k.U0 + k.U1 * dt)) >= 0 ? r0 : r0 - 1);
+}
+
+// ----------------------------------------------------------------------------
 // Exact rasteriser of Eq. 6 as a second-order DDA.
 // With Dt = t2 - t0 and k = 0..Dt, row(k) = floor(num(k) / Q) where
 //   num(k) = (Dt-k)^2 f0 + 2 (Dt-k) k f1 + k^2 f2 = A + B k + C k^2,

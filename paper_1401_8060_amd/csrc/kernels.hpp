@@ -626,6 +626,55 @@ __global__ __launch_bounds__(1024) void k_reduce_keys(const uint64_t *keys, int6
     }
 }
 
+// ---------------------------------------------------------------- templates with a free t_mid
+// A free-t_mid template's rows have no recurrence: each column's row is an
+// independent root (row_tm). One wave per template, lane l taking columns
+// t0 + l, t0 + l + 64, ...: each lane sums its terms in FP32 (at most 46),
+// then the wave adds the lanes' sums in FP64 by a butterfly, the same total in
+// every lane. Four templates per workgroup.
+
+__device__ __forceinline__ bool track_tm_ok(const TrkTm &t, const MapP &m)
+{
+    const uint32_t lim = (uint32_t)m.F << 8;
+    return t.t0 >= 0 && t.t0 < t.t2 && t.t2 < m.T && t.t1 >= t.t0 && t.t1 <= t.t2 && t.f0 < lim && t.f1 < lim &&
+           t.f2 < lim;
+}
+
+__global__ __launch_bounds__(256) void k_make_tracks_tm(GenP g, uint64_t first, int64_t n, TrkTm *out)
+{
+    const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    if (i < n) out[i] = draw_track_tm(g, first + (uint64_t)i);
+}
+
+template <bool EXPL, bool HW, int MAPT>
+__global__ __launch_bounds__(256) void k_score_tm(MapP m, GenP g, const TrkTm *tr, uint64_t first, int64_t n,
+                                                  int32_t norm, float *snr, uint64_t *best)
+{
+    const int lane = threadIdx.x & 63;
+    const int64_t i = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);  // wave-uniform
+    uint64_t key = 0;
+    if (i < n) {
+        const TrkTm t = EXPL ? tr[i] : draw_track_tm(g, first + (uint64_t)i);
+        float z = __builtin_nanf("");
+        if (!EXPL || track_tm_ok(t, m)) {
+            const RowTm k = row_tm_init(t);
+            const PhaseK pk = phase_k(m, t.dtau);
+            float part = 0.0f;
+            for (int32_t dt = lane; dt <= t.t2 - t.t0; dt += 64) {
+                const int32_t row = row_tm(k, dt);
+                part = add_term<HW>(part, pk, row, load_p<MAPT>(m, (int64_t)(t.t0 + dt) * m.ld + row));
+            }
+            double sum = part;
+#pragma unroll
+            for (int off = 32; off > 0; off >>= 1) sum += __shfl_xor(sum, off);
+            z = finish(sum, t.t2 - t.t0 + 1, norm);
+        }
+        if (lane == 0 && snr) snr[i] = z;
+        key = key_encode(z, (uint32_t)(first + (uint64_t)i));
+    }
+    merge_key(best, key);
+}
+
 // ---------------------------------------------------------------- delay-maximised scoring
 // The maximum of Eq. 8 over a grid of delays per template (a reading of
 // "phase-maximised"): the template keeps its geometry and its own delay is

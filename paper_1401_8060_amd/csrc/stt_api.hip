@@ -746,6 +746,64 @@ stt_status stt_score_maxdelay(stt_ctx *c, const stt_map *map, const stt_gen *gen
                                                tau_idx_dev, best_key_dev);
 }
 
+stt_status stt_make_tracks_tm(stt_ctx *c, const stt_gen *gen, int32_t T, int32_t F, int64_t first, int64_t n,
+                              stt_track_tm *out_dev)
+{
+    if (!c) return STT_EINVAL;
+    stt_status s = check_range(c, first, n);
+    if (s != STT_OK) return s;
+    GenP g;
+    if ((s = make_genp(c, gen, T, F, g)) != STT_OK) return s;
+    if (n == 0) return STT_OK;
+    if (!out_dev) return fail(c, STT_EINVAL, "out_dev is NULL");
+    STT_HIP(c, hipSetDevice(c->device));
+    hipLaunchKernelGGL(k_make_tracks_tm, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, c->stream, g,
+                       (uint64_t)first, n, (TrkTm *)out_dev);
+    STT_HIP(c, hipGetLastError());
+    return STT_OK;
+}
+
+stt_status stt_score_tm(stt_ctx *c, const stt_map *map, const stt_gen *gen, const stt_track_tm *tracks_dev,
+                        int64_t first, int64_t n, int32_t norm, float *snr_dev, uint64_t *best_key_dev)
+{
+    if (!c) return STT_EINVAL;
+    stt_status s = check_map(c, map);
+    if (s != STT_OK) return s;
+    if ((s = check_range(c, first, n)) != STT_OK) return s;
+    if (norm != STT_NORM_SQRT_N && norm != STT_NORM_N) return fail(c, STT_EINVAL, "norm=%d", norm);
+    GenP g{};
+    if (!tracks_dev) {
+        if ((s = make_genp(c, gen, map->T, map->F, g)) != STT_OK) return s;
+    }
+    if (n == 0) return STT_OK;
+    STT_HIP(c, hipSetDevice(c->device));
+    const MapP m = to_mapp(map);
+    const TrkTm *tr = (const TrkTm *)tracks_dev;
+    const dim3 grid((unsigned)((n + 3) / 4)), block(256);
+    if ((s = ev_begin(c)) != STT_OK) return s;
+    ev_record(c, 4);
+    ev_record(c, 0);
+#define STT_TM_LAUNCH(E, H, M)                                                                                  \
+    hipLaunchKernelGGL((k_score_tm<E, H, M>), grid, block, 0, c->stream, m, g, tr, (uint64_t)first, n, norm,  \
+                       snr_dev, best_key_dev)
+    const bool p16 = map->dtype == STT_P16;
+    if (tracks_dev) {
+        if (p16) { if (c->hw_trig) STT_TM_LAUNCH(true, true, kMapP16); else STT_TM_LAUNCH(true, false, kMapP16); }
+        else { if (c->hw_trig) STT_TM_LAUNCH(true, true, kMapF32); else STT_TM_LAUNCH(true, false, kMapF32); }
+    } else {
+        if (p16) { if (c->hw_trig) STT_TM_LAUNCH(false, true, kMapP16); else STT_TM_LAUNCH(false, false, kMapP16); }
+        else { if (c->hw_trig) STT_TM_LAUNCH(false, true, kMapF32); else STT_TM_LAUNCH(false, false, kMapF32); }
+    }
+#undef STT_TM_LAUNCH
+    STT_HIP(c, hipGetLastError());
+    ev_record(c, 1);
+    c->used[0] = true;
+    ev_record(c, 5);
+    c->used[2] = true;
+    ev_end(c);
+    return STT_OK;
+}
+
 stt_status stt_argmax(stt_ctx *c, const float *snr_dev, int64_t n, int64_t first, uint64_t *best_key_dev)
 {
     if (!c) return STT_EINVAL;

@@ -293,6 +293,42 @@ class Context:
                                     C.c_void_p(best_key.data_ptr())))
         return snr, best_key
 
+    def make_tracks_tm(self, gen: Gen, T: int, F: int, first: int, n: int) -> torch.Tensor:
+        """Free-t_mid templates j = first .. first+n-1 as an [n][7] int32 tensor (t0, t1, t2, f0, f1, f2, dtau)."""
+        out = torch.empty((max(n, 1), 7), dtype=torch.int32, device="cuda")
+        g = gen.c()
+        self._chk(self._L.stt_make_tracks_tm(self.h, C.byref(g), T, F, first, n, C.c_void_p(out.data_ptr())))
+        return out[:n]
+
+    def score_tm(self, m: Map, gen: Gen | None = None, tracks: torch.Tensor | None = None, first: int = 0,
+                 n: int | None = None, norm: int = NORM_SQRT_N, snr: torch.Tensor | bool | None = True,
+                 best_key: torch.Tensor | None = None):
+        """Score free-t_mid templates (generated from gen, or the given [n][7] int32 tracks): (snr, best_key)."""
+        if tracks is not None:
+            if tracks.dtype != torch.int32 or tracks.dim() != 2 or tracks.shape[1] != 7 or not tracks.is_contiguous():
+                raise ValueError("tracks must be a contiguous [n][7] int32 tensor")
+            if n is None:
+                n = tracks.shape[0]
+            if n > tracks.shape[0]:
+                raise ValueError("n exceeds the number of given tracks")
+        if n is None:
+            raise ValueError("n is required with generated tracks")
+        if snr is True:
+            snr = torch.empty(n, dtype=torch.float32, device=m.Y.device)
+        if snr is False:
+            snr = None
+        if snr is not None and (snr.dtype != torch.float32 or snr.numel() < n or not snr.is_contiguous()):
+            raise ValueError("snr must be a contiguous float32 tensor of at least n elements")
+        if best_key is None:
+            best_key = torch.zeros(1, dtype=torch.int64, device=m.Y.device)
+        mc = m.c()
+        g = gen.c() if gen is not None else None
+        self._chk(self._L.stt_score_tm(self.h, C.byref(mc), C.byref(g) if g is not None else None,
+                                       C.c_void_p(tracks.data_ptr()) if tracks is not None else None, first, n,
+                                       norm, C.c_void_p(snr.data_ptr()) if snr is not None else None,
+                                       C.c_void_p(best_key.data_ptr())))
+        return snr, best_key
+
     def score_maxdelay(self, m: Map, dtau0: int, dtau_step: int, n_tau: int, gen: Gen | None = None,
                        tracks: torch.Tensor | None = None, first: int = 0, n: int | None = None,
                        norm: int = NORM_SQRT_N, snr: torch.Tensor | bool | None = True,

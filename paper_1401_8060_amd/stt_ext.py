@@ -15,6 +15,8 @@ def bind(L) -> None:
         "stt_autotune": ([vp, vp, vp, i64, C.c_char_p, vp], i32),
         "stt_autotune_batch": ([vp, vp, i32, vp, vp, C.c_char_p, vp], i32),
         "stt_score_maxdelay": ([vp, vp, vp, vp, i64, i64, i32, i32, i32, i32, vp, vp, vp], i32),
+        "stt_make_tracks_tm": ([vp, vp, i32, i32, i64, i64, vp], i32),
+        "stt_score_tm": ([vp, vp, vp, vp, i64, i64, i32, vp, vp], i32),
         "stt_tracks_at": ([vp, vp, i32, i32, vp, i64, vp], i32),
         "stt_tracks_to_theta": ([vp, vp, i64, vp, vp], i32),
         "stt_smooth": ([vp, vp, vp, vp, i32, vp], i32),
@@ -28,4 +30,5 @@ def bind(L) -> None:
 
 
 EXPORTED = ["stt_map_pack_p16", "stt_topk", "stt_rescore_f64", "stt_score_batch", "stt_set_graph", "stt_autotune", "stt_autotune_batch", "stt_score_maxdelay",
+            "stt_make_tracks_tm", "stt_score_tm",
             "stt_tracks_at", "stt_tracks_to_theta", "stt_smooth", "stt_grad", "stt_refine"]

@@ -9,6 +9,8 @@
 //   rot   ph pr pi                     -> Re[exp(2 pi i ph/2^32)(pr + i pi)] as %.9e
 //   phx   fq4_lo dfq4 dtau row         -> the scorers' phase argument (FP32 turns in [1, 2))
 //   key   z j                          -> 64-bit key (hex)
+//   drawtm seed stream j T F L D       -> t0 t1 t2 f0 f1 f2 dtau (free t_mid)
+//   rowstm t0 t1 t2 f0 f1 f2           -> N rows of a free-t_mid template
 #include <cmath>
 #include <cstdio>
 #include <cstring>
@@ -42,6 +44,30 @@ int main()
             draw_extent(g, j, a, b);
             if (a != t.t0 || b != t.t2) return 3;
             std::printf("%d %d %u %u %u %d\n", t.t0, t.t2, t.f0, t.f1, t.f2, t.dtau);
+        } else if (!std::strcmp(cmd, "drawtm")) {
+            unsigned long long seed, j;
+            unsigned stream;
+            int T, F, L, D;
+            if (std::scanf("%llu %u %llu %d %d %d %d", &seed, &stream, &j, &T, &F, &L, &D) != 7) return 2;
+            GenP g;
+            const long long npos = T - L + 1;
+            g.key0 = (uint32_t)seed;
+            g.key1 = (uint32_t)(seed >> 32);
+            g.stream = stream;
+            g.npairs = (uint32_t)(npos * (npos + 1) / 2);
+            g.L = L;
+            g.frange = (uint32_t)F << 8;
+            g.dmax = D;
+            g.dspan = 2u * (uint32_t)D + 1u;
+            const TrkTm t = draw_track_tm(g, j);
+            std::printf("%d %d %d %u %u %u %d\n", t.t0, t.t1, t.t2, t.f0, t.f1, t.f2, t.dtau);
+        } else if (!std::strcmp(cmd, "rowstm")) {
+            TrkTm t;
+            if (std::scanf("%d %d %d %u %u %u", &t.t0, &t.t1, &t.t2, &t.f0, &t.f1, &t.f2) != 6) return 2;
+            t.dtau = 0;
+            const RowTm k = row_tm_init(t);
+            for (int dt = 0; dt <= t.t2 - t.t0; ++dt) std::printf(dt ? " %d" : "%d", row_tm(k, dt));
+            std::printf("\n");
         } else if (!std::strcmp(cmd, "rows")) {
             Trk t;
             if (std::scanf("%d %d %u %u %u", &t.t0, &t.t2, &t.f0, &t.f1, &t.f2) != 5) return 2;

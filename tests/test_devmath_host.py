@@ -18,6 +18,8 @@ from fractions import Fraction
 import numpy as np
 import pytest
 
+D10MS = 2684355  # 10 ms in 2^-28 s units
+
 ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 
 
@@ -175,3 +177,36 @@ def test_key_order_and_special_values(devmath):
     assert keys[0] < keys[1] < keys[2] < keys[3] < keys[4]
     assert keys[4] < keys[5] < keys[6] < keys[7] < keys[8]
     assert keys[9] >> 32 == keys[0] >> 32  # NaN counts as -inf
+
+
+def test_free_tmid_draw_bit_exact(orc, devmath):
+    """draw_track_tm (the kernels' generator of free-t_mid templates) against the oracle's."""
+    T, F, L = 700, 300, 10
+    want = orc.draw_tm_many(21, 4, 1000, 3000, T, F, L, D10MS)
+    got = devmath([f"drawtm 21 4 {1000 + i} {T} {F} {L} {D10MS}" for i in range(3000)])
+    assert [tuple(int(x) for x in g.split()) for g in got] == [tuple(int(v) for v in w) for w in want.tolist()]
+
+
+def test_free_tmid_rows_bit_exact(orc, devmath):
+    """row_tm (FP64 with the exact fallback) against the oracle's exact integer rows: random
+    templates over the full size range, every t1 of small templates, and control frequencies on
+    row boundaries (where the fallback decides)."""
+    rng = np.random.default_rng(41)
+    cases = []
+    F = 32767
+    for _ in range(400):
+        T = int(rng.integers(2, 2897))
+        t0 = int(rng.integers(0, T - 1))
+        t2 = int(rng.integers(t0 + 1, T))
+        cases.append((t0, int(rng.integers(t0, t2 + 1)), t2, *[int(x) for x in rng.integers(0, F * 256, 3)]))
+    for t0, t2 in [(0, 1), (3, 9), (0, 40), (100, 131)]:
+        for t1 in range(t0, t2 + 1):
+            cases.append((t0, t1, t2, 256 * int(rng.integers(0, 50)), 256 * int(rng.integers(0, 50)),
+                          256 * int(rng.integers(0, 50))))
+            cases.append((t0, t1, t2, *[int(x) for x in rng.integers(0, 50 * 256, 3)]))
+    cases += [(0, 0, 2895, 0, F * 256 - 1, 0), (0, 2895, 2895, F * 256 - 1, 0, F * 256 - 1),
+              (7, 7, 2000, 12345, 12345, 12345)]
+    got = devmath([f"rowstm {' '.join(str(v) for v in c)}" for c in cases])
+    for c, g in zip(cases, got):
+        tr = np.array([c + (0,)], dtype=orc.TRACK_TM_DTYPE)
+        assert [int(x) for x in g.split()] == orc.rows_tm(tr, F).tolist(), c

@@ -1,0 +1,122 @@
+"""GPU parity of free-t_mid templates (stt_make_tracks_tm, stt_score_tm) against the oracle:
+templates bit-exact, scores within 1e-5 * max(1, |z|), argmax up to a certified near-tie."""
+from __future__ import annotations
+
+import math
+import sys
+
+import numpy as np
+import pytest
+
+import synth
+from tests.parity_util import assert_argmax, assert_close, key_to_host, to_dev
+
+pytestmark = pytest.mark.gpu
+
+D10MS = 2684355
+
+
+@pytest.fixture(scope="module")
+def stt():
+    import paper_1401_8060_amd.stt as stt
+    return stt
+
+
+@pytest.fixture(scope="module")
+def ctx(stt):
+    c = stt.Context(0)
+    yield c
+    c.close()
+
+
+def _say(*a):
+    print(*a, flush=True, file=sys.stderr)
+
+
+@pytest.mark.parametrize("T,F,L,seed,stream,first,n", [(100, 128, 10, 1, 0, 0, 10000),
+                                                        (2896, 32767, 2, 2 ** 63 + 5, 2 ** 32 - 1, 2 ** 32 - 777, 777)])
+def test_make_tracks_tm_bit_exact(orc, stt, ctx, T, F, L, seed, stream, first, n):
+    _say("make_tracks_tm", T, F)
+    got = ctx.make_tracks_tm(stt.Gen(seed=seed, stream=stream, min_len=L, dtau_max=D10MS), T, F, first, n)
+    want = orc.draw_tm_many(seed, stream, first, n, T, F, L, D10MS)
+    got = got.cpu().numpy()
+    for k, name in enumerate(("t0", "t1", "t2", "f0", "f1", "f2", "dtau")):
+        assert np.array_equal(got[:, k].astype(np.int64), want[name].astype(np.int64)), name
+
+
+@pytest.mark.parametrize("p16", [False, True])
+def test_score_tm_matches_oracle(orc, stt, ctx, p16):
+    _say("score_tm, p16", p16)
+    T, F, n = 400, 300, 20_000
+    Y, s = synth.noise_map(T, F, seed=81, sigma=("loguniform", 0.5, 2.0))
+    m = stt.Map(*to_dev(Y, s))
+    g = stt.Gen(seed=3, min_len=10, dtau_max=D10MS)
+    if p16:
+        m = ctx.pack_p16(m)
+        _, _, deq = orc.quantize_p16(Y, s)
+        om = orc.Map(deq, np.ones((T, F)))
+    else:
+        om = orc.Map(Y, s)
+    z, key = ctx.score_tm(m, gen=g, n=n)
+    z = z.cpu().numpy()
+    z_orc = orc.score_tm_gen_idx(om, 3, 0, 10, D10MS, np.arange(n, dtype=np.uint64))
+    assert_close(z, z_orc, what=f"score_tm p16={p16}")
+    zk, jk = stt.key_decode(key_to_host(key))
+    assert jk == int(np.argmax(z)) and zk == z[jk]
+    assert_argmax(jk, z_orc)
+
+
+def test_score_tm_explicit_and_invalid(orc, stt, ctx):
+    _say("score_tm explicit")
+    import torch
+    T, F = 150, 90
+    Y, s = synth.noise_map(T, F, seed=82, sigma=("loguniform", 0.5, 2.0))
+    m = stt.Map(*to_dev(Y, s))
+    om = orc.Map(Y, s)
+    good = orc.draw_tm_many(4, 2, 0, 4000, T, F, 2, D10MS)
+    edge = np.array([(0, 0, T - 1, 0, F * 256 - 1, 0, D10MS), (0, T - 1, T - 1, F * 256 - 1, 0, 256, -D10MS),
+                     (10, 20, 30, 256 * 7, 256 * 7, 256 * 7, 0), (5, 6, 7, 100, 200, 300, 1),
+                     (T - 2, T - 2, T - 1, 0, 0, 0, 0)], dtype=orc.TRACK_TM_DTYPE)
+    bad = np.array([(-1, 0, 10, 0, 0, 0, 0), (5, 4, 9, 0, 0, 0, 0), (5, 10, 9, 0, 0, 0, 0), (3, 3, 3, 0, 0, 0, 0),
+                    (0, 5, T, 0, 0, 0, 0), (0, 5, 20, F * 256, 0, 0, 0)], dtype=orc.TRACK_TM_DTYPE)
+    allt = np.concatenate([good, edge, bad])
+    dev = torch.from_numpy(allt.view(np.int32).reshape(-1, 7).copy()).cuda()
+    z, key = ctx.score_tm(m, tracks=dev, first=9)
+    z = z.cpu().numpy()
+    z_orc = orc.score_tm_list(om, allt)
+    assert np.isnan(z[-len(bad):]).all() and np.isnan(z_orc[-len(bad):]).all()
+    assert_close(z, z_orc, what="score_tm explicit")
+    assert_argmax(stt.key_decode(key_to_host(key))[1] - 9, z_orc)
+
+
+def test_score_tm_full_scale_sampled(orc, stt, ctx):
+    """The search map (T = F = 1000, one injection), 10^7 free-t_mid templates: the key against
+    the score array, a sample and the 20 best against the oracle."""
+    _say("score_tm full scale")
+    T, F, n = 1000, 1000, 10_000_000
+    Y, s = synth.noise_map(T, F, seed=1002, sigma=("loguniform", 0.5, 2.0))
+    cols, rows = synth.bezier_rows_float(200, 799, 250.5, 600.25, 450.75)
+    dt0 = int(round(0.003 / 2.0 ** -28))
+    synth.add_pixels(Y, s, cols, rows, 8.0 / math.sqrt(cols.size), -((100.0 + rows) * dt0 * 2.0 ** -28))
+    m = stt.Map(*to_dev(Y, s))
+    g = stt.Gen(seed=2, min_len=10, dtau_max=D10MS)
+    z, key = ctx.score_tm(m, gen=g, n=n)
+    z = z.cpu().numpy()
+    zk, jk = stt.key_decode(key_to_host(key))
+    assert jk == int(np.argmax(z)) and zk == z[jk]
+    om = orc.Map(Y, s)
+    idx = np.concatenate([np.random.default_rng(6).choice(n, 1500, replace=False), [0, n - 1],
+                          np.argsort(z)[-20:]]).astype(np.uint64)
+    z_orc = orc.score_tm_gen_idx(om, 2, 0, 10, D10MS, idx)
+    assert_close(z[idx.astype(np.int64)], z_orc, what="score_tm full scale")
+    top = idx[-20:]
+    assert_argmax(int(np.where(top == jk)[0][0]), orc.score_tm_gen_idx(om, 2, 0, 10, D10MS, top))
+
+
+def test_score_tm_argument_errors(stt, ctx):
+    Y, s = synth.noise_map(40, 30, seed=83, sigma="unit")
+    m = stt.Map(*to_dev(Y, s))
+    with pytest.raises(stt.SttError):
+        ctx.score_tm(m, gen=stt.Gen(seed=1, min_len=41, dtau_max=D10MS), n=10)  # min_len > T
+    with pytest.raises(stt.SttError):
+        ctx.score_tm(m, gen=stt.Gen(seed=1, min_len=10, dtau_max=D10MS), first=2 ** 32 - 5, n=10)
