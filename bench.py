@@ -55,6 +55,9 @@ WORKLOADS = {
     # differentiation: T=1000 x F=1000 with 8 injected tracks at SNR 5..10; top-1024 of 10^6 refined 50 steps
     "refine_1000x1000_1e6": dict(kind="refine", T=1000, F=1000, n=1_000_000, seed=5, L=10, dtau_s=0.01,
                                  sigma=("loguniform", 0.5, 2.0), K=1024, steps=50, n_inj=8, inject=None),
+    # free t_mid: the search map, 10^7 templates with all six random numbers (t1 anywhere in [t0, t2])
+    "tmid_1000x1000_1e7": dict(kind="tmid", T=1000, F=1000, n=10_000_000, seed=2, L=10, dtau_s=0.01,
+                               sigma=("loguniform", 0.5, 2.0), inject=(200, 799, 250.5, 600.25, 450.75)),
     # delay-maximised: the search map, 10^6 templates each maximised over 16 delays spanning +-10 ms
     "maxdelay_1000x1000_1e6x16": dict(kind="maxdelay", T=1000, F=1000, n=1_000_000, seed=2, L=10, dtau_s=0.01,
                                       sigma=("loguniform", 0.5, 2.0), n_tau=16,
@@ -337,6 +340,50 @@ def run_precision(args, name, w):
     return out
 
 
+def run_tmid(args, name, w):
+    import torch
+    import paper_1401_8060_amd.stt as stt
+    dtau_max = stt.dtau_units(w["dtau_s"])
+    log(f"bench: building map {w['T']}x{w['F']}")
+    Y, s, sha = make_map(w)
+    dev = torch.device("cuda:0")
+    m = stt.Map(torch.from_numpy(Y).to(dev), torch.from_numpy(s).to(dev))
+    ctx = stt.Context(0)
+    g = stt.Gen(seed=w["seed"], stream=0, min_len=w["L"], dtau_max=dtau_max)
+    n = w["n"]
+    px = count_px(ctx, g, w["T"], w["F"], n)  # a free t_mid keeps the time extent, so the pixel count
+    snr = torch.empty(n, dtype=torch.float32, device=dev)
+    key = torch.zeros(1, dtype=torch.int64, device=dev)
+
+    def step_fn():
+        key.zero_()
+        ctx.score_tm(m, gen=g, n=n, snr=snr, best_key=key)
+
+    for _ in range(args.warmup):
+        step_fn()
+    torch.cuda.synchronize()
+    ctx.set_timing(True)
+    ms_step = timed(argparse.Namespace(warmup=0, steps=args.steps), step_fn, torch)
+    score_ms, cnt = ctx.kernel_ms_total(stt.STAGE_SCORE)
+    ctx.set_timing(False)
+    kern_ms = score_ms / max(cnt, 1)
+    zk, jk = stt.decode_best(key)
+    log(f"bench: {ms_step:.3f} ms/step, free-t_mid scoring kernel {kern_ms:.3f} ms; best z={zk:.4f} j={jk}")
+    out = base_record(args, name, w, n, ms_step, px, "f32")
+    out["config"].update({"T": w["T"], "F": w["F"], "n_tracks": n, "templates": "free t_mid",
+                          "map_sha256": sha[:16]})
+    # per template pixel: the root and the Bezier (sqrt, divide, 2 FMA, scale: about 10 flops), the
+    # phase and term as in the plain scorer (8)
+    fl = 18
+    sec = kern_ms * 1e-3
+    out["roofline"] = {"bound": "alu", "achieved": px * fl / sec / 1e12, "peak": ALU_PEAK_TFLOPS, "unit": "TFLOP/s",
+                       "frac": px * fl / sec / 1e12 / ALU_PEAK_TFLOPS, "traffic": None, "kernel": "k_score_tm",
+                       "kernel_ms": kern_ms, "flops_per_track_px": fl}
+    out["best"] = {"z": zk, "j": jk}
+    ctx.close()
+    return out
+
+
 def run_maxdelay(args, name, w):
     import torch
     import paper_1401_8060_amd.stt as stt
@@ -461,7 +508,7 @@ def main():
         sys.exit(2)
     w = WORKLOADS[args.workload]
     runner = {"single": run_single, "batch": run_batch, "precision": run_precision, "refine": run_refine,
-              "maxdelay": run_maxdelay}[w["kind"]]
+              "maxdelay": run_maxdelay, "tmid": run_tmid}[w["kind"]]
     out = runner(args, args.workload, w)
     if args.copy_probe_mb:
         import torch

@@ -628,10 +628,12 @@ __global__ __launch_bounds__(1024) void k_reduce_keys(const uint64_t *keys, int6
 
 // ---------------------------------------------------------------- templates with a free t_mid
 // A free-t_mid template's rows have no recurrence: each column's row is an
-// independent root (row_tm). One wave per template, lane l taking columns
-// t0 + l, t0 + l + 64, ...: each lane sums its terms in FP32 (at most 46),
-// then the wave adds the lanes' sums in FP64 by a butterfly, the same total in
-// every lane. Four templates per workgroup.
+// independent root (row_tm). Both scorers below walk a template's columns on
+// the flush grid of the plain scorers (FP32 partial sums per group of kFlush
+// aligned columns, FP64 across groups in column order), so they give the same
+// bits: k_score_tm_slab (binned templates, LDS slabs, like k_score_md_slab) for
+// generated templates, k_score_tm (one wave per template, lanes over groups,
+// like k_score_wave) for small calls and given lists.
 
 __device__ __forceinline__ bool track_tm_ok(const TrkTm &t, const MapP &m)
 {
@@ -659,20 +661,157 @@ __global__ __launch_bounds__(256) void k_score_tm(MapP m, GenP g, const TrkTm *t
         if (!EXPL || track_tm_ok(t, m)) {
             const RowTm k = row_tm_init(t);
             const PhaseK pk = phase_k(m, t.dtau);
-            float part = 0.0f;
-            for (int32_t dt = lane; dt <= t.t2 - t.t0; dt += 64) {
-                const int32_t row = row_tm(k, dt);
-                part = add_term<HW>(part, pk, row, load_p<MAPT>(m, (int64_t)(t.t0 + dt) * m.ld + row));
-            }
-            double sum = part;
+            const int gfirst = t.t0 / kFlush, glast = t.t2 / kFlush;
+            float gp[kWaveRounds];
 #pragma unroll
-            for (int off = 32; off > 0; off >>= 1) sum += __shfl_xor(sum, off);
-            z = finish(sum, t.t2 - t.t0 + 1, norm);
+            for (int r = 0; r < kWaveRounds; ++r) {
+                gp[r] = 0.0f;
+                const int gi = gfirst + r * 64 + lane;
+                if (gi > glast) continue;
+                const int ca = max(t.t0, gi * kFlush), cb = min(t.t2, gi * kFlush + kFlush - 1);
+                float part = 0.0f;
+                for (int c = ca; c <= cb; ++c) {
+                    const int32_t row = row_tm(k, c - t.t0);
+                    part = add_term<HW>(part, pk, row, load_p<MAPT>(m, (int64_t)c * m.ld + row));
+                }
+                gp[r] = part;
+            }
+            const int ng = glast - gfirst + 1;
+            double acc = 0.0;
+#pragma unroll
+            for (int r = 0; r < kWaveRounds; ++r) {
+                const int cnt = min(64, ng - r * 64);
+                for (int l = 0; l < cnt; ++l)
+                    acc += __builtin_bit_cast(float, __builtin_amdgcn_readlane(__builtin_bit_cast(int, gp[r]), l));
+            }
+            if ((t.t2 & (kFlush - 1)) == kFlush - 1) acc = acc + 0.0f;
+            z = finish(acc, t.t2 - t.t0 + 1, norm);
         }
         if (lane == 0 && snr) snr[i] = z;
         key = key_encode(z, (uint32_t)(first + (uint64_t)i));
     }
     merge_key(best, key);
+}
+
+// Column walk of the free-t_mid slab scorer (as walk, with an independent row per column).
+template <int TPT, bool MASK, bool HW>
+__device__ __forceinline__ void walk_tm(int ca, int cb, int c0, const float2 *slab, int ldc, const int32_t (&t0)[TPT],
+                                        const uint32_t (&span)[TPT], const RowTm (&rk)[TPT],
+                                        const PhaseK (&pk)[TPT], float (&part)[TPT], double (&acc)[TPT])
+{
+    for (int c = ca; c <= cb;) {
+        const int ce = min(cb, c | (kFlush - 1));
+        for (; c <= ce; ++c) {
+            const float2 *col = slab + (c - c0) * ldc;
+#pragma unroll
+            for (int q = 0; q < TPT; ++q) {
+                const int32_t dt = c - t0[q];
+                const bool act = !MASK || (uint32_t)dt <= span[q];
+                const int32_t row = row_tm(rk[q], act ? dt : 0);
+                const float v = add_term<HW>(part[q], pk[q], row, col[row]);
+                part[q] = act ? v : part[q];
+            }
+        }
+        if ((ce & (kFlush - 1)) == kFlush - 1) {  // wave-uniform
+#pragma unroll
+            for (int q = 0; q < TPT; ++q) {
+                acc[q] += part[q];
+                part[q] = 0.0f;
+            }
+        }
+    }
+}
+
+template <int WG, int TPT, bool HW>
+__global__ __launch_bounds__(WG) void k_score_tm_slab(MapP m, GenP g, const uint32_t *order, uint64_t first,
+                                                      int64_t n, int S, int32_t norm, float *snr, uint64_t *wg_keys)
+{
+    extern __shared__ float2 slab[];
+    __shared__ int bnd[2];
+    __shared__ uint64_t kred[WG / 64];
+    if (threadIdx.x == 0) { bnd[0] = 0x7fffffff; bnd[1] = -1; }
+    const int lane = threadIdx.x & 63;
+    const int64_t wbase = (int64_t)blockIdx.x * (WG * TPT) + (int64_t)(threadIdx.x >> 6) * (64 * TPT);
+    int32_t t0[TPT];
+    uint32_t span[TPT], idx[TPT];
+    bool live[TPT];
+    RowTm rk[TPT];
+    PhaseK pk[TPT];
+    int lo = 0x7fffffff, hi = -1, clo = -1, chi = 0x7fffffff;
+#pragma unroll
+    for (int q = 0; q < TPT; ++q) {
+        const int64_t e = wbase + q * 64 + lane;
+        live[q] = e < n;
+        idx[q] = live[q] ? order[e] : 0u;
+        TrkTm t = draw_track_tm(g, first + idx[q]);
+        if (!live[q]) t = TrkTm{0, 0, 1, 0u, 0u, 0u, 0};  // never active: (c - t0) > span below
+        rk[q] = row_tm_init(t);
+        pk[q] = phase_k(m, t.dtau);
+        t0[q] = live[q] ? t.t0 : 0x7fffffff;
+        span[q] = live[q] ? (uint32_t)(t.t2 - t.t0) : 0u;
+        if (live[q]) {
+            lo = min(lo, t.t0);
+            hi = max(hi, t.t2);
+            clo = max(clo, t.t0);
+            chi = min(chi, t.t2);
+        } else {
+            clo = 0x7fffffff;
+            chi = -1;
+        }
+    }
+    lo = wave_min_i32(lo);
+    hi = wave_max_i32(hi);
+    clo = wave_max_i32(clo);
+    chi = wave_min_i32(chi);
+    if (clo > chi) { clo = hi + 1; chi = hi; }
+    float part[TPT];
+    double acc[TPT];
+#pragma unroll
+    for (int q = 0; q < TPT; ++q) { part[q] = 0.0f; acc[q] = 0.0; }
+    __syncthreads();
+    if (lane == 0) {
+        atomicMin(&bnd[0], lo);
+        atomicMax(&bnd[1], hi);
+    }
+    __syncthreads();
+    const int c_first = __builtin_amdgcn_readfirstlane(bnd[0]), c_last = __builtin_amdgcn_readfirstlane(bnd[1]);
+    const int ldc = (int)m.ld, per_col = ldc / kDmaPix;
+    const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    auto issue = [&](int c0, int bsel) {
+        const int nchunk = min(S, c_last - c0 + 1) * per_col;
+        const float2 *src = m.Y + (int64_t)c0 * ldc + lane * 2;
+        float2 *dst = slab + (size_t)bsel * S * ldc;
+        for (int ch = wave; ch < nchunk; ch += WG / 64) lds_dma_16(src + ch * kDmaPix, dst + ch * kDmaPix);
+    };
+    if (c_first <= c_last) issue(c_first, 0);
+    int kk = 0;
+    for (int c0 = c_first; c0 <= c_last; c0 += S, ++kk) {
+        __builtin_amdgcn_s_waitcnt(0);  // this wave's copies of slab kk have landed
+        __syncthreads();                // so have everyone's, and slab kk-1 is no longer read
+        if (c0 + S <= c_last) issue(c0 + S, (kk + 1) & 1);
+        const float2 *cur = slab + (size_t)(kk & 1) * S * ldc;
+        const int ncol = min(S, c_last - c0 + 1);
+        const int ca = max(c0, lo), cb = min(c0 + ncol - 1, hi);
+        walk_tm<TPT, true, HW>(ca, min(cb, clo - 1), c0, cur, ldc, t0, span, rk, pk, part, acc);
+        walk_tm<TPT, false, HW>(max(ca, clo), min(cb, chi), c0, cur, ldc, t0, span, rk, pk, part, acc);
+        walk_tm<TPT, true, HW>(max(ca, chi + 1), cb, c0, cur, ldc, t0, span, rk, pk, part, acc);
+    }
+    uint64_t key = 0;
+#pragma unroll
+    for (int q = 0; q < TPT; ++q) {
+        if (!live[q]) continue;
+        const float z = finish(acc[q] + part[q], (int32_t)span[q] + 1, norm);
+        if (snr) snr[idx[q]] = z;
+        const uint64_t k = key_encode(z, (uint32_t)(first + idx[q]));
+        key = k > key ? k : key;
+    }
+    key = wave_max_u64(key);
+    if (lane == 0) kred[threadIdx.x >> 6] = key;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        for (int w = 1; w < WG / 64; ++w) key = kred[w] > key ? kred[w] : key;
+        wg_keys[blockIdx.x] = key;
+    }
 }
 
 // ---------------------------------------------------------------- delay-maximised scoring

@@ -779,9 +779,53 @@ stt_status stt_score_tm(stt_ctx *c, const stt_map *map, const stt_gen *gen, cons
     STT_HIP(c, hipSetDevice(c->device));
     const MapP m = to_mapp(map);
     const TrkTm *tr = (const TrkTm *)tracks_dev;
-    const dim3 grid((unsigned)((n + 3) / 4)), block(256);
+    // generated templates: binned by time extent (a free t_mid keeps it) and scored from LDS slabs
+    // (512 lanes x 2 templates, at most 80 KB of slabs) when a column fits; otherwise one wave each
+    constexpr int kTmWG = 512, kTmTPT = 2;
+    const int lds = std::min(c->lds_bytes, 80 * 1024);
+    const int64_t ldc = fold_ld(m.F);
+    const bool slab = !tracks_dev && c->dma && dma_slab_cols(lds, ldc) >= 1 && c->path != 1 && c->path != 3 &&
+                      (c->path == 2 || n >= 4096);
     if ((s = ev_begin(c)) != STT_OK) return s;
     ev_record(c, 4);
+    if (slab) {
+        uint32_t *order = nullptr;
+        uint64_t *wg_keys = nullptr;
+        if ((s = bin_templates<false>(c, m, g, nullptr, first, n, order, wg_keys)) != STT_OK) return s;
+        const size_t pb = sizeof(float2) * (size_t)m.T * (size_t)ldc;
+        if ((s = ensure_pbuf(c, pb)) != STT_OK) return s;
+        const unsigned fg = (unsigned)std::min<int64_t>(((int64_t)m.T * ldc + 255) / 256, 4096);
+        if (map->dtype == STT_P16)
+            hipLaunchKernelGGL(k_fold_p<kMapP16>, dim3(fg), dim3(256), 0, c->stream, m, (float2 *)c->pbuf, ldc);
+        else
+            hipLaunchKernelGGL(k_fold_p<kMapF32>, dim3(fg), dim3(256), 0, c->stream, m, (float2 *)c->pbuf, ldc);
+        MapP mf = m;
+        mf.Y = (const float2 *)c->pbuf;
+        mf.sig = nullptr;
+        mf.ld = ldc;
+        const int S = std::min(dma_slab_cols(lds, ldc), m.T);
+        const size_t shm = 2 * sizeof(float2) * (size_t)S * ldc;
+        const unsigned grid = (unsigned)((n + kTmWG * kTmTPT - 1) / (kTmWG * kTmTPT));
+        auto kern = c->hw_trig ? k_score_tm_slab<kTmWG, kTmTPT, true> : k_score_tm_slab<kTmWG, kTmTPT, false>;
+        if (shm > 64 * 1024)
+            STT_HIP(c, hipFuncSetAttribute((const void *)kern, hipFuncAttributeMaxDynamicSharedMemorySize, (int)shm));
+        ev_record(c, 0);
+        hipLaunchKernelGGL(kern, dim3(grid), dim3(kTmWG), shm, c->stream, mf, g, (const uint32_t *)order,
+                           (uint64_t)first, n, S, norm, snr_dev, wg_keys);
+        STT_HIP(c, hipGetLastError());
+        ev_record(c, 1);
+        c->used[0] = true;
+        if (best_key_dev) {
+            hipLaunchKernelGGL(k_reduce_keys, dim3(1), dim3(1024), 0, c->stream, (const uint64_t *)wg_keys,
+                               (int64_t)grid, best_key_dev);
+            STT_HIP(c, hipGetLastError());
+        }
+        ev_record(c, 5);
+        c->used[2] = true;
+        ev_end(c);
+        return STT_OK;
+    }
+    const dim3 grid((unsigned)((n + 3) / 4)), block(256);
     ev_record(c, 0);
 #define STT_TM_LAUNCH(E, H, M)                                                                                  \
     hipLaunchKernelGGL((k_score_tm<E, H, M>), grid, block, 0, c->stream, m, g, tr, (uint64_t)first, n, norm,  \

@@ -120,3 +120,21 @@ def test_score_tm_argument_errors(stt, ctx):
         ctx.score_tm(m, gen=stt.Gen(seed=1, min_len=41, dtau_max=D10MS), n=10)  # min_len > T
     with pytest.raises(stt.SttError):
         ctx.score_tm(m, gen=stt.Gen(seed=1, min_len=10, dtau_max=D10MS), first=2 ** 32 - 5, n=10)
+
+
+def test_score_tm_slab_and_wave_paths_bit_identical(stt, ctx):
+    """Generated free-t_mid templates: the LDS-slab scorer (binned) and the one-wave-per-template
+    scorer walk each template on the same flush grid and give the same bits."""
+    _say("score_tm paths")
+    T, F = 600, 400
+    Y, s = synth.noise_map(T, F, seed=84, sigma=("loguniform", 0.5, 2.0))
+    m = stt.Map(*to_dev(Y, s))
+    g = stt.Gen(seed=5, stream=2, min_len=10, dtau_max=D10MS)
+    out = []
+    for path in (3, 2, 0):
+        ctx.set_path(path)
+        z, key = ctx.score_tm(m, gen=g, first=1234, n=60_000)
+        out.append((z.cpu().numpy(), key_to_host(key)))
+    ctx.set_path(0)
+    for o in out[1:]:
+        assert np.array_equal(out[0][0], o[0]) and out[0][1] == o[1]
