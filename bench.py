@@ -377,7 +377,7 @@ def run_tmid(args, name, w):
     fl = 18
     sec = kern_ms * 1e-3
     out["roofline"] = {"bound": "alu", "achieved": px * fl / sec / 1e12, "peak": ALU_PEAK_TFLOPS, "unit": "TFLOP/s",
-                       "frac": px * fl / sec / 1e12 / ALU_PEAK_TFLOPS, "traffic": None, "kernel": "k_score_tm",
+                       "frac": px * fl / sec / 1e12 / ALU_PEAK_TFLOPS, "traffic": None, "kernel": "k_score_tm_slab",
                        "kernel_ms": kern_ms, "flops_per_track_px": fl}
     out["best"] = {"z": zk, "j": jk}
     ctx.close()
@@ -424,11 +424,15 @@ def run_maxdelay(args, name, w):
     out["template_delays_per_s"] = n * nt / (ms_step * 1e-3)
     # one template-delay pixel: phase (2), sine and cosine (2), term (3), accumulation (1); the row (4)
     # is shared by the delays
+    # the grid runs in launches of up to 8 delays; the stage time covers all of them, so one launch
+    # averages kern_ms / launches over (on average) that share of the flops
+    launches = (nt + 7) // 8
     flops = px * (4 + 8 * nt)
     sec = kern_ms * 1e-3
     out["roofline"] = {"bound": "alu", "achieved": flops / sec / 1e12, "peak": ALU_PEAK_TFLOPS, "unit": "TFLOP/s",
                        "frac": flops / sec / 1e12 / ALU_PEAK_TFLOPS, "traffic": None, "kernel": "k_score_md_slab",
-                       "kernel_ms": kern_ms, "flops_per_track_px": 4 + 8 * nt}
+                       "kernel_ms": kern_ms / launches, "launches_per_step": launches,
+                       "flops_per_track_px": 4 + 8 * nt}
     out["best"] = {"z": zk, "j": jk, "delay_index": mk}
     ctx.close()
     return out
