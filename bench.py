@@ -62,6 +62,12 @@ WORKLOADS = {
     "maxdelay_1000x1000_1e6x16": dict(kind="maxdelay", T=1000, F=1000, n=1_000_000, seed=2, L=10, dtau_s=0.01,
                                       sigma=("loguniform", 0.5, 2.0), n_tau=16,
                                       inject=(200, 799, 250.5, 600.25, 450.75)),
+    # map formation: two detectors' strain, 500.5 s at 4096 Hz (white noise plus a chirp reaching J 3 ms
+    # after I), columns of 1 s overlapping by half -> T=1000, 100-1099 Hz -> F=1000, P' from 4 columns a
+    # side; 256 time slides of J by 2k columns, i.e. 256 background maps of 1000 x 1000
+    "mapform_1000x1000_256slides": dict(kind="mapform", fs=4096.0, M=4096, T=1000, k_lo=100, F=1000, nb=4,
+                                        n_slides=256, slide_cols=2, seed=6,
+                                        chirp=dict(f0=250.0, rate=1.0, amp=0.02, t0=100.0, t1=400.0, delay=0.003)),
     # precision: T=2000 x F=2000 stored in FP16, 10^8 tracks, top-1024 re-scored in FP64
     "precision_2000x2000_1e8": dict(kind="precision", T=2000, F=2000, n=100_000_000, seed=4, L=10, dtau_s=0.01,
                                     sigma=("loguniform", 0.5, 2.0), K=1024,
@@ -438,6 +444,87 @@ def run_maxdelay(args, name, w):
     return out
 
 
+def run_mapform(args, name, w):
+    import numpy as np
+    import torch
+    import synth
+    import paper_1401_8060_amd.stt as stt
+    p = stt.Spectro(w["fs"], w["M"], w["k_lo"], w["F"], w["nb"])
+    T, F, ns = w["T"], w["F"], w["n_slides"]
+    n = (T + 1) * w["M"] // 2
+    log(f"bench: building {n} samples of strain per detector")
+    strains = []
+    for k in range(2):
+        x = synth.white_strain(n, seed=w["seed"], stream=k)
+        ch = w["chirp"]
+        synth.add_tone(x, w["fs"], ch["f0"], ch["amp"], delay_s=ch["delay"] * k, t_start_s=ch["t0"],
+                       t_stop_s=ch["t1"], chirp_hz_per_s=ch["rate"])
+        strains.append(x)
+    dev = torch.device("cuda:0")
+    xi, xj = (torch.from_numpy(x).to(dev) for x in strains)
+    ctx = stt.Context(0)
+    shifts = [w["slide_cols"] * k for k in range(ns)]
+    si = torch.empty((T, F), dtype=torch.complex64, device=dev)
+    sj = torch.empty_like(si)
+    pi = torch.empty((T, F), dtype=torch.float32, device=dev)
+    pj = torch.empty_like(pi)
+    maps = ctx.form_maps(p, *ctx.spectra(xi, p, T, si, pi), *ctx.spectra(xj, p, T, sj, pj), shifts)
+
+    def step_fn():
+        ctx.spectra(xi, p, T, si, pi)
+        ctx.spectra(xj, p, T, sj, pj)
+        ctx.form_maps(p, si, pi, sj, pj, shifts, out=maps)
+
+    for _ in range(args.warmup):
+        step_fn()
+    torch.cuda.synchronize()
+    ctx.set_timing(True)
+    ms_step = timed(argparse.Namespace(warmup=0, steps=args.steps), step_fn, torch)
+    form_ms, cnt = ctx.kernel_ms_total(stt.STAGE_SCORE)
+    form_ms /= max(cnt, 1)
+    # a second pass for the whole-call brackets (a total query forgets the calls it summed)
+    timed(argparse.Namespace(warmup=0, steps=args.steps), step_fn, torch)
+    call_ms, ncall = ctx.kernel_ms_total(stt.STAGE_CALL)
+    ctx.set_timing(False)
+    launches = (ns + 15) // 16
+    spectra_ms = call_ms / args.steps - form_ms  # the two stt_spectra calls of a step
+    launch_ms = form_ms / launches
+    px = ns * T * F
+    log(f"bench: {ms_step:.3f} ms/step; spectra+P' {spectra_ms:.3f} ms, {ns} slide maps {form_ms:.3f} ms "
+        f"({launches} launches of k_form_maps, {launch_ms * 1e3:.1f} us each)")
+    # algorithmic bytes of one k_form_maps launch: its slides' maps written (8 B Y + 4 B sigma per
+    # pixel) and both detectors' spectra and P' read once (2 x 12 B per pixel)
+    per_launch = [min(16, ns - k) for k in range(0, ns, 16)]
+    bytes_launch = sum(12 * T * F * m + 24 * T * F for m in per_launch) / launches
+    achieved = bytes_launch / (launch_ms * 1e-3) / 1e9
+    fq4_lo, dfq4 = p.fq4()
+    out = {
+        "metric": "cross-power map pixels formed/sec per MI355X (time-slide background maps)",
+        "value": px / (ms_step * 1e-3), "unit": "map pixels/s", "n_gpus": 1, "steps": args.steps,
+        "warmup": args.warmup, "ms_per_step": ms_step, "higher_is_better": True, "scaling": "weak",
+        "vs_baseline": None, "dtype": "f32", "data": "synthetic",
+        "config": {"workload": name, "fs": w["fs"], "M": w["M"], "T": T, "F": F, "k_lo": w["k_lo"], "nb": w["nb"],
+                   "n_slides": ns, "slide_cols": w["slide_cols"], "fq4_lo": fq4_lo, "dfq4": dfq4},
+        "maps_per_s": ns / (ms_step * 1e-3),
+        "roofline": {"bound": "hbm", "achieved": achieved, "peak": 8000.0, "unit": "GB/s", "frac": achieved / 8000.0,
+                     "traffic": None, "kernel": "k_form_maps", "kernel_ms": launch_ms,
+                     "launches_per_step": launches, "bytes_per_launch": bytes_launch},
+        "spectra_ms": spectra_ms,
+    }
+    if not args.no_cpu_baseline:
+        log("bench: timing the map-formation oracle")
+        from oracle import mapform
+        k = ns  # the whole step takes the oracle a few seconds
+        t = time.perf_counter()
+        mapform.form_maps(strains[0], strains[1], w["fs"], w["M"], T, w["k_lo"], F, w["nb"], shifts[:k])
+        dt = time.perf_counter() - t
+        out["cpu_baseline"] = dict(value=k * T * F / dt, unit="map pixels/s", cores=1, kind="oracle",
+                                   sample=f"the whole step (both detectors' spectra and P', all {k} slide maps), "
+                                          f"numpy FP64, one thread, {dt:.1f} s")
+    ctx.close()
+    return out
+
+
 def run_refine(args, name, w):
     import numpy as np
     import torch
@@ -512,7 +599,7 @@ def main():
         sys.exit(2)
     w = WORKLOADS[args.workload]
     runner = {"single": run_single, "batch": run_batch, "precision": run_precision, "refine": run_refine,
-              "maxdelay": run_maxdelay, "tmid": run_tmid}[w["kind"]]
+              "maxdelay": run_maxdelay, "tmid": run_tmid, "mapform": run_mapform}[w["kind"]]
     out = runner(args, args.workload, w)
     if args.copy_probe_mb:
         import torch

@@ -204,6 +204,52 @@ stt_status stt_score_maxdelay(stt_ctx *ctx, const stt_map *map, const stt_gen *g
                               int64_t first, int64_t n, int32_t dtau0, int32_t dtau_step, int32_t n_tau, int32_t norm,
                               float *snr_dev, int32_t *tau_idx_dev, uint64_t *best_key_dev);
 
+/* ---- Map formation: the complex SNR maps the search scores, from strain ----
+ *
+ * Two detectors' strain streams I and J become cross-power maps (Y, sigma) in
+ * the layout above (Sec. II, Eq. 7, and the formalism appendix), with the
+ * segmenting of Sec. IV (columns of M samples overlapping by half, each
+ * weighted by the periodic Hann window w[n] = sin^2(pi n / M)):
+ *   s~(t; k) = dt sum_n w[n] s[t M/2 + n] e^{-2 pi i k n / M}   (dt = 1/fs)
+ *   Nrm = M dt 3/8   (DFT normalisation with the window's mean square)
+ *   P'(t; k) = mean of (2/Nrm) |s~(t'; k)|^2 over 2 <= |t' - t| <= nb + 1
+ *              (the neighbouring columns that share no samples with t)
+ *   Y = (2/Nrm) conj(s~_I(t; k)) s~_J(t'; k),  sigma = sqrt(P'_I(t) P'_J(t') / 2)
+ * with t' = (t + shift) mod T for a time slide of J by `shift` columns (0:
+ * zero lag). This is the appendix's estimator with the direction filter set to
+ * 1: the direction enters through Eq. 8's phase factor. Y / sigma is then twice
+ * the paper's lambda s~_I^* s~_J, with unit-variance real and imaginary parts
+ * in Gaussian noise. Row r = k - k_lo has frequency (k_lo + r) fs / M Hz, so a
+ * map from these entry points scores with fq4_lo = 16 k_lo fs / M and
+ * dfq4 = 16 fs / M (integers when fs / M is a multiple of 1/16 Hz).
+ * Computed in FP32: scale strain so that |s~|^2 stays a normal FP32 number
+ * (the maps' Y / sigma does not depend on a scale of either stream). */
+typedef struct {
+    double fs;      /* sample rate, Hz (> 0) */
+    int32_t M;      /* samples per column: a power of two in [8, 8192]; columns start every M/2 samples */
+    int32_t k_lo;   /* first frequency bin kept */
+    int32_t F;      /* bins kept, k_lo .. k_lo + F - 1, all < M/2 */
+    int32_t nb;     /* neighbour columns per side in P' (>= 1) */
+} stt_spectro;
+
+/* Column spectra and P' of one detector. strain_dev: n_samples FP32 samples,
+ * 8-byte aligned; columns t = 0 .. T-1 cover samples [t M/2, t M/2 + M), so
+ * (T + 1) M / 2 <= n_samples; 4 <= T <= 65535. Outputs (caller-owned):
+ * spec_dev [T][F] complex64 (interleaved FP32, 8-byte aligned) = s~, and
+ * psd_dev [T][F] FP32 = P'. */
+stt_status stt_spectra(stt_ctx *ctx, const stt_spectro *p, const float *strain_dev, int64_t n_samples, int32_t T,
+                       float *spec_dev, float *psd_dev);
+
+/* Time-slide maps from two detectors' stt_spectra outputs (same p and T).
+ * For k < n_slides: map k pairs column t of I with column (t + shifts[k]) mod T
+ * of J (shifts: host array, any integers) and writes Y into Y_dev[k] and sigma
+ * into sigma_dev[k] (host arrays of caller-owned device pointers; each map is
+ * [T][ld], ld >= F, Y complex64 8-byte aligned, sigma FP32). Shifts of at
+ * least 2 columns decorrelate a transient shorter than the shift. */
+stt_status stt_form_maps(stt_ctx *ctx, const stt_spectro *p, int32_t T, const float *spec_i_dev,
+                         const float *psd_i_dev, const float *spec_j_dev, const float *psd_j_dev, int32_t n_slides,
+                         const int32_t *shifts, int64_t ld, float *const *Y_dev, float *const *sigma_dev);
+
 /* Max/argmax over an existing score array: *best_key_dev is max-merged with
  * the best key over snr_dev[0..n), the index of element i being first + i. */
 stt_status stt_argmax(stt_ctx *ctx, const float *snr_dev, int64_t n, int64_t first,

@@ -13,6 +13,7 @@
 
 #include "stt.h"
 #include "kernels.hpp"
+#include "mapform.hpp"
 
 using namespace stt;
 
@@ -57,6 +58,9 @@ struct stt_ctx {
     hipGraph_t graph = nullptr;
     hipGraphExec_t gexec = nullptr;
     int n_cu = 0;
+    // map formation: FFT twiddles and window of the current column length
+    void *fft_tab = nullptr;
+    int fft_M = 0;
 };
 
 namespace {
@@ -525,6 +529,51 @@ stt_status maxdelay_impl(stt_ctx *c, const stt_map *map, const GenP &g, const Tr
     return STT_OK;
 }
 
+// Twiddles e^{-2 pi i j / M} (j < M/2) then the periodic Hann window sin^2(pi n / M) (n < M),
+// evaluated in FP64 and rounded once; rewritten (after the stream drains) when M changes.
+stt_status ensure_fft_tab(stt_ctx *c, int M)
+{
+    if (c->fft_tab && c->fft_M == M) return STT_OK;
+    const int N = M / 2;
+    std::vector<float> h((size_t)2 * N + M);
+    for (int j = 0; j < N; ++j) {
+        const double a = 2.0 * M_PI * (double)j / (double)M;
+        h[2 * j] = (float)std::cos(a);
+        h[2 * j + 1] = (float)-std::sin(a);
+    }
+    for (int n = 0; n < M; ++n) {
+        const double v = std::sin(M_PI * (double)n / (double)M);
+        h[(size_t)2 * N + n] = (float)(v * v);
+    }
+    if (!c->fft_tab) {
+        const size_t most = sizeof(float) * (size_t)2 * kMaxFftM;  // room for the largest M
+        if (hipMalloc(&c->fft_tab, most) != hipSuccess) {
+            (void)hipGetLastError();
+            c->fft_tab = nullptr;
+            return fail(c, STT_ENOMEM, "cannot allocate the FFT table");
+        }
+    }
+    STT_HIP(c, hipStreamSynchronize(c->stream));  // earlier transforms may still read the old table
+    STT_HIP(c, hipMemcpy(c->fft_tab, h.data(), sizeof(float) * h.size(), hipMemcpyHostToDevice));
+    c->fft_M = M;
+    return STT_OK;
+}
+
+stt_status check_spectro(stt_ctx *c, const stt_spectro *p)
+{
+    if (!p) return fail(c, STT_EINVAL, "null spectrogram parameters");
+    if (!(p->fs > 0) || !std::isfinite(p->fs)) return fail(c, STT_EINVAL, "fs must be positive");
+    if (p->M < 8 || p->M > kMaxFftM || (p->M & (p->M - 1)))
+        return fail(c, STT_ERANGE, "M=%d: need a power of two in [8, %d]", p->M, kMaxFftM);
+    if (p->k_lo < 0 || p->F < 1 || (int64_t)p->k_lo + p->F > p->M / 2)
+        return fail(c, STT_ERANGE, "bins [%d, %d) outside [0, M/2)", p->k_lo, p->k_lo + p->F);
+    if (p->nb < 1) return fail(c, STT_EINVAL, "nb=%d: need >= 1", p->nb);
+    return STT_OK;
+}
+
+// 2 / Nrm with Nrm = M dt 3/8 (the Hann window's mean square)
+float cross_scale(const stt_spectro *p) { return (float)(2.0 / ((double)p->M / p->fs * 0.375)); }
+
 }  // namespace
 
 extern "C" {
@@ -568,6 +617,7 @@ stt_status stt_destroy(stt_ctx *c)
     if (c->pbuf) (void)hipFree(c->pbuf);
     if (c->mdbuf) (void)hipFree(c->mdbuf);
     if (c->bdev) (void)hipFree(c->bdev);
+    if (c->fft_tab) (void)hipFree(c->fft_tab);
     if (c->gexec) (void)hipGraphExecDestroy(c->gexec);
     if (c->graph) (void)hipGraphDestroy(c->graph);
     if (c->cap_stream) (void)hipStreamDestroy(c->cap_stream);
@@ -954,6 +1004,83 @@ stt_status stt_rescore_f64(stt_ctx *c, const stt_map *map, const stt_gen *gen, c
 }
 
 // ----------------------------------------------------------------------------- batches
+
+stt_status stt_spectra(stt_ctx *c, const stt_spectro *p, const float *strain_dev, int64_t n_samples, int32_t T,
+                       float *spec_dev, float *psd_dev)
+{
+    if (!c) return STT_EINVAL;
+    stt_status s = check_spectro(c, p);
+    if (s != STT_OK) return s;
+    if (!strain_dev || !spec_dev || !psd_dev) return fail(c, STT_EINVAL, "null buffer");
+    if (((uintptr_t)strain_dev & 7) || ((uintptr_t)spec_dev & 7) || ((uintptr_t)psd_dev & 3))
+        return fail(c, STT_EINVAL, "strain and spec must be 8-byte aligned, psd 4-byte aligned");
+    if (T < 4 || T > 65535) return fail(c, STT_ERANGE, "T=%d: need 4 <= T <= 65535", T);
+    if (n_samples < 0 || (int64_t)(T + 1) * (p->M / 2) > n_samples)
+        return fail(c, STT_ERANGE, "%d columns of %d samples need %lld samples, have %lld", T, p->M,
+                    (long long)(T + 1) * (p->M / 2), (long long)n_samples);
+    STT_HIP(c, hipSetDevice(c->device));
+    if ((s = ensure_fft_tab(c, p->M)) != STT_OK) return s;
+    if ((s = ev_begin(c)) != STT_OK) return s;
+    const int N = p->M / 2;
+    int lg = 0;
+    while ((1 << lg) < N) ++lg;
+    ev_record(c, 4);
+    hipLaunchKernelGGL(k_col_fft, dim3(T), dim3(kFftThreads), sizeof(float2) * N, c->stream, strain_dev, p->M, lg,
+                       p->k_lo, p->F, (float)(1.0 / p->fs), (const float2 *)c->fft_tab, (float2 *)spec_dev);
+    STT_HIP(c, hipGetLastError());
+    hipLaunchKernelGGL(k_psd, dim3((p->F + 255) / 256, T), dim3(256), 0, c->stream, (const float2 *)spec_dev, T, p->F,
+                       p->nb, cross_scale(p), psd_dev);
+    STT_HIP(c, hipGetLastError());
+    ev_record(c, 5);
+    c->used[2] = true;
+    ev_end(c);
+    return STT_OK;
+}
+
+stt_status stt_form_maps(stt_ctx *c, const stt_spectro *p, int32_t T, const float *spec_i_dev, const float *psd_i_dev,
+                         const float *spec_j_dev, const float *psd_j_dev, int32_t n_slides, const int32_t *shifts,
+                         int64_t ld, float *const *Y_dev, float *const *sigma_dev)
+{
+    if (!c) return STT_EINVAL;
+    stt_status s = check_spectro(c, p);
+    if (s != STT_OK) return s;
+    if (!spec_i_dev || !psd_i_dev || !spec_j_dev || !psd_j_dev) return fail(c, STT_EINVAL, "null spectrum");
+    if (((uintptr_t)spec_i_dev & 7) || ((uintptr_t)spec_j_dev & 7)) return fail(c, STT_EINVAL, "spectra must be 8-byte aligned");
+    if (T < 4 || T > 65535) return fail(c, STT_ERANGE, "T=%d: need 4 <= T <= 65535", T);
+    if (n_slides < 0) return fail(c, STT_EINVAL, "n_slides=%d", n_slides);
+    if (ld < p->F) return fail(c, STT_EINVAL, "ld=%lld < F=%d", (long long)ld, p->F);
+    if (n_slides == 0) return STT_OK;
+    if (!shifts || !Y_dev || !sigma_dev) return fail(c, STT_EINVAL, "null slide table");
+    for (int k = 0; k < n_slides; ++k) {
+        if (!Y_dev[k] || !sigma_dev[k]) return fail(c, STT_EINVAL, "slide %d: null output", k);
+        if (((uintptr_t)Y_dev[k] & 7) || ((uintptr_t)sigma_dev[k] & 3))
+            return fail(c, STT_EINVAL, "slide %d: misaligned output", k);
+    }
+    STT_HIP(c, hipSetDevice(c->device));
+    if ((s = ev_begin(c)) != STT_OK) return s;
+    ev_record(c, 4);
+    ev_record(c, 0);
+    for (int k0 = 0; k0 < n_slides; k0 += kSlidesPerLaunch) {
+        SlideArgs a{};
+        a.n = std::min(kSlidesPerLaunch, n_slides - k0);
+        for (int k = 0; k < a.n; ++k) {
+            a.Y[k] = (float2 *)Y_dev[k0 + k];
+            a.sigma[k] = sigma_dev[k0 + k];
+            const int64_t sh = shifts[k0 + k] % T;
+            a.shift[k] = (int32_t)(sh < 0 ? sh + T : sh);
+        }
+        hipLaunchKernelGGL(k_form_maps, dim3((p->F + 255) / 256, T), dim3(256), 0, c->stream,
+                           (const float2 *)spec_i_dev, psd_i_dev, (const float2 *)spec_j_dev, psd_j_dev, T, p->F,
+                           cross_scale(p), ld, a);
+        STT_HIP(c, hipGetLastError());
+    }
+    ev_record(c, 1);
+    ev_record(c, 5);
+    c->used[0] = true;
+    c->used[2] = true;
+    ev_end(c);
+    return STT_OK;
+}
 
 }  // extern "C"
 

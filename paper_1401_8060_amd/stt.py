@@ -48,6 +48,35 @@ class _Map(C.Structure):
                 ("fq4_lo", C.c_int32), ("dfq4", C.c_int32)]
 
 
+class _Spectro(C.Structure):
+    _fields_ = [("fs", C.c_double), ("M", C.c_int32), ("k_lo", C.c_int32), ("F", C.c_int32), ("nb", C.c_int32)]
+
+
+@dataclass
+class Spectro:
+    """Map-formation parameters (stt_spectro): sample rate, samples per column (a power of two;
+    columns overlap by half), the kept bins k_lo .. k_lo+F-1, neighbour columns per side in P'."""
+    fs: float
+    M: int
+    k_lo: int
+    F: int
+    nb: int = 4
+
+    def c(self) -> _Spectro:
+        return _Spectro(float(self.fs), self.M, self.k_lo, self.F, self.nb)
+
+    def fq4(self) -> tuple[int, int]:
+        """(fq4_lo, dfq4) of the formed maps: row r at (k_lo + r) fs / M Hz, in 1/16 Hz."""
+        d = 16.0 * self.fs / self.M
+        if d != int(d):
+            raise ValueError(f"fs/M = {self.fs / self.M} Hz is not a multiple of 1/16 Hz")
+        return int(d) * self.k_lo, int(d)
+
+    def n_columns(self, n_samples: int) -> int:
+        """Largest T with every column inside n_samples samples."""
+        return max(0, 2 * n_samples // self.M - 1)
+
+
 _lib = None
 
 
@@ -519,6 +548,63 @@ class Context:
         self._chk(self._L.stt_score_batch(self.h, arr, nm, C.byref(g), ns, norm, C.c_void_p(best_keys.data_ptr()),
                                           ptrs))
         return best_keys
+
+    # -- map formation
+    def spectra(self, strain: torch.Tensor, p: Spectro, T: int | None = None, spec: torch.Tensor | None = None,
+                psd: torch.Tensor | None = None) -> tuple[torch.Tensor, torch.Tensor]:
+        """Column spectra s~ (complex64 [T][F]) and P' (float32 [T][F]) of one detector's strain."""
+        if strain.dtype != torch.float32 or not strain.is_cuda or not strain.is_contiguous():
+            raise ValueError("strain must be a contiguous float32 CUDA tensor")
+        n = strain.numel()
+        if T is None:
+            T = p.n_columns(n)
+        dev = strain.device
+        if spec is None:
+            spec = torch.empty((T, p.F), dtype=torch.complex64, device=dev)
+        if psd is None:
+            psd = torch.empty((T, p.F), dtype=torch.float32, device=dev)
+        for t, dt in ((spec, torch.complex64), (psd, torch.float32)):
+            if t.dtype != dt or tuple(t.shape) != (T, p.F) or not t.is_contiguous():
+                raise ValueError("spec / psd must be contiguous [T][F] complex64 / float32")
+        pc = p.c()
+        self._chk(self._L.stt_spectra(self.h, C.byref(pc), C.c_void_p(strain.data_ptr()), n, T,
+                                      C.c_void_p(spec.data_ptr()), C.c_void_p(psd.data_ptr())))
+        return spec, psd
+
+    def form_maps(self, p: Spectro, spec_i: torch.Tensor, psd_i: torch.Tensor, spec_j: torch.Tensor,
+                  psd_j: torch.Tensor, shifts, ld: int | None = None, out: list | None = None) -> list:
+        """One Map per time slide: column t of I against column (t + shift) mod T of J.
+
+        ``out`` may give the Maps to write (same T, F; reused across calls); otherwise new
+        [T][ld] buffers are allocated (ld defaults to F)."""
+        T = spec_i.shape[0]
+        for t, dt in ((spec_i, torch.complex64), (spec_j, torch.complex64), (psd_i, torch.float32),
+                      (psd_j, torch.float32)):
+            if t.dtype != dt or tuple(t.shape) != (T, p.F) or not t.is_contiguous() or not t.is_cuda:
+                raise ValueError("spectra and P' must be contiguous [T][F] CUDA tensors of one shape")
+        shifts = [int(x) for x in shifts]
+        fq4_lo, dfq4 = p.fq4()
+        if out is None:
+            ld = p.F if ld is None else ld
+            out = []
+            for _ in shifts:
+                Y = torch.empty((T, ld), dtype=torch.complex64, device=spec_i.device)[:, :p.F]
+                sg = torch.empty((T, ld), dtype=torch.float32, device=spec_i.device)[:, :p.F]
+                out.append(Map(Y, sg, fq4_lo, dfq4))
+        if len(out) != len(shifts):
+            raise ValueError("one output map per shift")
+        for m in out:
+            if (m.T, m.F) != (T, p.F) or m.ld != out[0].ld:
+                raise ValueError("output maps must be [T][F] with one column stride")
+        ns = len(shifts)
+        sh = (C.c_int32 * max(ns, 1))(*shifts)
+        yp = (C.c_void_p * max(ns, 1))(*[m.Y.data_ptr() for m in out])
+        sp = (C.c_void_p * max(ns, 1))(*[m.sigma.data_ptr() for m in out])
+        pc = p.c()
+        self._chk(self._L.stt_form_maps(self.h, C.byref(pc), T, C.c_void_p(spec_i.data_ptr()),
+                                        C.c_void_p(psd_i.data_ptr()), C.c_void_p(spec_j.data_ptr()),
+                                        C.c_void_p(psd_j.data_ptr()), ns, sh, out[0].ld if out else p.F, yp, sp))
+        return out
 
     def argmax(self, snr: torch.Tensor, first: int = 0, best_key: torch.Tensor | None = None) -> torch.Tensor:
         if snr.dtype != torch.float32 or not snr.is_contiguous():
