@@ -78,7 +78,7 @@ __global__ __launch_bounds__(kFftThreads) void k_col_fft(const float *__restrict
 }
 
 // P'(t; f) = scale * mean |spec(t', f)|^2 over 2 <= |t' - t| <= nb + 1 inside [0, T).
-// Grid: (ceil(F / 256), T); every column has a neighbour (T >= 3, checked by the host).
+// Grid: (ceil(F / 256), T); every column has a neighbour (T >= 4, checked by the host).
 __global__ __launch_bounds__(256) void k_psd(const float2 *__restrict__ spec, int T, int F, int nb, float scale,
                                              float *__restrict__ psd)
 {
@@ -96,25 +96,45 @@ __global__ __launch_bounds__(256) void k_psd(const float2 *__restrict__ spec, in
     psd[(int64_t)t * F + f] = scale * acc / (float)cnt;
 }
 
-// One launch writes up to kSlidesPerLaunch slide maps; lanes run along frequency, so every
-// store is a coalesced row segment. Grid: (ceil(F / 256), T).
+// One launch writes up to kSlidesPerLaunch slide maps. Lanes run along frequency, P bins each
+// (P = 2 when F and ld are even and the buffers 16-byte aligned: one 16-byte and one 8-byte store
+// per lane per slide), so every store is a coalesced row segment. Workgroups go round-robin to the
+// 8 XCDs; the remap gives each XCD a contiguous run of columns t, so the J columns t + shift that
+// its slides read stay in its own L2 instead of crossing to the MALL once per slide.
+// Grid: 1-D, ceil(nbx * T / 8) * 8 workgroups of 256 lanes, nbx = ceil(F / (256 P)).
+template <int P>
 __global__ __launch_bounds__(256) void k_form_maps(const float2 *__restrict__ si, const float *__restrict__ pi,
                                                    const float2 *__restrict__ sj, const float *__restrict__ pj,
                                                    int T, int F, float scale, int64_t ld, SlideArgs a)
 {
-    const int f = blockIdx.x * 256 + threadIdx.x;
-    const int t = blockIdx.y;
+    const int nbx = (F + 256 * P - 1) / (256 * P);
+    const int64_t nblk = (int64_t)nbx * T;
+    const int64_t per = (nblk + 7) / 8;
+    const int64_t L = (int64_t)(blockIdx.x % 8) * per + blockIdx.x / 8;
+    if (L >= nblk) return;
+    const int t = (int)(L / nbx);
+    const int f = P * ((int)(L % nbx) * 256 + (int)threadIdx.x);
     if (f >= F) return;
-    const float2 u = si[(int64_t)t * F + f];
-    const float pu = pi[(int64_t)t * F + f];
+    typedef float fv __attribute__((ext_vector_type(2 * P)));  // P complex values
+    typedef float pv __attribute__((ext_vector_type(P)));      // P powers
+    const fv u = *reinterpret_cast<const fv *>(si + (int64_t)t * F + f);
+    const pv pu = *reinterpret_cast<const pv *>(pi + (int64_t)t * F + f);
     for (int k = 0; k < a.n; ++k) {
         int tj = t + a.shift[k];
         if (tj >= T) tj -= T;
-        const float2 v = sj[(int64_t)tj * F + f];
-        const float pv = pj[(int64_t)tj * F + f];
-        const float yr = scale * (u.x * v.x + u.y * v.y), yi = scale * (u.x * v.y - u.y * v.x);
-        a.Y[k][(int64_t)t * ld + f] = make_float2(yr, yi);
-        a.sigma[k][(int64_t)t * ld + f] = sqrtf(0.5f * pu * pv);
+        const fv v = *reinterpret_cast<const fv *>(sj + (int64_t)tj * F + f);
+        const pv pq = *reinterpret_cast<const pv *>(pj + (int64_t)tj * F + f);
+        fv y;
+        pv sg;
+#pragma unroll
+        for (int q = 0; q < P; ++q) {
+            const float ur = u[2 * q], ui = u[2 * q + 1], vr = v[2 * q], vi = v[2 * q + 1];
+            y[2 * q] = scale * (ur * vr + ui * vi);
+            y[2 * q + 1] = scale * (ur * vi - ui * vr);
+            sg[q] = sqrtf(0.5f * pu[q] * pq[q]);
+        }
+        *reinterpret_cast<fv *>(a.Y[k] + (int64_t)t * ld + f) = y;
+        *reinterpret_cast<pv *>(a.sigma[k] + (int64_t)t * ld + f) = sg;
     }
 }
 

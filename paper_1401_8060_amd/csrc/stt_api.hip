@@ -1056,6 +1056,14 @@ stt_status stt_form_maps(stt_ctx *c, const stt_spectro *p, int32_t T, const floa
         if (((uintptr_t)Y_dev[k] & 7) || ((uintptr_t)sigma_dev[k] & 3))
             return fail(c, STT_EINVAL, "slide %d: misaligned output", k);
     }
+    // two bins per lane where every row segment stays 16-byte aligned
+    bool pair = (p->F % 2 == 0) && (ld % 2 == 0) && !((uintptr_t)spec_i_dev & 15) && !((uintptr_t)spec_j_dev & 15) &&
+                !((uintptr_t)psd_i_dev & 7) && !((uintptr_t)psd_j_dev & 7);
+    for (int k = 0; k < n_slides && pair; ++k)
+        pair = !((uintptr_t)Y_dev[k] & 15) && !((uintptr_t)sigma_dev[k] & 7);
+    const int per_lane = pair ? 2 : 1;
+    const int64_t nblk = (int64_t)((p->F + 256 * per_lane - 1) / (256 * per_lane)) * T;
+    const dim3 grid((unsigned)((nblk + 7) / 8 * 8));
     STT_HIP(c, hipSetDevice(c->device));
     if ((s = ev_begin(c)) != STT_OK) return s;
     ev_record(c, 4);
@@ -1069,9 +1077,12 @@ stt_status stt_form_maps(stt_ctx *c, const stt_spectro *p, int32_t T, const floa
             const int64_t sh = shifts[k0 + k] % T;
             a.shift[k] = (int32_t)(sh < 0 ? sh + T : sh);
         }
-        hipLaunchKernelGGL(k_form_maps, dim3((p->F + 255) / 256, T), dim3(256), 0, c->stream,
-                           (const float2 *)spec_i_dev, psd_i_dev, (const float2 *)spec_j_dev, psd_j_dev, T, p->F,
-                           cross_scale(p), ld, a);
+        if (pair)
+            hipLaunchKernelGGL(k_form_maps<2>, grid, dim3(256), 0, c->stream, (const float2 *)spec_i_dev, psd_i_dev,
+                               (const float2 *)spec_j_dev, psd_j_dev, T, p->F, cross_scale(p), ld, a);
+        else
+            hipLaunchKernelGGL(k_form_maps<1>, grid, dim3(256), 0, c->stream, (const float2 *)spec_i_dev, psd_i_dev,
+                               (const float2 *)spec_j_dev, psd_j_dev, T, p->F, cross_scale(p), ld, a);
         STT_HIP(c, hipGetLastError());
     }
     ev_record(c, 1);
