@@ -7,4 +7,4 @@ library in ``paper_1401_8060_amd``.
 """
 from .oracle import *  # noqa: F401,F403
 from .build import build, lib_path  # noqa: F401
-from . import mapform  # noqa: F401,E402
+from . import mapform, significance  # noqa: F401,E402
