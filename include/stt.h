@@ -204,6 +204,23 @@ stt_status stt_score_maxdelay(stt_ctx *ctx, const stt_map *map, const stt_gen *g
                               int64_t first, int64_t n, int32_t dtau0, int32_t dtau_step, int32_t n_tau, int32_t norm,
                               float *snr_dev, int32_t *tau_idx_dev, uint64_t *best_key_dev);
 
+/* ---- Significance of per-map maxima (the step after the search) ----
+ *
+ * The search keeps the best key of every map (Sec. V records the maximum per
+ * spectrogram); over background maps (time slides) these give the maximum's
+ * distribution in noise. For each foreground key i < n_fg:
+ *   n_louder_dev[i] = number of background keys at least as loud (int64),
+ *   fap_dev[i] = n_louder_dev[i] / n_bg (FP32), the false-alarm probability;
+ * and *z_alpha_dev = the ceil(alpha n_bg)-th largest background score (at least
+ * the largest one), so that a foreground maximum strictly above it has FAP <
+ * alpha (Sec. IV detects at FAP < 0.1 %). Loudness compares the keys' FP32
+ * scores; an empty key (0) is quieter than any score and counts as -inf in the
+ * threshold. Keys are 8-byte device arrays as written by the scorers. Any of
+ * the three outputs may be NULL (z_alpha needs 0 < alpha <= 1 and
+ * ceil(alpha n_bg) <= 8192); n_bg >= 1. Exact counts: n_fg * n_bg comparisons. */
+stt_status stt_significance(stt_ctx *ctx, const uint64_t *bg_keys_dev, int64_t n_bg, const uint64_t *fg_keys_dev,
+                            int64_t n_fg, double alpha, int64_t *n_louder_dev, float *fap_dev, float *z_alpha_dev);
+
 /* ---- Map formation: the complex SNR maps the search scores, from strain ----
  *
  * Two detectors' strain streams I and J become cross-power maps (Y, sigma) in

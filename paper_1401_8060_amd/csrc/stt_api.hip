@@ -14,6 +14,7 @@
 #include "stt.h"
 #include "kernels.hpp"
 #include "mapform.hpp"
+#include "signif.hpp"
 
 using namespace stt;
 
@@ -1004,6 +1005,42 @@ stt_status stt_rescore_f64(stt_ctx *c, const stt_map *map, const stt_gen *gen, c
 }
 
 // ----------------------------------------------------------------------------- batches
+
+stt_status stt_significance(stt_ctx *c, const uint64_t *bg_keys_dev, int64_t n_bg, const uint64_t *fg_keys_dev,
+                            int64_t n_fg, double alpha, int64_t *n_louder_dev, float *fap_dev, float *z_alpha_dev)
+{
+    if (!c) return STT_EINVAL;
+    if (n_bg < 1) return fail(c, STT_EINVAL, "need at least one background map");
+    if (n_fg < 0) return fail(c, STT_EINVAL, "n_fg=%lld", (long long)n_fg);
+    if (!bg_keys_dev) return fail(c, STT_EINVAL, "null background keys");
+    if (n_fg > 0 && !fg_keys_dev && (n_louder_dev || fap_dev)) return fail(c, STT_EINVAL, "null foreground keys");
+    int32_t m = 0;
+    if (z_alpha_dev) {
+        if (!(alpha > 0.0 && alpha <= 1.0)) return fail(c, STT_EINVAL, "alpha must be in (0, 1]");
+        const double mm = std::max(1.0, std::ceil(alpha * (double)n_bg));
+        if (mm > 8192) return fail(c, STT_ERANGE, "ceil(alpha n_bg) = %.0f exceeds 8192", mm);
+        m = (int32_t)mm;
+    }
+    STT_HIP(c, hipSetDevice(c->device));
+    stt_status s;
+    if (n_fg > 0 && (n_louder_dev || fap_dev)) {
+        hipLaunchKernelGGL(k_count_louder, dim3((unsigned)((n_fg + 255) / 256)), dim3(256), 0, c->stream, bg_keys_dev,
+                           n_bg, fg_keys_dev, n_fg, n_louder_dev, fap_dev, (double)n_bg);
+        STT_HIP(c, hipGetLastError());
+    }
+    if (z_alpha_dev) {
+        // the m-th largest background score: decode the keys, select the top m, keep the last
+        if ((s = ensure_mdbuf(c, sizeof(float) * ((size_t)n_bg + (size_t)m))) != STT_OK) return s;
+        float *scores = (float *)c->mdbuf;
+        float *top = scores + n_bg;
+        hipLaunchKernelGGL(k_key_scores, dim3((unsigned)((n_bg + 255) / 256)), dim3(256), 0, c->stream, bg_keys_dev,
+                           n_bg, scores);
+        STT_HIP(c, hipGetLastError());
+        if ((s = stt_topk(c, scores, n_bg, 0, m, nullptr, top)) != STT_OK) return s;
+        STT_HIP(c, hipMemcpyAsync(z_alpha_dev, top + (m - 1), sizeof(float), hipMemcpyDeviceToDevice, c->stream));
+    }
+    return STT_OK;
+}
 
 stt_status stt_spectra(stt_ctx *c, const stt_spectro *p, const float *strain_dev, int64_t n_samples, int32_t T,
                        float *spec_dev, float *psd_dev)

@@ -549,6 +549,41 @@ class Context:
                                           ptrs))
         return best_keys
 
+    # -- significance
+    def significance(self, bg_keys: torch.Tensor, fg_keys: torch.Tensor | None = None, alpha: float = 1e-3):
+        """(n_louder int64 [n_fg], fap float32 [n_fg], z_alpha float32 [1]) of foreground best keys
+        against background best keys (one per map); z_alpha is None when alpha is None."""
+        for t in (bg_keys, fg_keys):
+            if t is not None and (t.dtype != torch.int64 or not t.is_contiguous() or not t.is_cuda):
+                raise ValueError("keys must be contiguous int64 CUDA tensors")
+        n_fg = 0 if fg_keys is None else fg_keys.numel()
+        dev = bg_keys.device
+        cnt = torch.empty(n_fg, dtype=torch.int64, device=dev)
+        fap = torch.empty(n_fg, dtype=torch.float32, device=dev)
+        za = torch.empty(1, dtype=torch.float32, device=dev) if alpha is not None else None
+        self._chk(self._L.stt_significance(
+            self.h, C.c_void_p(bg_keys.data_ptr()), bg_keys.numel(),
+            C.c_void_p(fg_keys.data_ptr()) if n_fg else None, n_fg, float(alpha or 0.0),
+            C.c_void_p(cnt.data_ptr()) if n_fg else None, C.c_void_p(fap.data_ptr()) if n_fg else None,
+            C.c_void_p(za.data_ptr()) if za is not None else None))
+        return cnt, fap, za
+
+    def follow_up(self, maps, keys: torch.Tensor, gen: Gen, n_deep: int, k: int = 10) -> list[int]:
+        """Search the k loudest maps again with n_deep templates drawn with ``gen`` (use a seed the
+        first search did not) and max-merge the results into ``keys`` in place -- the follow-up of
+        the loudest events and the combination of runs by their maximum (Sec. V). Map m's
+        templates use Philox stream gen.stream + m, as in score_batch. Returns the indices of the
+        maps searched (ranked by the count of maps at least as loud; ties may add maps)."""
+        if keys.dtype != torch.int64 or keys.numel() != len(maps) or not keys.is_contiguous():
+            raise ValueError("one int64 key per map")
+        cnt, _, _ = self.significance(keys, keys, alpha=None)
+        order = cnt.cpu().tolist()
+        chosen = [m for m, c in enumerate(order) if c <= k]
+        for m in chosen:
+            gm = Gen(seed=gen.seed, stream=gen.stream + m, min_len=gen.min_len, dtau_max=gen.dtau_max)
+            self.score(maps[m], gen=gm, n=n_deep, snr=None, best_key=keys[m:m + 1])
+        return chosen
+
     # -- map formation
     def spectra(self, strain: torch.Tensor, p: Spectro, T: int | None = None, spec: torch.Tensor | None = None,
                 psd: torch.Tensor | None = None) -> tuple[torch.Tensor, torch.Tensor]:
