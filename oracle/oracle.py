@@ -151,6 +151,20 @@ def draw_many(seed: int, stream: int, first: int, n: int, T: int, F: int, L: int
     return out
 
 
+def draw_patch_many(seed: int, stream: int, first: int, n: int, T: int, F: int, L: int, D: int,
+                    center: int) -> np.ndarray:
+    """Templates whose delay prior is a sky patch instead of the whole sky (Sec. VI): the delay is
+    uniform on the integers [center - D, center + D] -- the isotropic draw on [-D, D] moved by
+    ``center``, with every other field as draw_many. Under isotropy within a band of directions
+    whose angle to the baseline spans [theta_1, theta_2], the delay is exactly uniform on the
+    matching interval; a patch is taken as such a band."""
+    if abs(center) + D >= 1 << 30:
+        raise ValueError("the patch leaves the delay range")
+    out = draw_many(seed, stream, first, n, T, F, L, D)
+    out["dtau"] = out["dtau"].astype(np.int64) + center
+    return out
+
+
 def _as_track(tr) -> _Track:
     tr = np.asarray(tr, dtype=TRACK_DTYPE)
     return _Track(int(tr["t0"]), int(tr["t2"]), int(tr["f0"]), int(tr["f1"]), int(tr["f2"]),
