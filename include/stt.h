@@ -86,8 +86,11 @@ typedef struct {
     uint64_t seed;     /* Philox4x32-10 key (low word, high word) */
     uint32_t stream;   /* Philox counter word 2: an independent sequence per map */
     int32_t min_len;   /* L: minimum pixels per track (the paper's t_min), >= 2 */
-    int32_t dtau_max;  /* delays are uniform on [-dtau_max, dtau_max], 2^-28 s units; 0 = targeted (Eq. 5) */
-    int32_t reserved;  /* must be 0 */
+    int32_t dtau_max;  /* delays are uniform on [dtau_center - dtau_max, dtau_center + dtau_max], 2^-28 s
+                          units; 0 = one fixed delay (the targeted search of Eq. 5) */
+    int32_t dtau_center; /* 0 for the all-sky (isotropic) prior; otherwise the centre of a sky patch's delay
+                            band (Sec. VI: a patch of sky instead of the isotropic prior; a band of directions
+                            about the baseline gives uniform delays on its interval). |center| + max < 2^30 */
 } stt_gen;
 
 typedef struct {
@@ -160,8 +163,10 @@ stt_status stt_set_trig(stt_ctx *ctx, int32_t hw);
  * i in [0, n): Philox4x32-10 with key = seed, counter = (j, stream, b) for
  * blocks b = 0, 1; the time extent is uniform over the pairs (t0, t2) with
  * t2 - t0 + 1 >= min_len, the control frequencies are uniform on [0, F) and
- * the delay uniform on the integers [-dtau_max, dtau_max]. Requires
- * 2 <= min_len <= T <= STT_MAX_T, 1 <= F <= STT_MAX_F, 0 <= dtau_max < 2^30,
+ * the delay uniform on the integers [dtau_center - dtau_max, dtau_center +
+ * dtau_max] (the same random word whatever the centre, so a patch moves every
+ * delay by exactly dtau_center). Requires 2 <= min_len <= T <= STT_MAX_T,
+ * 1 <= F <= STT_MAX_F, 0 <= dtau_max, |dtau_center| + dtau_max < 2^30,
  * first + n <= 2^32. n = 0 is a no-op. */
 stt_status stt_make_tracks(stt_ctx *ctx, const stt_gen *gen, int32_t T, int32_t F, int64_t first,
                            int64_t n, stt_track *out_dev);

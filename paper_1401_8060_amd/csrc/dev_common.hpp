@@ -57,7 +57,7 @@ struct GenP {
     uint32_t npairs;      // number of (t0, t2) pairs with >= L pixels
     int32_t L;            // minimum pixels
     uint32_t frange;      // F << 8
-    int32_t dmax;         // delay bound (2^-28 s units)
+    int32_t dmax;         // minus the lowest delay: D - center (2^-28 s units)
     uint32_t dspan;       // 2*dmax + 1
 };
 

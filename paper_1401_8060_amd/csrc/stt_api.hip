@@ -188,11 +188,13 @@ stt_status check_map(stt_ctx *c, const stt_map *m)
 stt_status make_genp(stt_ctx *c, const stt_gen *g, int32_t T, int32_t F, GenP &p)
 {
     if (!g) return fail(c, STT_EINVAL, "gen is NULL");
-    if (g->reserved != 0) return fail(c, STT_EINVAL, "gen.reserved must be 0");
     if (T < 2 || T > STT_MAX_T) return fail(c, STT_ERANGE, "T=%d outside [2, %d]", T, STT_MAX_T);
     if (F < 1 || F > STT_MAX_F) return fail(c, STT_ERANGE, "F=%d outside [1, %d]", F, STT_MAX_F);
     if (g->min_len < 2 || g->min_len > T) return fail(c, STT_ERANGE, "min_len=%d outside [2, T=%d]", g->min_len, T);
     if (g->dtau_max < 0 || g->dtau_max >= (1 << 30)) return fail(c, STT_ERANGE, "dtau_max=%d outside [0, 2^30)", g->dtau_max);
+    if (std::llabs((int64_t)g->dtau_center) + g->dtau_max >= ((int64_t)1 << 30))
+        return fail(c, STT_ERANGE, "delay patch [%d - %d, %d + %d] leaves (-2^30, 2^30)", g->dtau_center, g->dtau_max,
+                    g->dtau_center, g->dtau_max);
     const int64_t npos = (int64_t)T - g->min_len + 1;
     p.key0 = (uint32_t)g->seed;
     p.key1 = (uint32_t)(g->seed >> 32);
@@ -200,7 +202,7 @@ stt_status make_genp(stt_ctx *c, const stt_gen *g, int32_t T, int32_t F, GenP &p
     p.npairs = (uint32_t)(npos * (npos + 1) / 2);
     p.L = g->min_len;
     p.frange = (uint32_t)F << 8;
-    p.dmax = g->dtau_max;
+    p.dmax = g->dtau_max - g->dtau_center;  // the draw subtracts this: delays on [center - D, center + D]
     p.dspan = 2u * (uint32_t)g->dtau_max + 1u;
     return STT_OK;
 }

@@ -39,7 +39,7 @@ class Track(C.Structure):
 
 class _Gen(C.Structure):
     _fields_ = [("seed", C.c_uint64), ("stream", C.c_uint32), ("min_len", C.c_int32),
-                ("dtau_max", C.c_int32), ("reserved", C.c_int32)]
+                ("dtau_max", C.c_int32), ("dtau_center", C.c_int32)]
 
 
 class _Map(C.Structure):
@@ -136,14 +136,16 @@ EXPORTED = [
 
 @dataclass
 class Gen:
-    """Template law: Philox seed/stream, minimum length L (pixels), delay bound (2^-28 s units)."""
+    """Template law: Philox seed/stream, minimum length L (pixels), delay half-width and centre
+    (2^-28 s units; centre 0 is the all-sky prior, another centre a sky patch's delay band)."""
     seed: int = 1
     stream: int = 0
     min_len: int = 10
     dtau_max: int = 2684355  # 10 ms
+    dtau_center: int = 0
 
     def c(self) -> _Gen:
-        return _Gen(self.seed, self.stream, self.min_len, self.dtau_max, 0)
+        return _Gen(self.seed, self.stream, self.min_len, self.dtau_max, self.dtau_center)
 
 
 def dtau_units(seconds: float) -> int:
@@ -580,7 +582,8 @@ class Context:
         order = cnt.cpu().tolist()
         chosen = [m for m, c in enumerate(order) if c <= k]
         for m in chosen:
-            gm = Gen(seed=gen.seed, stream=gen.stream + m, min_len=gen.min_len, dtau_max=gen.dtau_max)
+            gm = Gen(seed=gen.seed, stream=gen.stream + m, min_len=gen.min_len, dtau_max=gen.dtau_max,
+                     dtau_center=gen.dtau_center)
             self.score(maps[m], gen=gm, n=n_deep, snr=None, best_key=keys[m:m + 1])
         return chosen
 
