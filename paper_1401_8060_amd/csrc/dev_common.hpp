@@ -139,33 +139,77 @@ STT_HD TrkTm draw_track_tm(const GenP &g, uint64_t j)
 // 1e-6 of an integer (end columns, perfect squares) is settled exactly by the
 // sign of V sqrt(D) - (r W - U), from signs and 128-bit squares. For a = 0 (t1
 // at the midpoint) xi = dt / Dt and the row is the plain rasteriser's.
+// Hardware square root and reciprocal, each within 1 ulp; the host build (tests) uses the
+// correctly rounded operations, or moves them by one ulp when STT_HOST_ULP_PERTURB is set.
+#if defined(STT_HOST_ULP_PERTURB)
+float stt_host_perturb(float);
+#endif
+STT_HD float sqrt_1ulp(float x)
+{
+#if defined(__HIP_DEVICE_COMPILE__)
+    return __builtin_amdgcn_sqrtf(x);
+#elif defined(STT_HOST_ULP_PERTURB)
+    return stt_host_perturb(std::sqrt(x));
+#else
+    return std::sqrt(x);
+#endif
+}
+STT_HD float rcp_1ulp(float x)
+{
+#if defined(__HIP_DEVICE_COMPILE__)
+    return __builtin_amdgcn_rcpf(x);
+#elif defined(STT_HOST_ULP_PERTURB)
+    return stt_host_perturb(1.0f / x);
+#else
+    return 1.0f / x;
+#endif
+}
+
+// x * y for |x|, |y| < 2^23 (one full-rate 24-bit multiply on the device)
+STT_HD int32_t mul_i24(int32_t x, int32_t y)
+{
+#if defined(__HIP_DEVICE_COMPILE__)
+    return __mul24(x, y);
+#else
+    return x * y;
+#endif
+}
+
+// Row state of a free-t_mid template. Column t0 + dt has time parameter xi, the root in [0, 1]
+// of a xi^2 + b xi = dt (a = t0 - 2 t1 + t2, b = 2 (t1 - t0) >= 0), taken in the stable form
+// xi = 2 dt / (b + sqrt(D)) with D = b^2 + 4 a dt, and row floor(f(xi) / 256),
+// f = f0 + B xi + C xi^2 (B = 2 (f1 - f0), C = f0 - 2 f1 + f2).
 struct RowTm {
-    int64_t a, b, V, U0, U1, W, A0, B0, C0, Q0;  // A0..Q0: the a = 0 (linear) case
-    double fd, Bd, Cd, bd;
-    uint32_t f0;
+    int32_t t0, t1, t2;
+    uint32_t f0, f1, f2;
+    int32_t bb, a4;        // b^2 and 4 a: D = bb + a4 dt, exact in 32 bits for T <= 2896
+    float bf, fs, Bs, Cs;  // b, f0/256, B/256, C/256
+    float tol;             // bound on |y32 - f(xi)/256| over the template, in rows
 };
 
 STT_HD RowTm row_tm_init(const TrkTm &t)
 {
     RowTm k;
-    const int64_t f0 = t.f0, f1 = t.f1, f2 = t.f2;
-    const int64_t B = 2 * (f1 - f0), C = f0 - 2 * f1 + f2;
-    k.a = (int64_t)t.t0 - 2 * (int64_t)t.t1 + t.t2;
-    k.b = 2 * ((int64_t)t.t1 - t.t0);
-    k.V = k.a * B - C * k.b;
-    k.U0 = 2 * k.a * k.a * f0 - k.b * k.V;
-    k.U1 = 2 * k.a * C;
-    k.W = 512 * k.a * k.a;
-    const int64_t Dt = (int64_t)t.t2 - t.t0;
-    k.A0 = Dt * Dt * f0;
-    k.B0 = 2 * Dt * (f1 - f0);
-    k.C0 = C;
-    k.Q0 = (Dt * Dt) << 8;
-    k.fd = (double)f0;
-    k.Bd = (double)B;
-    k.Cd = (double)C;
-    k.bd = (double)k.b;
-    k.f0 = t.f0;
+    k.t0 = t.t0; k.t1 = t.t1; k.t2 = t.t2;
+    k.f0 = t.f0; k.f1 = t.f1; k.f2 = t.f2;
+    const int32_t a = t.t0 - 2 * t.t1 + t.t2, b = 2 * (t.t1 - t.t0);
+    const int64_t B = 2 * ((int64_t)t.f1 - t.f0), C = (int64_t)t.f0 - 2 * (int64_t)t.f1 + t.f2;
+    k.bb = b * b;
+    k.a4 = 4 * a;
+    k.bf = (float)b;
+    k.fs = (float)t.f0 * (1.0f / 256.0f);
+    k.Bs = (float)B * (1.0f / 256.0f);
+    k.Cs = (float)C * (1.0f / 256.0f);
+    // Error of the FP32 pass, to first order in u = 2^-24, with each of sqrt and rcp within
+    // 1 ulp (2u relative): (float)D, sqrt, b + s (b, sqrt(D) >= 0: no cancellation), rcp and
+    // * 2dt leave xi = xi_exact (1 + e), |e| <= 6.5u. The rounded B/256 and C/256 (u each) and
+    // the two FMAs (u each) then give, for xi <= 1,
+    //   |g32 - g| <= 8.5u xi |C'| + 2u |B'|             (g = B' + C' xi)
+    //   |y32 - y| <= 9.5u |B'| + 16u |C'| + u f0'       (y = f0' + g xi, primes: / 256).
+    // The window is 1.5 times (10u |B'| + 17u |C'| + u f0'), plus 2^-20.
+    const double u = 1.0 / 16777216.0;
+    const double aB = std::fabs((double)B) / 256.0, aC = std::fabs((double)C) / 256.0;
+    k.tol = (float)(1.5 * (10.0 * u * aB + 17.0 * u * aC + u * (double)t.f0 / 256.0) + 1.0 / 1048576.0);
     return k;
 }
 
@@ -181,20 +225,50 @@ STT_HD int cmp_vsqrtd(int64_t V, int64_t D, int64_t X)
     return V > 0 ? c : -c;
 }
 
-STT_HD int32_t row_tm(const RowTm &k, int32_t dt)
+// The row where the FP32 pass is too close to a boundary to decide (or undefined: b = 0 at
+// dt = 0). Linear time (a = 0) and dt = 0 are exact integer cases. Otherwise FP64 refines the
+// FP32 root: sqrt(D) by one Newton step from s32 (D - s32^2 is exact in FP64), 1 / (b + sqrt(D))
+// by one Newton step from the 1-ulp reciprocal; xi's relative error stays below 1e-13, so
+// |y - f/256| < 3e-8 rows for F <= 32767 and a value farther than 1e-6 from a boundary is
+// decided. Within 1e-6 the floor is the nearest integer r0 or r0 - 1: with xi = (sqrt(D) - b)/(2a),
+// f/256 = (V sqrt(D) + U0 + U1 dt) / W (V = aB - Cb, U0 = 2a^2 f0 - bV, U1 = 2aC, W = 512 a^2 > 0),
+// so the sign of V sqrt(D) - (r0 W - U0 - U1 dt), taken exactly in 128-bit integers, decides it.
+STT_HD int32_t row_tm_exact(const RowTm &k, int32_t dt, int32_t D, float s32)
 {
-    if (k.a == 0) {  // linear time: num(dt) / Q exactly (num < 2^48)
-        const int64_t num = k.A0 + k.B0 * dt + k.C0 * (int64_t)dt * dt;
-        return (int32_t)(num / k.Q0);
+    const int64_t a = (int64_t)k.t0 - 2 * (int64_t)k.t1 + k.t2, b = 2 * ((int64_t)k.t1 - k.t0);
+    const int64_t f0 = k.f0, B = 2 * ((int64_t)k.f1 - f0), C = f0 - 2 * (int64_t)k.f1 + k.f2;
+    if (a == 0) {  // linear time: num(dt) / Q exactly (num < 2^48)
+        const int64_t Dt = (int64_t)k.t2 - k.t0;
+        const int64_t num = Dt * Dt * f0 + 2 * Dt * ((int64_t)k.f1 - f0) * dt + C * (int64_t)dt * dt;
+        return (int32_t)(num / ((Dt * Dt) << 8));
     }
     if (dt == 0) return (int32_t)(k.f0 >> 8);
-    const int64_t D = k.b * k.b + 4 * k.a * dt;
-    const double xi = 2.0 * (double)dt / (k.bd + sqrt((double)D));
-    const double y = fma(xi, fma(xi, k.Cd, k.Bd), k.fd) * (1.0 / 256.0);
+    const double s0 = (double)s32;
+    const double s = D == 0 ? 0.0 : fma(fma(-s0, s0, (double)D), 0.5 * (double)rcp_1ulp(s32), s0);
+    const double den = (double)b + s;
+    const double r0 = (double)rcp_1ulp((float)den);
+    const double xi = (double)(2 * dt) * fma(r0, fma(-den, r0, 1.0), r0);
+    const double y = fma(xi, fma(xi, (double)C, (double)B), (double)f0) * (1.0 / 256.0);
     const double r = floor(y);
     if (y - r > 1e-6 && y - r < 1.0 - 1e-6) return (int32_t)r;
-    const int64_t r0 = (int64_t)floor(y + 0.5);  // the nearest integer: the floor is r0 or r0 - 1
-    return (int32_t)(cmp_vsqrtd(k.V, D, r0 * k.W - (k.U0 + k.U1 * dt)) >= 0 ? r0 : r0 - 1);
+    const int64_t V = a * B - C * b, U0 = 2 * a * a * f0 - b * V, U1 = 2 * a * C, W = 512 * a * a;
+    const int64_t ri = (int64_t)floor(y + 0.5);  // the nearest integer: the floor is ri or ri - 1
+    return (int32_t)(cmp_vsqrtd(V, D, ri * W - (U0 + U1 * dt)) >= 0 ? ri : ri - 1);
+}
+
+// Row of column t0 + dt (0 <= dt <= t2 - t0): an FP32 pass whose result stands when it lies
+// farther than tol from a row boundary (the FP32 error is below tol, so the exact value is on the
+// same side); otherwise the exact path.
+STT_HD int32_t row_tm(const RowTm &k, int32_t dt)
+{
+    const int32_t D = k.bb + mul_i24(k.a4, dt);
+    const float s32 = sqrt_1ulp((float)D);
+    const float xi = (float)(2 * dt) * rcp_1ulp(k.bf + s32);
+    const float y = fmaf(xi, fmaf(xi, k.Cs, k.Bs), k.fs);
+    const float r = floorf(y);
+    const float fr = y - r;  // exact
+    if (fr > k.tol && fr < 1.0f - k.tol) return (int32_t)r;
+    return row_tm_exact(k, dt, D, s32);
 }
 
 // ----------------------------------------------------------------------------

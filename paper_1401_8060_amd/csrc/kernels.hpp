@@ -707,7 +707,7 @@ __device__ __forceinline__ void walk_tm(int ca, int cb, int c0, const float2 *sl
             for (int q = 0; q < TPT; ++q) {
                 const int32_t dt = c - t0[q];
                 const bool act = !MASK || (uint32_t)dt <= span[q];
-                const int32_t row = row_tm(rk[q], act ? dt : 0);
+                const int32_t row = row_tm(rk[q], act ? dt : 1);  // dt = 1 is valid for every template
                 const float v = add_term<HW>(part[q], pk[q], row, col[row]);
                 part[q] = act ? v : part[q];
             }

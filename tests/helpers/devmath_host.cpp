@@ -11,6 +11,8 @@
 //   key   z j                          -> 64-bit key (hex)
 //   drawtm seed stream j T F L D       -> t0 t1 t2 f0 f1 f2 dtau (free t_mid)
 //   rowstm t0 t1 t2 f0 f1 f2           -> N rows of a free-t_mid template
+//   tmstat t0 t1 t2 f0 f1 f2           -> columns whose FP32 pass fell back to the exact path
+//   tmerr t0 t1 t2 f0 f1 f2            -> largest |y32 - y| / tol over the columns (y in FP64)
 #include <cmath>
 #include <cstdio>
 #include <cstring>
@@ -19,6 +21,21 @@
 #include "dev_common.hpp"
 
 using namespace stt;
+
+#ifdef STT_HOST_ULP_PERTURB
+// One-ulp moves of the square roots and reciprocals of the free-t_mid rows' FP32 pass, in a
+// pseudo-random direction: a harsher error than the hardware's (within 1 ulp), so that rows
+// staying exact here show the certified window covers the device.
+namespace stt {
+float stt_host_perturb(float x)
+{
+    static uint32_t s = 0x9E3779B9u;
+    s = s * 1664525u + 1013904223u;
+    if (x == 0.0f) return x;
+    return std::nextafter(x, (s >> 31) ? INFINITY : -INFINITY);
+}
+}  // namespace stt
+#endif
 
 int main()
 {
@@ -68,6 +85,37 @@ int main()
             const RowTm k = row_tm_init(t);
             for (int dt = 0; dt <= t.t2 - t.t0; ++dt) std::printf(dt ? " %d" : "%d", row_tm(k, dt));
             std::printf("\n");
+        } else if (!std::strcmp(cmd, "tmstat")) {
+            TrkTm t;
+            if (std::scanf("%d %d %d %u %u %u", &t.t0, &t.t1, &t.t2, &t.f0, &t.f1, &t.f2) != 6) return 2;
+            t.dtau = 0;
+            const RowTm k = row_tm_init(t);
+            int nfb = 0;
+            for (int dt = 1; dt <= t.t2 - t.t0; ++dt) {
+                const int32_t D = k.bb + k.a4 * dt;
+                const float xi = (float)(2 * dt) * rcp_1ulp(k.bf + sqrt_1ulp((float)D));
+                const float y = fmaf(xi, fmaf(xi, k.Cs, k.Bs), k.fs);
+                const float fr = y - floorf(y);
+                nfb += !(fr > k.tol && fr < 1.0f - k.tol);
+            }
+            std::printf("%d %.6e\n", nfb, (double)k.tol);
+        } else if (!std::strcmp(cmd, "tmerr")) {
+            TrkTm t;
+            if (std::scanf("%d %d %d %u %u %u", &t.t0, &t.t1, &t.t2, &t.f0, &t.f1, &t.f2) != 6) return 2;
+            t.dtau = 0;
+            const RowTm k = row_tm_init(t);
+            const double b = 2.0 * (t.t1 - t.t0);
+            const double B = 2.0 * ((double)t.f1 - t.f0), C = (double)t.f0 - 2.0 * t.f1 + t.f2;
+            double worst = 0.0;
+            for (int dt = 1; dt <= t.t2 - t.t0; ++dt) {
+                const int32_t D = k.bb + k.a4 * dt;
+                const float xi32 = (float)(2 * dt) * rcp_1ulp(k.bf + sqrt_1ulp((float)D));
+                const float y32 = fmaf(xi32, fmaf(xi32, k.Cs, k.Bs), k.fs);
+                const double xi = 2.0 * dt / (b + std::sqrt((double)D));
+                const double y = (t.f0 + xi * (B + C * xi)) / 256.0;
+                worst = std::fmax(worst, std::fabs((double)y32 - y) / (double)k.tol);
+            }
+            std::printf("%.6f\n", worst);
         } else if (!std::strcmp(cmd, "rows")) {
             Trk t;
             if (std::scanf("%d %d %u %u %u", &t.t0, &t.t2, &t.f0, &t.f1, &t.f2) != 5) return 2;

@@ -23,14 +23,13 @@ D10MS = 2684355  # 10 ms in 2^-28 s units
 ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 
 
-@pytest.fixture(scope="module")
-def devmath(tmp_path_factory):
+def _build_devmath(tmp_path_factory, defines=()):
     hipcc = shutil.which("hipcc") or "/opt/rocm/bin/hipcc"
     if not os.path.exists(hipcc):
         pytest.skip("hipcc not available")
     out = tmp_path_factory.mktemp("devmath") / "devmath"
     src = os.path.join(ROOT, "tests", "helpers", "devmath_host.cpp")
-    subprocess.run([hipcc, "-O2", "-x", "hip", "--offload-arch=gfx950", "-w",
+    subprocess.run([hipcc, "-O2", "-x", "hip", "--offload-arch=gfx950", "-w", *[f"-D{d}" for d in defines],
                     "-I", os.path.join(ROOT, "paper_1401_8060_amd", "csrc"), src, "-o", str(out)],
                    check=True, capture_output=True)
 
@@ -38,6 +37,18 @@ def devmath(tmp_path_factory):
         r = subprocess.run([str(out)], input="\n".join(lines) + "\n", capture_output=True, text=True, check=True)
         return r.stdout.strip().split("\n")
     return run
+
+
+@pytest.fixture(scope="module")
+def devmath(tmp_path_factory):
+    return _build_devmath(tmp_path_factory)
+
+
+@pytest.fixture(scope="module")
+def devmath_ulp(tmp_path_factory):
+    """The same harness with every FP32 square root and reciprocal of the free-t_mid rows moved by
+    one ulp (a harsher error than the hardware's)."""
+    return _build_devmath(tmp_path_factory, ["STT_HOST_ULP_PERTURB"])
 
 
 def test_generated_templates_bit_exact(orc, devmath):
@@ -187,10 +198,13 @@ def test_free_tmid_draw_bit_exact(orc, devmath):
     assert [tuple(int(x) for x in g.split()) for g in got] == [tuple(int(v) for v in w) for w in want.tolist()]
 
 
-def test_free_tmid_rows_bit_exact(orc, devmath):
-    """row_tm (FP64 with the exact fallback) against the oracle's exact integer rows: random
-    templates over the full size range, every t1 of small templates, and control frequencies on
-    row boundaries (where the fallback decides)."""
+@pytest.mark.parametrize("mode", ["rounded", "one_ulp_off"])
+def test_free_tmid_rows_bit_exact(orc, devmath, devmath_ulp, mode):
+    """row_tm (an FP32 pass within a certified window, else FP64 with the exact fallback) against
+    the oracle's exact integer rows: random templates over the full size range, every t1 of small
+    templates, and control frequencies on row boundaries (where the fallbacks decide); once with
+    correctly rounded FP32 square roots and reciprocals and once with each moved by one ulp."""
+    run = devmath if mode == "rounded" else devmath_ulp
     rng = np.random.default_rng(41)
     cases = []
     F = 32767
@@ -206,7 +220,44 @@ def test_free_tmid_rows_bit_exact(orc, devmath):
             cases.append((t0, t1, t2, *[int(x) for x in rng.integers(0, 50 * 256, 3)]))
     cases += [(0, 0, 2895, 0, F * 256 - 1, 0), (0, 2895, 2895, F * 256 - 1, 0, F * 256 - 1),
               (7, 7, 2000, 12345, 12345, 12345)]
-    got = devmath([f"rowstm {' '.join(str(v) for v in c)}" for c in cases])
+    for _ in range(400):  # the search maps' band, F = 1000
+        t0 = int(rng.integers(0, 999))
+        t2 = int(rng.integers(t0 + 1, 1000))
+        cases.append((t0, int(rng.integers(t0, t2 + 1)), t2, *[int(x) for x in rng.integers(0, 1000 * 256, 3)]))
+    got = run([f"rowstm {' '.join(str(v) for v in c)}" for c in cases])
     for c, g in zip(cases, got):
         tr = np.array([c + (0,)], dtype=orc.TRACK_TM_DTYPE)
         assert [int(x) for x in g.split()] == orc.rows_tm(tr, F).tolist(), c
+
+
+def test_free_tmid_fp32_pass_mostly_stands(devmath):
+    """On the search maps' band (F = 1000) the FP32 pass decides almost every column: the exact
+    path runs for under 1 % of them."""
+    rng = np.random.default_rng(42)
+    cases = []
+    for _ in range(300):
+        t0 = int(rng.integers(0, 900))
+        t2 = int(rng.integers(t0 + 50, 1000))
+        cases.append((t0, int(rng.integers(t0, t2 + 1)), t2, *[int(x) for x in rng.integers(0, 1000 * 256, 3)]))
+    got = devmath([f"tmstat {' '.join(str(v) for v in c)}" for c in cases])
+    fb = sum(int(g.split()[0]) for g in got)
+    cols = sum(c[2] - c[0] for c in cases)
+    assert fb / cols < 0.01, (fb, cols)
+
+
+@pytest.mark.parametrize("mode", ["rounded", "one_ulp_off"])
+def test_free_tmid_fp32_error_inside_window(devmath, devmath_ulp, mode):
+    """The FP32 pass's actual error against an FP64 evaluation stays well inside its certified
+    window on every column of random templates (both bands, all shapes of t1), also when each
+    square root and reciprocal is one ulp off."""
+    run = devmath if mode == "rounded" else devmath_ulp
+    rng = np.random.default_rng(43)
+    cases = []
+    for F, T in ((1000, 1000), (32767, 2896), (151, 500)):
+        for _ in range(250):
+            t0 = int(rng.integers(0, T - 1))
+            t2 = int(rng.integers(t0 + 1, T))
+            t1 = int(rng.choice([t0, t2, int(rng.integers(t0, t2 + 1))]))
+            cases.append((t0, t1, t2, *[int(x) for x in rng.integers(0, F * 256, 3)]))
+    worst = max(float(w) for w in run([f"tmerr {' '.join(str(v) for v in c)}" for c in cases]))
+    assert worst < 0.8, worst
