@@ -233,7 +233,9 @@ STT_HD int cmp_vsqrtd(int64_t V, int64_t D, int64_t X)
 // decided. Within 1e-6 the floor is the nearest integer r0 or r0 - 1: with xi = (sqrt(D) - b)/(2a),
 // f/256 = (V sqrt(D) + U0 + U1 dt) / W (V = aB - Cb, U0 = 2a^2 f0 - bV, U1 = 2aC, W = 512 a^2 > 0),
 // so the sign of V sqrt(D) - (r0 W - U0 - U1 dt), taken exactly in 128-bit integers, decides it.
-STT_HD int32_t row_tm_exact(const RowTm &k, int32_t dt, int32_t D, float s32)
+// Kept out of line: inlined, its rarely used FP64 and 128-bit temporaries would double the
+// scorers' register count.
+__host__ __device__ __attribute__((noinline)) int32_t row_tm_exact(const RowTm &k, int32_t dt, int32_t D, float s32)
 {
     const int64_t a = (int64_t)k.t0 - 2 * (int64_t)k.t1 + k.t2, b = 2 * ((int64_t)k.t1 - k.t0);
     const int64_t f0 = k.f0, B = 2 * ((int64_t)k.f1 - f0), C = f0 - 2 * (int64_t)k.f1 + k.f2;
