@@ -225,17 +225,9 @@ STT_HD int cmp_vsqrtd(int64_t V, int64_t D, int64_t X)
     return V > 0 ? c : -c;
 }
 
-// The row where the FP32 pass is too close to a boundary to decide (or undefined: b = 0 at
-// dt = 0). Linear time (a = 0) and dt = 0 are exact integer cases. Otherwise FP64 refines the
-// FP32 root: sqrt(D) by one Newton step from s32 (D - s32^2 is exact in FP64), 1 / (b + sqrt(D))
-// by one Newton step from the 1-ulp reciprocal; xi's relative error stays below 1e-13, so
-// |y - f/256| < 3e-8 rows for F <= 32767 and a value farther than 1e-6 from a boundary is
-// decided. Within 1e-6 the floor is the nearest integer r0 or r0 - 1: with xi = (sqrt(D) - b)/(2a),
-// f/256 = (V sqrt(D) + U0 + U1 dt) / W (V = aB - Cb, U0 = 2a^2 f0 - bV, U1 = 2aC, W = 512 a^2 > 0),
-// so the sign of V sqrt(D) - (r0 W - U0 - U1 dt), taken exactly in 128-bit integers, decides it.
-// Kept out of line: inlined, its rarely used FP64 and 128-bit temporaries would double the
-// scorers' register count.
-__host__ __device__ __attribute__((noinline)) int32_t row_tm_exact(const RowTm &k, int32_t dt, int32_t D, float s32)
+// Linear time (a = 0: an exact int64 quotient) and values within 1e-6 of a row boundary (the
+// 128-bit decision): rare, so out of line.
+__host__ __device__ __attribute__((noinline)) int32_t row_tm_decide(const RowTm &k, int32_t dt, int32_t D, double y)
 {
     const int64_t a = (int64_t)k.t0 - 2 * (int64_t)k.t1 + k.t2, b = 2 * ((int64_t)k.t1 - k.t0);
     const int64_t f0 = k.f0, B = 2 * ((int64_t)k.f1 - f0), C = f0 - 2 * (int64_t)k.f1 + k.f2;
@@ -244,18 +236,34 @@ __host__ __device__ __attribute__((noinline)) int32_t row_tm_exact(const RowTm &
         const int64_t num = Dt * Dt * f0 + 2 * Dt * ((int64_t)k.f1 - f0) * dt + C * (int64_t)dt * dt;
         return (int32_t)(num / ((Dt * Dt) << 8));
     }
-    if (dt == 0) return (int32_t)(k.f0 >> 8);
-    const double s0 = (double)s32;
-    const double s = D == 0 ? 0.0 : fma(fma(-s0, s0, (double)D), 0.5 * (double)rcp_1ulp(s32), s0);
-    const double den = (double)b + s;
-    const double r0 = (double)rcp_1ulp((float)den);
-    const double xi = (double)(2 * dt) * fma(r0, fma(-den, r0, 1.0), r0);
-    const double y = fma(xi, fma(xi, (double)C, (double)B), (double)f0) * (1.0 / 256.0);
-    const double r = floor(y);
-    if (y - r > 1e-6 && y - r < 1.0 - 1e-6) return (int32_t)r;
     const int64_t V = a * B - C * b, U0 = 2 * a * a * f0 - b * V, U1 = 2 * a * C, W = 512 * a * a;
     const int64_t ri = (int64_t)floor(y + 0.5);  // the nearest integer: the floor is ri or ri - 1
     return (int32_t)(cmp_vsqrtd(V, D, ri * W - (U0 + U1 * dt)) >= 0 ? ri : ri - 1);
+}
+
+// The row where the FP32 pass is too close to a boundary to decide (or undefined: b = 0 at
+// dt = 0). FP64 refines the FP32 root: sqrt(D) by one Newton step from s32 (D - s32^2 is exact
+// in FP64), 1 / (b + sqrt(D)) by one Newton step from the 1-ulp reciprocal; xi's relative error
+// stays below 1e-13, so |y - f/256| < 3e-8 rows for F <= 32767 and a value farther than 1e-6
+// from a boundary is decided here. Within 1e-6 the floor is the nearest integer r0 or r0 - 1:
+// with xi = (sqrt(D) - b)/(2a), f/256 = (V sqrt(D) + U0 + U1 dt) / W (V = aB - Cb,
+// U0 = 2a^2 f0 - bV, U1 = 2aC, W = 512 a^2 > 0), and the sign of V sqrt(D) - (r0 W - U0 - U1 dt),
+// taken exactly in 128-bit integers by row_tm_decide, settles it. That call (and linear time)
+// stays out of line: inlined, its 128-bit temporaries would raise the scorers' register count.
+STT_HD int32_t row_tm_exact(const RowTm &k, int32_t dt, int32_t D, float s32)
+{
+    if (k.t0 - 2 * k.t1 + k.t2 == 0) return row_tm_decide(k, dt, D, 0.0);
+    if (dt == 0) return (int32_t)(k.f0 >> 8);
+    const double s0 = (double)s32;
+    const double s = D == 0 ? 0.0 : fma(fma(-s0, s0, (double)D), 0.5 * (double)rcp_1ulp(s32), s0);
+    const double den = (double)(2 * (k.t1 - k.t0)) + s;
+    const double r0 = (double)rcp_1ulp((float)den);
+    const double xi = (double)(2 * dt) * fma(r0, fma(-den, r0, 1.0), r0);
+    const double B = 2.0 * ((double)k.f1 - (double)k.f0), C = (double)k.f0 - 2.0 * (double)k.f1 + (double)k.f2;
+    const double y = fma(xi, fma(xi, C, B), (double)k.f0) * (1.0 / 256.0);
+    const double r = floor(y);
+    if (y - r > 1e-6 && y - r < 1.0 - 1e-6) return (int32_t)r;
+    return row_tm_decide(k, dt, D, y);
 }
 
 // Row of column t0 + dt (0 <= dt <= t2 - t0): an FP32 pass whose result stands when it lies
