@@ -458,9 +458,9 @@ stt_status maxdelay_impl(stt_ctx *c, const stt_map *map, const GenP &g, const Tr
                          int32_t d0, int32_t step, int32_t n_tau, int32_t norm, float *snr, int32_t *tidx,
                          uint64_t *best)
 {
-    // 512 lanes x 2 templates, at most 80 KB of slabs: two workgroups per CU, the four waves per SIMD
-    // that the kernel's registers allow
-    constexpr int kMdWG = 512, kMdTPT = 2;
+    // 1024 lanes x 1 template, at most 80 KB of slabs (measured on the search map: 512 x 2, 1024 x 2,
+    // 256 x 4 and smaller slabs were 15-75 % slower; one template per lane leaves room for more waves)
+    constexpr int kMdWG = 1024, kMdTPT = 1;
     const int lds = std::min(c->lds_bytes, 80 * 1024);
     const MapP m = to_mapp(map);
     const int64_t ldc = fold_ld(m.F);
