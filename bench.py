@@ -34,6 +34,13 @@ BYTES_P16 = 4   # FP16 (re, im) of p = Y/sigma
 # cosine (1 each); Re[e^{i phi} p] = cos*p_re - sin*p_im (2 multiplies, 1 add);
 # accumulation (1 add).
 FLOPS_PER_TRACK_PX = 12
+# The scorer's core loop per template pixel, as issued on gfx950: FP64 fma + 2 FP64 adds (row),
+# a VOP3 shift-add (LDS address), v_mad_u64_u32 and v_alignbit_b32 (phase), hardware sine and
+# cosine, 2 FP32 FMAs (term). With the issue rates measured by a probe of independent instructions
+# (lanes per clock per CU: FP64 46, VOP3 integer 57, mad_u64 51, sin/cos 28, FP32 FMA 81), one CU
+# completes 1 / sum(1 / rate) template pixels per clock.
+CORE_MIX = {"f64": (3, 46.0), "vop3_int": (2, 57.0), "mad_u64": (1, 51.0), "trans": (2, 28.0), "fma_f32": (2, 81.0)}
+ISSUE_CEILING_PX_S = 256 * 2.4e9 / sum(k / r for k, r in CORE_MIX.values())
 # Vector ALU peak without packed FP32 (the build disables packed FP32 ops):
 # 256 CUs x 64 lanes x 2 flops (FMA) x 2.4 GHz, also the FP64 vector peak.
 ALU_PEAK_TFLOPS = 78.6
@@ -183,7 +190,11 @@ def roofline(kernel, kernel_ms, px, bpp, traffic=None):
             "frac": achieved / ALU_PEAK_TFLOPS, "traffic": traffic, "kernel": kernel, "kernel_ms": kernel_ms,
             "flops_per_track_px": FLOPS_PER_TRACK_PX,
             "gather_line": {"bytes_per_track_px": bpp, "achieved": gather, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                            "frac": gather / HBM_PEAK_GBS}}
+                            "frac": gather / HBM_PEAK_GBS},
+            # the same kernel against the issue rate of its own instruction mix (sine, cosine and FP64
+            # issue below the FP32 FMA rate, so the flop peak above is out of its reach)
+            "issue_model": {"achieved_px_s": px / sec, "ceiling_px_s": ISSUE_CEILING_PX_S,
+                            "frac": px / sec / ISSUE_CEILING_PX_S}}
 
 
 def timed(args, fn, torch):
