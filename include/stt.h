@@ -222,7 +222,8 @@ stt_status stt_score_maxdelay(stt_ctx *ctx, const stt_map *map, const stt_gen *g
  * scores; an empty key (0) is quieter than any score and counts as -inf in the
  * threshold. Keys are 8-byte device arrays as written by the scorers. Any of
  * the three outputs may be NULL (z_alpha needs 0 < alpha <= 1 and
- * ceil(alpha n_bg) <= 8192); n_bg >= 1. Exact counts: n_fg * n_bg comparisons. */
+ * ceil(alpha n_bg) <= 8192); 1 <= n_bg <= 2^38, n_fg <= 2^38. Exact counts: n_fg * n_bg
+ * comparisons. */
 stt_status stt_significance(stt_ctx *ctx, const uint64_t *bg_keys_dev, int64_t n_bg, const uint64_t *fg_keys_dev,
                             int64_t n_fg, double alpha, int64_t *n_louder_dev, float *fap_dev, float *z_alpha_dev);
 

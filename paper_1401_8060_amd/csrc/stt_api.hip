@@ -1016,6 +1016,8 @@ stt_status stt_significance(stt_ctx *c, const uint64_t *bg_keys_dev, int64_t n_b
     if (n_fg < 0) return fail(c, STT_EINVAL, "n_fg=%lld", (long long)n_fg);
     if (!bg_keys_dev) return fail(c, STT_EINVAL, "null background keys");
     if (n_fg > 0 && !fg_keys_dev && (n_louder_dev || fap_dev)) return fail(c, STT_EINVAL, "null foreground keys");
+    if (n_bg > ((int64_t)1 << 38) || n_fg > ((int64_t)1 << 38))
+        return fail(c, STT_ERANGE, "more than 2^38 keys");  // keeps the 1-D grids below 2^31 workgroups
     int32_t m = 0;
     if (z_alpha_dev) {
         if (!(alpha > 0.0 && alpha <= 1.0)) return fail(c, STT_EINVAL, "alpha must be in (0, 1]");
