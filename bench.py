@@ -26,6 +26,7 @@ METRIC = "Bézier tracks scored/sec per MI355X (track-pixels/s, % gather rooflin
 HBM_PEAK_GBS = 8000.0
 TUNE_CACHE = os.path.join(ROOT, "paper_1401_8060_amd", "tuning", "gfx950.json")
 KERNEL_SOURCES = [os.path.join(ROOT, "paper_1401_8060_amd", "csrc", f) for f in ("kernels.hpp", "dev_common.hpp")]
+MAPFORM_SOURCES = [os.path.join(ROOT, "paper_1401_8060_amd", "csrc", "mapform.hpp")]
 BYTES_F32 = 12  # complex64 Y + float32 sigma: the pixel record one template pixel reads
 BYTES_P16 = 4   # FP16 (re, im) of p = Y/sigma
 # Arithmetic of one template pixel (Eq. 6 row, Eq. 8 term), counted as flops:
@@ -151,18 +152,19 @@ def base_record(args, workload, w, n_tracks, ms_step, px, dtype):
     }
 
 
-def kernel_source_hash():
+def kernel_source_hash(sources=None):
     import hashlib
     h = hashlib.sha256()
-    for f in KERNEL_SOURCES:
+    for f in sources or KERNEL_SOURCES:
         with open(f, "rb") as fh:
             h.update(fh.read())
     return h.hexdigest()
 
 
-def measured_traffic(workload, shape):
+def measured_traffic(workload, shape, sources=None):
     """HBM-side bytes per launch from the committed counter summary of this workload, if it was
-    taken on the current kernel sources and the same slab shape; otherwise None."""
+    taken on the current kernel sources (``sources``, the scorers' by default) and the same slab
+    shape; otherwise None."""
     path = os.path.join(ROOT, "profiles", f"traffic_{workload}.txt")
     if not os.path.exists(path):
         return None
@@ -171,7 +173,7 @@ def measured_traffic(workload, shape):
         if ":" in line and not line.startswith("#"):
             k, v = line.split(":", 1)
             kv[k.strip()] = v.strip()
-    if kv.get("kernel_source_sha256") != kernel_source_hash():
+    if kv.get("kernel_source_sha256") != kernel_source_hash(sources):
         return None
     if shape is not None and kv.get("slab_shape") != "x".join(str(x) for x in shape):
         return None
@@ -525,7 +527,8 @@ def run_mapform(args, name, w):
                    "n_slides": ns, "slide_cols": w["slide_cols"], "fq4_lo": fq4_lo, "dfq4": dfq4},
         "maps_per_s": ns / (ms_step * 1e-3),
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": 8000.0, "unit": "GB/s", "frac": achieved / 8000.0,
-                     "traffic": None, "kernel": "k_form_maps", "kernel_ms": launch_ms,
+                     "traffic": measured_traffic(name, None, MAPFORM_SOURCES), "kernel": "k_form_maps",
+                     "kernel_ms": launch_ms,
                      "launches_per_step": launches, "bytes_per_launch": bytes_launch},
         "spectra_ms": spectra_ms,
     }
