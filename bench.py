@@ -675,6 +675,22 @@ def run_refine(args, name, w):
                      "best_plain_z_after_refine": zp.max().item(),
                      "mean_smooth_gain": (zs.double() - z_s0).mean().item(),
                      "improved_fraction": (zp.double() > z_plain0).double().mean().item()}
+    # the refinement kernel alone, from calls without the plain re-score: each of its steps + 1
+    # evaluations gathers the 4 bilinear neighbours (12 B each) of every sample of every template
+    ctx.set_timing(True)
+    for _ in range(3):
+        ctx.refine(m, res["th0"], res["K"], w["L"], dtau_max, steps=w["steps"], plain=False)
+    ref_ms, cnt = ctx.kernel_ms_total(stt.STAGE_SCORE)
+    ctx.set_timing(False)
+    ref_ms /= max(cnt, 1)
+    gbytes = (w["steps"] + 1) * int(res["K"].sum().item()) * 4 * 12
+    achieved = gbytes / (ref_ms * 1e-3) / 1e9
+    log(f"bench: k_refine {ref_ms:.3f} ms per launch, {gbytes / 1e6:.0f} MB gathered ({achieved:.0f} GB/s)")
+    out["roofline"] = {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                       "frac": achieved / HBM_PEAK_GBS, "traffic": None, "kernel": "k_refine", "kernel_ms": ref_ms,
+                       "bytes_per_launch": gbytes,
+                       "note": "bilinear gathers served from L2/MALL: the kernel waits on their latency, "
+                               "not on HBM bandwidth"}
     ctx.close()
     return out
 

@@ -1512,6 +1512,10 @@ stt_status stt_refine(stt_ctx *c, const stt_map *map, int32_t min_len, int32_t d
     p.ms1 = sched_host ? sched_host[3] : 0.01;
     p.steps = steps;
     const MapP m = to_mapp(map);
+    // timing: the refinement kernel is this call's stage 0 (the plain re-score below records its own)
+    if ((s = ev_begin(c)) != STT_OK) return s;
+    ev_record(c, 4);
+    ev_record(c, 0);
     if (map->dtype == STT_P16)
         hipLaunchKernelGGL(k_refine<kMapP16>, dim3((unsigned)n), dim3(kSmoothWG), 0, c->stream, m, theta_dev, K_dev, n,
                            z_smooth_dev, p);
@@ -1519,6 +1523,11 @@ stt_status stt_refine(stt_ctx *c, const stt_map *map, int32_t min_len, int32_t d
         hipLaunchKernelGGL(k_refine<kMapF32>, dim3((unsigned)n), dim3(kSmoothWG), 0, c->stream, m, theta_dev, K_dev, n,
                            z_smooth_dev, p);
     STT_HIP(c, hipGetLastError());
+    ev_record(c, 1);
+    ev_record(c, 5);
+    c->used[0] = true;
+    c->used[2] = true;
+    ev_end(c);
     if (plain_dev) {
         hipLaunchKernelGGL(k_theta_to_track, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, c->stream,
                            (const float *)theta_dev, (int64_t)n,
