@@ -1512,16 +1512,25 @@ stt_status stt_refine(stt_ctx *c, const stt_map *map, int32_t min_len, int32_t d
     p.ms1 = sched_host ? sched_host[3] : 0.01;
     p.steps = steps;
     const MapP m = to_mapp(map);
+    // The steps gather p = Y/sigma from the folded copy the scorers use (bit-identical to forming
+    // it at each gather: one division per pixel instead of one per gather, 8 bytes instead of 12).
+    const int64_t ldc = fold_ld(m.F);
+    if ((s = ensure_pbuf(c, sizeof(float2) * (size_t)m.T * (size_t)ldc)) != STT_OK) return s;
     // timing: the refinement kernel is this call's stage 0 (the plain re-score below records its own)
     if ((s = ev_begin(c)) != STT_OK) return s;
     ev_record(c, 4);
-    ev_record(c, 0);
+    const unsigned fg = (unsigned)std::min<int64_t>(((int64_t)m.T * ldc + 255) / 256, 4096);
     if (map->dtype == STT_P16)
-        hipLaunchKernelGGL(k_refine<kMapP16>, dim3((unsigned)n), dim3(kSmoothWG), 0, c->stream, m, theta_dev, K_dev, n,
-                           z_smooth_dev, p);
+        hipLaunchKernelGGL(k_fold_p<kMapP16>, dim3(fg), dim3(256), 0, c->stream, m, (float2 *)c->pbuf, ldc);
     else
-        hipLaunchKernelGGL(k_refine<kMapF32>, dim3((unsigned)n), dim3(kSmoothWG), 0, c->stream, m, theta_dev, K_dev, n,
-                           z_smooth_dev, p);
+        hipLaunchKernelGGL(k_fold_p<kMapF32>, dim3(fg), dim3(256), 0, c->stream, m, (float2 *)c->pbuf, ldc);
+    MapP mf = m;
+    mf.Y = (const float2 *)c->pbuf;
+    mf.sig = nullptr;
+    mf.ld = ldc;
+    ev_record(c, 0);
+    hipLaunchKernelGGL(k_refine<kMapPF>, dim3((unsigned)n), dim3(kSmoothWG), 0, c->stream, mf, theta_dev, K_dev, n,
+                       z_smooth_dev, p);
     STT_HIP(c, hipGetLastError());
     ev_record(c, 1);
     ev_record(c, 5);
