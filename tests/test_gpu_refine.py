@@ -115,6 +115,8 @@ def test_refine_invariants_and_plain_rescore(orc, stt, ctx):
     z0 = ctx.smooth(m, th0, K)
     th, zs, tr, zp = ctx.refine(m, th0, K, L, D10MS, steps=50)
     th_h, zs_h, tr_h, zp_h = th.cpu().numpy(), zs.cpu().numpy(), tr.cpu().numpy(), zp.cpu().numpy()
+    # the steps read the folded p, stt_smooth forms Y/sigma at each gather: the same values bit for bit
+    assert torch.equal(zs, ctx.smooth(m, th, K))
     assert (zs_h >= z0.cpu().numpy() - 1e-6).all()
     assert (th_h[:, 0] >= 0).all() and (th_h[:, 1] <= T - 1).all() and (th_h[:, 1] - th_h[:, 0] >= L - 1 - 1e-4).all()
     assert (th_h[:, 2:5] >= 0).all() and (th_h[:, 2:5] < F).all() and (np.abs(th_h[:, 5]) <= 10.0 + 1e-5).all()
@@ -130,6 +132,27 @@ def test_refine_invariants_and_plain_rescore(orc, stt, ctx):
     gain = zs_h - z0.cpu().numpy()
     _say(f"refine: mean z~ gain {gain.mean():.3f}, max {gain.max():.3f}")
     assert gain.mean() > 0.1
+
+
+def test_refine_on_an_fp16_map(orc, stt, ctx):
+    """Refinement on an FP16 map: the best z~ is stt_smooth's at the returned theta (bit for bit)
+    and the oracle's on the dequantised map; the plain re-score matches the oracle there too."""
+    import torch
+    _say("refine fp16")
+    T, F, n, L = 250, 180, 128, 10
+    Y, s = synth.noise_map(T, F, seed=44, sigma=("loguniform", 0.5, 2.0))
+    m16 = ctx.pack_p16(stt.Map(*to_dev(Y, s)))
+    _, _, deq = orc.quantize_p16(Y, s)
+    om = orc.Map(deq, np.ones((T, F)))
+    g = stt.Gen(seed=8, min_len=L, dtau_max=D10MS)
+    th0, K = ctx.tracks_to_theta(ctx.make_tracks(g, T, F, 0, n))
+    th, zs, tr, zp = ctx.refine(m16, th0, K, L, D10MS, steps=30)
+    assert torch.equal(zs, ctx.smooth(m16, th, K))
+    th_h, K_h = th.cpu().numpy(), K.cpu().numpy()
+    zo = np.array([orc.smooth(om, th_h[i].astype(np.float64), int(K_h[i]))[0] for i in range(n)])
+    assert_close(zs.cpu().numpy(), zo, tol=2e-5, what="fp16 best z~")
+    assert_close(zp.cpu().numpy(), orc.score_list(om, tr.cpu().numpy().view(orc.TRACK_DTYPE).reshape(-1)),
+                 what="fp16 plain rescore")
 
 
 def test_refine_recovers_an_injection(orc, stt, ctx):
