@@ -69,3 +69,11 @@ def test_strerror_and_create_without_device(libstt):
     h = C.c_void_p()
     assert libstt.stt_create(4096, None, C.byref(h)) == -4
     assert libstt.stt_create(0, None, None) == -1
+
+
+def test_build_entry_compiles_the_oracle():
+    """The build entry point's oracle step resolves the build function and produces the library."""
+    import os
+    import __graft_entry__ as ge
+    out = ge.build_oracle()
+    assert os.path.exists(out) and out.endswith("libstt_oracle.so")
