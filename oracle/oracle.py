@@ -101,6 +101,9 @@ def _bind_ext(L):
     L.orc_smooth.restype = C.c_double
     L.orc_refine.argtypes = [C.POINTER(_Map), C.c_void_p, C.c_int32, C.c_int32, C.c_int32, C.c_double, C.c_void_p]
     L.orc_refine.restype = C.c_double
+    L.orc_refine_trace.argtypes = [C.POINTER(_Map), C.c_void_p, C.c_int32, C.c_int32, C.c_int32, C.c_double,
+                                   C.c_void_p, C.c_void_p]
+    L.orc_refine_trace.restype = C.c_double
     L.orc_theta_to_track.argtypes = [C.c_void_p, C.c_int32, C.c_int32, C.c_int32, C.c_int32, C.POINTER(_Track)]
     L.orc_theta_to_track.restype = None
 
@@ -317,6 +320,17 @@ def refine(m: Map, theta, K: int, steps: int, L: int, dtau_max_ms: float, sched=
     sc = np.ascontiguousarray(np.asarray(sched, dtype=np.float64))
     z = lib().orc_refine(C.byref(m.c), th.ctypes.data, K, steps, L, dtau_max_ms, sc.ctypes.data)
     return th, float(z)
+
+
+def refine_trace(m: Map, theta, K: int, steps: int, L: int, dtau_max_ms: float, sched=(1.0, 0.02, 0.5, 0.01)):
+    """As refine, plus every iterate: returns (best theta, its z~, trace[steps + 1][7]) where
+    trace[s] = (theta_s, z~(theta_s)), theta_0 the projected start."""
+    th = np.ascontiguousarray(np.asarray(theta, dtype=np.float64).reshape(6)).copy()
+    sc = np.ascontiguousarray(np.asarray(sched, dtype=np.float64))
+    tr = np.zeros((steps + 1, 7), dtype=np.float64)
+    z = lib().orc_refine_trace(C.byref(m.c), th.ctypes.data, K, steps, L, dtau_max_ms, sc.ctypes.data,
+                               tr.ctypes.data)
+    return th, float(z), tr
 
 
 def theta_to_track(theta, T: int, F: int, L: int, dtau_max: int) -> np.ndarray:

@@ -161,14 +161,21 @@ static void project(double *th, int32_t T, int32_t F, int32_t L, double dmax_ms)
     if (th[5] < -dmax_ms) th[5] = -dmax_ms;
 }
 
-double orc_refine(const orc_map2 *m, double *theta, int32_t K, int32_t steps, int32_t L, double dmax_ms,
-                  const double *sched /* px0, px1, ms0, ms1 */)
+/* The same ascent with every iterate recorded: trace (may be NULL) receives
+ * (steps + 1) rows of 7 doubles, row s = (theta_s[0..5], z~(theta_s)) where
+ * theta_0 is the projected start and theta_{s+1} follows ascent step s. */
+double orc_refine_trace(const orc_map2 *m, double *theta, int32_t K, int32_t steps, int32_t L, double dmax_ms,
+                        const double *sched /* px0, px1, ms0, ms1 */, double *trace)
 {
     double th[6], best[6], g[6];
     memcpy(th, theta, sizeof th);
     project(th, m->T, m->F, L, dmax_ms);
     memcpy(best, th, sizeof th);
     double zbest = orc_smooth(m, th, K, g);
+    if (trace) {
+        memcpy(trace, th, sizeof th);
+        trace[6] = zbest;
+    }
     for (int32_t s = 0; s < steps; ++s) {
         const double w = steps > 1 ? (double)s / (double)(steps - 1) : 0.0;
         const double epx = sched[0] + w * (sched[1] - sched[0]);
@@ -183,6 +190,10 @@ double orc_refine(const orc_map2 *m, double *theta, int32_t K, int32_t steps, in
         else if (g[5] < 0) th[5] -= ems;
         project(th, m->T, m->F, L, dmax_ms);
         const double z = orc_smooth(m, th, K, g);
+        if (trace) {
+            memcpy(trace + 7 * (s + 1), th, sizeof th);
+            trace[7 * (s + 1) + 6] = z;
+        }
         if (z > zbest) {
             zbest = z;
             memcpy(best, th, sizeof th);
@@ -190,6 +201,12 @@ double orc_refine(const orc_map2 *m, double *theta, int32_t K, int32_t steps, in
     }
     memcpy(theta, best, sizeof best);
     return zbest;
+}
+
+double orc_refine(const orc_map2 *m, double *theta, int32_t K, int32_t steps, int32_t L, double dmax_ms,
+                  const double *sched /* px0, px1, ms0, ms1 */)
+{
+    return orc_refine_trace(m, theta, K, steps, L, dmax_ms, sched, NULL);
 }
 
 /* ------------------------------------------------------------------------ */

@@ -22,7 +22,7 @@ D10MS = 2684355
 mpmath = pytest.importorskip("mpmath")
 
 
-def _row_reference(t0, t1, t2, f0, f1, f2, t):
+def _row_reference(t0, t1, t2, f0, f1, f2, t, dps=50):
     """floor(f(xi)/256) at column t, from the definition: a xi^2 + b xi + (t0 - t) = 0, xi in [0, 1]."""
     a, b, c = t0 - 2 * t1 + t2, 2 * (t1 - t0), t0 - t
     def freq(xi):
@@ -34,13 +34,13 @@ def _row_reference(t0, t1, t2, f0, f1, f2, t):
     if s * s == D:  # rational root: exact
         xi = Fraction(-b + s, 2 * a)
         return math.floor(freq(xi) / 256)
-    mp = mpmath.mp
-    mp.dps = 50
-    xi = (-b + mpmath.sqrt(D)) / (2 * a)
-    v = freq(xi) / 256
-    r = int(mpmath.floor(v))
-    # an irrational value stays far (> 1e-19 here) from every integer
-    assert abs(v - mpmath.nint(v)) > mpmath.mpf("1e-30")
+    with mpmath.workdps(dps):
+        xi = (-b + mpmath.sqrt(D)) / (2 * a)
+        v = freq(xi) / 256
+        r = int(mpmath.floor(v))
+        # an irrational value (U + V sqrt(D))/W keeps a distance of at least 1/(W (|U| + |V| sqrt(D) + W))
+        # from every integer: above 1e-32 for T <= 2896 and F <= 32767, far above the working precision
+        assert abs(v - mpmath.nint(v)) > mpmath.mpf("1e-40")
     return r
 
 
@@ -59,6 +59,33 @@ def test_rows_against_the_definition(orc):
         got = orc.rows_tm(tr, F)
         want = [_row_reference(t0, t1, t2, f[0], f[1], f[2], t) for t in range(t0, t2 + 1)]
         assert got.tolist() == want, (t0, t1, t2, f)
+
+
+def test_rows_against_the_definition_at_full_size(orc):
+    """The same definition at the sizes the kernels run: T up to 2896 columns, F up to 32767 rows,
+    sampled columns of long templates (60-digit evaluation), including near-linear time (t1 close to
+    the midpoint, where the elimination's integers are largest relative to the row) and both ends."""
+    rng = np.random.default_rng(34)
+    for it in range(240):
+        T = int(rng.choice([1000, 2000, 2896]))
+        F = int(rng.choice([1000, 2000, 32767]))
+        t0 = int(rng.integers(0, T // 3))
+        t2 = int(rng.integers(max(t0 + 2, T - T // 3), T))
+        mid = (t0 + t2) // 2
+        if it % 4 == 0:
+            t1 = mid + int(rng.integers(-2, 3))  # a = t0 - 2 t1 + t2 within a few units of 0
+        else:
+            t1 = int(rng.integers(t0, t2 + 1))
+        t1 = min(max(t1, t0), t2)
+        f = [int(x) for x in rng.integers(0, F * 256, 3)]
+        if it % 6 == 0:
+            f = [256 * int(x) for x in rng.integers(0, F, 3)]
+        tr = np.array([(t0, t1, t2, f[0], f[1], f[2], 0)], dtype=orc.TRACK_TM_DTYPE)
+        got = orc.rows_tm(tr, F)
+        cols = np.unique(np.concatenate([[t0, t0 + 1, t2 - 1, t2], rng.integers(t0, t2 + 1, 24)]))
+        for t in cols:
+            want = _row_reference(t0, t1, t2, f[0], f[1], f[2], int(t), dps=60)
+            assert int(got[t - t0]) == want, (T, F, t0, t1, t2, f, int(t))
 
 
 def test_midpoint_reduces_to_plain_rasteriser_and_end_rows(orc):
