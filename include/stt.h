@@ -80,7 +80,7 @@ typedef struct {
     int32_t t0, t1, t2;
     uint32_t f0, f1, f2;
     int32_t dtau;
-} stt_track_tm;              /* 24 bytes */
+} stt_track_tm;
 
 typedef struct {
     uint64_t seed;     /* Philox4x32-10 key (low word, high word) */
@@ -182,6 +182,21 @@ stt_status stt_make_tracks(stt_ctx *ctx, const stt_gen *gen, int32_t T, int32_t 
 stt_status stt_score(stt_ctx *ctx, const stt_map *map, const stt_gen *gen, const stt_track *tracks_dev,
                      int64_t first, int64_t n, int32_t norm, float *snr_dev, uint64_t *best_key_dev);
 
+/* Free-t_mid templates (an addition: the paper's six random numbers, with t_mid
+ * free instead of at the midpoint). Generation as stt_make_tracks, plus
+ * t1 = t0 + floor(x * (t2 - t0 + 1) / 2^32) from the last word x of the second
+ * Philox block. Scoring as stt_score (Eq. 8, one pixel per column): at column
+ * t the row is floor(f(xi)/256), xi the root in [0, 1] of t(xi) = t, computed
+ * exactly (an FP32 evaluation inside a certified error window, else FP64
+ * Newton refinement of the root, else an exact 128-bit integer decision).
+ * Generated templates (from 4096 on, when two slabs of a column fit 80 KB) are
+ * binned by time extent and scored from LDS slabs; given lists and small
+ * calls take one wave per template. Both give the same bits. */
+stt_status stt_make_tracks_tm(stt_ctx *ctx, const stt_gen *gen, int32_t T, int32_t F, int64_t first, int64_t n,
+                              stt_track_tm *out_dev);
+stt_status stt_score_tm(stt_ctx *ctx, const stt_map *map, const stt_gen *gen, const stt_track_tm *tracks_dev,
+                        int64_t first, int64_t n, int32_t norm, float *snr_dev, uint64_t *best_key_dev);
+
 /* Delay-maximised scores: the reading of "phase-maximised" (Sec. III, Eq. 8)
  * that maximises the statistic over the delay per template instead of drawing
  * one. Track j (generated or given, as in stt_score) keeps its time extent and
@@ -193,18 +208,6 @@ stt_status stt_score(stt_ctx *ctx, const stt_map *map, const stt_gen *gen, const
  * key of (max, j) is max-merged into *best_key_dev (may be NULL). Requires
  * 1 <= n_tau <= 65536 and every grid delay in (-2^30, 2^30). The row walk and
  * the pixel gathers are shared by the delays (8 per kernel launch). */
-/* Free-t_mid templates (an addition: the paper's six random numbers, with t_mid
- * free instead of at the midpoint). Generation as stt_make_tracks, plus
- * t1 = t0 + floor(x * (t2 - t0 + 1) / 2^32) from the last word x of the second
- * Philox block. Scoring as stt_score (Eq. 8, one pixel per column): at column
- * t the row is floor(f(xi)/256), xi the root in [0, 1] of t(xi) = t, computed
- * exactly (FP64 with an exact 128-bit integer decision near row boundaries).
- * One wave per template. */
-stt_status stt_make_tracks_tm(stt_ctx *ctx, const stt_gen *gen, int32_t T, int32_t F, int64_t first, int64_t n,
-                              stt_track_tm *out_dev);
-stt_status stt_score_tm(stt_ctx *ctx, const stt_map *map, const stt_gen *gen, const stt_track_tm *tracks_dev,
-                        int64_t first, int64_t n, int32_t norm, float *snr_dev, uint64_t *best_key_dev);
-
 stt_status stt_score_maxdelay(stt_ctx *ctx, const stt_map *map, const stt_gen *gen, const stt_track *tracks_dev,
                               int64_t first, int64_t n, int32_t dtau0, int32_t dtau_step, int32_t n_tau, int32_t norm,
                               float *snr_dev, int32_t *tau_idx_dev, uint64_t *best_key_dev);
@@ -226,6 +229,23 @@ stt_status stt_score_maxdelay(stt_ctx *ctx, const stt_map *map, const stt_gen *g
  * comparisons. */
 stt_status stt_significance(stt_ctx *ctx, const uint64_t *bg_keys_dev, int64_t n_bg, const uint64_t *fg_keys_dev,
                             int64_t n_fg, double alpha, int64_t *n_louder_dev, float *fap_dev, float *z_alpha_dev);
+
+/* Follow-up of the loudest maps (Sec. V: the ~10 loudest events are searched
+ * again, deeper and with a new seed, and runs combine by their maximum).
+ * keys_dev[m] (device, n_maps 8-byte keys as the scorers write them) holds map
+ * m's best key. Map m's rank is the number of maps at least as loud, itself
+ * included (counted on the device as stt_significance counts). Every map of
+ * rank <= k (k >= 1; ties at the k-th place can leave maps out) is scored
+ * again with templates j = 0 .. n_deep-1 drawn from `gen` with Philox stream
+ * gen->stream + m (use a seed the first search did not, or it repeats its
+ * templates), and that search's best key is max-merged into keys_dev[m].
+ * chosen_host (host, room for n_maps, may be NULL) receives the searched
+ * maps' indices in increasing order and *n_chosen (host, may be NULL) their
+ * number. The maps (host array of n_maps descriptors) are validated first;
+ * the call then synchronises the stream once to read the ranks back. */
+stt_status stt_follow_up(stt_ctx *ctx, const stt_map *maps_host, int32_t n_maps, uint64_t *keys_dev,
+                         const stt_gen *gen, int64_t n_deep, int32_t k, int32_t norm, int32_t *chosen_host,
+                         int32_t *n_chosen);
 
 /* ---- Map formation: the complex SNR maps the search scores, from strain ----
  *
@@ -273,8 +293,11 @@ stt_status stt_form_maps(stt_ctx *ctx, const stt_spectro *p, int32_t T, const fl
                          const float *psd_i_dev, const float *spec_j_dev, const float *psd_j_dev, int32_t n_slides,
                          const int32_t *shifts, int64_t ld, float *const *Y_dev, float *const *sigma_dev);
 
-/* Max/argmax over an existing score array: *best_key_dev is max-merged with
- * the best key over snr_dev[0..n), the index of element i being first + i. */
+/* Max/argmax over an existing score array (Sec. III keeps the template with
+ * the largest statistic; Sec. V records that maximum per spectrogram and
+ * combines runs by their maximum): *best_key_dev is max-merged with the best
+ * key over snr_dev[0..n), the index of element i being first + i. Ties go to
+ * the lowest index, NaN never wins (the key format above). */
 stt_status stt_argmax(stt_ctx *ctx, const float *snr_dev, int64_t n, int64_t first,
                       uint64_t *best_key_dev);
 

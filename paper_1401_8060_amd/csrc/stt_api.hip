@@ -1046,6 +1046,52 @@ stt_status stt_significance(stt_ctx *c, const uint64_t *bg_keys_dev, int64_t n_b
     return STT_OK;
 }
 
+stt_status stt_follow_up(stt_ctx *c, const stt_map *maps_host, int32_t n_maps, uint64_t *keys_dev, const stt_gen *gen,
+                         int64_t n_deep, int32_t k, int32_t norm, int32_t *chosen_host, int32_t *n_chosen)
+{
+    if (!c) return STT_EINVAL;
+    if (n_chosen) *n_chosen = 0;
+    if (n_maps < 1 || !maps_host || !keys_dev) return fail(c, STT_EINVAL, "need at least one map and its key");
+    if (k < 1) return fail(c, STT_EINVAL, "k=%d must be >= 1", k);
+    if (!gen) return fail(c, STT_EINVAL, "gen is NULL");
+    if (norm != STT_NORM_SQRT_N && norm != STT_NORM_N) return fail(c, STT_EINVAL, "norm=%d", norm);
+    stt_status s;
+    if ((s = check_range(c, 0, n_deep)) != STT_OK) return s;
+    if ((uint64_t)gen->stream + (uint64_t)(n_maps - 1) > 0xFFFFFFFFull)
+        return fail(c, STT_ERANGE, "Philox streams gen->stream + m overflow 32 bits");
+    for (int32_t m = 0; m < n_maps; ++m) {
+        if ((s = check_map(c, &maps_host[m])) != STT_OK) return s;
+        GenP g;
+        if ((s = make_genp(c, gen, maps_host[m].T, maps_host[m].F, g)) != STT_OK) return s;
+    }
+    STT_HIP(c, hipSetDevice(c->device));
+    // rank of map m = the number of maps at least as loud, itself included (as stt_significance counts)
+    if ((s = ensure_aux(c, sizeof(int64_t) * (size_t)n_maps)) != STT_OK) return s;
+    int64_t *rank_dev = (int64_t *)c->aux;
+    hipLaunchKernelGGL(k_count_louder, dim3((unsigned)((n_maps + 255) / 256)), dim3(256), 0, c->stream,
+                       (const uint64_t *)keys_dev, (int64_t)n_maps, (const uint64_t *)keys_dev, (int64_t)n_maps,
+                       rank_dev, (float *)nullptr, 1.0);
+    STT_HIP(c, hipGetLastError());
+    std::vector<int64_t> rank((size_t)n_maps);
+    STT_HIP(c, hipMemcpyAsync(rank.data(), rank_dev, sizeof(int64_t) * (size_t)n_maps, hipMemcpyDeviceToHost,
+                              c->stream));
+    STT_HIP(c, hipStreamSynchronize(c->stream));
+    int32_t done = 0;
+    for (int32_t m = 0; m < n_maps; ++m) {
+        if (rank[(size_t)m] > k) continue;
+        if (n_deep > 0) {
+            stt_gen gm = *gen;
+            gm.stream = gen->stream + (uint32_t)m;
+            if ((s = stt_score(c, &maps_host[m], &gm, nullptr, 0, n_deep, norm, nullptr, keys_dev + m)) != STT_OK)
+                return s;
+        }
+        if (chosen_host) chosen_host[done] = m;
+        ++done;
+        if (n_chosen) *n_chosen = done;
+    }
+    return STT_OK;
+}
+
 stt_status stt_spectra(stt_ctx *c, const stt_spectro *p, const float *strain_dev, int64_t n_samples, int32_t T,
                        float *spec_dev, float *psd_dev)
 {

@@ -570,22 +570,21 @@ class Context:
             C.c_void_p(za.data_ptr()) if za is not None else None))
         return cnt, fap, za
 
-    def follow_up(self, maps, keys: torch.Tensor, gen: Gen, n_deep: int, k: int = 10) -> list[int]:
-        """Search the k loudest maps again with n_deep templates drawn with ``gen`` (use a seed the
-        first search did not) and max-merge the results into ``keys`` in place -- the follow-up of
-        the loudest events and the combination of runs by their maximum (Sec. V). Map m's
-        templates use Philox stream gen.stream + m, as in score_batch. Returns the indices of the
-        maps searched (ranked by the count of maps at least as loud; ties may add maps)."""
-        if keys.dtype != torch.int64 or keys.numel() != len(maps) or not keys.is_contiguous():
-            raise ValueError("one int64 key per map")
-        cnt, _, _ = self.significance(keys, keys, alpha=None)
-        order = cnt.cpu().tolist()
-        chosen = [m for m, c in enumerate(order) if c <= k]
-        for m in chosen:
-            gm = Gen(seed=gen.seed, stream=gen.stream + m, min_len=gen.min_len, dtau_max=gen.dtau_max,
-                     dtau_center=gen.dtau_center)
-            self.score(maps[m], gen=gm, n=n_deep, snr=None, best_key=keys[m:m + 1])
-        return chosen
+    def follow_up(self, maps, keys: torch.Tensor, gen: Gen, n_deep: int, k: int = 10,
+                  norm: int = NORM_SQRT_N) -> list[int]:
+        """stt_follow_up: search the maps of rank <= k again with n_deep templates drawn with
+        ``gen`` (Philox stream gen.stream + m) and max-merge into ``keys`` in place (Sec. V).
+        Returns the indices of the maps searched."""
+        if keys.dtype != torch.int64 or keys.numel() != len(maps) or not keys.is_contiguous() or not keys.is_cuda:
+            raise ValueError("one int64 CUDA key per map")
+        nm = len(maps)
+        arr = (_Map * max(nm, 1))(*[m.c() for m in maps])
+        chosen = (C.c_int32 * max(nm, 1))()
+        n_chosen = C.c_int32(0)
+        g = gen.c()
+        self._chk(self._L.stt_follow_up(self.h, arr, nm, C.c_void_p(keys.data_ptr()), C.byref(g), int(n_deep), int(k),
+                                        norm, chosen, C.byref(n_chosen)))
+        return [int(chosen[i]) for i in range(n_chosen.value)]
 
     # -- map formation
     def spectra(self, strain: torch.Tensor, p: Spectro, T: int | None = None, spec: torch.Tensor | None = None,
