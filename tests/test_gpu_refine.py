@@ -175,3 +175,77 @@ def test_refine_recovers_an_injection(orc, stt, ctx):
     tho, zo = orc.refine(orc.Map(Y, s), th0[0].astype(np.float64), int(K[0]), 50, 10, 10.0)
     assert abs(th[5] - dt0) < 0.1 and np.abs(th[2:5] - [r0, 0.5 * (r0 + r2), r2]).max() < 1.0
     assert float(zs.item()) == pytest.approx(zo, rel=0.02)
+
+
+# ---------------------------------------------------------------- the ascent step by step
+
+DMS = D10MS * 1e3 / 2 ** 28  # the delay bound in ms, as the library converts it
+
+
+def _clear_trace(orc, om, trace, K, first, delta=2e-4, dz=1e-4, dg=1e-3):
+    """True when the oracle's trajectory has no near-decision for FP32 rounding to flip: samples
+    of iterates >= first lie more than delta (px) from every grid line (where the bilinear
+    gradient jumps), the delay derivative and the position gradient are clearly nonzero before
+    each step (sign step, normalisation), and z~ rises by more than dz at every step (so the best
+    iterate is the last)."""
+    xi = np.arange(K) / (K - 1)
+    b = np.stack([(1 - xi) ** 2, 2 * xi * (1 - xi), xi ** 2])
+    for s, row in enumerate(trace):
+        th = row[:6]
+        if s >= first:
+            u = th[0] + xi * (th[1] - th[0])
+            v = b.T @ th[2:5] - 0.5
+            if (np.abs(u - np.round(u)) <= delta).any() or (np.abs(v - np.round(v)) <= delta).any():
+                return False
+        if s < len(trace) - 1:
+            _, g = orc.smooth(om, th, K)
+            if abs(g[5]) <= dg or np.linalg.norm(g[:5]) <= 1e-2 or trace[s + 1][6] <= row[6] + dz:
+                return False
+    return True
+
+
+@pytest.mark.parametrize("start", ["plain", "offgrid"])
+def test_refine_step_by_step_matches_oracle(orc, stt, ctx, start):
+    """k_refine after 1, 2 and 3 ascent steps against the oracle's iterates (each run has its own
+    linear schedule: steps=1 moves 1 px and 0.5 ms; steps=2 moves 1 then 0.02 px; steps=3 1, 0.51,
+    0.02). On templates whose trajectory has no near-decision (see _clear_trace) the returned
+    point is the last iterate, and theta and z~ match the oracle's to 1e-5 * max(1, |x|).
+    'plain' starts from drawn templates (integer times: every start sample sits on a grid line,
+    where both sides take the cell floor(u) of the same FP64 position); 'offgrid' from random
+    real points."""
+    import torch
+    T, F, L, n = 200, 150, 10, 3000
+    Y, s = synth.noise_map(T, F, seed=45, sigma=("loguniform", 0.5, 2.0))
+    m = stt.Map(*to_dev(Y, s))
+    om = orc.Map(Y, s)
+    if start == "plain":
+        tr = orc.draw_many(9, 0, 0, n, T, F, L, D10MS)
+        th0 = np.stack([tr["t0"], tr["t2"], tr["f0"] / 256.0, tr["f1"] / 256.0, tr["f2"] / 256.0,
+                        tr["dtau"] * (1e3 / 2 ** 28)], axis=1).astype(np.float32)
+        K = (tr["t2"] - tr["t0"] + 1).astype(np.int32)
+        first = 1
+    else:
+        sel = np.random.default_rng(3)
+        K = sel.integers(10, 120, n).astype(np.int32)
+        a = sel.uniform(0, T - 130, n)
+        th0 = np.stack([a, a + K - 1 + sel.uniform(0, 8, n), *sel.uniform(1, F - 1, (3, n)),
+                        sel.uniform(-9, 9, n)], axis=1).astype(np.float32)
+        first = 0
+    for steps in (1, 2, 3):
+        _say(f"refine steps={steps} start={start}")
+        th, zs, _, _ = ctx.refine(m, torch.from_numpy(th0).cuda(), torch.from_numpy(K).cuda(), L, D10MS,
+                                  steps=steps, plain=False)
+        th, zs = th.cpu().numpy().astype(np.float64), zs.cpu().numpy().astype(np.float64)
+        picked = []
+        for i in range(n):
+            _, _, trc = orc.refine_trace(om, th0[i].astype(np.float64), int(K[i]), steps, L, DMS)
+            if _clear_trace(orc, om, trc, int(K[i]), first):
+                picked.append((i, trc[-1]))
+        assert len(picked) >= 1000, len(picked)
+        idx = np.array([i for i, _ in picked])
+        want = np.array([r for _, r in picked])
+        d_th = np.abs(th[idx] - want[:, :6]) / np.maximum(1.0, np.abs(want[:, :6]))
+        _say(f"  {len(idx)} clear trajectories: max theta err {d_th.max():.2e}, "
+             f"max z err {np.max(np.abs(zs[idx] - want[:, 6]) / np.maximum(1.0, np.abs(want[:, 6]))):.2e}")
+        assert d_th.max() <= 1e-5, (int(idx[np.argmax(d_th.max(axis=1))]), d_th.max())
+        assert_close(zs[idx], want[:, 6], tol=1e-5, what=f"z~ after {steps} steps")
