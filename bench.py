@@ -364,11 +364,31 @@ def run_precision(args, name, w):
     err = (res["val"].double() - res["z64"]).abs()
     best = int(torch.argmax(res["z64"]).item())
     log(f"bench: {ms_step:.3f} ms/step, FP16 scoring kernel {kern_ms:.3f} ms; top-{K} |dz| max {err.max().item():.2e}")
+
     out = base_record(args, name, w, n, ms_step, px, "f16")
     out["config"].update({"T": w["T"], "F": w["F"], "n_tracks": n, "map_dtype": "p16", "scale_exp": pm.scale_exp,
                           "top_k": K, "rescore": "f64", "map_sha256": sha[:16], "slab_shape": list(choice)})
     out["roofline"] = roofline("k_score_slab", kern_ms, px, BYTES_P16, measured_traffic(name, choice))
-    out["topk_fp16_vs_fp64"] = {"max_abs_dz": err.max().item(), "mean_abs_dz": err.mean().item()}
+    out["topk_fp16_vs_fp64"] = {"max_abs_dz": err.max().item(), "mean_abs_dz": err.mean().item(),
+                                "reference": "the library's FP64 re-score (k_rescore_f64) of the same templates"}
+    if not args.no_cpu_baseline:
+        # the CPU leg: the oracle (FP64, on the FP32 map) scores the top-K templates; its time is the CPU
+        # baseline and its scores the reference of the FP16 error record (relative to max(1, |z|))
+        import numpy as np
+        import oracle
+        log(f"bench: the CPU oracle on the top {K}")
+        idx = res["idx"].cpu().numpy().astype(np.uint64)
+        t = time.perf_counter()
+        z_orc = oracle.score_gen_idx(oracle.Map(Y, s), w["seed"], 0, w["L"], dtau_max, idx)
+        dt = time.perf_counter() - t
+        z16 = res["val"].cpu().numpy().astype(np.float64)
+        rel = np.abs(z16 - z_orc) / np.maximum(1.0, np.abs(z_orc))
+        out["topk_fp16_vs_oracle"] = {"max_rel_dz": float(rel.max()), "mean_rel_dz": float(rel.mean()),
+                                      "relative_to": "max(1, |z_oracle|)",
+                                      "reference": f"the FP64 CPU oracle on the FP32 map, the top {K} templates"}
+        out["cpu_baseline"] = dict(value=K / dt, unit="tracks/s", cores=1, kind="oracle",
+                                   sample=f"the top {K} templates of the step (FP64 on the FP32 map), one thread, "
+                                          f"{dt:.2f} s")
     out["best"] = {"z64": res["z64"][best].item(), "j": int(res["idx"][best].item())}
     ctx.close()
     return out
@@ -684,14 +704,15 @@ def run_refine(args, name, w):
                      "mean_smooth_gain": (zs.double() - z_s0).mean().item(),
                      "improved_fraction": (zp.double() > z_plain0).double().mean().item()}
     # the refinement kernel alone, from calls without the plain re-score: each of its steps + 1
-    # evaluations gathers the 4 bilinear neighbours (12 B each) of every sample of every template
+    # evaluations gathers the 4 bilinear neighbours of every sample of every template, 8 B each (p of
+    # the folded complex map)
     ctx.set_timing(True)
     for _ in range(3):
         ctx.refine(m, res["th0"], res["K"], w["L"], dtau_max, steps=w["steps"], plain=False)
     ref_ms, cnt = ctx.kernel_ms_total(stt.STAGE_SCORE)
     ctx.set_timing(False)
     ref_ms /= max(cnt, 1)
-    gbytes = (w["steps"] + 1) * int(res["K"].sum().item()) * 4 * 12
+    gbytes = (w["steps"] + 1) * int(res["K"].sum().item()) * 4 * 8
     achieved = gbytes / (ref_ms * 1e-3) / 1e9
     log(f"bench: k_refine {ref_ms:.3f} ms per launch, {gbytes / 1e6:.0f} MB gathered ({achieved:.0f} GB/s)")
     out["roofline"] = {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
@@ -700,6 +721,54 @@ def run_refine(args, name, w):
                        "note": "bilinear gathers served from L2/MALL: the kernel waits on their latency, "
                                "not on HBM bandwidth"}
     ctx.close()
+    return out
+
+
+def issue_rates(iters: int = 4096) -> dict:
+    """Vector-ALU issue rates (lane-instructions per shader clock per CU) of the instructions in the
+    scorers' inner loops, from the probe library (eight independent register chains per lane, eight
+    waves per SIMD; the shader clock measured inside each launch)."""
+    import ctypes as C
+    path = os.path.join(ROOT, "paper_1401_8060_amd", "libstt_probe.so")
+    if not os.path.exists(path):
+        raise ImportError(f"{path} is missing: build it with __graft_entry__.build()")
+    L = C.CDLL(path)
+    L.stt_probe_name.restype = C.c_char_p
+    L.stt_probe_issue.argtypes = [C.c_int, C.c_int, C.c_int] + [C.POINTER(C.c_double)] * 3
+    rates, mhz = {}, []
+    for op in range(L.stt_probe_count()):
+        r, f, ms = C.c_double(), C.c_double(), C.c_double()
+        rc = L.stt_probe_issue(0, op, iters, C.byref(r), C.byref(f), C.byref(ms))
+        name = L.stt_probe_name(op).decode()
+        if rc != 0:
+            raise RuntimeError(f"issue probe {name} failed ({rc})")
+        rates[name] = round(r.value, 2)
+        mhz.append(f.value)
+        log(f"bench: {name:16s} {r.value:7.2f} lanes/clk/CU  ({ms.value:.2f} ms at {f.value:.0f} MHz)")
+    return {"lanes_per_clk_per_cu": rates, "shader_mhz": [round(min(mhz)), round(max(mhz))],
+            "method": "8 independent register chains per lane, unrolled x4, 8 waves per SIMD, "
+                      f"{iters} iterations; clock from the cycle and wall counters of the first wave"}
+
+
+def summarize_pmc(paths: list[str], kernel: str) -> dict:
+    """Mean per dispatch of every counter that rocprofv3 --pmc wrote (counter_collection.csv files)
+    for the kernels whose name contains ``kernel``, with the dispatch count and register counts."""
+    import csv
+    vals, disp, regs = {}, set(), set()
+    for path in paths:
+        with open(path, newline="") as fh:
+            for row in csv.DictReader(fh):
+                if kernel not in row["Kernel_Name"]:
+                    continue
+                d = (path, row["Dispatch_Id"])
+                disp.add(d)
+                regs.add((row.get("VGPR_Count"), row.get("SGPR_Count"), row.get("LDS_Block_Size"),
+                          row.get("Workgroup_Size"), row.get("Grid_Size")))
+                vals.setdefault(row["Counter_Name"], {})
+                vals[row["Counter_Name"]][d] = vals[row["Counter_Name"]].get(d, 0.0) + float(row["Counter_Value"])
+    out = {"kernel": kernel, "dispatches": len(disp),
+           "launch": [dict(zip(("vgpr", "sgpr", "lds", "wg", "grid"), r)) for r in sorted(regs, key=str)]}
+    out["mean_per_dispatch"] = {k: sum(v.values()) / len(v) for k, v in sorted(vals.items())}
     return out
 
 
@@ -716,7 +785,19 @@ def main():
                     help="autotuner cache (JSON); a missing entry is searched on the GPU and stored")
     ap.add_argument("--copy-probe-mb", type=int, default=0,
                     help="after the run, copy this many MiB device-to-device (a known-size kernel for counter scaling)")
+    ap.add_argument("--issue-rates", action="store_true",
+                    help="measure the vector-ALU issue rates of the scorers' instructions and exit")
+    ap.add_argument("--summarize-pmc", nargs="+", metavar="CSV",
+                    help="print the mean per dispatch of the counters in rocprofv3 counter_collection.csv files "
+                         "for the kernel named by --kernel, and exit (no GPU needed)")
+    ap.add_argument("--kernel", default="k_score_slab", help="kernel name filter of --summarize-pmc")
     args = ap.parse_args()
+    if args.summarize_pmc:
+        print(json.dumps(summarize_pmc(args.summarize_pmc, args.kernel), indent=1), flush=True)
+        return
+    if args.issue_rates:
+        print(json.dumps({"issue_rates": issue_rates()}), flush=True)
+        return
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for {args.gpus}); the search shards by template range "
               "or by map with no communication but a max, which is not implemented here.", file=sys.stderr)

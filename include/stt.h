@@ -31,7 +31,10 @@
  *  - Statistic (Eq. 8, with the complex SNR p = Y/sigma of Eq. 7 and the
  *    appendix): S = sum over the N pixels of Re[exp(2 pi i f dtau) Y/sigma];
  *    z = S/sqrt(N) (STT_NORM_SQRT_N, standard normal on noise) or S/N
- *    (STT_NORM_N, the paper's literal 1/N).
+ *    (STT_NORM_N, the paper's literal 1/N). The scorers evaluate each term
+ *    as |p| cos(2 pi (f dtau + arg p)) from a polar copy of p (one cosine
+ *    per pixel), in FP32 with FP64 sums every 16 columns; scores agree with
+ *    the FP64 definition to 1e-5 max(1, |z|).
  *  - Best key: a 64-bit word (ordered bits of the FP32 score << 32) |
  *    (0xFFFFFFFF - j) where j is the track index. A larger key is a higher
  *    score, then a lower index. NaN scores count as -inf, -0 as +0. Every
@@ -145,12 +148,13 @@ stt_status stt_set_path(stt_ctx *ctx, int32_t path, int32_t lds_bytes);
  * 1024x2, 512x2). Default 1024x4. */
 stt_status stt_set_slab_shape(stt_ctx *ctx, int32_t wg, int32_t tpt);
 
-/* Slab staging: dma = 1 (default) folds p (Y/sigma of an FP32 map, or the
- * exact FP32 values of an FP16 map) into a context-owned complex64 copy of the
- * map (columns padded to 128 pixels) and streams slabs into two LDS buffers
- * with direct global-to-LDS copies, overlapping the next slab with the
- * current one; dma = 0 stages through registers into one buffer, converting
- * on the way. Scores are identical. */
+/* Slab staging. Every scoring call first folds p (Y/sigma of an FP32 map, or
+ * the exact FP32 values of an FP16 map) into a context-owned polar copy of the
+ * map: |p| as float32 and arg p as a 32-bit fraction of a turn, 8 bytes per
+ * pixel, columns padded to 128 pixels. dma = 1 (default) streams slabs of it
+ * into two LDS buffers with direct global-to-LDS copies, overlapping the next
+ * slab with the current one; dma = 0 stages through registers into one buffer.
+ * Scores are identical. */
 stt_status stt_set_staging(stt_ctx *ctx, int32_t dma);
 
 /* Phase-factor evaluation: hw = 1 (default) the hardware sine/cosine
@@ -355,8 +359,9 @@ stt_status stt_set_graph(stt_ctx *ctx, int32_t on);
  * applies the fastest to the context (stt_set_slab_shape, stt_set_path's
  * lds_bytes) and writes it as choice_out[3] = {wg, tpt, lds_bytes} (host,
  * may be NULL). With cache_path (a JSON file, may be NULL) the choice is
- * looked up first under a key of (GPU architecture, F, dtype, power-of-two
- * buckets of T and n, trig mode) and stored after a search. Synchronises. */
+ * looked up first under a key of (GPU architecture, generation tag of the
+ * scorers' inner loop, F, dtype, power-of-two buckets of T and n, trig mode)
+ * and stored after a search. Synchronises. */
 stt_status stt_autotune(stt_ctx *ctx, const stt_map *map, const stt_gen *gen, int64_t n, const char *cache_path,
                         int32_t *choice_out);
 
@@ -364,7 +369,7 @@ stt_status stt_autotune(stt_ctx *ctx, const stt_map *map, const stt_gen *gen, in
  * launch of stt_score_batch itself on these maps (direct launches, one warm-up
  * and two timed batches per candidate, kernel time only), since the best shape
  * of a queue of many uneven maps differs from a single map's. Arguments as in
- * stt_score_batch; cache key (GPU architecture, "batch", largest F, dtype,
+ * stt_score_batch; cache key (GPU architecture, generation tag, "batch", largest F, dtype,
  * power-of-two buckets of the longest T, of n_maps and of the total template
  * count, trig mode). Uses a temporary device buffer of n_maps keys. Applies and
  * returns the choice as stt_autotune does. Synchronises. */

@@ -30,9 +30,15 @@ def hipcc() -> str:
     return p
 
 
-def build(verbose: bool = False, extra: list[str] | None = None) -> str:
-    srcs = [os.path.join(CSRC, s) for s in SOURCES]
-    tmp = LIB + ".tmp"
+# The issue-rate probe (vector-ALU rates of the scorers' instructions), a measurement aid of its
+# own: bench.py --issue-rates loads it; nothing on the search path does.
+PROBE_LIB = os.path.join(PKG, "libstt_probe.so")
+PROBE_SOURCES = ["probe_issue.hip"]
+
+
+def _hipcc_shared(sources: list[str], out: str, verbose: bool, extra: list[str] | None) -> str:
+    srcs = [os.path.join(CSRC, s) for s in sources]
+    tmp = out + ".tmp"
     cmd = [hipcc(), *HIP_FLAGS, *(extra or []), "-I", os.path.join(ROOT, "include"), "-I", CSRC,
            "-o", tmp, *srcs]
     if verbose:
@@ -40,8 +46,13 @@ def build(verbose: bool = False, extra: list[str] | None = None) -> str:
     r = subprocess.run(cmd, capture_output=True, text=True)
     if r.returncode != 0:
         raise RuntimeError(f"hipcc failed ({r.returncode}):\n{r.stderr[-4000:]}")
-    os.replace(tmp, LIB)
-    return LIB
+    os.replace(tmp, out)
+    return out
+
+
+def build(verbose: bool = False, extra: list[str] | None = None) -> str:
+    _hipcc_shared(PROBE_SOURCES, PROBE_LIB, verbose, extra)
+    return _hipcc_shared(SOURCES, LIB, verbose, extra)
 
 
 if __name__ == "__main__":

@@ -32,11 +32,13 @@ struct MapP {
     float scale;       // FP16 map: p = stored * scale (a power of two)
 };
 
-// Map element formats of the scorers: the caller's (Y, sigma) FP32 map, the
-// FP16 p map, and p = Y/sigma folded into complex64 by k_fold_p (columns padded
-// to a multiple of 128 pixels so that slabs can be copied into LDS in 1 KB
-// pieces).
-enum : int { kMapF32 = 0, kMapP16 = 1, kMapPF = 2 };
+// Map element formats: the caller's (Y, sigma) FP32 map, the FP16 p map,
+// p = Y/sigma folded into complex64 by k_fold_p (read by the smooth statistic),
+// and p folded into polar form by k_fold_polar (read by every scorer of Eq. 8):
+// |p| as FP32 and arg p as a 32-bit fraction of a turn, 8 bytes per pixel.
+// Folded maps pad columns to a multiple of 128 pixels so that slabs can be
+// copied into LDS in 1 KB pieces.
+enum : int { kMapF32 = 0, kMapP16 = 1, kMapPF = 2, kMapPol = 3 };
 constexpr int kDmaPix = 128;  // pixels one wave moves per LDS-DMA instruction (64 lanes x 16 B)
 
 // The complex SNR p = Y/sigma of pixel element e (Eq. 7 with the appendix's rho = Y/sigma).
@@ -48,7 +50,7 @@ __device__ __forceinline__ float2 load_p(const MapP &m, int64_t e)
         const float2 f = __half22float2(h);
         return make_float2(f.x * m.scale, f.y * m.scale);
     }
-    if (MAPT == kMapPF) return m.Y[e];
+    if (MAPT == kMapPF || MAPT == kMapPol) return m.Y[e];  // (a polar map's element is returned as stored)
     const float2 y = m.Y[e];
     const float w = 1.0f / m.sig[e];
     return make_float2(y.x * w, y.y * w);
@@ -65,6 +67,60 @@ __global__ __launch_bounds__(256) void k_fold_p(MapP m, float2 *out, int64_t ld_
     for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < n; i += (int64_t)gridDim.x * 256) {
         const int64_t t = i / ld_out, r = i - t * ld_out;
         out[i] = r < m.F ? load_p<MAPT>(m, t * m.ld + r) : make_float2(0.0f, 0.0f);
+    }
+}
+
+// Polar form of p: (|p| rounded to FP32, arg p in 2^-32 turn as the bits of the second word).
+// The FP32 components are exact in FP64, so |p|^2 = x^2 + y^2 is rounded once, its square root
+// once more and the result once to FP32; the FP64 argument is within a few 1e-16 turn of arg p
+// before its rounding to the 2^-32 grid (wrapping modulo one turn).
+__device__ __forceinline__ float2 polar_of(float2 p)
+{
+    const double x = p.x, y = p.y;
+    const float mag = (float)sqrt(fma(x, x, y * y));
+    const double turns = atan2(y, x) * 0.15915494309189535;  // in [-1/2, 1/2]
+    const uint32_t arg = (uint32_t)(int64_t)rint(turns * 4294967296.0);
+    return make_float2(mag, __uint_as_float(arg));
+}
+
+// p of every pixel in polar form into a map with column stride ld_out (pixels F..ld_out-1 of a
+// column are zero): from Y/sigma of an FP32 map, or from the exact FP32 values of an FP16 map's
+// entries (load_p's expression).
+template <int MAPT>
+__global__ __launch_bounds__(256) void k_fold_polar(MapP m, float2 *out, int64_t ld_out)
+{
+    const int64_t n = (int64_t)m.T * ld_out;
+    for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < n; i += (int64_t)gridDim.x * 256) {
+        const int64_t t = i / ld_out, r = i - t * ld_out;
+        out[i] = r < m.F ? polar_of(load_p<MAPT>(m, t * m.ld + r)) : make_float2(0.0f, 0.0f);
+    }
+}
+
+// One polar fold of a batch: map src into dst (column stride ld_out); its pixels are px0 ..
+// px0 + T*ld_out - 1 of the batch's run (px0 ascending over the maps).
+struct FoldJob {
+    MapP src;
+    float2 *dst;
+    int64_t ld_out;
+    uint64_t px0;
+};
+
+// Every map of a batch in one launch: the grid strides over the batch's pixel run and finds
+// each pixel's map by bisection of px0 (jobs[n_jobs].px0 = the total).
+template <int MAPT>
+__global__ __launch_bounds__(256) void k_fold_polar_batch(const FoldJob *jobs, int n_jobs)
+{
+    const uint64_t total = jobs[n_jobs].px0;
+    for (uint64_t i = (uint64_t)blockIdx.x * 256 + threadIdx.x; i < total; i += (uint64_t)gridDim.x * 256) {
+        int lo = 0, hi = n_jobs;  // jobs[lo].px0 <= i < jobs[hi].px0
+        while (hi - lo > 1) {
+            const int mid = (lo + hi) >> 1;
+            if (jobs[mid].px0 <= i) lo = mid; else hi = mid;
+        }
+        const FoldJob &j = jobs[lo];
+        const int64_t k = (int64_t)(i - j.px0);
+        const int64_t t = k / j.ld_out, r = k - t * j.ld_out;
+        j.dst[k] = r < j.src.F ? polar_of(load_p<MAPT>(j.src, t * j.src.ld + r)) : make_float2(0.0f, 0.0f);
     }
 }
 
@@ -148,6 +204,30 @@ __device__ __forceinline__ float add_term(float part, const PhaseK &k, int32_t r
     }
 }
 
+// The same term from the polar form (|p|, arg p): Re[exp(2 pi i phase) p] = |p| cos(2 pi (phase +
+// arg p)). The two phases add exactly in 32-bit turns, so one cosine and one fused multiply-add
+// replace the sine, the cosine and the two products of the Cartesian form. HW: the hardware cosine
+// of the sum rounded once to FP32 turns; HW = false: the polynomial of rot_re.
+template <bool HW>
+__device__ __forceinline__ float add_term_pol(float part, const PhaseK &k, int32_t row, float2 pp)
+{
+    const uint32_t arg = __float_as_uint(pp.y);
+    if constexpr (HW) {
+        const float x = phase_turns(k.pa + arg, k.pb, row);
+        return fmaf(__builtin_amdgcn_cosf(x), pp.x, part);
+    } else {
+        return part + rot_re(k.pa + arg + (uint32_t)row * k.pb, pp.x, 0.0f);
+    }
+}
+
+// The Eq. 8 term of one pixel element of map format MAPT (polar or Cartesian).
+template <bool HW, int MAPT>
+__device__ __forceinline__ float add_term_m(float part, const PhaseK &k, int32_t row, float2 v)
+{
+    if constexpr (MAPT == kMapPol) return add_term_pol<HW>(part, k, row, v);
+    else return add_term<HW>(part, k, row, v);
+}
+
 // A fill kernel rather than a memset node, so that captured graphs replay it faithfully.
 __global__ __launch_bounds__(256) void k_fill_u32(uint32_t *p, int64_t n, uint32_t v)
 {
@@ -184,7 +264,7 @@ __global__ __launch_bounds__(kWG) void k_score_direct(MapP m, GenP g, const Trk 
             for (int32_t k = 0; k < N; ++k) {
                 const int32_t row = ddaf_row(s);
                 const float2 p = load_p<MAPT>(m, base + row);
-                part = add_term<HW>(part, pk, row, p);
+                part = add_term_m<HW, MAPT>(part, pk, row, p);
                 if (((t.t0 + k) & (kFlush - 1)) == kFlush - 1) { acc += part; part = 0.0f; }
                 ddaf_step(s);
                 base += m.ld;
@@ -232,7 +312,7 @@ __global__ __launch_bounds__(256) void k_score_wave(MapP m, GenP g, const Trk *t
                 float part = 0.0f;
                 for (int c = ca; c <= cb; ++c) {
                     const int32_t row = ddaf_row(s);
-                    part = add_term<HW>(part, pk, row, load_p<MAPT>(m, base + row));
+                    part = add_term_m<HW, MAPT>(part, pk, row, load_p<MAPT>(m, base + row));
                     ddaf_step(s);
                     base += m.ld;
                 }
@@ -420,7 +500,7 @@ __device__ __forceinline__ void lds_dma_16(const float2 *src, float2 *lds_dst)
 // Walk columns ca..cb of the current slab (column c0 at slab[0]) for the TPT
 // templates of this lane. MASK = false is the wave's core, where every
 // template of the wave covers every column: no select and no clamp.
-template <int TPT, bool MASK, bool HW>
+template <int TPT, bool MASK, bool HW, int MAPT>
 __device__ __forceinline__ void walk(int ca, int cb, int c0, const float2 *slab, int ldc, const int32_t (&t0)[TPT],
                                      const uint32_t (&span)[TPT], const PhaseK (&pk)[TPT], DdaF (&st)[TPT],
                                      float (&part)[TPT], double (&acc)[TPT])
@@ -435,10 +515,10 @@ __device__ __forceinline__ void walk(int ca, int cb, int c0, const float2 *slab,
                 const int32_t row = ddaf_row(st[q]);
                 if (MASK) {
                     const bool act = (uint32_t)c - (uint32_t)t0[q] <= span[q];
-                    const float v = add_term<HW>(part[q], pk[q], row, col[act ? row : 0]);
+                    const float v = add_term_m<HW, MAPT>(part[q], pk[q], row, col[act ? row : 0]);
                     part[q] = act ? v : part[q];
                 } else {
-                    part[q] = add_term<HW>(part[q], pk[q], row, col[row]);
+                    part[q] = add_term_m<HW, MAPT>(part[q], pk[q], row, col[row]);
                 }
                 ddaf_step(st[q]);
             }
@@ -456,10 +536,12 @@ __device__ __forceinline__ void walk(int ca, int cb, int c0, const float2 *slab,
 // One block of WG*TPT consecutive entries of `order` (block index b): the
 // whole slab sweep for those templates. slab is the dynamic LDS (S*F float2),
 // bnd two LDS ints. Callable repeatedly by a persistent workgroup.
-// MAPT == kMapPF stages with LDS DMA into two slab buffers (double buffering:
-// slab k+1 streams in while slab k is walked); the other formats stage through
-// registers into one buffer, converting on the way.
-template <int WG, int TPT, bool EXPL, bool HW, int MAPT>
+// DMA: a folded map (kMapPol or kMapPF: 8 bytes per pixel, columns padded to
+// kDmaPix) is staged with LDS DMA into two slab buffers (double buffering: slab
+// k+1 streams in while slab k is walked). Otherwise the lanes stage through
+// registers into one buffer (unfolded formats are converted to Cartesian p on
+// the way; a polar map is copied as it is).
+template <int WG, int TPT, bool EXPL, bool HW, int MAPT, bool DMA>
 __device__ __forceinline__ uint64_t score_block(const MapP &m, const GenP &g, const Trk *tr, const uint32_t *order,
                                                 uint64_t first, int64_t n, int64_t b, int S, int32_t norm, float *snr,
                                                 float2 *slab, int *bnd, uint64_t *kred)
@@ -524,8 +606,10 @@ __device__ __forceinline__ uint64_t score_block(const MapP &m, const GenP &g, co
     __syncthreads();
     const int c_first = __builtin_amdgcn_readfirstlane(bnd[0]), c_last = __builtin_amdgcn_readfirstlane(bnd[1]);
     const int F = m.F;
+    // element format of the slab: the map's own for the folded formats, p in Cartesian form otherwise
+    constexpr int SM = (MAPT == kMapPol) ? kMapPol : kMapPF;
 
-    if (MAPT == kMapPF) {
+    if constexpr (DMA) {
         // m.ld is a multiple of kDmaPix and the columns are contiguous, so the
         // slab of columns c0.. is one run of pieces of kDmaPix pixels (1 KB),
         // piece ch at pixel offset ch * kDmaPix in the map and in the buffer.
@@ -547,9 +631,9 @@ __device__ __forceinline__ uint64_t score_block(const MapP &m, const GenP &g, co
             const float2 *cur = slab + (size_t)(k & 1) * S * ldc;
             const int ncol = min(S, c_last - c0 + 1);
             const int ca = max(c0, lo), cb = min(c0 + ncol - 1, hi);  // this wave's columns in the slab
-            walk<TPT, true, HW>(ca, min(cb, clo - 1), c0, cur, ldc, t0, span, pk, st, part, acc);
-            walk<TPT, false, HW>(max(ca, clo), min(cb, chi), c0, cur, ldc, t0, span, pk, st, part, acc);
-            walk<TPT, true, HW>(max(ca, chi + 1), cb, c0, cur, ldc, t0, span, pk, st, part, acc);
+            walk<TPT, true, HW, SM>(ca, min(cb, clo - 1), c0, cur, ldc, t0, span, pk, st, part, acc);
+            walk<TPT, false, HW, SM>(max(ca, clo), min(cb, chi), c0, cur, ldc, t0, span, pk, st, part, acc);
+            walk<TPT, true, HW, SM>(max(ca, chi + 1), cb, c0, cur, ldc, t0, span, pk, st, part, acc);
         }
     } else {
         // staging walk: element e = tid + i*WG of the slab is (column e / F, row e % F)
@@ -571,9 +655,9 @@ __device__ __forceinline__ uint64_t score_block(const MapP &m, const GenP &g, co
             }
             __syncthreads();
             const int ca = max(c0, lo), cb = min(c0 + ncol - 1, hi);  // this wave's columns in the slab
-            walk<TPT, true, HW>(ca, min(cb, clo - 1), c0, slab, F, t0, span, pk, st, part, acc);
-            walk<TPT, false, HW>(max(ca, clo), min(cb, chi), c0, slab, F, t0, span, pk, st, part, acc);
-            walk<TPT, true, HW>(max(ca, chi + 1), cb, c0, slab, F, t0, span, pk, st, part, acc);
+            walk<TPT, true, HW, SM>(ca, min(cb, clo - 1), c0, slab, F, t0, span, pk, st, part, acc);
+            walk<TPT, false, HW, SM>(max(ca, clo), min(cb, chi), c0, slab, F, t0, span, pk, st, part, acc);
+            walk<TPT, true, HW, SM>(max(ca, chi + 1), cb, c0, slab, F, t0, span, pk, st, part, acc);
         }
     }
 
@@ -598,7 +682,7 @@ __device__ __forceinline__ uint64_t score_block(const MapP &m, const GenP &g, co
 // One block of binned templates per workgroup. Each workgroup stores its best
 // key in its own slot of wg_keys (no atomics: many same-address atomics from
 // every wave serialise across the chip); k_reduce_keys folds the slots.
-template <int WG, int TPT, bool EXPL, bool HW, int MAPT>
+template <int WG, int TPT, bool EXPL, bool HW, int MAPT, bool DMA>
 __global__ __launch_bounds__(WG) void k_score_slab(MapP m, GenP g, const Trk *tr, const uint32_t *order,
                                                    uint64_t first, int64_t n, int S, int32_t norm, float *snr,
                                                    uint64_t *wg_keys)
@@ -606,8 +690,8 @@ __global__ __launch_bounds__(WG) void k_score_slab(MapP m, GenP g, const Trk *tr
     extern __shared__ float2 slab[];
     __shared__ int bnd[2];
     __shared__ uint64_t kred[WG / 64];
-    const uint64_t key = score_block<WG, TPT, EXPL, HW, MAPT>(m, g, tr, order, first, n, (int64_t)blockIdx.x, S,
-                                                              norm, snr, slab, bnd, kred);
+    const uint64_t key = score_block<WG, TPT, EXPL, HW, MAPT, DMA>(m, g, tr, order, first, n, (int64_t)blockIdx.x,
+                                                                   S, norm, snr, slab, bnd, kred);
     if (threadIdx.x == 0) wg_keys[blockIdx.x] = key;
 }
 
@@ -672,7 +756,7 @@ __global__ __launch_bounds__(256) void k_score_tm(MapP m, GenP g, const TrkTm *t
                 float part = 0.0f;
                 for (int c = ca; c <= cb; ++c) {
                     const int32_t row = row_tm(k, c - t.t0);
-                    part = add_term<HW>(part, pk, row, load_p<MAPT>(m, (int64_t)c * m.ld + row));
+                    part = add_term_m<HW, MAPT>(part, pk, row, load_p<MAPT>(m, (int64_t)c * m.ld + row));
                 }
                 gp[r] = part;
             }
@@ -708,7 +792,7 @@ __device__ __forceinline__ void walk_tm(int ca, int cb, int c0, const float2 *sl
                 const int32_t dt = c - t0[q];
                 const bool act = !MASK || (uint32_t)dt <= span[q];
                 const int32_t row = row_tm(rk[q], act ? dt : 1);  // dt = 1 is valid for every template
-                const float v = add_term<HW>(part[q], pk[q], row, col[row]);
+                const float v = add_term_pol<HW>(part[q], pk[q], row, col[row]);
                 part[q] = act ? v : part[q];
             }
         }
@@ -825,10 +909,12 @@ __global__ __launch_bounds__(WG) void k_score_tm_slab(MapP m, GenP g, const uint
 constexpr int kMD = 8;
 
 // The grid is uniform, so at row r the phase of delay k of a launch is
-// phase_0(r) + k * dphase(r) (32-bit, exact): the first delay's phase factor
-// comes from the hardware sine and cosine exactly as in the plain scorer, and
-// each further one is the previous times exp(2 pi i dphase(r)), one complex
-// multiply (at most kMD - 1 = 7 in a row, a few 1e-7 relative).
+// phase_0(r) + k * dphase(r) (32-bit, exact). The map is in polar form, so the
+// term of delay k is |p| cos(theta_k) with theta_k = 2 pi (phase_k + arg p):
+// the first delay's term is the plain scorer's (add_term_pol, the same bits),
+// and each further (cos, sin) theta_k is the previous one rotated by
+// exp(2 pi i dphase(r)), one complex multiply (at most kMD - 1 = 7 in a row, a
+// few 1e-7 relative).
 struct DelayGrid {
     PhaseK k0;       // phase constants of the launch's first delay
     PhaseK dk;       // phase constants of the grid step
@@ -848,19 +934,20 @@ __device__ __forceinline__ DelayGrid delay_grid(const MapP &m, int32_t d0, int32
 
 // Adds the template's Eq. 8 terms at `row` for all kMD delays of the launch.
 template <bool HW, bool MASK>
-__device__ __forceinline__ void add_terms_md(float (&part)[kMD], const DelayGrid &dg, int32_t row, float2 p, bool act)
+__device__ __forceinline__ void add_terms_md(float (&part)[kMD], const DelayGrid &dg, int32_t row, float2 pp, bool act)
 {
-    const float v0 = add_term<HW>(part[0], dg.k0, row, p);
+    const float v0 = add_term_pol<HW>(part[0], dg.k0, row, pp);
     part[0] = !MASK || act ? v0 : part[0];
+    const uint32_t arg = __float_as_uint(pp.y);
     float c, s, cr, sr;
     if constexpr (HW) {
-        const float x0 = phase_turns(dg.k0.pa, dg.k0.pb, row), xr = phase_turns(dg.dk.pa, dg.dk.pb, row);
+        const float x0 = phase_turns(dg.k0.pa + arg, dg.k0.pb, row), xr = phase_turns(dg.dk.pa, dg.dk.pb, row);
         c = __builtin_amdgcn_cosf(x0);
         s = __builtin_amdgcn_sinf(x0);
         cr = __builtin_amdgcn_cosf(xr);
         sr = __builtin_amdgcn_sinf(xr);
     } else {
-        const uint32_t ph0 = dg.k0.pa + (uint32_t)row * dg.k0.pb, phr = dg.dk.pa + (uint32_t)row * dg.dk.pb;
+        const uint32_t ph0 = dg.k0.pa + arg + (uint32_t)row * dg.k0.pb, phr = dg.dk.pa + (uint32_t)row * dg.dk.pb;
         c = rot_re(ph0, 1.0f, 0.0f);
         s = rot_re(ph0 - 0x40000000u, 1.0f, 0.0f);  // cos(x - pi/2) = sin x
         cr = rot_re(phr, 1.0f, 0.0f);
@@ -871,7 +958,7 @@ __device__ __forceinline__ void add_terms_md(float (&part)[kMD], const DelayGrid
         const float cn = fmaf(c, cr, -s * sr), sn = fmaf(s, cr, c * sr);
         c = cn;
         s = sn;
-        const float v = fmaf(-s, p.y, fmaf(c, p.x, part[k]));
+        const float v = fmaf(c, pp.x, part[k]);
         part[k] = !MASK || act ? v : part[k];
     }
 }
@@ -1185,7 +1272,7 @@ __global__ __launch_bounds__(256) void k_bin_scatter_batch(const BatchMap *maps,
     }
 }
 
-template <int WG, int TPT, bool HW, int MAPT>
+template <int WG, int TPT, bool HW, int MAPT, bool DMA>
 __global__ __launch_bounds__(WG) void k_score_batch(const BatchMap *maps, int n_maps, const uint32_t *item_start,
                                                     uint32_t *queue, const uint32_t *order, int32_t norm,
                                                     uint64_t *best)
@@ -1203,7 +1290,7 @@ __global__ __launch_bounds__(WG) void k_score_batch(const BatchMap *maps, int n_
         if (item >= total) break;  // every workgroup reaches this: the queue only grows
         const int mi = find_map(item_start, n_maps, item);
         const BatchMap d = maps[mi];
-        const uint64_t key = score_block<WG, TPT, false, HW, MAPT>(d.m, d.g, nullptr, order + d.order0, 0, d.n,
+        const uint64_t key = score_block<WG, TPT, false, HW, MAPT, DMA>(d.m, d.g, nullptr, order + d.order0, 0, d.n,
                                                                    (int64_t)(item - item_start[mi]), d.S, norm,
                                                                    d.snr, slab, bnd, kred);
         // one atomic per item, spread over the maps' keys

@@ -272,11 +272,11 @@ int bucket_shift(int T, int64_t n)
     return wb;
 }
 
-template <int WG, int TPT, bool EXPL, bool HW, int MAPT>
+template <int WG, int TPT, bool EXPL, bool HW, int MAPT, bool DMA>
 stt_status launch_slab_t(stt_ctx *c, const MapP &m, const GenP &g, const Trk *tr, const uint32_t *order,
                          int64_t first, int64_t n, int S, size_t shm, int32_t norm, float *snr, uint64_t *wg_keys)
 {
-    auto kern = k_score_slab<WG, TPT, EXPL, HW, MAPT>;
+    auto kern = k_score_slab<WG, TPT, EXPL, HW, MAPT, DMA>;
     if (shm > 64 * 1024)
         STT_HIP(c, hipFuncSetAttribute((const void *)kern, hipFuncAttributeMaxDynamicSharedMemorySize, (int)shm));
     const unsigned grid = (unsigned)((n + WG * TPT - 1) / (WG * TPT));
@@ -289,14 +289,14 @@ stt_status launch_slab_t(stt_ctx *c, const MapP &m, const GenP &g, const Trk *tr
 // The (workgroup size, templates per lane) shapes compiled into the library.
 static const int kShapes[][2] = {{1024, 4}, {512, 4}, {256, 4}, {1024, 2}, {512, 2}};
 
-template <bool EXPL, bool HW, int MAPT>
+template <bool EXPL, bool HW, int MAPT, bool DMA>
 stt_status launch_slab_h(stt_ctx *c, int wg, int tpt, const MapP &m, const GenP &g, const Trk *tr,
                          const uint32_t *order, int64_t first, int64_t n, int S, size_t shm, int32_t norm, float *snr,
                          uint64_t *wg_keys)
 {
-#define STT_SLAB_CASE(W, P)                                                                                 \
-    if (wg == W && tpt == P)                                                                                \
-        return launch_slab_t<W, P, EXPL, HW, MAPT>(c, m, g, tr, order, first, n, S, shm, norm, snr, wg_keys);
+#define STT_SLAB_CASE(W, P)                                                                                      \
+    if (wg == W && tpt == P)                                                                                     \
+        return launch_slab_t<W, P, EXPL, HW, MAPT, DMA>(c, m, g, tr, order, first, n, S, shm, norm, snr, wg_keys);
     STT_SLAB_CASE(1024, 4)
     STT_SLAB_CASE(512, 4)
     STT_SLAB_CASE(256, 4)
@@ -306,14 +306,14 @@ stt_status launch_slab_h(stt_ctx *c, int wg, int tpt, const MapP &m, const GenP 
     return fail(c, STT_EUNSUPPORTED, "no slab scorer compiled for workgroup %d x %d templates", wg, tpt);
 }
 
-template <bool EXPL, int MAPT>
+template <bool EXPL, int MAPT, bool DMA>
 stt_status launch_slab(stt_ctx *c, int wg, int tpt, const MapP &m, const GenP &g, const Trk *tr,
                        const uint32_t *order, int64_t first, int64_t n, int S, size_t shm, int32_t norm, float *snr,
                        uint64_t *wg_keys)
 {
     if (c->hw_trig)
-        return launch_slab_h<EXPL, true, MAPT>(c, wg, tpt, m, g, tr, order, first, n, S, shm, norm, snr, wg_keys);
-    return launch_slab_h<EXPL, false, MAPT>(c, wg, tpt, m, g, tr, order, first, n, S, shm, norm, snr, wg_keys);
+        return launch_slab_h<EXPL, true, MAPT, DMA>(c, wg, tpt, m, g, tr, order, first, n, S, shm, norm, snr, wg_keys);
+    return launch_slab_h<EXPL, false, MAPT, DMA>(c, wg, tpt, m, g, tr, order, first, n, S, shm, norm, snr, wg_keys);
 }
 
 template <bool EXPL, bool HW, int MAPT>
@@ -329,6 +329,18 @@ void launch_direct(stt_ctx *c, bool per_wave, const MapP &m, const GenP &g, cons
     hipLaunchKernelGGL((k_score_direct<EXPL, HW, MAPT>), dim3(grid), dim3(kWG), 0, c->stream, m, g, tr,
                        (uint64_t)first, n, norm, snr, best);
 }
+
+// Work memory handed to a scoring call instead of the context's own (which grows
+// on demand): the binning scratch and the folded map, both big enough for the
+// call (checked by the caller).
+struct FixedBufs {
+    void *scratch;  // bucket tables, binned order, per-workgroup keys
+    void *pbuf;     // folded map
+};
+
+// p of the map in polar form (k_fold_polar) into the context's folded-map buffer, or into fb's:
+// every scorer of Eq. 8 reads this copy. mf is its view (kMapPol, column stride fold_ld(F)).
+stt_status fold_polar(stt_ctx *c, const stt_map *map, const FixedBufs *fb, MapP &mf);
 
 // Scratch of a scoring call of n templates: bucket totals and cursors, the
 // binned order (padded to an even count), then one best-key slot per scorer
@@ -351,15 +363,17 @@ bool slab_shape_ok(int wg, int tpt)
 // the per-workgroup key slots that follow it.
 template <bool EXPL>
 stt_status bin_templates(stt_ctx *c, const MapP &m, const GenP &g, const Trk *tr, int64_t first, int64_t n,
-                         uint32_t *&order, uint64_t *&wg_keys)
+                         const FixedBufs *fb, uint32_t *&order, uint64_t *&wg_keys)
 {
     const int wb = bucket_shift(m.T, n);
     const int nb = ((m.T - 1) >> wb) + 1;
     const int nbins = nb * (nb + 1) / 2;
     const size_t n_order = ((size_t)n + 1) & ~(size_t)1;  // keeps the key slots 8-byte aligned
-    stt_status s = ensure_scratch(c, score_scratch_bytes(n));
-    if (s != STT_OK) return s;
-    uint32_t *totals = (uint32_t *)c->scratch;
+    if (!fb) {
+        stt_status s = ensure_scratch(c, score_scratch_bytes(n));
+        if (s != STT_OK) return s;
+    }
+    uint32_t *totals = (uint32_t *)(fb ? fb->scratch : c->scratch);
     uint32_t *cursor = totals + kMaxBins;
     order = cursor + kMaxBins;
     wg_keys = (uint64_t *)(order + n_order);
@@ -377,63 +391,54 @@ stt_status bin_templates(stt_ctx *c, const MapP &m, const GenP &g, const Trk *tr
     return STT_OK;
 }
 
-template <bool EXPL, int MAPT>
+template <bool EXPL>
 stt_status score_impl(stt_ctx *c, const stt_map *map, const GenP &g, const Trk *tr, int64_t first, int64_t n,
-                      int32_t norm, float *snr, uint64_t *best)
+                      int32_t norm, float *snr, uint64_t *best, const FixedBufs *fb = nullptr)
 {
-    const MapP m = to_mapp(map);
+    const int F = map->F;
     // the slab plus the kernel's few static LDS words must fit the 160 KB of a CU
-    const int slab_cols = std::min<int>(64, (c->lds_bytes - 256) / (8 * m.F));
+    const int slab_cols = std::min<int>(64, (c->lds_bytes - 256) / (8 * F));
     bool slab = slab_cols >= 1;
     if (c->path == 1 || c->path == 3) slab = false;
     if (c->path == 0 && n < 4096) slab = false;
     // without slabs: one wave per template for calls too small to fill the chip lane by lane
     const bool per_wave = c->path == 3 || (c->path == 0 && n < 65536);
     if (c->path == 2 && !slab)
-        return fail(c, STT_EUNSUPPORTED, "F=%d too wide for an LDS slab of %d bytes", m.F, c->lds_bytes);
+        return fail(c, STT_EUNSUPPORTED, "F=%d too wide for an LDS slab of %d bytes", F, c->lds_bytes);
 
-    {
-        stt_status s0 = ev_begin(c);
-        if (s0 != STT_OK) return s0;
-    }
+    stt_status s = ev_begin(c);
+    if (s != STT_OK) return s;
     ev_record(c, 4);
+    MapP m;
+    if ((s = fold_polar(c, map, fb, m)) != STT_OK) return s;
     if (!slab) {
         ev_record(c, 0);
         if (c->hw_trig)
-            launch_direct<EXPL, true, MAPT>(c, per_wave, m, g, tr, first, n, norm, snr, best);
+            launch_direct<EXPL, true, kMapPol>(c, per_wave, m, g, tr, first, n, norm, snr, best);
         else
-            launch_direct<EXPL, false, MAPT>(c, per_wave, m, g, tr, first, n, norm, snr, best);
+            launch_direct<EXPL, false, kMapPol>(c, per_wave, m, g, tr, first, n, norm, snr, best);
         STT_HIP(c, hipGetLastError());
         ev_record(c, 1);
         c->used[0] = true;
     } else {
         uint32_t *order = nullptr;
         uint64_t *wg_keys = nullptr;
-        stt_status s = bin_templates<EXPL>(c, m, g, tr, first, n, order, wg_keys);
-        if (s != STT_OK) return s;
-        const int64_t ldc = fold_ld(m.F);
+        if ((s = bin_templates<EXPL>(c, m, g, tr, first, n, fb, order, wg_keys)) != STT_OK) return s;
+        const int64_t ldc = m.ld;
         if (c->dma && dma_slab_cols(c, ldc) >= 1) {
-            // fold p (Y/sigma, or the FP16 entries' exact FP32 values) once, then stream slabs
-            // into LDS with double-buffered DMA
-            const size_t pb = sizeof(float2) * (size_t)m.T * (size_t)ldc;
-            if ((s = ensure_pbuf(c, pb)) != STT_OK) return s;
-            const unsigned fg = (unsigned)std::min<int64_t>(((int64_t)m.T * ldc + 255) / 256, 4096);
-            hipLaunchKernelGGL(k_fold_p<MAPT>, dim3(fg), dim3(256), 0, c->stream, m, (float2 *)c->pbuf, ldc);
-            MapP mf = m;
-            mf.Y = (const float2 *)c->pbuf;
-            mf.sig = nullptr;
-            mf.ld = ldc;
+            // slabs of the folded map streamed into LDS with double-buffered DMA
             const int S = std::min(dma_slab_cols(c, ldc), m.T);
             const size_t shm = 2 * sizeof(float2) * (size_t)S * ldc;
             ev_record(c, 0);
-            s = launch_slab<EXPL, kMapPF>(c, c->slab_wg, c->slab_tpt, mf, g, tr, order, first, n, S, shm, norm, snr,
-                                          wg_keys);
+            s = launch_slab<EXPL, kMapPol, true>(c, c->slab_wg, c->slab_tpt, m, g, tr, order, first, n, S, shm, norm,
+                                                 snr, wg_keys);
         } else {
+            // one slab buffer, staged through registers (maps too wide for two DMA slabs)
             const int S = std::min(slab_cols, m.T);
-            const size_t shm = sizeof(float2) * (size_t)S * m.F;
+            const size_t shm = sizeof(float2) * (size_t)S * F;
             ev_record(c, 0);
-            s = launch_slab<EXPL, MAPT>(c, c->slab_wg, c->slab_tpt, m, g, tr, order, first, n, S, shm, norm, snr,
-                                        wg_keys);
+            s = launch_slab<EXPL, kMapPol, false>(c, c->slab_wg, c->slab_tpt, m, g, tr, order, first, n, S, shm, norm,
+                                                  snr, wg_keys);
         }
         if (s != STT_OK) return s;
         ev_record(c, 1);
@@ -450,10 +455,33 @@ stt_status score_impl(stt_ctx *c, const stt_map *map, const GenP &g, const Trk *
     return STT_OK;
 }
 
+stt_status fold_polar(stt_ctx *c, const stt_map *map, const FixedBufs *fb, MapP &mf)
+{
+    const MapP m = to_mapp(map);
+    const int64_t ldc = fold_ld(m.F);
+    if (!fb) {
+        const stt_status s = ensure_pbuf(c, sizeof(float2) * (size_t)m.T * (size_t)ldc);
+        if (s != STT_OK) return s;
+    }
+    float2 *pbuf = (float2 *)(fb ? fb->pbuf : c->pbuf);
+    const unsigned fg = (unsigned)std::min<int64_t>(((int64_t)m.T * ldc + 255) / 256, 8192);
+    if (map->dtype == STT_P16)
+        hipLaunchKernelGGL(k_fold_polar<kMapP16>, dim3(fg), dim3(256), 0, c->stream, m, pbuf, ldc);
+    else
+        hipLaunchKernelGGL(k_fold_polar<kMapF32>, dim3(fg), dim3(256), 0, c->stream, m, pbuf, ldc);
+    STT_HIP(c, hipGetLastError());
+    mf = m;
+    mf.Y = pbuf;
+    mf.sig = nullptr;
+    mf.ld = ldc;
+    mf.scale = 1.0f;
+    return STT_OK;
+}
+
 // The delay grid in launches of kMD delays. Slabs (binned templates, folded map,
 // LDS-DMA) from 4096 templates on when two slabs of a column fit; otherwise one
 // lane per template with direct gathers. Both give bit-identical results.
-template <bool EXPL, int MAPT>
+template <bool EXPL>
 stt_status maxdelay_impl(stt_ctx *c, const stt_map *map, const GenP &g, const Trk *tr, int64_t first, int64_t n,
                          int32_t d0, int32_t step, int32_t n_tau, int32_t norm, float *snr, int32_t *tidx,
                          uint64_t *best)
@@ -462,11 +490,10 @@ stt_status maxdelay_impl(stt_ctx *c, const stt_map *map, const GenP &g, const Tr
     // 256 x 4 and smaller slabs were 15-75 % slower; one template per lane leaves room for more waves)
     constexpr int kMdWG = 1024, kMdTPT = 1;
     const int lds = std::min(c->lds_bytes, 80 * 1024);
-    const MapP m = to_mapp(map);
-    const int64_t ldc = fold_ld(m.F);
+    const int64_t ldc = fold_ld(map->F);
     bool slab = c->dma && dma_slab_cols(lds, ldc) >= 1 && c->path != 1 && c->path != 3 && (c->path == 2 || n >= 4096);
     if (c->path == 2 && !slab)
-        return fail(c, STT_EUNSUPPORTED, "F=%d too wide for two LDS slabs of %d bytes", m.F, lds);
+        return fail(c, STT_EUNSUPPORTED, "F=%d too wide for two LDS slabs of %d bytes", map->F, lds);
     stt_status s;
     if (!snr || !tidx) {
         if ((s = ensure_mdbuf(c, (sizeof(float) + sizeof(int32_t)) * (size_t)n)) != STT_OK) return s;
@@ -475,6 +502,8 @@ stt_status maxdelay_impl(stt_ctx *c, const stt_map *map, const GenP &g, const Tr
     }
     if ((s = ev_begin(c)) != STT_OK) return s;
     ev_record(c, 4);
+    MapP mf;
+    if ((s = fold_polar(c, map, nullptr, mf)) != STT_OK) return s;
     const int n_launch = (n_tau + kMD - 1) / kMD;
     if (!slab) {
         ev_record(c, 0);
@@ -482,11 +511,11 @@ stt_status maxdelay_impl(stt_ctx *c, const stt_map *map, const GenP &g, const Tr
         for (int l = 0; l < n_launch; ++l) {
             const int32_t m0 = l * kMD, cnt = std::min(kMD, n_tau - m0), last = l == n_launch - 1;
             if (c->hw_trig)
-                hipLaunchKernelGGL((k_score_md_direct<EXPL, true, MAPT>), dim3(grid), dim3(kWG), 0, c->stream, m, g,
-                                   tr, (uint64_t)first, n, norm, d0, step, m0, cnt, last, snr, tidx, best);
-            else
-                hipLaunchKernelGGL((k_score_md_direct<EXPL, false, MAPT>), dim3(grid), dim3(kWG), 0, c->stream, m,
+                hipLaunchKernelGGL((k_score_md_direct<EXPL, true, kMapPol>), dim3(grid), dim3(kWG), 0, c->stream, mf,
                                    g, tr, (uint64_t)first, n, norm, d0, step, m0, cnt, last, snr, tidx, best);
+            else
+                hipLaunchKernelGGL((k_score_md_direct<EXPL, false, kMapPol>), dim3(grid), dim3(kWG), 0, c->stream,
+                                   mf, g, tr, (uint64_t)first, n, norm, d0, step, m0, cnt, last, snr, tidx, best);
         }
         STT_HIP(c, hipGetLastError());
         ev_record(c, 1);
@@ -494,16 +523,8 @@ stt_status maxdelay_impl(stt_ctx *c, const stt_map *map, const GenP &g, const Tr
     } else {
         uint32_t *order = nullptr;
         uint64_t *wg_keys = nullptr;
-        if ((s = bin_templates<EXPL>(c, m, g, tr, first, n, order, wg_keys)) != STT_OK) return s;
-        const size_t pb = sizeof(float2) * (size_t)m.T * (size_t)ldc;
-        if ((s = ensure_pbuf(c, pb)) != STT_OK) return s;
-        const unsigned fg = (unsigned)std::min<int64_t>(((int64_t)m.T * ldc + 255) / 256, 4096);
-        hipLaunchKernelGGL(k_fold_p<MAPT>, dim3(fg), dim3(256), 0, c->stream, m, (float2 *)c->pbuf, ldc);
-        MapP mf = m;
-        mf.Y = (const float2 *)c->pbuf;
-        mf.sig = nullptr;
-        mf.ld = ldc;
-        const int S = std::min(dma_slab_cols(lds, ldc), m.T);
+        if ((s = bin_templates<EXPL>(c, mf, g, tr, first, n, nullptr, order, wg_keys)) != STT_OK) return s;
+        const int S = std::min(dma_slab_cols(lds, ldc), mf.T);
         const size_t shm = 2 * sizeof(float2) * (size_t)S * ldc;
         const unsigned grid = (unsigned)((n + kMdWG * kMdTPT - 1) / (kMdWG * kMdTPT));
         auto kh = k_score_md_slab<kMdWG, kMdTPT, EXPL, true>;
@@ -758,12 +779,9 @@ stt_status stt_score(stt_ctx *c, const stt_map *map, const stt_gen *gen, const s
     }
     if (n == 0) return STT_OK;
     STT_HIP(c, hipSetDevice(c->device));
-    const bool p16 = map->dtype == STT_P16;
     if (tracks_dev)
-        return p16 ? score_impl<true, kMapP16>(c, map, g, (const Trk *)tracks_dev, first, n, norm, snr_dev, best_key_dev)
-                   : score_impl<true, kMapF32>(c, map, g, (const Trk *)tracks_dev, first, n, norm, snr_dev, best_key_dev);
-    return p16 ? score_impl<false, kMapP16>(c, map, g, nullptr, first, n, norm, snr_dev, best_key_dev)
-               : score_impl<false, kMapF32>(c, map, g, nullptr, first, n, norm, snr_dev, best_key_dev);
+        return score_impl<true>(c, map, g, (const Trk *)tracks_dev, first, n, norm, snr_dev, best_key_dev);
+    return score_impl<false>(c, map, g, nullptr, first, n, norm, snr_dev, best_key_dev);
 }
 
 stt_status stt_score_maxdelay(stt_ctx *c, const stt_map *map, const stt_gen *gen, const stt_track *tracks_dev,
@@ -786,17 +804,12 @@ stt_status stt_score_maxdelay(stt_ctx *c, const stt_map *map, const stt_gen *gen
     }
     if (n == 0) return STT_OK;
     STT_HIP(c, hipSetDevice(c->device));
-    const bool p16 = map->dtype == STT_P16;
     const Trk *tr = (const Trk *)tracks_dev;
     if (tracks_dev)
-        return p16 ? maxdelay_impl<true, kMapP16>(c, map, g, tr, first, n, dtau0, dtau_step, n_tau, norm, snr_dev,
-                                                  tau_idx_dev, best_key_dev)
-                   : maxdelay_impl<true, kMapF32>(c, map, g, tr, first, n, dtau0, dtau_step, n_tau, norm, snr_dev,
-                                                  tau_idx_dev, best_key_dev);
-    return p16 ? maxdelay_impl<false, kMapP16>(c, map, g, nullptr, first, n, dtau0, dtau_step, n_tau, norm, snr_dev,
-                                               tau_idx_dev, best_key_dev)
-               : maxdelay_impl<false, kMapF32>(c, map, g, nullptr, first, n, dtau0, dtau_step, n_tau, norm, snr_dev,
-                                               tau_idx_dev, best_key_dev);
+        return maxdelay_impl<true>(c, map, g, tr, first, n, dtau0, dtau_step, n_tau, norm, snr_dev, tau_idx_dev,
+                                   best_key_dev);
+    return maxdelay_impl<false>(c, map, g, nullptr, first, n, dtau0, dtau_step, n_tau, norm, snr_dev, tau_idx_dev,
+                                best_key_dev);
 }
 
 stt_status stt_make_tracks_tm(stt_ctx *c, const stt_gen *gen, int32_t T, int32_t F, int64_t first, int64_t n,
@@ -830,33 +843,23 @@ stt_status stt_score_tm(stt_ctx *c, const stt_map *map, const stt_gen *gen, cons
     }
     if (n == 0) return STT_OK;
     STT_HIP(c, hipSetDevice(c->device));
-    const MapP m = to_mapp(map);
     const TrkTm *tr = (const TrkTm *)tracks_dev;
     // generated templates: binned by time extent (a free t_mid keeps it) and scored from LDS slabs
     // (512 lanes x 2 templates, at most 80 KB of slabs) when a column fits; otherwise one wave each
     constexpr int kTmWG = 512, kTmTPT = 2;
     const int lds = std::min(c->lds_bytes, 80 * 1024);
-    const int64_t ldc = fold_ld(m.F);
+    const int64_t ldc = fold_ld(map->F);
     const bool slab = !tracks_dev && c->dma && dma_slab_cols(lds, ldc) >= 1 && c->path != 1 && c->path != 3 &&
                       (c->path == 2 || n >= 4096);
     if ((s = ev_begin(c)) != STT_OK) return s;
     ev_record(c, 4);
+    MapP mf;
+    if ((s = fold_polar(c, map, nullptr, mf)) != STT_OK) return s;
     if (slab) {
         uint32_t *order = nullptr;
         uint64_t *wg_keys = nullptr;
-        if ((s = bin_templates<false>(c, m, g, nullptr, first, n, order, wg_keys)) != STT_OK) return s;
-        const size_t pb = sizeof(float2) * (size_t)m.T * (size_t)ldc;
-        if ((s = ensure_pbuf(c, pb)) != STT_OK) return s;
-        const unsigned fg = (unsigned)std::min<int64_t>(((int64_t)m.T * ldc + 255) / 256, 4096);
-        if (map->dtype == STT_P16)
-            hipLaunchKernelGGL(k_fold_p<kMapP16>, dim3(fg), dim3(256), 0, c->stream, m, (float2 *)c->pbuf, ldc);
-        else
-            hipLaunchKernelGGL(k_fold_p<kMapF32>, dim3(fg), dim3(256), 0, c->stream, m, (float2 *)c->pbuf, ldc);
-        MapP mf = m;
-        mf.Y = (const float2 *)c->pbuf;
-        mf.sig = nullptr;
-        mf.ld = ldc;
-        const int S = std::min(dma_slab_cols(lds, ldc), m.T);
+        if ((s = bin_templates<false>(c, mf, g, nullptr, first, n, nullptr, order, wg_keys)) != STT_OK) return s;
+        const int S = std::min(dma_slab_cols(lds, ldc), mf.T);
         const size_t shm = 2 * sizeof(float2) * (size_t)S * ldc;
         const unsigned grid = (unsigned)((n + kTmWG * kTmTPT - 1) / (kTmWG * kTmTPT));
         auto kern = c->hw_trig ? k_score_tm_slab<kTmWG, kTmTPT, true> : k_score_tm_slab<kTmWG, kTmTPT, false>;
@@ -880,16 +883,13 @@ stt_status stt_score_tm(stt_ctx *c, const stt_map *map, const stt_gen *gen, cons
     }
     const dim3 grid((unsigned)((n + 3) / 4)), block(256);
     ev_record(c, 0);
-#define STT_TM_LAUNCH(E, H, M)                                                                                  \
-    hipLaunchKernelGGL((k_score_tm<E, H, M>), grid, block, 0, c->stream, m, g, tr, (uint64_t)first, n, norm,  \
+#define STT_TM_LAUNCH(E, H)                                                                                        \
+    hipLaunchKernelGGL((k_score_tm<E, H, kMapPol>), grid, block, 0, c->stream, mf, g, tr, (uint64_t)first, n, norm, \
                        snr_dev, best_key_dev)
-    const bool p16 = map->dtype == STT_P16;
     if (tracks_dev) {
-        if (p16) { if (c->hw_trig) STT_TM_LAUNCH(true, true, kMapP16); else STT_TM_LAUNCH(true, false, kMapP16); }
-        else { if (c->hw_trig) STT_TM_LAUNCH(true, true, kMapF32); else STT_TM_LAUNCH(true, false, kMapF32); }
+        if (c->hw_trig) STT_TM_LAUNCH(true, true); else STT_TM_LAUNCH(true, false);
     } else {
-        if (p16) { if (c->hw_trig) STT_TM_LAUNCH(false, true, kMapP16); else STT_TM_LAUNCH(false, false, kMapP16); }
-        else { if (c->hw_trig) STT_TM_LAUNCH(false, true, kMapF32); else STT_TM_LAUNCH(false, false, kMapF32); }
+        if (c->hw_trig) STT_TM_LAUNCH(false, true); else STT_TM_LAUNCH(false, false);
     }
 #undef STT_TM_LAUNCH
     STT_HIP(c, hipGetLastError());
@@ -1184,12 +1184,12 @@ stt_status stt_form_maps(stt_ctx *c, const stt_spectro *p, int32_t T, const floa
 
 namespace {
 
-template <int WG, int TPT, bool HW, int MAPT>
+template <int WG, int TPT, bool HW, bool DMA>
 stt_status launch_batch_t(stt_ctx *c, hipStream_t st, const BatchMap *maps, int n_maps, const uint32_t *item_start,
                           uint32_t total_items, uint32_t *queue, const uint32_t *order, int32_t norm, uint64_t *best,
                           size_t shm)
 {
-    auto kern = k_score_batch<WG, TPT, HW, MAPT>;
+    auto kern = k_score_batch<WG, TPT, HW, kMapPol, DMA>;
     if (shm > 64 * 1024)
         STT_HIP(c, hipFuncSetAttribute((const void *)kern, hipFuncAttributeMaxDynamicSharedMemorySize, (int)shm));
     int per_cu = 0;
@@ -1202,15 +1202,15 @@ stt_status launch_batch_t(stt_ctx *c, hipStream_t st, const BatchMap *maps, int 
     return STT_OK;
 }
 
-template <bool HW, int MAPT>
+template <bool HW, bool DMA>
 stt_status launch_batch_h(stt_ctx *c, hipStream_t st, const BatchMap *maps, int n_maps, const uint32_t *item_start,
                           uint32_t total_items, uint32_t *queue, const uint32_t *order, int32_t norm, uint64_t *best,
                           size_t shm)
 {
-#define STT_BATCH_CASE(W, P)                                                                                     \
-    if (c->slab_wg == W && c->slab_tpt == P)                                                                     \
-        return launch_batch_t<W, P, HW, MAPT>(c, st, maps, n_maps, item_start, total_items, queue, order, norm, best, \
-                                              shm);
+#define STT_BATCH_CASE(W, P)                                                                                    \
+    if (c->slab_wg == W && c->slab_tpt == P)                                                                    \
+        return launch_batch_t<W, P, HW, DMA>(c, st, maps, n_maps, item_start, total_items, queue, order, norm, best, \
+                                             shm);
     STT_BATCH_CASE(1024, 4)
     STT_BATCH_CASE(512, 4)
     STT_BATCH_CASE(256, 4)
@@ -1254,7 +1254,7 @@ stt_status stt_score_batch(stt_ctx *c, const stt_map *maps_host, int32_t n_maps,
     const int per_item = c->slab_wg * c->slab_tpt;
     uint64_t norder = 0, nchunks = 0, nitems = 0;
     size_t shm = 0;
-    bool fold_ok = c->dma;  // every map's column fits two DMA slabs
+    bool dma_ok = c->dma;  // every map's column fits two DMA slabs
     uint64_t fold_px = 0;
     std::vector<uint64_t> fold_off(n_maps, 0);
     for (int i = 0; i < n_maps; ++i) {
@@ -1280,7 +1280,7 @@ stt_status stt_score_batch(stt_ctx *c, const stt_map *maps_host, int32_t n_maps,
         shm = std::max(shm, sizeof(float2) * (size_t)d.S * mp->F);
         {
             const int64_t ldc = fold_ld(mp->F);
-            fold_ok = fold_ok && dma_slab_cols(c, ldc) >= 1;
+            dma_ok = dma_ok && dma_slab_cols(c, ldc) >= 1;
             fold_off[i] = fold_px;
             fold_px += (uint64_t)mp->T * (uint64_t)ldc;
         }
@@ -1297,22 +1297,32 @@ stt_status stt_score_batch(stt_ctx *c, const stt_map *maps_host, int32_t n_maps,
     chunk_start[n_maps] = (uint32_t)nchunks;
     item_start[n_maps] = (uint32_t)nitems;
     STT_HIP(c, hipSetDevice(c->device));
+    // every map is scored from its polar fold (one launch folds them all); slabs stream in by DMA
+    // when every map's column fits two of them, else through registers
     std::vector<MapP> orig(n_maps);
     for (int i = 0; i < n_maps; ++i) orig[i] = bm[i].m;
-    if (fold_ok) {
+    {
         stt_status sf = ensure_pbuf(c, sizeof(float2) * (size_t)fold_px);
         if (sf != STT_OK) return sf;
-        shm = 0;
-        for (int i = 0; i < n_maps; ++i) {
-            BatchMap &d = bm[i];
-            const int64_t ldc = fold_ld(d.m.F);
-            d.m.Y = (const float2 *)c->pbuf + fold_off[i];
-            d.m.sig = nullptr;
-            d.m.ld = ldc;
+    }
+    std::vector<FoldJob> jobs(n_maps + 1);
+    shm = 0;
+    for (int i = 0; i < n_maps; ++i) {
+        BatchMap &d = bm[i];
+        const int64_t ldc = fold_ld(d.m.F);
+        jobs[i] = FoldJob{orig[i], (float2 *)c->pbuf + fold_off[i], ldc, fold_off[i]};
+        d.m.Y = (const float2 *)c->pbuf + fold_off[i];
+        d.m.sig = nullptr;
+        d.m.ld = ldc;
+        d.m.scale = 1.0f;
+        if (dma_ok) {
             d.S = std::min(dma_slab_cols(c, ldc), d.m.T);
             shm = std::max(shm, 2 * sizeof(float2) * (size_t)d.S * (size_t)ldc);
+        } else {
+            shm = std::max(shm, sizeof(float2) * (size_t)d.S * (size_t)d.m.F);
         }
     }
+    jobs[n_maps] = FoldJob{MapP{}, nullptr, 0, fold_px};
     if (!c->n_cu) STT_HIP(c, hipDeviceGetAttribute(&c->n_cu, hipDeviceAttributeMultiprocessorCount, c->device));
 
     // scratch: [totals | cursor | queue | order]
@@ -1335,7 +1345,7 @@ stt_status stt_score_batch(stt_ctx *c, const stt_map *maps_host, int32_t n_maps,
     key_add(key, c->slab_tpt);
     key_add(key, c->lds_bytes);
     key_add(key, c->hw_trig);
-    key_add(key, fold_ok);
+    key_add(key, dma_ok);
     key_add(key, c->pbuf);
     for (const auto &d : bm) key_add(key, d);
     for (const auto &o : orig) key_add(key, o);
@@ -1343,7 +1353,7 @@ stt_status stt_score_batch(stt_ctx *c, const stt_map *maps_host, int32_t n_maps,
 
     if (!same) {
         // descriptor tables to the device (synchronous: they must outlive the call)
-        const size_t tbl = sizeof(BatchMap) * n_maps + sizeof(uint32_t) * 2 * (n_maps + 1);
+        const size_t tbl = sizeof(BatchMap) * n_maps + sizeof(FoldJob) * (n_maps + 1) + sizeof(uint32_t) * 2 * (n_maps + 1);
         if (tbl > c->bdev_bytes) {
             STT_HIP(c, hipStreamSynchronize(c->stream));
             if (c->bdev) (void)hipFree(c->bdev);
@@ -1357,9 +1367,11 @@ stt_status stt_score_batch(stt_ctx *c, const stt_map *maps_host, int32_t n_maps,
         }
         STT_HIP(c, hipStreamSynchronize(c->stream));  // the previous batch may still read the tables
         BatchMap *dmaps = (BatchMap *)c->bdev;
-        uint32_t *dchunk = (uint32_t *)(dmaps + n_maps);
+        FoldJob *djobs = (FoldJob *)(dmaps + n_maps);
+        uint32_t *dchunk = (uint32_t *)(djobs + (n_maps + 1));
         uint32_t *ditem = dchunk + (n_maps + 1);
         STT_HIP(c, hipMemcpy(dmaps, bm.data(), sizeof(BatchMap) * n_maps, hipMemcpyHostToDevice));
+        STT_HIP(c, hipMemcpy(djobs, jobs.data(), sizeof(FoldJob) * (n_maps + 1), hipMemcpyHostToDevice));
         STT_HIP(c, hipMemcpy(dchunk, chunk_start.data(), sizeof(uint32_t) * (n_maps + 1), hipMemcpyHostToDevice));
         STT_HIP(c, hipMemcpy(ditem, item_start.data(), sizeof(uint32_t) * (n_maps + 1), hipMemcpyHostToDevice));
         if (c->gexec) { (void)hipGraphExecDestroy(c->gexec); c->gexec = nullptr; }
@@ -1369,17 +1381,15 @@ stt_status stt_score_batch(stt_ctx *c, const stt_map *maps_host, int32_t n_maps,
         auto enqueue = [&](hipStream_t st) -> stt_status {
             const bool timed = st == c->stream;  // events only outside graph capture
             if (timed) ev_record(c, 2);
-            if (fold_ok)
-                for (int i = 0; i < n_maps; ++i) {
-                    const int64_t ldc = bm[i].m.ld;
-                    const unsigned fg = (unsigned)std::min<int64_t>(((int64_t)orig[i].T * ldc + 255) / 256, 4096);
-                    if (dtype == STT_P16)
-                        hipLaunchKernelGGL(k_fold_p<kMapP16>, dim3(fg), dim3(256), 0, st, orig[i], (float2 *)bm[i].m.Y,
-                                           ldc);
-                    else
-                        hipLaunchKernelGGL(k_fold_p<kMapF32>, dim3(fg), dim3(256), 0, st, orig[i], (float2 *)bm[i].m.Y,
-                                           ldc);
-                }
+            {
+                const unsigned fg = (unsigned)std::min<uint64_t>((fold_px + 255) / 256, 16384);
+                if (dtype == STT_P16)
+                    hipLaunchKernelGGL(k_fold_polar_batch<kMapP16>, dim3(fg), dim3(256), 0, st,
+                                       (const FoldJob *)djobs, n_maps);
+                else
+                    hipLaunchKernelGGL(k_fold_polar_batch<kMapF32>, dim3(fg), dim3(256), 0, st,
+                                       (const FoldJob *)djobs, n_maps);
+            }
             hipLaunchKernelGGL(k_fill_u32, dim3((unsigned)((nb_all + 64 + 255) / 256)), dim3(256), 0, st, totals,
                                (int64_t)(nb_all), 0u);
             hipLaunchKernelGGL(k_fill_u32, dim3(1), dim3(256), 0, st, queue, (int64_t)1, 0u);
@@ -1398,21 +1408,17 @@ stt_status stt_score_batch(stt_ctx *c, const stt_map *maps_host, int32_t n_maps,
                 c->used[0] = c->used[1] = true;
             }
             stt_status r;
-            if (fold_ok)
-                r = c->hw_trig ? launch_batch_h<true, kMapPF>(c, st, dmaps, n_maps, ditem, (uint32_t)nitems, queue,
-                                                              order, norm, best_key_per_map_dev, shm)
-                               : launch_batch_h<false, kMapPF>(c, st, dmaps, n_maps, ditem, (uint32_t)nitems, queue,
-                                                               order, norm, best_key_per_map_dev, shm);
-            else if (dtype == STT_P16)
-                r = c->hw_trig ? launch_batch_h<true, kMapP16>(c, st, dmaps, n_maps, ditem, (uint32_t)nitems, queue,
-                                                                  order, norm, best_key_per_map_dev, shm)
-                                  : launch_batch_h<false, kMapP16>(c, st, dmaps, n_maps, ditem, (uint32_t)nitems,
-                                                                   queue, order, norm, best_key_per_map_dev, shm);
+            const uint32_t ni = (uint32_t)nitems;
+            if (dma_ok)
+                r = c->hw_trig ? launch_batch_h<true, true>(c, st, dmaps, n_maps, ditem, ni, queue, order, norm,
+                                                            best_key_per_map_dev, shm)
+                               : launch_batch_h<false, true>(c, st, dmaps, n_maps, ditem, ni, queue, order, norm,
+                                                             best_key_per_map_dev, shm);
             else
-                r = c->hw_trig ? launch_batch_h<true, kMapF32>(c, st, dmaps, n_maps, ditem, (uint32_t)nitems, queue,
-                                                               order, norm, best_key_per_map_dev, shm)
-                               : launch_batch_h<false, kMapF32>(c, st, dmaps, n_maps, ditem, (uint32_t)nitems, queue,
-                                                                order, norm, best_key_per_map_dev, shm);
+                r = c->hw_trig ? launch_batch_h<true, false>(c, st, dmaps, n_maps, ditem, ni, queue, order, norm,
+                                                             best_key_per_map_dev, shm)
+                               : launch_batch_h<false, false>(c, st, dmaps, n_maps, ditem, ni, queue, order, norm,
+                                                              best_key_per_map_dev, shm);
             if (timed) ev_record(c, 1);
             return r;
         };
@@ -1625,20 +1631,24 @@ int log2_floor(int64_t v)
     return b;
 }
 
+// Generation of the scorers' inner loop: part of every cache key, so that choices timed on an
+// earlier loop are searched again. "pol1": polar folded map, one cosine per pixel.
+constexpr const char *kCoreTag = "pol1";
+
 // maps of similar duration (power-of-two bucket) and call size share a choice
 std::string tune_key(const stt_ctx *c, const stt_map *m, int64_t n)
 {
-    char buf[160];
-    snprintf(buf, sizeof buf, "%s/F=%d/dtype=%d/T=2^%d/n=2^%d/trig=%d", gpu_arch(c).c_str(), m->F, m->dtype,
-             log2_floor(m->T), log2_floor(n), c->hw_trig ? 1 : 0);
+    char buf[192];
+    snprintf(buf, sizeof buf, "%s/%s/F=%d/dtype=%d/T=2^%d/n=2^%d/trig=%d", gpu_arch(c).c_str(), kCoreTag, m->F,
+             m->dtype, log2_floor(m->T), log2_floor(n), c->hw_trig ? 1 : 0);
     return buf;
 }
 
 std::string tune_key_batch(const stt_ctx *c, int F, int dtype, int T, int n_maps, int64_t n_total)
 {
-    char buf[192];
-    snprintf(buf, sizeof buf, "%s/batch/F=%d/dtype=%d/T=2^%d/maps=2^%d/n=2^%d/trig=%d", gpu_arch(c).c_str(), F, dtype,
-             log2_floor(T), log2_floor(n_maps), log2_floor(n_total), c->hw_trig ? 1 : 0);
+    char buf[224];
+    snprintf(buf, sizeof buf, "%s/%s/batch/F=%d/dtype=%d/T=2^%d/maps=2^%d/n=2^%d/trig=%d", gpu_arch(c).c_str(),
+             kCoreTag, F, dtype, log2_floor(T), log2_floor(n_maps), log2_floor(n_total), c->hw_trig ? 1 : 0);
     return buf;
 }
 

@@ -50,3 +50,41 @@ def bench_tuning_copy(tmp_path) -> str:
     dst = str(tmp_path / "tune.json")
     shutil.copyfile(TUNE_CACHE, dst)
     return dst
+
+
+# Error of one FP32 node value G = Re[exp(2 pi i f dtau) p] of the smooth statistic, per unit |p|:
+# the phase rounded to FP32 turns (2^-25 turn = 1.9e-7 rad), the hardware sine and cosine (1.25e-7
+# each, measured), the two products and the difference (3 roundings of 2^-24 relative) give
+# |dG| <= (|Re p| + |Im p|)(1.9e-7 + 1.25e-7) + 1.2e-7 |G| <= 6e-7 |p|.
+SMOOTH_EPS_G = 6e-7
+
+
+def smooth_fp32_bound(p: np.ndarray, theta: np.ndarray, K: int) -> float:
+    """Bound on |z~_fp32 - z~| for the smooth statistic at theta (sample points and bilinear
+    weights in FP64 on both sides, node values G in FP32): SMOOTH_EPS_G times K^-1/2 times the sum
+    over samples of the bilinear weights times |p| at the four nodes. p: complex [T][F]."""
+    T, F = p.shape
+    xi = np.arange(K) / (K - 1) if K > 1 else np.zeros(1)
+    b = np.stack([(1 - xi) ** 2, 2 * xi * (1 - xi), xi ** 2])
+    u = np.clip(theta[0] + xi * (theta[1] - theta[0]), 0, T - 1)
+    v = np.clip(b.T @ theta[2:5] - 0.5, 0, F - 1)
+    i = np.minimum(np.floor(u).astype(np.int64), T - 2)
+    r = np.minimum(np.floor(v).astype(np.int64), F - 2)
+    a, c = u - i, v - r
+    ap = np.abs(p)
+    s = ((1 - a) * (1 - c) * ap[i, r] + a * (1 - c) * ap[i + 1, r] + (1 - a) * c * ap[i, r + 1]
+         + a * c * ap[i + 1, r + 1]).sum()
+    return SMOOTH_EPS_G * s / np.sqrt(K)
+
+
+def assert_smooth_close(z_gpu, z_orc, p, thetas, Ks, what=""):
+    """FP32 smooth statistics against the oracle's at the same points: |dz| <= 1e-5 max(1, |z|)
+    plus the FP32 node-value bound of smooth_fp32_bound."""
+    z_gpu = np.asarray(z_gpu, dtype=np.float64)
+    z_orc = np.asarray(z_orc, dtype=np.float64)
+    lim = np.array([TOL * max(1.0, abs(zo)) + smooth_fp32_bound(p, np.asarray(t, dtype=np.float64), int(k))
+                    for zo, t, k in zip(z_orc, thetas, Ks)])
+    d = np.abs(z_gpu - z_orc)
+    i = int(np.argmax(d / lim))
+    assert (d <= lim).all(), f"{what}: worst |dz|={d[i]:.3e} at {i} (z={z_orc[i]:.6f}), limit {lim[i]:.3e}"
+    return float(d.max())

@@ -9,7 +9,7 @@ import numpy as np
 import pytest
 
 import synth
-from tests.parity_util import assert_close, to_dev
+from tests.parity_util import assert_smooth_close, smooth_fp32_bound, assert_close, to_dev
 
 pytestmark = pytest.mark.gpu
 D10MS = 2684355
@@ -79,7 +79,9 @@ def test_smooth_and_gradient_match_oracle(orc, stt, ctx, p16):
     go = np.empty((n, 6))
     for i in range(n):
         zo[i], go[i] = orc.smooth(om, th[i].astype(np.float64), int(K[i]))
-    assert_close(z, zo, tol=2e-5, what="smooth z")
+    pm = deq if p16 else Y.astype(np.complex128) / s
+    dmax = assert_smooth_close(z, zo, pm, th, K, what="smooth z")
+    _say(f"smooth z max |dz| {dmax:.2e}")
     err = np.abs(g - go) / np.maximum(1.0, np.abs(go))
     assert err.max() < 2e-4, err.max()
 
@@ -122,7 +124,7 @@ def test_refine_invariants_and_plain_rescore(orc, stt, ctx):
     assert (th_h[:, 2:5] >= 0).all() and (th_h[:, 2:5] < F).all() and (np.abs(th_h[:, 5]) <= 10.0 + 1e-5).all()
     # the kept iterate's z~ is the smooth statistic at the returned theta
     zo = np.array([orc.smooth(om, th_h[i].astype(np.float64), int(K[i]))[0] for i in range(n)])
-    assert_close(zs_h, zo, tol=2e-5, what="best z~")
+    assert_smooth_close(zs_h, zo, Y.astype(np.complex128) / s, th_h, K.cpu().numpy(), what="best z~")
     # rounding to plain templates and their plain scores, exactly as the oracle defines them
     K_h = K.cpu().numpy()
     for i in range(n):
@@ -150,7 +152,7 @@ def test_refine_on_an_fp16_map(orc, stt, ctx):
     assert torch.equal(zs, ctx.smooth(m16, th, K))
     th_h, K_h = th.cpu().numpy(), K.cpu().numpy()
     zo = np.array([orc.smooth(om, th_h[i].astype(np.float64), int(K_h[i]))[0] for i in range(n)])
-    assert_close(zs.cpu().numpy(), zo, tol=2e-5, what="fp16 best z~")
+    assert_smooth_close(zs.cpu().numpy(), zo, deq, th_h, K_h, what="fp16 best z~")
     assert_close(zp.cpu().numpy(), orc.score_list(om, tr.cpu().numpy().view(orc.TRACK_DTYPE).reshape(-1)),
                  what="fp16 plain rescore")
 
@@ -209,7 +211,10 @@ def test_refine_step_by_step_matches_oracle(orc, stt, ctx, start):
     """k_refine after 1, 2 and 3 ascent steps against the oracle's iterates (each run has its own
     linear schedule: steps=1 moves 1 px and 0.5 ms; steps=2 moves 1 then 0.02 px; steps=3 1, 0.51,
     0.02). On templates whose trajectory has no near-decision (see _clear_trace) the returned
-    point is the last iterate, and theta and z~ match the oracle's to 1e-5 * max(1, |x|).
+    point is the last iterate, and theta matches the oracle's to 1e-5 * max(1, |x|). z~ is checked
+    at the returned point against the oracle's smooth statistic there (the FP32 forward bound of
+    assert_smooth_close), and against the oracle's last iterate within that bound plus the first-
+    order change of z~ over the two points' difference (|grad| . |d theta|, with a factor 2).
     'plain' starts from drawn templates (integer times: every start sample sits on a grid line,
     where both sides take the cell floor(u) of the same FP64 position); 'offgrid' from random
     real points."""
@@ -248,4 +253,12 @@ def test_refine_step_by_step_matches_oracle(orc, stt, ctx, start):
         _say(f"  {len(idx)} clear trajectories: max theta err {d_th.max():.2e}, "
              f"max z err {np.max(np.abs(zs[idx] - want[:, 6]) / np.maximum(1.0, np.abs(want[:, 6]))):.2e}")
         assert d_th.max() <= 1e-5, (int(idx[np.argmax(d_th.max(axis=1))]), d_th.max())
-        assert_close(zs[idx], want[:, 6], tol=1e-5, what=f"z~ after {steps} steps")
+        p = Y.astype(np.complex128) / s
+        z_at = np.array([orc.smooth(om, th[i], int(K[i]), grad=False)[0] for i in idx])
+        assert_smooth_close(zs[idx], z_at, p, th[idx], K[idx], what=f"z~ at the returned point, {steps} steps")
+        prop = np.array([2.0 * np.abs(orc.smooth(om, want[j, :6], int(K[i]))[1]) @ np.abs(th[i] - want[j, :6])
+                         for j, i in enumerate(idx)])
+        lim = np.array([1e-5 * max(1.0, abs(want[j, 6])) + smooth_fp32_bound(p, th[i], int(K[i]))
+                        for j, i in enumerate(idx)]) + prop
+        dz = np.abs(zs[idx] - want[:, 6])
+        assert (dz <= lim).all(), (int(idx[np.argmax(dz / lim)]), float(dz.max()))
