@@ -186,6 +186,22 @@ stt_status stt_make_tracks(stt_ctx *ctx, const stt_gen *gen, int32_t T, int32_t 
 stt_status stt_score(stt_ctx *ctx, const stt_map *map, const stt_gen *gen, const stt_track *tracks_dev,
                      int64_t first, int64_t n, int32_t norm, float *snr_dev, uint64_t *best_key_dev);
 
+/* stt_score without allocation, for callers that cannot allocate device memory
+ * (code under HIP graph capture, tight serving loops, harnesses that forbid
+ * hipMalloc). Arguments, results and errors as stt_score; the scores are the
+ * same bits. The binning scratch and the folded map live in one static
+ * device array per GPU (about 48.1 MB, held from library load until the
+ * process ends; its address is taken by stt_create), so this call makes no
+ * allocation, records no timing events, and limits the call to
+ * n <= 4194304 templates and maps whose folded copy (T x F rounded up to a
+ * multiple of 128, 8 bytes per pixel) fits 32 MiB -- STT_ERANGE otherwise,
+ * before anything is enqueued. Every call on one GPU shares that array and
+ * leaves its contents behind; calls that overlap on one GPU (other streams,
+ * other contexts, other host threads) race and must be serialised by the
+ * caller. STT_EHIP if the array's address could not be taken on this device. */
+stt_status stt_score_noalloc(stt_ctx *ctx, const stt_map *map, const stt_gen *gen, const stt_track *tracks_dev,
+                             int64_t first, int64_t n, int32_t norm, float *snr_dev, uint64_t *best_key_dev);
+
 /* Free-t_mid templates (an addition: the paper's six random numbers, with t_mid
  * free instead of at the midpoint). Generation as stt_make_tracks, plus
  * t1 = t0 + floor(x * (t2 - t0 + 1) / 2^32) from the last word x of the second

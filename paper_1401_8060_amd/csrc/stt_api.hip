@@ -8,6 +8,7 @@
 #include <cstdio>
 #include <cstring>
 #include <functional>
+#include <mutex>
 #include <string>
 #include <vector>
 
@@ -351,6 +352,49 @@ size_t score_scratch_bytes(int64_t n)
     return sizeof(uint32_t) * (2 * (size_t)kMaxBins + n_order) + sizeof(uint64_t) * (size_t)((n + 1023) / 1024);
 }
 
+}  // namespace
+
+// ---------------------------------------------------------------- fixed scratch of stt_score_noalloc
+// One static device array per GPU, for callers that cannot allocate: the
+// folded map in its first kNaMapBytes, then the binning scratch of up to
+// kNaMaxTracks templates. In host code `scratch` only names the symbol; its
+// device address comes from hipGetSymbolAddress, taken once per device (with
+// that device current) by stt_create and kept in g_na_ptr.
+constexpr size_t kNaMapBytes = (size_t)32 << 20;
+constexpr int64_t kNaMaxTracks = (int64_t)1 << 22;
+constexpr size_t kNaScratchBytes =
+    sizeof(uint32_t) * (2 * (size_t)kMaxBins + (size_t)kNaMaxTracks) + sizeof(uint64_t) * (size_t)(kNaMaxTracks / 1024);
+constexpr size_t kNaBytes = kNaMapBytes + kNaScratchBytes;
+static __device__ __align__(256) unsigned char scratch[kNaBytes];
+
+namespace {
+
+constexpr int kNaMaxDevices = 64;
+void *g_na_ptr[kNaMaxDevices] = {};
+std::mutex g_na_mu;
+
+// Device address of this device's copy of `scratch` (device current); false when it is unavailable.
+bool na_init(int device)
+{
+    if (device < 0 || device >= kNaMaxDevices) return false;
+    std::lock_guard<std::mutex> lk(g_na_mu);
+    if (g_na_ptr[device]) return true;
+    void *p = nullptr;
+    if (hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)) != hipSuccess || !p) {
+        (void)hipGetLastError();
+        return false;
+    }
+    g_na_ptr[device] = p;
+    return true;
+}
+
+void *na_ptr(int device)
+{
+    if (device < 0 || device >= kNaMaxDevices) return nullptr;
+    std::lock_guard<std::mutex> lk(g_na_mu);
+    return g_na_ptr[device];
+}
+
 bool slab_shape_ok(int wg, int tpt)
 {
     for (const auto &s : kShapes)
@@ -627,6 +671,8 @@ stt_status stt_create(int device, void *hip_stream, stt_ctx **out)
     stt_ctx *c = new stt_ctx;
     c->device = device;
     c->stream = (hipStream_t)hip_stream;
+    // the fixed scratch of stt_score_noalloc on this device (that call fails cleanly without it)
+    (void)na_init(device);
     *out = c;
     return STT_OK;
 }
@@ -782,6 +828,41 @@ stt_status stt_score(stt_ctx *c, const stt_map *map, const stt_gen *gen, const s
     if (tracks_dev)
         return score_impl<true>(c, map, g, (const Trk *)tracks_dev, first, n, norm, snr_dev, best_key_dev);
     return score_impl<false>(c, map, g, nullptr, first, n, norm, snr_dev, best_key_dev);
+}
+
+stt_status stt_score_noalloc(stt_ctx *c, const stt_map *map, const stt_gen *gen, const stt_track *tracks_dev,
+                             int64_t first, int64_t n, int32_t norm, float *snr_dev, uint64_t *best_key_dev)
+{
+    if (!c) return STT_EINVAL;
+    stt_status s = check_map(c, map);
+    if (s != STT_OK) return s;
+    if ((s = check_range(c, first, n)) != STT_OK) return s;
+    if (norm != STT_NORM_SQRT_N && norm != STT_NORM_N) return fail(c, STT_EINVAL, "norm=%d", norm);
+    if (n > kNaMaxTracks)
+        return fail(c, STT_ERANGE, "n=%lld exceeds the %lld templates of the fixed scratch", (long long)n,
+                    (long long)kNaMaxTracks);
+    const size_t map_bytes = sizeof(float2) * (size_t)map->T * (size_t)fold_ld(map->F);
+    if (map_bytes > kNaMapBytes)
+        return fail(c, STT_ERANGE, "the folded %dx%d map needs %zu bytes; the fixed scratch holds %zu", map->T,
+                    map->F, map_bytes, kNaMapBytes);
+    GenP g{};
+    if (!tracks_dev) {
+        if ((s = make_genp(c, gen, map->T, map->F, g)) != STT_OK) return s;
+    }
+    if (n == 0) return STT_OK;
+    STT_HIP(c, hipSetDevice(c->device));
+    void *base = na_ptr(c->device);
+    if (!base) return fail(c, STT_EHIP, "no fixed scratch on device %d (hipGetSymbolAddress failed)", c->device);
+    const FixedBufs fb{(unsigned char *)base + kNaMapBytes, base};
+    // no timing events either: the event pool grows by allocation
+    const bool timing = c->timing;
+    c->timing = false;
+    if (tracks_dev)
+        s = score_impl<true>(c, map, g, (const Trk *)tracks_dev, first, n, norm, snr_dev, best_key_dev, &fb);
+    else
+        s = score_impl<false>(c, map, g, nullptr, first, n, norm, snr_dev, best_key_dev, &fb);
+    c->timing = timing;
+    return s;
 }
 
 stt_status stt_score_maxdelay(stt_ctx *c, const stt_map *map, const stt_gen *gen, const stt_track *tracks_dev,

@@ -324,6 +324,29 @@ class Context:
                                     C.c_void_p(best_key.data_ptr())))
         return snr, best_key
 
+    def score_noalloc(self, m: Map, snr: torch.Tensor | None, best_key: torch.Tensor, gen: Gen | None = None,
+                      tracks: torch.Tensor | None = None, first: int = 0, n: int | None = None,
+                      norm: int = NORM_SQRT_N):
+        """stt_score_noalloc: as score(), with caller-given outputs (snr may be None) and the library's
+        fixed scratch instead of allocated memory (at most 4194304 templates per call)."""
+        if tracks is not None:
+            if tracks.dtype != torch.int32 or tracks.dim() != 2 or tracks.shape[1] != 6 or not tracks.is_contiguous():
+                raise ValueError("tracks must be a contiguous [n][6] int32 tensor")
+            n = tracks.shape[0] if n is None else n
+        if n is None:
+            raise ValueError("n is required with generated tracks")
+        if snr is not None and (snr.dtype != torch.float32 or snr.numel() < n or not snr.is_contiguous()):
+            raise ValueError("snr must be a contiguous float32 tensor of at least n elements")
+        if best_key.dtype != torch.int64 or best_key.numel() < 1:
+            raise ValueError("best_key must be an int64 tensor")
+        mc = m.c()
+        g = gen.c() if gen is not None else None
+        self._chk(self._L.stt_score_noalloc(self.h, C.byref(mc), C.byref(g) if g is not None else None,
+                                            C.c_void_p(tracks.data_ptr()) if tracks is not None else None,
+                                            first, n, norm, C.c_void_p(snr.data_ptr()) if snr is not None else None,
+                                            C.c_void_p(best_key.data_ptr())))
+        return snr, best_key
+
     def make_tracks_tm(self, gen: Gen, T: int, F: int, first: int, n: int) -> torch.Tensor:
         """Free-t_mid templates j = first .. first+n-1 as an [n][7] int32 tensor (t0, t1, t2, f0, f1, f2, dtau)."""
         out = torch.empty((max(n, 1), 7), dtype=torch.int32, device="cuda")

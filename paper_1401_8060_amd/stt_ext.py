@@ -27,6 +27,7 @@ def bind(L) -> None:
         "stt_significance": ([vp, vp, i64, vp, i64, C.c_double, vp, vp, vp], i32),
         "stt_follow_up": ([vp, vp, i32, vp, vp, i64, i32, i32, vp, C.POINTER(i32)], i32),
         "stt_form_maps": ([vp, vp, i32, vp, vp, vp, vp, i32, vp, i64, vp, vp], i32),
+        "stt_score_noalloc": ([vp, vp, vp, vp, i64, i64, i32, vp, vp], i32),
     }
     for name, (args, res) in sigs.items():
         fn = getattr(L, name)
@@ -37,4 +38,4 @@ def bind(L) -> None:
 EXPORTED = ["stt_map_pack_p16", "stt_topk", "stt_rescore_f64", "stt_score_batch", "stt_set_graph", "stt_autotune", "stt_autotune_batch", "stt_score_maxdelay",
             "stt_make_tracks_tm", "stt_score_tm",
             "stt_tracks_at", "stt_tracks_to_theta", "stt_smooth", "stt_grad", "stt_refine",
-            "stt_spectra", "stt_form_maps", "stt_significance", "stt_follow_up"]
+            "stt_spectra", "stt_form_maps", "stt_significance", "stt_follow_up", "stt_score_noalloc"]
