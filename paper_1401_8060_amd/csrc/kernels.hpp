@@ -533,15 +533,47 @@ __device__ __forceinline__ void walk(int ca, int cb, int c0, const float2 *slab,
     }
 }
 
+// Walk of one aligned slab of SC columns c0 .. c0 + SC - 1 (c0 a multiple of
+// SC, SC a divisor of kFlush) at slab[0 .. SC*ldc): straight-line code, SC
+// columns x TPT templates. MASK = false when every template of the wave covers
+// every column of the slab.
+template <int SC, int TPT, bool MASK, bool HW, int SM>
+__device__ __forceinline__ void walk_slab(int c0, const float2 *slab, int ldc, const int32_t (&t0)[TPT],
+                                          const uint32_t (&span)[TPT], const PhaseK (&pk)[TPT], DdaF (&st)[TPT],
+                                          float (&part)[TPT])
+{
+#pragma unroll
+    for (int j = 0; j < SC; ++j) {
+        const float2 *col = slab + j * ldc;
+#pragma unroll
+        for (int q = 0; q < TPT; ++q) {
+            const int32_t row = ddaf_row(st[q]);
+            if (MASK) {
+                const bool act = (uint32_t)(c0 + j) - (uint32_t)t0[q] <= span[q];
+                const float v = add_term_m<HW, SM>(part[q], pk[q], row, col[act ? row : 0]);
+                part[q] = act ? v : part[q];
+            } else {
+                part[q] = add_term_m<HW, SM>(part[q], pk[q], row, col[row]);
+            }
+            ddaf_step(st[q]);
+        }
+    }
+}
+
 // One block of WG*TPT consecutive entries of `order` (block index b): the
 // whole slab sweep for those templates. slab is the dynamic LDS (S*F float2),
 // bnd two LDS ints. Callable repeatedly by a persistent workgroup.
-// DMA: a folded map (kMapPol or kMapPF: 8 bytes per pixel, columns padded to
-// kDmaPix) is staged with LDS DMA into two slab buffers (double buffering: slab
-// k+1 streams in while slab k is walked). Otherwise the lanes stage through
-// registers into one buffer (unfolded formats are converted to Cartesian p on
-// the way; a polar map is copied as it is).
-template <int WG, int TPT, bool EXPL, bool HW, int MAPT, bool DMA>
+// SC > 0: a folded map (kMapPol or kMapPF: 8 bytes per pixel, columns padded
+// to kDmaPix) is staged with LDS DMA into two slab buffers of SC columns
+// (double buffering: slab k+1 streams in while slab k is walked). Slabs are
+// aligned to multiples of SC on the absolute column grid, so the FP32 partial
+// sums are flushed between slabs and a slab is one straight-line walk_slab;
+// each wave starts its rows at its first aligned column (columns before a
+// template's start and after its end are masked, so the extra columns change
+// nothing). SC = 0: the lanes stage S columns through registers into one
+// buffer (unfolded formats are converted to Cartesian p on the way; a polar
+// map is copied as it is) and walk them column by column.
+template <int WG, int TPT, bool EXPL, bool HW, int MAPT, int SC>
 __device__ __forceinline__ uint64_t score_block(const MapP &m, const GenP &g, const Trk *tr, const uint32_t *order,
                                                 uint64_t first, int64_t n, int64_t b, int S, int32_t norm, float *snr,
                                                 float2 *slab, int *bnd, uint64_t *kred)
@@ -591,7 +623,8 @@ __device__ __forceinline__ uint64_t score_block(const MapP &m, const GenP &g, co
     DdaF st[TPT];
     float part[TPT];
     double acc[TPT];
-    const int start = lo == 0x7fffffff ? 0 : lo;
+    // the rows start at the wave's first column (aligned down to a slab boundary when slabs are)
+    const int start = lo == 0x7fffffff ? 0 : (SC > 0 ? lo & ~(SC - 1) : lo);
 #pragma unroll
     for (int q = 0; q < TPT; ++q) {
         st[q] = ddaf_init_at(tk[q], start - tk[q].t0);
@@ -609,31 +642,42 @@ __device__ __forceinline__ uint64_t score_block(const MapP &m, const GenP &g, co
     // element format of the slab: the map's own for the folded formats, p in Cartesian form otherwise
     constexpr int SM = (MAPT == kMapPol) ? kMapPol : kMapPF;
 
-    if constexpr (DMA) {
+    if constexpr (SC > 0) {
+        static_assert(kFlush % SC == 0, "slabs must tile the flush grid");
         // m.ld is a multiple of kDmaPix and the columns are contiguous, so the
         // slab of columns c0.. is one run of pieces of kDmaPix pixels (1 KB),
         // piece ch at pixel offset ch * kDmaPix in the map and in the buffer.
         const int ldc = (int)m.ld, per_col = ldc / kDmaPix;
         const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
         auto issue = [&](int c0, int bsel) {
-            const int nchunk = min(S, c_last - c0 + 1) * per_col;
+            const int nchunk = min(SC, c_last - c0 + 1) * per_col;
             const float2 *src = m.Y + (int64_t)c0 * ldc + lane * 2;
-            float2 *dst = slab + (size_t)bsel * S * ldc;
+            float2 *dst = slab + (size_t)bsel * SC * ldc;
             for (int ch = wave; ch < nchunk; ch += WG / 64)
                 lds_dma_16(src + ch * kDmaPix, dst + ch * kDmaPix);
         };
-        if (c_first <= c_last) issue(c_first, 0);
+        const int a_first = c_first & ~(SC - 1);
+        // this wave's slabs: from its aligned first column to its last; the core slabs lie in [clo, chi]
+        const int w_lo = start, w_hi = hi;
+        if (c_first <= c_last) issue(a_first, 0);
         int k = 0;
-        for (int c0 = c_first; c0 <= c_last; c0 += S, ++k) {
+        for (int c0 = a_first; c0 <= c_last; c0 += SC, ++k) {
             __builtin_amdgcn_s_waitcnt(0);  // this wave's copies of slab k have landed
             __syncthreads();                // so have everyone's, and slab k-1 is no longer read
-            if (c0 + S <= c_last) issue(c0 + S, (k + 1) & 1);
-            const float2 *cur = slab + (size_t)(k & 1) * S * ldc;
-            const int ncol = min(S, c_last - c0 + 1);
-            const int ca = max(c0, lo), cb = min(c0 + ncol - 1, hi);  // this wave's columns in the slab
-            walk<TPT, true, HW, SM>(ca, min(cb, clo - 1), c0, cur, ldc, t0, span, pk, st, part, acc);
-            walk<TPT, false, HW, SM>(max(ca, clo), min(cb, chi), c0, cur, ldc, t0, span, pk, st, part, acc);
-            walk<TPT, true, HW, SM>(max(ca, chi + 1), cb, c0, cur, ldc, t0, span, pk, st, part, acc);
+            if (c0 + SC <= c_last) issue(c0 + SC, (k + 1) & 1);
+            if (c0 < w_lo || c0 > w_hi) continue;  // wave-uniform
+            const float2 *cur = slab + (size_t)(k & 1) * SC * ldc;
+            if (c0 >= clo && c0 + SC - 1 <= chi)
+                walk_slab<SC, TPT, false, HW, SM>(c0, cur, ldc, t0, span, pk, st, part);
+            else
+                walk_slab<SC, TPT, true, HW, SM>(c0, cur, ldc, t0, span, pk, st, part);
+            if (((c0 + SC) & (kFlush - 1)) == 0) {  // wave-uniform: the slab ends a flush group
+#pragma unroll
+                for (int q = 0; q < TPT; ++q) {
+                    acc[q] += part[q];
+                    part[q] = 0.0f;
+                }
+            }
         }
     } else {
         // staging walk: element e = tid + i*WG of the slab is (column e / F, row e % F)
@@ -682,7 +726,7 @@ __device__ __forceinline__ uint64_t score_block(const MapP &m, const GenP &g, co
 // One block of binned templates per workgroup. Each workgroup stores its best
 // key in its own slot of wg_keys (no atomics: many same-address atomics from
 // every wave serialise across the chip); k_reduce_keys folds the slots.
-template <int WG, int TPT, bool EXPL, bool HW, int MAPT, bool DMA>
+template <int WG, int TPT, bool EXPL, bool HW, int MAPT, int SC>
 __global__ __launch_bounds__(WG) void k_score_slab(MapP m, GenP g, const Trk *tr, const uint32_t *order,
                                                    uint64_t first, int64_t n, int S, int32_t norm, float *snr,
                                                    uint64_t *wg_keys)
@@ -690,7 +734,7 @@ __global__ __launch_bounds__(WG) void k_score_slab(MapP m, GenP g, const Trk *tr
     extern __shared__ float2 slab[];
     __shared__ int bnd[2];
     __shared__ uint64_t kred[WG / 64];
-    const uint64_t key = score_block<WG, TPT, EXPL, HW, MAPT, DMA>(m, g, tr, order, first, n, (int64_t)blockIdx.x,
+    const uint64_t key = score_block<WG, TPT, EXPL, HW, MAPT, SC>(m, g, tr, order, first, n, (int64_t)blockIdx.x,
                                                                    S, norm, snr, slab, bnd, kred);
     if (threadIdx.x == 0) wg_keys[blockIdx.x] = key;
 }
@@ -1272,7 +1316,7 @@ __global__ __launch_bounds__(256) void k_bin_scatter_batch(const BatchMap *maps,
     }
 }
 
-template <int WG, int TPT, bool HW, int MAPT, bool DMA>
+template <int WG, int TPT, bool HW, int MAPT, int SC>
 __global__ __launch_bounds__(WG) void k_score_batch(const BatchMap *maps, int n_maps, const uint32_t *item_start,
                                                     uint32_t *queue, const uint32_t *order, int32_t norm,
                                                     uint64_t *best)
@@ -1290,7 +1334,7 @@ __global__ __launch_bounds__(WG) void k_score_batch(const BatchMap *maps, int n_
         if (item >= total) break;  // every workgroup reaches this: the queue only grows
         const int mi = find_map(item_start, n_maps, item);
         const BatchMap d = maps[mi];
-        const uint64_t key = score_block<WG, TPT, false, HW, MAPT, DMA>(d.m, d.g, nullptr, order + d.order0, 0, d.n,
+        const uint64_t key = score_block<WG, TPT, false, HW, MAPT, SC>(d.m, d.g, nullptr, order + d.order0, 0, d.n,
                                                                    (int64_t)(item - item_start[mi]), d.S, norm,
                                                                    d.snr, slab, bnd, kred);
         // one atomic per item, spread over the maps' keys

@@ -273,11 +273,11 @@ int bucket_shift(int T, int64_t n)
     return wb;
 }
 
-template <int WG, int TPT, bool EXPL, bool HW, int MAPT, bool DMA>
+template <int WG, int TPT, bool EXPL, bool HW, int MAPT, int SC>
 stt_status launch_slab_t(stt_ctx *c, const MapP &m, const GenP &g, const Trk *tr, const uint32_t *order,
                          int64_t first, int64_t n, int S, size_t shm, int32_t norm, float *snr, uint64_t *wg_keys)
 {
-    auto kern = k_score_slab<WG, TPT, EXPL, HW, MAPT, DMA>;
+    auto kern = k_score_slab<WG, TPT, EXPL, HW, MAPT, SC>;
     if (shm > 64 * 1024)
         STT_HIP(c, hipFuncSetAttribute((const void *)kern, hipFuncAttributeMaxDynamicSharedMemorySize, (int)shm));
     const unsigned grid = (unsigned)((n + WG * TPT - 1) / (WG * TPT));
@@ -290,14 +290,14 @@ stt_status launch_slab_t(stt_ctx *c, const MapP &m, const GenP &g, const Trk *tr
 // The (workgroup size, templates per lane) shapes compiled into the library.
 static const int kShapes[][2] = {{1024, 4}, {512, 4}, {256, 4}, {1024, 2}, {512, 2}};
 
-template <bool EXPL, bool HW, int MAPT, bool DMA>
+template <bool EXPL, bool HW, int MAPT, int SC>
 stt_status launch_slab_h(stt_ctx *c, int wg, int tpt, const MapP &m, const GenP &g, const Trk *tr,
                          const uint32_t *order, int64_t first, int64_t n, int S, size_t shm, int32_t norm, float *snr,
                          uint64_t *wg_keys)
 {
-#define STT_SLAB_CASE(W, P)                                                                                      \
-    if (wg == W && tpt == P)                                                                                     \
-        return launch_slab_t<W, P, EXPL, HW, MAPT, DMA>(c, m, g, tr, order, first, n, S, shm, norm, snr, wg_keys);
+#define STT_SLAB_CASE(W, P)                                                                                     \
+    if (wg == W && tpt == P)                                                                                    \
+        return launch_slab_t<W, P, EXPL, HW, MAPT, SC>(c, m, g, tr, order, first, n, S, shm, norm, snr, wg_keys);
     STT_SLAB_CASE(1024, 4)
     STT_SLAB_CASE(512, 4)
     STT_SLAB_CASE(256, 4)
@@ -307,14 +307,41 @@ stt_status launch_slab_h(stt_ctx *c, int wg, int tpt, const MapP &m, const GenP 
     return fail(c, STT_EUNSUPPORTED, "no slab scorer compiled for workgroup %d x %d templates", wg, tpt);
 }
 
-template <bool EXPL, int MAPT, bool DMA>
-stt_status launch_slab(stt_ctx *c, int wg, int tpt, const MapP &m, const GenP &g, const Trk *tr,
+template <bool EXPL, int MAPT, int SC>
+stt_status launch_slab_sc(stt_ctx *c, int wg, int tpt, const MapP &m, const GenP &g, const Trk *tr,
+                          const uint32_t *order, int64_t first, int64_t n, int S, size_t shm, int32_t norm, float *snr,
+                          uint64_t *wg_keys)
+{
+    if (c->hw_trig)
+        return launch_slab_h<EXPL, true, MAPT, SC>(c, wg, tpt, m, g, tr, order, first, n, S, shm, norm, snr, wg_keys);
+    return launch_slab_h<EXPL, false, MAPT, SC>(c, wg, tpt, m, g, tr, order, first, n, S, shm, norm, snr, wg_keys);
+}
+
+// The widest aligned slab (a power of two dividing the 16-column flush grid) of which two fit
+// `cols` columns of LDS; 0 when not even two single columns fit.
+int aligned_slab(int cols)
+{
+    int sc = 16;
+    while (sc > cols) sc >>= 1;
+    return sc;
+}
+
+// sc > 0: LDS-DMA slabs of sc aligned columns (sc in 1, 2, 4, 8, 16); sc = 0: register staging of
+// S columns.
+template <bool EXPL, int MAPT>
+stt_status launch_slab(stt_ctx *c, int sc, int wg, int tpt, const MapP &m, const GenP &g, const Trk *tr,
                        const uint32_t *order, int64_t first, int64_t n, int S, size_t shm, int32_t norm, float *snr,
                        uint64_t *wg_keys)
 {
-    if (c->hw_trig)
-        return launch_slab_h<EXPL, true, MAPT, DMA>(c, wg, tpt, m, g, tr, order, first, n, S, shm, norm, snr, wg_keys);
-    return launch_slab_h<EXPL, false, MAPT, DMA>(c, wg, tpt, m, g, tr, order, first, n, S, shm, norm, snr, wg_keys);
+    switch (sc) {
+    case 0: return launch_slab_sc<EXPL, MAPT, 0>(c, wg, tpt, m, g, tr, order, first, n, S, shm, norm, snr, wg_keys);
+    case 1: return launch_slab_sc<EXPL, MAPT, 1>(c, wg, tpt, m, g, tr, order, first, n, S, shm, norm, snr, wg_keys);
+    case 2: return launch_slab_sc<EXPL, MAPT, 2>(c, wg, tpt, m, g, tr, order, first, n, S, shm, norm, snr, wg_keys);
+    case 4: return launch_slab_sc<EXPL, MAPT, 4>(c, wg, tpt, m, g, tr, order, first, n, S, shm, norm, snr, wg_keys);
+    case 8: return launch_slab_sc<EXPL, MAPT, 8>(c, wg, tpt, m, g, tr, order, first, n, S, shm, norm, snr, wg_keys);
+    case 16: return launch_slab_sc<EXPL, MAPT, 16>(c, wg, tpt, m, g, tr, order, first, n, S, shm, norm, snr, wg_keys);
+    default: return fail(c, STT_EUNSUPPORTED, "no slab scorer for %d-column slabs", sc);
+    }
 }
 
 template <bool EXPL, bool HW, int MAPT>
@@ -470,19 +497,19 @@ stt_status score_impl(stt_ctx *c, const stt_map *map, const GenP &g, const Trk *
         if ((s = bin_templates<EXPL>(c, m, g, tr, first, n, fb, order, wg_keys)) != STT_OK) return s;
         const int64_t ldc = m.ld;
         if (c->dma && dma_slab_cols(c, ldc) >= 1) {
-            // slabs of the folded map streamed into LDS with double-buffered DMA
-            const int S = std::min(dma_slab_cols(c, ldc), m.T);
+            // aligned slabs of the folded map streamed into LDS with double-buffered DMA
+            const int S = aligned_slab(dma_slab_cols(c, ldc));
             const size_t shm = 2 * sizeof(float2) * (size_t)S * ldc;
             ev_record(c, 0);
-            s = launch_slab<EXPL, kMapPol, true>(c, c->slab_wg, c->slab_tpt, m, g, tr, order, first, n, S, shm, norm,
-                                                 snr, wg_keys);
+            s = launch_slab<EXPL, kMapPol>(c, S, c->slab_wg, c->slab_tpt, m, g, tr, order, first, n, S, shm, norm,
+                                           snr, wg_keys);
         } else {
             // one slab buffer, staged through registers (maps too wide for two DMA slabs)
             const int S = std::min(slab_cols, m.T);
             const size_t shm = sizeof(float2) * (size_t)S * F;
             ev_record(c, 0);
-            s = launch_slab<EXPL, kMapPol, false>(c, c->slab_wg, c->slab_tpt, m, g, tr, order, first, n, S, shm, norm,
-                                                  snr, wg_keys);
+            s = launch_slab<EXPL, kMapPol>(c, 0, c->slab_wg, c->slab_tpt, m, g, tr, order, first, n, S, shm, norm,
+                                           snr, wg_keys);
         }
         if (s != STT_OK) return s;
         ev_record(c, 1);
@@ -1265,12 +1292,12 @@ stt_status stt_form_maps(stt_ctx *c, const stt_spectro *p, int32_t T, const floa
 
 namespace {
 
-template <int WG, int TPT, bool HW, bool DMA>
+template <int WG, int TPT, bool HW, int SC>
 stt_status launch_batch_t(stt_ctx *c, hipStream_t st, const BatchMap *maps, int n_maps, const uint32_t *item_start,
                           uint32_t total_items, uint32_t *queue, const uint32_t *order, int32_t norm, uint64_t *best,
                           size_t shm)
 {
-    auto kern = k_score_batch<WG, TPT, HW, kMapPol, DMA>;
+    auto kern = k_score_batch<WG, TPT, HW, kMapPol, SC>;
     if (shm > 64 * 1024)
         STT_HIP(c, hipFuncSetAttribute((const void *)kern, hipFuncAttributeMaxDynamicSharedMemorySize, (int)shm));
     int per_cu = 0;
@@ -1283,15 +1310,15 @@ stt_status launch_batch_t(stt_ctx *c, hipStream_t st, const BatchMap *maps, int 
     return STT_OK;
 }
 
-template <bool HW, bool DMA>
+template <bool HW, int SC>
 stt_status launch_batch_h(stt_ctx *c, hipStream_t st, const BatchMap *maps, int n_maps, const uint32_t *item_start,
                           uint32_t total_items, uint32_t *queue, const uint32_t *order, int32_t norm, uint64_t *best,
                           size_t shm)
 {
-#define STT_BATCH_CASE(W, P)                                                                                    \
-    if (c->slab_wg == W && c->slab_tpt == P)                                                                    \
-        return launch_batch_t<W, P, HW, DMA>(c, st, maps, n_maps, item_start, total_items, queue, order, norm, best, \
-                                             shm);
+#define STT_BATCH_CASE(W, P)                                                                                   \
+    if (c->slab_wg == W && c->slab_tpt == P)                                                                   \
+        return launch_batch_t<W, P, HW, SC>(c, st, maps, n_maps, item_start, total_items, queue, order, norm, best, \
+                                            shm);
     STT_BATCH_CASE(1024, 4)
     STT_BATCH_CASE(512, 4)
     STT_BATCH_CASE(256, 4)
@@ -1388,6 +1415,10 @@ stt_status stt_score_batch(stt_ctx *c, const stt_map *maps_host, int32_t n_maps,
     }
     std::vector<FoldJob> jobs(n_maps + 1);
     shm = 0;
+    // one aligned slab width for the whole batch: the narrowest any map's columns allow
+    int sc_all = 16;
+    if (dma_ok)
+        for (int i = 0; i < n_maps; ++i) sc_all = std::min(sc_all, aligned_slab(dma_slab_cols(c, fold_ld(bm[i].m.F))));
     for (int i = 0; i < n_maps; ++i) {
         BatchMap &d = bm[i];
         const int64_t ldc = fold_ld(d.m.F);
@@ -1397,7 +1428,7 @@ stt_status stt_score_batch(stt_ctx *c, const stt_map *maps_host, int32_t n_maps,
         d.m.ld = ldc;
         d.m.scale = 1.0f;
         if (dma_ok) {
-            d.S = std::min(dma_slab_cols(c, ldc), d.m.T);
+            d.S = sc_all;
             shm = std::max(shm, 2 * sizeof(float2) * (size_t)d.S * (size_t)ldc);
         } else {
             shm = std::max(shm, sizeof(float2) * (size_t)d.S * (size_t)d.m.F);
@@ -1427,6 +1458,7 @@ stt_status stt_score_batch(stt_ctx *c, const stt_map *maps_host, int32_t n_maps,
     key_add(key, c->lds_bytes);
     key_add(key, c->hw_trig);
     key_add(key, dma_ok);
+    key_add(key, sc_all);
     key_add(key, c->pbuf);
     for (const auto &d : bm) key_add(key, d);
     for (const auto &o : orig) key_add(key, o);
@@ -1490,16 +1522,22 @@ stt_status stt_score_batch(stt_ctx *c, const stt_map *maps_host, int32_t n_maps,
             }
             stt_status r;
             const uint32_t ni = (uint32_t)nitems;
-            if (dma_ok)
-                r = c->hw_trig ? launch_batch_h<true, true>(c, st, dmaps, n_maps, ditem, ni, queue, order, norm,
-                                                            best_key_per_map_dev, shm)
-                               : launch_batch_h<false, true>(c, st, dmaps, n_maps, ditem, ni, queue, order, norm,
-                                                             best_key_per_map_dev, shm);
-            else
-                r = c->hw_trig ? launch_batch_h<true, false>(c, st, dmaps, n_maps, ditem, ni, queue, order, norm,
-                                                             best_key_per_map_dev, shm)
-                               : launch_batch_h<false, false>(c, st, dmaps, n_maps, ditem, ni, queue, order, norm,
-                                                              best_key_per_map_dev, shm);
+            const int sc = dma_ok ? sc_all : 0;
+#define STT_BATCH_SC(SCV)                                                                                      \
+    r = c->hw_trig ? launch_batch_h<true, SCV>(c, st, dmaps, n_maps, ditem, ni, queue, order, norm,            \
+                                               best_key_per_map_dev, shm)                                     \
+                   : launch_batch_h<false, SCV>(c, st, dmaps, n_maps, ditem, ni, queue, order, norm,           \
+                                                best_key_per_map_dev, shm)
+            switch (sc) {
+            case 0: STT_BATCH_SC(0); break;
+            case 1: STT_BATCH_SC(1); break;
+            case 2: STT_BATCH_SC(2); break;
+            case 4: STT_BATCH_SC(4); break;
+            case 8: STT_BATCH_SC(8); break;
+            case 16: STT_BATCH_SC(16); break;
+            default: r = fail(c, STT_EUNSUPPORTED, "no batch scorer for %d-column slabs", sc);
+            }
+#undef STT_BATCH_SC
             if (timed) ev_record(c, 1);
             return r;
         };
