@@ -63,7 +63,8 @@ typedef int32_t stt_status;
 #define STT_NORM_N 1
 
 #define STT_C64F32 0 /* Y: complex64 (re, im float32 interleaved); sigma: float32 */
-#define STT_P16 1    /* Y: the complex SNR p = Y/sigma as FP16 (re, im) pairs, p = stored * 2^scale_exp;
+#define STT_P16 1    /* Y: the complex SNR p = Y/sigma in FP16 polar form, one 32-bit word per pixel: arg p in
+                        units of 2^-16 turn in the low half, |p| * 2^-scale_exp as binary16 in the high half;
                         sigma: NULL (see stt_map_pack_p16) */
 
 #define STT_FBITS 8        /* fractional bits of control frequencies */
@@ -100,8 +101,8 @@ typedef struct {
     int32_t T, F;         /* columns, rows */
     int64_t ld;           /* elements between columns, ld >= F */
     int32_t dtype;        /* STT_C64F32 or STT_P16 */
-    int32_t scale_exp;    /* STT_P16 only: p = stored * 2^scale_exp */
-    const void *Y;        /* device: [T][ld] complex (complex64, or FP16 pairs for STT_P16) */
+    int32_t scale_exp;    /* STT_P16 only: |p| = stored magnitude * 2^scale_exp */
+    const void *Y;        /* device: [T][ld] complex64, or 32-bit polar words for STT_P16 */
     const void *sigma;    /* device: [T][ld] float32 sigma (STT_C64F32); NULL for STT_P16 */
     int32_t fq4_lo;       /* frequency of row 0 in 1/16 Hz (1600 = 100 Hz) */
     int32_t dfq4;         /* row spacing in 1/16 Hz (16 = 1 Hz) */
@@ -148,13 +149,13 @@ stt_status stt_set_path(stt_ctx *ctx, int32_t path, int32_t lds_bytes);
  * 1024x2, 512x2). Default 1024x4. */
 stt_status stt_set_slab_shape(stt_ctx *ctx, int32_t wg, int32_t tpt);
 
-/* Slab staging. Every scoring call first folds p (Y/sigma of an FP32 map, or
- * the exact FP32 values of an FP16 map) into a context-owned polar copy of the
- * map: |p| as float32 and arg p as a 32-bit fraction of a turn, 8 bytes per
- * pixel, columns padded to 128 pixels. dma = 1 (default) streams slabs of it
- * into two LDS buffers with direct global-to-LDS copies, overlapping the next
- * slab with the current one; dma = 0 stages through registers into one buffer.
- * Scores are identical. */
+/* Slab staging. Every scoring call first folds the map into a context-owned
+ * copy with columns padded to whole 1 KB pieces: an FP32 map as p = Y/sigma in
+ * polar form (|p| as float32, arg p as a 32-bit fraction of a turn, 8 bytes per
+ * pixel), an FP16 map as its own 4-byte words. dma = 1 (default) streams slabs
+ * of it into two LDS buffers with direct global-to-LDS copies, overlapping the
+ * next slab with the current one; dma = 0 stages through registers into one
+ * buffer. Scores are identical. */
 stt_status stt_set_staging(stt_ctx *ctx, int32_t dma);
 
 /* Phase-factor evaluation: hw = 1 (default) the hardware sine/cosine
@@ -322,14 +323,20 @@ stt_status stt_argmax(stt_ctx *ctx, const float *snr_dev, int64_t n, int64_t fir
                       uint64_t *best_key_dev);
 
 /* FP16 storage of a map (a precision addition; the paper states no
- * precision). Packs an STT_C64F32 map into out_dev, [T][out_ld] FP16 pairs
- * (4 bytes per pixel, caller-owned, out_ld >= F): p = Y/sigma is formed in
- * FP32 with a correctly rounded division, scaled by 2^-e and rounded to
- * binary16 to nearest even, where e = ceil(log2(max |Re p|, |Im p|)) - 15
- * keeps every value below 2^15. Writes e to *scale_exp (host). Synchronises
- * the stream (the exponent is read back); STT_EINVAL if the map holds a
- * non-finite value. The packed map is used as stt_map{dtype = STT_P16,
- * Y = out_dev, sigma = NULL, scale_exp = e, ld = out_ld}. */
+ * precision). Packs an STT_C64F32 map into out_dev, [T][out_ld] 32-bit words
+ * (4 bytes per pixel, caller-owned, out_ld >= F), each the complex SNR
+ * p = Y/sigma (formed in FP32 with a correctly rounded division) in polar
+ * form: the magnitude |p| (FP64) scaled by 2^-e and rounded to binary16 to
+ * nearest even in the high half, e = ceil(log2(max |p|)) - 15 keeping every
+ * scaled magnitude at most 2^15; the argument atan2(Im p, Re p) as a fraction
+ * of a turn rounded to the nearest multiple of 2^-16 (ties to even, modulo one
+ * turn) in the low half. |p| keeps 11 significant bits and arg p is within
+ * pi 2^-16 rad, so |stored - p| <= (2^-11 + pi 2^-16) |p|: the precision of
+ * binary16 (re, im) pairs, in a form whose phase adds to Eq. 8's exactly (the
+ * scorers take one cosine per pixel). Writes e to *scale_exp (host).
+ * Synchronises the stream (the exponent is read back); STT_EINVAL if the map
+ * holds a non-finite value. The packed map is used as stt_map{dtype =
+ * STT_P16, Y = out_dev, sigma = NULL, scale_exp = e, ld = out_ld}. */
 stt_status stt_map_pack_p16(stt_ctx *ctx, const stt_map *map, void *out_dev, int64_t out_ld, int32_t *scale_exp);
 
 /* The K best scores of snr_dev[0..n) (Sec. V's follow-up of the loudest

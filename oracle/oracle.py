@@ -7,6 +7,7 @@ doubles, sigma -> doubles (exact widening of FP32 inputs).
 from __future__ import annotations
 
 import ctypes as C
+import math
 import os
 
 import numpy as np
@@ -344,19 +345,30 @@ def theta_to_track(theta, T: int, F: int, L: int, dtau_max: int) -> np.ndarray:
 
 
 def quantize_p16(Y: np.ndarray, sigma: np.ndarray):
-    """FP16 storage of the complex SNR p = Y/sigma with a per-map power-of-two scale.
+    """FP16 storage of the complex SNR p = Y/sigma: 32 bits per pixel in polar form, with a per-map
+    power-of-two scale.
 
-    p is formed in FP32 (correctly rounded division), the exponent e makes the
-    largest |component| of p * 2^-e at most 2^15, each component is rounded to
-    binary16 (round to nearest even, numpy's conversion). Returns (stored
-    complex float16 pairs as a [T][F][2] float16 array, e, dequantised p as
-    complex128).
+    p is formed in FP32 (correctly rounded division). Its magnitude |p| (FP64, from the exact squares
+    of the FP32 components: one rounding of the sum, one of the square root) is multiplied by 2^-e,
+    e = ceil(log2(max |p|)) - 15 so that every scaled magnitude is at most 2^15, and rounded to
+    binary16 (round to nearest even, straight from FP64: numpy's conversion). Its argument
+    atan2(Im p, Re p) / (2 pi), a fraction of a turn, is rounded to the nearest multiple of 2^-16
+    (ties to even) modulo one turn. Returns (the stored halves as a [T][F][2] uint16 array: [..., 0]
+    the argument in units of 2^-16 turn, [..., 1] the binary16 bits of the scaled magnitude; e;
+    the dequantised p = magnitude * 2^e * exp(2 pi i argument) as complex128).
     """
     pr = (Y.real.astype(np.float32) / sigma.astype(np.float32)).astype(np.float32)
     pi = (Y.imag.astype(np.float32) / sigma.astype(np.float32)).astype(np.float32)
-    amax = float(max(np.abs(pr).max(initial=0.0), np.abs(pi).max(initial=0.0)))
-    e = (int(np.ceil(np.log2(amax))) - 15) if amax > 0 else 0
-    sc = np.float32(2.0 ** -e)
-    q = np.stack([(pr * sc).astype(np.float16), (pi * sc).astype(np.float16)], axis=-1)
-    deq = (q[..., 0].astype(np.float64) + 1j * q[..., 1].astype(np.float64)) * 2.0 ** e
+    x, y = pr.astype(np.float64), pi.astype(np.float64)
+    mag = np.sqrt(x * x + y * y)
+    amax = float(mag.max(initial=0.0))
+    e = 0
+    if amax > 0:
+        fr, k = math.frexp(amax)  # amax = fr * 2^k, fr in [1/2, 1): ceil(log2 amax) is k, or k - 1 at fr = 1/2
+        e = (k if fr > 0.5 else k - 1) - 15
+    mag16 = (mag * 2.0 ** -e).astype(np.float16)
+    turns = np.arctan2(y, x) * 0.15915494309189535  # 1 / (2 pi), rounded
+    arg16 = (np.rint(turns * 65536.0).astype(np.int64) & 0xFFFF).astype(np.uint16)
+    q = np.stack([arg16, mag16.view(np.uint16)], axis=-1)
+    deq = mag16.astype(np.float64) * 2.0 ** e * np.exp(2j * np.pi * (arg16.astype(np.float64) / 65536.0))
     return q, e, deq

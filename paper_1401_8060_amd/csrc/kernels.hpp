@@ -32,28 +32,56 @@ struct MapP {
     float scale;       // FP16 map: p = stored * scale (a power of two)
 };
 
-// Map element formats: the caller's (Y, sigma) FP32 map, the FP16 p map,
-// p = Y/sigma folded into complex64 by k_fold_p (read by the smooth statistic),
-// and p folded into polar form by k_fold_polar (read by every scorer of Eq. 8):
-// |p| as FP32 and arg p as a 32-bit fraction of a turn, 8 bytes per pixel.
-// Folded maps pad columns to a multiple of 128 pixels so that slabs can be
-// copied into LDS in 1 KB pieces.
-enum : int { kMapF32 = 0, kMapP16 = 1, kMapPF = 2, kMapPol = 3 };
-constexpr int kDmaPix = 128;  // pixels one wave moves per LDS-DMA instruction (64 lanes x 16 B)
+// Map element formats: the caller's (Y, sigma) FP32 map; the caller's FP16 map
+// (one 32-bit word per pixel: arg p in 2^-16 turn in the low half, |p| * 2^-e
+// as binary16 in the high half); p = Y/sigma folded into complex64 by k_fold_p
+// (read by the smooth statistic); p folded into polar form by k_fold_polar
+// (read by every scorer of Eq. 8 on an FP32 map): |p| as FP32 and arg p as a
+// 32-bit fraction of a turn, 8 bytes per pixel; and the FP16 map's words copied
+// into the folded layout (read by every scorer on an FP16 map), 4 bytes per
+// pixel. Folded maps pad columns to whole 1 KB pieces (128 or 256 pixels) so
+// that slabs can be copied into LDS by 1 KB LDS-DMA instructions.
+enum : int { kMapF32 = 0, kMapP16 = 1, kMapPF = 2, kMapPol = 3, kMapPolH = 4 };
+constexpr int kDmaBytes = 1024;  // bytes one wave moves per LDS-DMA instruction (64 lanes x 16 B)
+
+// Element type of a map format in registers and LDS.
+template <int MAPT> struct ElemOf { using type = float2; };
+template <> struct ElemOf<kMapPolH> { using type = uint32_t; };
+template <int MAPT> using elem_t = typename ElemOf<MAPT>::type;
+template <int MAPT> constexpr int kDmaPix = kDmaBytes / (int)sizeof(elem_t<MAPT>);  // pixels per 1 KB piece
+
+// binary16 bits of the high half of a word, as FP32 (exact)
+__device__ __forceinline__ float half_hi(uint32_t w)
+{
+    return __half2float(__ushort_as_half((unsigned short)(w >> 16)));
+}
 
 // The complex SNR p = Y/sigma of pixel element e (Eq. 7 with the appendix's rho = Y/sigma).
+// FP16 map: |p| 2^e exp(2 pi i arg) evaluated in FP64 and rounded once per component.
 template <int MAPT>
 __device__ __forceinline__ float2 load_p(const MapP &m, int64_t e)
 {
-    if (MAPT == kMapP16) {
-        const __half2 h = reinterpret_cast<const __half2 *>(m.Y)[e];
-        const float2 f = __half22float2(h);
-        return make_float2(f.x * m.scale, f.y * m.scale);
+    if constexpr (MAPT == kMapP16) {
+        const uint32_t w = reinterpret_cast<const uint32_t *>(m.Y)[e];
+        const double mag = (double)half_hi(w) * (double)m.scale;
+        double sn, cs;
+        sincospi((double)(w & 0xFFFFu) * (1.0 / 32768.0), &sn, &cs);
+        return make_float2((float)(mag * cs), (float)(mag * sn));
+    } else if constexpr (MAPT == kMapPF || MAPT == kMapPol) {
+        return m.Y[e];  // (a polar map's element is returned as stored)
+    } else {
+        const float2 y = m.Y[e];
+        const float w = 1.0f / m.sig[e];
+        return make_float2(y.x * w, y.y * w);
     }
-    if (MAPT == kMapPF || MAPT == kMapPol) return m.Y[e];  // (a polar map's element is returned as stored)
-    const float2 y = m.Y[e];
-    const float w = 1.0f / m.sig[e];
-    return make_float2(y.x * w, y.y * w);
+}
+
+// One element of a map as its scorers hold it: a word of a folded FP16 map, p otherwise.
+template <int MAPT>
+__device__ __forceinline__ elem_t<MAPT> load_e(const MapP &m, int64_t e)
+{
+    if constexpr (MAPT == kMapPolH) return reinterpret_cast<const uint32_t *>(m.Y)[e];
+    else return load_p<MAPT>(m, e);
 }
 
 // p of every pixel into a complex64 map with column stride ld_out (pixels
@@ -96,19 +124,31 @@ __global__ __launch_bounds__(256) void k_fold_polar(MapP m, float2 *out, int64_t
     }
 }
 
-// One polar fold of a batch: map src into dst (column stride ld_out); its pixels are px0 ..
-// px0 + T*ld_out - 1 of the batch's run (px0 ascending over the maps).
+// The words of an FP16 map into the folded layout (column stride ld_out, pixels F..ld_out-1 zero).
+__global__ __launch_bounds__(256) void k_fold_words(MapP m, uint32_t *out, int64_t ld_out)
+{
+    const int64_t n = (int64_t)m.T * ld_out;
+    const uint32_t *w = reinterpret_cast<const uint32_t *>(m.Y);
+    for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < n; i += (int64_t)gridDim.x * 256) {
+        const int64_t t = i / ld_out, r = i - t * ld_out;
+        out[i] = r < m.F ? w[t * m.ld + r] : 0u;
+    }
+}
+
+// One fold of a batch: map src into dst (column stride ld_out); its pixels are px0 .. px0 +
+// T*ld_out - 1 of the batch's run (px0 ascending over the maps).
 struct FoldJob {
     MapP src;
-    float2 *dst;
+    void *dst;
     int64_t ld_out;
     uint64_t px0;
 };
 
 // Every map of a batch in one launch: the grid strides over the batch's pixel run and finds
-// each pixel's map by bisection of px0 (jobs[n_jobs].px0 = the total).
+// each pixel's map by bisection of px0 (jobs[n_jobs].px0 = the total). FP32 maps fold to polar
+// form (k_fold_polar), FP16 maps copy their words (k_fold_words).
 template <int MAPT>
-__global__ __launch_bounds__(256) void k_fold_polar_batch(const FoldJob *jobs, int n_jobs)
+__global__ __launch_bounds__(256) void k_fold_batch(const FoldJob *jobs, int n_jobs)
 {
     const uint64_t total = jobs[n_jobs].px0;
     for (uint64_t i = (uint64_t)blockIdx.x * 256 + threadIdx.x; i < total; i += (uint64_t)gridDim.x * 256) {
@@ -120,7 +160,12 @@ __global__ __launch_bounds__(256) void k_fold_polar_batch(const FoldJob *jobs, i
         const FoldJob &j = jobs[lo];
         const int64_t k = (int64_t)(i - j.px0);
         const int64_t t = k / j.ld_out, r = k - t * j.ld_out;
-        j.dst[k] = r < j.src.F ? polar_of(load_p<MAPT>(j.src, t * j.src.ld + r)) : make_float2(0.0f, 0.0f);
+        if constexpr (MAPT == kMapP16) {
+            ((uint32_t *)j.dst)[k] = r < j.src.F ? reinterpret_cast<const uint32_t *>(j.src.Y)[t * j.src.ld + r] : 0u;
+        } else {
+            ((float2 *)j.dst)[k] =
+                r < j.src.F ? polar_of(load_p<MAPT>(j.src, t * j.src.ld + r)) : make_float2(0.0f, 0.0f);
+        }
     }
 }
 
@@ -170,8 +215,10 @@ __device__ __forceinline__ void merge_key(uint64_t *best, uint64_t key)
     if (best && (threadIdx.x & 63) == 0 && key) atomicMax((unsigned long long *)best, (unsigned long long)key);
 }
 
-__device__ __forceinline__ float finish(double S, int32_t N, int32_t norm)
+// z of a template from its FP64 sum S of terms in units of `scale` (2^e of an FP16 map, else 1).
+__device__ __forceinline__ float finish(double S, int32_t N, int32_t norm, float scale)
 {
+    S *= (double)scale;
     return (float)(norm == 1 ? S / (double)N : S / sqrt((double)N));
 }
 
@@ -208,23 +255,30 @@ __device__ __forceinline__ float add_term(float part, const PhaseK &k, int32_t r
 // arg p)). The two phases add exactly in 32-bit turns, so one cosine and one fused multiply-add
 // replace the sine, the cosine and the two products of the Cartesian form. HW: the hardware cosine
 // of the sum rounded once to FP32 turns; HW = false: the polynomial of rot_re.
-template <bool HW>
-__device__ __forceinline__ float add_term_pol(float part, const PhaseK &k, int32_t row, float2 pp)
+// Polar elements: (|p|, arg p) of an FP32 map's fold, or an FP16 map's word (|p| 2^-e and arg p
+// in 2^-16 turn, which shifted left by 16 is the same 32-bit fraction of a turn, exactly).
+__device__ __forceinline__ float pol_mag(float2 v) { return v.x; }
+__device__ __forceinline__ uint32_t pol_arg(float2 v) { return __float_as_uint(v.y); }
+__device__ __forceinline__ float pol_mag(uint32_t w) { return half_hi(w); }
+__device__ __forceinline__ uint32_t pol_arg(uint32_t w) { return w << 16; }
+
+template <bool HW, typename E>
+__device__ __forceinline__ float add_term_pol(float part, const PhaseK &k, int32_t row, E v)
 {
-    const uint32_t arg = __float_as_uint(pp.y);
+    const uint32_t arg = pol_arg(v);
     if constexpr (HW) {
         const float x = phase_turns(k.pa + arg, k.pb, row);
-        return fmaf(__builtin_amdgcn_cosf(x), pp.x, part);
+        return fmaf(__builtin_amdgcn_cosf(x), pol_mag(v), part);
     } else {
-        return part + rot_re(k.pa + arg + (uint32_t)row * k.pb, pp.x, 0.0f);
+        return part + rot_re(k.pa + arg + (uint32_t)row * k.pb, pol_mag(v), 0.0f);
     }
 }
 
 // The Eq. 8 term of one pixel element of map format MAPT (polar or Cartesian).
 template <bool HW, int MAPT>
-__device__ __forceinline__ float add_term_m(float part, const PhaseK &k, int32_t row, float2 v)
+__device__ __forceinline__ float add_term_m(float part, const PhaseK &k, int32_t row, elem_t<MAPT> v)
 {
-    if constexpr (MAPT == kMapPol) return add_term_pol<HW>(part, k, row, v);
+    if constexpr (MAPT == kMapPol || MAPT == kMapPolH) return add_term_pol<HW>(part, k, row, v);
     else return add_term<HW>(part, k, row, v);
 }
 
@@ -263,13 +317,13 @@ __global__ __launch_bounds__(kWG) void k_score_direct(MapP m, GenP g, const Trk 
             float part = 0.0f;
             for (int32_t k = 0; k < N; ++k) {
                 const int32_t row = ddaf_row(s);
-                const float2 p = load_p<MAPT>(m, base + row);
+                const elem_t<MAPT> p = load_e<MAPT>(m, base + row);
                 part = add_term_m<HW, MAPT>(part, pk, row, p);
                 if (((t.t0 + k) & (kFlush - 1)) == kFlush - 1) { acc += part; part = 0.0f; }
                 ddaf_step(s);
                 base += m.ld;
             }
-            z = finish(acc + part, N, norm);
+            z = finish(acc + part, N, norm, m.scale);
         }
         if (snr) snr[i] = z;
         key = key_encode(z, (uint32_t)(first + (uint64_t)i));
@@ -312,7 +366,7 @@ __global__ __launch_bounds__(256) void k_score_wave(MapP m, GenP g, const Trk *t
                 float part = 0.0f;
                 for (int c = ca; c <= cb; ++c) {
                     const int32_t row = ddaf_row(s);
-                    part = add_term_m<HW, MAPT>(part, pk, row, load_p<MAPT>(m, base + row));
+                    part = add_term_m<HW, MAPT>(part, pk, row, load_e<MAPT>(m, base + row));
                     ddaf_step(s);
                     base += m.ld;
                 }
@@ -330,7 +384,7 @@ __global__ __launch_bounds__(256) void k_score_wave(MapP m, GenP g, const Trk *t
                     acc += __builtin_bit_cast(float, __builtin_amdgcn_readlane(__builtin_bit_cast(int, gp[r]), l));
             }
             if ((t.t2 & (kFlush - 1)) == kFlush - 1) acc = acc + 0.0f;
-            z = finish(acc, t.t2 - t.t0 + 1, norm);
+            z = finish(acc, t.t2 - t.t0 + 1, norm, m.scale);
         }
         if (lane == 0 && snr) snr[i] = z;
         key = key_encode(z, (uint32_t)(first + (uint64_t)i));
@@ -501,7 +555,7 @@ __device__ __forceinline__ void lds_dma_16(const float2 *src, float2 *lds_dst)
 // templates of this lane. MASK = false is the wave's core, where every
 // template of the wave covers every column: no select and no clamp.
 template <int TPT, bool MASK, bool HW, int MAPT>
-__device__ __forceinline__ void walk(int ca, int cb, int c0, const float2 *slab, int ldc, const int32_t (&t0)[TPT],
+__device__ __forceinline__ void walk(int ca, int cb, int c0, const elem_t<MAPT> *slab, int ldc, const int32_t (&t0)[TPT],
                                      const uint32_t (&span)[TPT], const PhaseK (&pk)[TPT], DdaF (&st)[TPT],
                                      float (&part)[TPT], double (&acc)[TPT])
 {
@@ -509,7 +563,7 @@ __device__ __forceinline__ void walk(int ca, int cb, int c0, const float2 *slab,
     for (int c = ca; c <= cb;) {
         const int ce = min(cb, c | (kFlush - 1));
         for (; c <= ce; ++c) {
-            const float2 *col = slab + (c - c0) * ldc;
+            const elem_t<MAPT> *col = slab + (c - c0) * ldc;
 #pragma unroll
             for (int q = 0; q < TPT; ++q) {
                 const int32_t row = ddaf_row(st[q]);
@@ -538,13 +592,13 @@ __device__ __forceinline__ void walk(int ca, int cb, int c0, const float2 *slab,
 // columns x TPT templates. MASK = false when every template of the wave covers
 // every column of the slab.
 template <int SC, int TPT, bool MASK, bool HW, int SM>
-__device__ __forceinline__ void walk_slab(int c0, const float2 *slab, int ldc, const int32_t (&t0)[TPT],
+__device__ __forceinline__ void walk_slab(int c0, const elem_t<SM> *slab, int ldc, const int32_t (&t0)[TPT],
                                           const uint32_t (&span)[TPT], const PhaseK (&pk)[TPT], DdaF (&st)[TPT],
                                           float (&part)[TPT])
 {
 #pragma unroll
     for (int j = 0; j < SC; ++j) {
-        const float2 *col = slab + j * ldc;
+        const elem_t<SM> *col = slab + j * ldc;
 #pragma unroll
         for (int q = 0; q < TPT; ++q) {
             const int32_t row = ddaf_row(st[q]);
@@ -561,28 +615,33 @@ __device__ __forceinline__ void walk_slab(int c0, const float2 *slab, int ldc, c
 }
 
 // One block of WG*TPT consecutive entries of `order` (block index b): the
-// whole slab sweep for those templates. slab is the dynamic LDS (S*F float2),
-// bnd two LDS ints. Callable repeatedly by a persistent workgroup.
-// SC > 0: a folded map (kMapPol or kMapPF: 8 bytes per pixel, columns padded
-// to kDmaPix) is staged with LDS DMA into two slab buffers of SC columns
-// (double buffering: slab k+1 streams in while slab k is walked). Slabs are
-// aligned to multiples of SC on the absolute column grid, so the FP32 partial
-// sums are flushed between slabs and a slab is one straight-line walk_slab;
-// each wave starts its rows at its first aligned column (columns before a
-// template's start and after its end are masked, so the extra columns change
-// nothing). SC = 0: the lanes stage S columns through registers into one
-// buffer (unfolded formats are converted to Cartesian p on the way; a polar
+// whole slab sweep for those templates. slab is the dynamic LDS, bnd two LDS
+// ints. Callable repeatedly by a persistent workgroup. Templates are drawn
+// (tr == NULL) or read from tr and validated.
+// SC > 0: a folded map (kMapPol: 8 bytes per pixel, kMapPolH: 4 bytes; columns
+// padded to whole 1 KB pieces) is staged with LDS DMA into two slab buffers of
+// SC columns (double buffering: slab k+1 streams in while slab k is walked).
+// Slabs are aligned to multiples of SC on the absolute column grid, so the FP32
+// partial sums are flushed between slabs and a slab is one straight-line
+// walk_slab; each wave starts its rows at its first aligned column (columns
+// before a template's start and after its end are masked, so the extra columns
+// change nothing). SC = 0: the lanes stage S columns through registers into one
+// buffer (unfolded formats are converted to Cartesian p on the way; a folded
 // map is copied as it is) and walk them column by column.
-template <int WG, int TPT, bool EXPL, bool HW, int MAPT, int SC>
+template <int WG, int TPT, bool HW, int MAPT, int SC>
 __device__ __forceinline__ uint64_t score_block(const MapP &m, const GenP &g, const Trk *tr, const uint32_t *order,
                                                 uint64_t first, int64_t n, int64_t b, int S, int32_t norm, float *snr,
-                                                float2 *slab, int *bnd, uint64_t *kred)
+                                                float2 *slab_raw, int *bnd, uint64_t *kred)
 {
+    // element format of the slab: the map's own for the folded formats, p in Cartesian form otherwise
+    constexpr int SM = (MAPT == kMapPol || MAPT == kMapPolH) ? MAPT : kMapPF;
+    using E = elem_t<SM>;
     __syncthreads();  // LDS of a previous block is no longer read
     if (threadIdx.x == 0) { bnd[0] = 0x7fffffff; bnd[1] = -1; }
 
     const int lane = threadIdx.x & 63;
     const int64_t wbase = b * (WG * TPT) + (int64_t)(threadIdx.x >> 6) * (64 * TPT);
+    const bool expl = tr != nullptr;
     Trk tk[TPT];
     int32_t t0[TPT];
     uint32_t span[TPT], idx[TPT];
@@ -595,8 +654,8 @@ __device__ __forceinline__ uint64_t score_block(const MapP &m, const GenP &g, co
         const int64_t e = wbase + q * 64 + lane;
         live[q] = e < n;
         idx[q] = live[q] ? order[e] : 0u;
-        Trk t = EXPL ? tr[idx[q]] : draw_track(g, first + idx[q]);
-        ok[q] = live[q] && (!EXPL || track_ok(t, m));
+        Trk t = expl ? tr[idx[q]] : draw_track(g, first + idx[q]);
+        ok[q] = live[q] && (!expl || track_ok(t, m));
         if (!ok[q]) t = Trk{0, 1, 0u, 0u, 0u, 0};  // never active: (c - t0) > span below
         tk[q] = t;
         t0[q] = ok[q] ? t.t0 : 0x7fffffff;
@@ -639,22 +698,21 @@ __device__ __forceinline__ uint64_t score_block(const MapP &m, const GenP &g, co
     __syncthreads();
     const int c_first = __builtin_amdgcn_readfirstlane(bnd[0]), c_last = __builtin_amdgcn_readfirstlane(bnd[1]);
     const int F = m.F;
-    // element format of the slab: the map's own for the folded formats, p in Cartesian form otherwise
-    constexpr int SM = (MAPT == kMapPol) ? kMapPol : kMapPF;
 
     if constexpr (SC > 0) {
         static_assert(kFlush % SC == 0, "slabs must tile the flush grid");
-        // m.ld is a multiple of kDmaPix and the columns are contiguous, so the
-        // slab of columns c0.. is one run of pieces of kDmaPix pixels (1 KB),
-        // piece ch at pixel offset ch * kDmaPix in the map and in the buffer.
-        const int ldc = (int)m.ld, per_col = ldc / kDmaPix;
+        // m.ld is a whole number of 1 KB pieces and the columns are contiguous, so
+        // the slab of columns c0.. is one run of pieces, piece ch at byte offset
+        // 1024 ch in the map and in the buffer (counted below in 8-byte units).
+        const int ldc = (int)m.ld;
+        const int col8 = ldc * (int)sizeof(E) / 8, per_col = col8 / (kDmaBytes / 8);
         const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
         auto issue = [&](int c0, int bsel) {
             const int nchunk = min(SC, c_last - c0 + 1) * per_col;
-            const float2 *src = m.Y + (int64_t)c0 * ldc + lane * 2;
-            float2 *dst = slab + (size_t)bsel * SC * ldc;
+            const float2 *src = m.Y + (int64_t)c0 * col8 + lane * 2;
+            float2 *dst = slab_raw + (size_t)bsel * SC * col8;
             for (int ch = wave; ch < nchunk; ch += WG / 64)
-                lds_dma_16(src + ch * kDmaPix, dst + ch * kDmaPix);
+                lds_dma_16(src + ch * (kDmaBytes / 8), dst + ch * (kDmaBytes / 8));
         };
         const int a_first = c_first & ~(SC - 1);
         // this wave's slabs: from its aligned first column to its last; the core slabs lie in [clo, chi]
@@ -666,7 +724,7 @@ __device__ __forceinline__ uint64_t score_block(const MapP &m, const GenP &g, co
             __syncthreads();                // so have everyone's, and slab k-1 is no longer read
             if (c0 + SC <= c_last) issue(c0 + SC, (k + 1) & 1);
             if (c0 < w_lo || c0 > w_hi) continue;  // wave-uniform
-            const float2 *cur = slab + (size_t)(k & 1) * SC * ldc;
+            const E *cur = reinterpret_cast<const E *>(slab_raw + (size_t)(k & 1) * SC * col8);
             if (c0 >= clo && c0 + SC - 1 <= chi)
                 walk_slab<SC, TPT, false, HW, SM>(c0, cur, ldc, t0, span, pk, st, part);
             else
@@ -680,6 +738,7 @@ __device__ __forceinline__ uint64_t score_block(const MapP &m, const GenP &g, co
             }
         }
     } else {
+        E *slab = reinterpret_cast<E *>(slab_raw);
         // staging walk: element e = tid + i*WG of the slab is (column e / F, row e % F)
         const int dcol = WG / F, drow = WG % F;
         const int col0 = threadIdx.x / F, row0 = threadIdx.x % F;
@@ -691,7 +750,7 @@ __device__ __forceinline__ uint64_t score_block(const MapP &m, const GenP &g, co
                 const int64_t base = (int64_t)c0 * m.ld;
 #pragma unroll 4
                 for (int e = threadIdx.x; e < ncol * F; e += WG) {
-                    slab[col * F + r] = load_p<MAPT>(m, base + (int64_t)col * m.ld + r);
+                    slab[col * F + r] = load_e<MAPT>(m, base + (int64_t)col * m.ld + r);
                     r += drow;
                     col += dcol;
                     if (r >= F) { r -= F; ++col; }
@@ -709,7 +768,7 @@ __device__ __forceinline__ uint64_t score_block(const MapP &m, const GenP &g, co
 #pragma unroll
     for (int q = 0; q < TPT; ++q) {
         if (!live[q]) continue;
-        const float z = ok[q] ? finish(acc[q] + part[q], (int32_t)span[q] + 1, norm) : __builtin_nanf("");
+        const float z = ok[q] ? finish(acc[q] + part[q], (int32_t)span[q] + 1, norm, m.scale) : __builtin_nanf("");
         if (snr) snr[idx[q]] = z;
         const uint64_t k = key_encode(z, (uint32_t)(first + idx[q]));
         key = k > key ? k : key;
@@ -726,7 +785,7 @@ __device__ __forceinline__ uint64_t score_block(const MapP &m, const GenP &g, co
 // One block of binned templates per workgroup. Each workgroup stores its best
 // key in its own slot of wg_keys (no atomics: many same-address atomics from
 // every wave serialise across the chip); k_reduce_keys folds the slots.
-template <int WG, int TPT, bool EXPL, bool HW, int MAPT, int SC>
+template <int WG, int TPT, bool HW, int MAPT, int SC>
 __global__ __launch_bounds__(WG) void k_score_slab(MapP m, GenP g, const Trk *tr, const uint32_t *order,
                                                    uint64_t first, int64_t n, int S, int32_t norm, float *snr,
                                                    uint64_t *wg_keys)
@@ -734,7 +793,7 @@ __global__ __launch_bounds__(WG) void k_score_slab(MapP m, GenP g, const Trk *tr
     extern __shared__ float2 slab[];
     __shared__ int bnd[2];
     __shared__ uint64_t kred[WG / 64];
-    const uint64_t key = score_block<WG, TPT, EXPL, HW, MAPT, SC>(m, g, tr, order, first, n, (int64_t)blockIdx.x,
+    const uint64_t key = score_block<WG, TPT, HW, MAPT, SC>(m, g, tr, order, first, n, (int64_t)blockIdx.x,
                                                                    S, norm, snr, slab, bnd, kred);
     if (threadIdx.x == 0) wg_keys[blockIdx.x] = key;
 }
@@ -800,7 +859,7 @@ __global__ __launch_bounds__(256) void k_score_tm(MapP m, GenP g, const TrkTm *t
                 float part = 0.0f;
                 for (int c = ca; c <= cb; ++c) {
                     const int32_t row = row_tm(k, c - t.t0);
-                    part = add_term_m<HW, MAPT>(part, pk, row, load_p<MAPT>(m, (int64_t)c * m.ld + row));
+                    part = add_term_m<HW, MAPT>(part, pk, row, load_e<MAPT>(m, (int64_t)c * m.ld + row));
                 }
                 gp[r] = part;
             }
@@ -813,7 +872,7 @@ __global__ __launch_bounds__(256) void k_score_tm(MapP m, GenP g, const TrkTm *t
                     acc += __builtin_bit_cast(float, __builtin_amdgcn_readlane(__builtin_bit_cast(int, gp[r]), l));
             }
             if ((t.t2 & (kFlush - 1)) == kFlush - 1) acc = acc + 0.0f;
-            z = finish(acc, t.t2 - t.t0 + 1, norm);
+            z = finish(acc, t.t2 - t.t0 + 1, norm, m.scale);
         }
         if (lane == 0 && snr) snr[i] = z;
         key = key_encode(z, (uint32_t)(first + (uint64_t)i));
@@ -822,15 +881,15 @@ __global__ __launch_bounds__(256) void k_score_tm(MapP m, GenP g, const TrkTm *t
 }
 
 // Column walk of the free-t_mid slab scorer (as walk, with an independent row per column).
-template <int TPT, bool MASK, bool HW>
-__device__ __forceinline__ void walk_tm(int ca, int cb, int c0, const float2 *slab, int ldc, const int32_t (&t0)[TPT],
+template <int TPT, bool MASK, bool HW, typename E>
+__device__ __forceinline__ void walk_tm(int ca, int cb, int c0, const E *slab, int ldc, const int32_t (&t0)[TPT],
                                         const uint32_t (&span)[TPT], const RowTm (&rk)[TPT],
                                         const PhaseK (&pk)[TPT], float (&part)[TPT], double (&acc)[TPT])
 {
     for (int c = ca; c <= cb;) {
         const int ce = min(cb, c | (kFlush - 1));
         for (; c <= ce; ++c) {
-            const float2 *col = slab + (c - c0) * ldc;
+            const E *col = slab + (c - c0) * ldc;
 #pragma unroll
             for (int q = 0; q < TPT; ++q) {
                 const int32_t dt = c - t0[q];
@@ -850,7 +909,7 @@ __device__ __forceinline__ void walk_tm(int ca, int cb, int c0, const float2 *sl
     }
 }
 
-template <int WG, int TPT, bool HW>
+template <int WG, int TPT, bool HW, int MAPT>
 __global__ __launch_bounds__(WG) void k_score_tm_slab(MapP m, GenP g, const uint32_t *order, uint64_t first,
                                                       int64_t n, int S, int32_t norm, float *snr, uint64_t *wg_keys)
 {
@@ -903,13 +962,16 @@ __global__ __launch_bounds__(WG) void k_score_tm_slab(MapP m, GenP g, const uint
     }
     __syncthreads();
     const int c_first = __builtin_amdgcn_readfirstlane(bnd[0]), c_last = __builtin_amdgcn_readfirstlane(bnd[1]);
-    const int ldc = (int)m.ld, per_col = ldc / kDmaPix;
+    using E = elem_t<MAPT>;
+    const int ldc = (int)m.ld;
+    const int col8 = ldc * (int)sizeof(E) / 8, per_col = col8 / (kDmaBytes / 8);  // 8-byte units per column
     const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
     auto issue = [&](int c0, int bsel) {
         const int nchunk = min(S, c_last - c0 + 1) * per_col;
-        const float2 *src = m.Y + (int64_t)c0 * ldc + lane * 2;
-        float2 *dst = slab + (size_t)bsel * S * ldc;
-        for (int ch = wave; ch < nchunk; ch += WG / 64) lds_dma_16(src + ch * kDmaPix, dst + ch * kDmaPix);
+        const float2 *src = m.Y + (int64_t)c0 * col8 + lane * 2;
+        float2 *dst = slab + (size_t)bsel * S * col8;
+        for (int ch = wave; ch < nchunk; ch += WG / 64)
+            lds_dma_16(src + ch * (kDmaBytes / 8), dst + ch * (kDmaBytes / 8));
     };
     if (c_first <= c_last) issue(c_first, 0);
     int kk = 0;
@@ -917,7 +979,7 @@ __global__ __launch_bounds__(WG) void k_score_tm_slab(MapP m, GenP g, const uint
         __builtin_amdgcn_s_waitcnt(0);  // this wave's copies of slab kk have landed
         __syncthreads();                // so have everyone's, and slab kk-1 is no longer read
         if (c0 + S <= c_last) issue(c0 + S, (kk + 1) & 1);
-        const float2 *cur = slab + (size_t)(kk & 1) * S * ldc;
+        const E *cur = reinterpret_cast<const E *>(slab + (size_t)(kk & 1) * S * col8);
         const int ncol = min(S, c_last - c0 + 1);
         const int ca = max(c0, lo), cb = min(c0 + ncol - 1, hi);
         walk_tm<TPT, true, HW>(ca, min(cb, clo - 1), c0, cur, ldc, t0, span, rk, pk, part, acc);
@@ -928,7 +990,7 @@ __global__ __launch_bounds__(WG) void k_score_tm_slab(MapP m, GenP g, const uint
 #pragma unroll
     for (int q = 0; q < TPT; ++q) {
         if (!live[q]) continue;
-        const float z = finish(acc[q] + part[q], (int32_t)span[q] + 1, norm);
+        const float z = finish(acc[q] + part[q], (int32_t)span[q] + 1, norm, m.scale);
         if (snr) snr[idx[q]] = z;
         const uint64_t k = key_encode(z, (uint32_t)(first + idx[q]));
         key = k > key ? k : key;
@@ -977,12 +1039,13 @@ __device__ __forceinline__ DelayGrid delay_grid(const MapP &m, int32_t d0, int32
 }
 
 // Adds the template's Eq. 8 terms at `row` for all kMD delays of the launch.
-template <bool HW, bool MASK>
-__device__ __forceinline__ void add_terms_md(float (&part)[kMD], const DelayGrid &dg, int32_t row, float2 pp, bool act)
+template <bool HW, bool MASK, typename E>
+__device__ __forceinline__ void add_terms_md(float (&part)[kMD], const DelayGrid &dg, int32_t row, E pp, bool act)
 {
     const float v0 = add_term_pol<HW>(part[0], dg.k0, row, pp);
     part[0] = !MASK || act ? v0 : part[0];
-    const uint32_t arg = __float_as_uint(pp.y);
+    const uint32_t arg = pol_arg(pp);
+    const float mag = pol_mag(pp);
     float c, s, cr, sr;
     if constexpr (HW) {
         const float x0 = phase_turns(dg.k0.pa + arg, dg.k0.pb, row), xr = phase_turns(dg.dk.pa, dg.dk.pb, row);
@@ -1002,7 +1065,7 @@ __device__ __forceinline__ void add_terms_md(float (&part)[kMD], const DelayGrid
         const float cn = fmaf(c, cr, -s * sr), sn = fmaf(s, cr, c * sr);
         c = cn;
         s = sn;
-        const float v = fmaf(c, pp.x, part[k]);
+        const float v = fmaf(c, mag, part[k]);
         part[k] = !MASK || act ? v : part[k];
     }
 }
@@ -1011,7 +1074,8 @@ __device__ __forceinline__ void add_terms_md(float (&part)[kMD], const DelayGrid
 // maximum of earlier launches (strictly greater wins, so ties keep the lowest
 // index). A NaN score (from NaN map data) makes the result NaN with index -1.
 __device__ __forceinline__ void merge_delays(const double (&acc)[kMD], const float (&part)[kMD], int32_t N,
-                                             int32_t norm, const DelayGrid &dg, bool ok, float &z, int32_t &mi)
+                                             int32_t norm, float scale, const DelayGrid &dg, bool ok, float &z,
+                                             int32_t &mi)
 {
     z = __builtin_nanf("");
     mi = -1;
@@ -1020,7 +1084,7 @@ __device__ __forceinline__ void merge_delays(const double (&acc)[kMD], const flo
 #pragma unroll
     for (int k = 0; k < kMD; ++k) {
         if (k >= dg.cnt) break;
-        const float v = finish(acc[k] + part[k], N, norm);
+        const float v = finish(acc[k] + part[k], N, norm, scale);
         if (v != v) nan = true;
         else if (mi < 0 || v > z) { z = v; mi = dg.m0 + k; }
     }
@@ -1057,7 +1121,7 @@ __global__ __launch_bounds__(kWG) void k_score_md_direct(MapP m, GenP g, const T
             int64_t base = (int64_t)t.t0 * m.ld;
             for (int32_t k = 0; k < N; ++k) {
                 const int32_t row = ddaf_row(s);
-                const float2 p = load_p<MAPT>(m, base + row);
+                const elem_t<MAPT> p = load_e<MAPT>(m, base + row);
                 add_terms_md<HW, false>(part, dg, row, p, true);
                 if (((t.t0 + k) & (kFlush - 1)) == kFlush - 1) {
 #pragma unroll
@@ -1069,7 +1133,7 @@ __global__ __launch_bounds__(kWG) void k_score_md_direct(MapP m, GenP g, const T
         }
         float z;
         int32_t mi;
-        merge_delays(acc, part, N, norm, dg, ok, z, mi);
+        merge_delays(acc, part, N, norm, m.scale, dg, ok, z, mi);
         merge_running(z, mi, m0 ? snr[i] : 0.0f, m0 ? tidx[i] : 0, m0 == 0);
         snr[i] = z;
         tidx[i] = mi;
@@ -1079,20 +1143,20 @@ __global__ __launch_bounds__(kWG) void k_score_md_direct(MapP m, GenP g, const T
 }
 
 // Column walk of the delay-maximised slab scorer (as walk, with kMD delays).
-template <int TPT, bool MASK, bool HW>
-__device__ __forceinline__ void walk_md(int ca, int cb, int c0, const float2 *slab, int ldc,
+template <int TPT, bool MASK, bool HW, typename E>
+__device__ __forceinline__ void walk_md(int ca, int cb, int c0, const E *slab, int ldc,
                                         const int32_t (&t0)[TPT], const uint32_t (&span)[TPT], const DelayGrid &dg,
                                         DdaF (&st)[TPT], float (&part)[TPT][kMD], double (&acc)[TPT][kMD])
 {
     for (int c = ca; c <= cb;) {
         const int ce = min(cb, c | (kFlush - 1));
         for (; c <= ce; ++c) {
-            const float2 *col = slab + (c - c0) * ldc;
+            const E *col = slab + (c - c0) * ldc;
 #pragma unroll
             for (int q = 0; q < TPT; ++q) {
                 const int32_t row = ddaf_row(st[q]);
                 const bool act = !MASK || (uint32_t)c - (uint32_t)t0[q] <= span[q];
-                const float2 p = col[act ? row : 0];
+                const E p = col[act ? row : 0];
                 add_terms_md<HW, MASK>(part[q], dg, row, p, act);
                 ddaf_step(st[q]);
             }
@@ -1109,7 +1173,7 @@ __device__ __forceinline__ void walk_md(int ca, int cb, int c0, const float2 *sl
 // Slab scorer of the delay grid: the folded map streamed into LDS by DMA as in
 // score_block, WG lanes x TPT binned templates per workgroup; on the last launch
 // each workgroup stores its best key in wg_keys[blockIdx.x].
-template <int WG, int TPT, bool EXPL, bool HW>
+template <int WG, int TPT, bool EXPL, bool HW, int MAPT>
 __global__ __launch_bounds__(WG) void k_score_md_slab(MapP m, GenP g, const Trk *tr, const uint32_t *order,
                                                       uint64_t first, int64_t n, int S, int32_t norm, int32_t d0,
                                                       int32_t step, int32_t m0, int32_t cnt, int32_t last, float *snr,
@@ -1170,13 +1234,16 @@ __global__ __launch_bounds__(WG) void k_score_md_slab(MapP m, GenP g, const Trk 
     }
     __syncthreads();
     const int c_first = __builtin_amdgcn_readfirstlane(bnd[0]), c_last = __builtin_amdgcn_readfirstlane(bnd[1]);
-    const int ldc = (int)m.ld, per_col = ldc / kDmaPix;
+    using E = elem_t<MAPT>;
+    const int ldc = (int)m.ld;
+    const int col8 = ldc * (int)sizeof(E) / 8, per_col = col8 / (kDmaBytes / 8);  // 8-byte units per column
     const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
     auto issue = [&](int c0, int bsel) {
         const int nchunk = min(S, c_last - c0 + 1) * per_col;
-        const float2 *src = m.Y + (int64_t)c0 * ldc + lane * 2;
-        float2 *dst = slab + (size_t)bsel * S * ldc;
-        for (int ch = wave; ch < nchunk; ch += WG / 64) lds_dma_16(src + ch * kDmaPix, dst + ch * kDmaPix);
+        const float2 *src = m.Y + (int64_t)c0 * col8 + lane * 2;
+        float2 *dst = slab + (size_t)bsel * S * col8;
+        for (int ch = wave; ch < nchunk; ch += WG / 64)
+            lds_dma_16(src + ch * (kDmaBytes / 8), dst + ch * (kDmaBytes / 8));
     };
     if (c_first <= c_last) issue(c_first, 0);
     int kk = 0;
@@ -1184,7 +1251,7 @@ __global__ __launch_bounds__(WG) void k_score_md_slab(MapP m, GenP g, const Trk 
         __builtin_amdgcn_s_waitcnt(0);  // this wave's copies of slab kk have landed
         __syncthreads();                // so have everyone's, and slab kk-1 is no longer read
         if (c0 + S <= c_last) issue(c0 + S, (kk + 1) & 1);
-        const float2 *cur = slab + (size_t)(kk & 1) * S * ldc;
+        const E *cur = reinterpret_cast<const E *>(slab + (size_t)(kk & 1) * S * col8);
         const int ncol = min(S, c_last - c0 + 1);
         const int ca = max(c0, lo), cb = min(c0 + ncol - 1, hi);
         walk_md<TPT, true, HW>(ca, min(cb, clo - 1), c0, cur, ldc, t0, span, dg, st, part, acc);
@@ -1197,7 +1264,7 @@ __global__ __launch_bounds__(WG) void k_score_md_slab(MapP m, GenP g, const Trk 
         if (!live[q]) continue;
         float z;
         int32_t mi;
-        merge_delays(acc[q], part[q], (int32_t)span[q] + 1, norm, dg, ok[q], z, mi);
+        merge_delays(acc[q], part[q], (int32_t)span[q] + 1, norm, m.scale, dg, ok[q], z, mi);
         merge_running(z, mi, m0 ? snr[idx[q]] : 0.0f, m0 ? tidx[idx[q]] : 0, m0 == 0);
         snr[idx[q]] = z;
         tidx[idx[q]] = mi;
@@ -1334,7 +1401,7 @@ __global__ __launch_bounds__(WG) void k_score_batch(const BatchMap *maps, int n_
         if (item >= total) break;  // every workgroup reaches this: the queue only grows
         const int mi = find_map(item_start, n_maps, item);
         const BatchMap d = maps[mi];
-        const uint64_t key = score_block<WG, TPT, false, HW, MAPT, SC>(d.m, d.g, nullptr, order + d.order0, 0, d.n,
+        const uint64_t key = score_block<WG, TPT, HW, MAPT, SC>(d.m, d.g, nullptr, order + d.order0, 0, d.n,
                                                                    (int64_t)(item - item_start[mi]), d.S, norm,
                                                                    d.snr, slab, bnd, kred);
         // one atomic per item, spread over the maps' keys
@@ -1343,26 +1410,54 @@ __global__ __launch_bounds__(WG) void k_score_batch(const BatchMap *maps, int n_
 }
 
 // ---------------------------------------------------------------- FP16 map packing
-// p = Y/sigma in FP32 (correctly rounded division), then p * 2^-e rounded to
-// binary16 (round to nearest even). k_absmax finds max |component| first.
+// p = Y/sigma in FP32 (correctly rounded division). Its magnitude in FP64 (the
+// FP32 components square exactly: one rounding of the sum, one of the square
+// root) times 2^-e is rounded to binary16, round to nearest even straight from
+// FP64; its argument atan2 / (2 pi) to the nearest 2^-16 turn (ties to even),
+// modulo one turn. Word = argument | binary16 bits << 16. k_absmax_p finds the
+// largest magnitude first (its FP64 bits: non-negative doubles order as
+// integers).
 
-__global__ __launch_bounds__(256) void k_absmax_p(MapP m, uint32_t *amax_bits)
+__device__ __forceinline__ double p_mag64(float x, float y)
 {
-    float mx = 0.0f;
-    const int64_t n = (int64_t)m.T * m.F;
-    for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < n; i += (int64_t)gridDim.x * 256) {
-        const int64_t t = i / m.F, r = i - t * m.F;
-        const int64_t e = t * m.ld + r;
-        const float2 y = m.Y[e];
-        const float sg = m.sig[e];
-        mx = fmaxf(mx, fmaxf(fabsf(y.x / sg), fabsf(y.y / sg)));
-    }
-#pragma unroll
-    for (int off = 32; off > 0; off >>= 1) mx = fmaxf(mx, __shfl_xor(mx, off));
-    if ((threadIdx.x & 63) == 0) atomicMax(amax_bits, __float_as_uint(mx));  // non-negative floats order as integers
+    const double dx = x, dy = y;
+    return sqrt(fma(dx, dx, dy * dy));
 }
 
-__global__ __launch_bounds__(256) void k_pack_p16(MapP m, float inv_scale, __half2 *out, int64_t out_ld)
+// binary16 bits of a non-negative double below 65520, rounded to nearest, ties to even
+__device__ __forceinline__ uint32_t f64_to_f16_rne(double d)
+{
+    const uint64_t b = (uint64_t)__double_as_longlong(d);
+    if (b == 0) return 0;
+    const int ex = (int)((b >> 52) & 0x7FF) - 1023;
+    const uint64_t sig = (b & 0xFFFFFFFFFFFFFull) | (1ull << 52);  // d = sig * 2^(ex - 52)
+    // normal results keep 11 significant bits (shift 42); subnormal ones count units of 2^-24
+    const int shift = ex >= -14 ? 42 : 28 - ex;
+    if (shift >= 64) return 0;  // below 2^-36: rounds to zero
+    uint64_t q = sig >> shift;
+    const uint64_t rem = sig & ((1ull << shift) - 1), half = 1ull << (shift - 1);
+    if (rem > half || (rem == half && (q & 1))) ++q;
+    // a normal q in [2^10, 2^11]: exponent field plus fraction; the carry of q = 2^11 moves the exponent
+    return ex >= -14 ? (uint32_t)(((uint32_t)(ex + 15) << 10) + (uint32_t)q - 1024u) : (uint32_t)q;
+}
+
+__global__ __launch_bounds__(256) void k_absmax_p(MapP m, unsigned long long *amax_bits)
+{
+    double mx = 0.0;
+    const int64_t n = (int64_t)m.T * m.F;
+    for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < n; i += (int64_t)gridDim.x * 256) {
+        const int64_t t = i / m.F, r = i - t * m.F;
+        const int64_t e = t * m.ld + r;
+        const float2 y = m.Y[e];
+        const float sg = m.sig[e];
+        mx = fmax(mx, p_mag64(y.x / sg, y.y / sg));
+    }
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) mx = fmax(mx, __shfl_xor(mx, off));
+    if ((threadIdx.x & 63) == 0) atomicMax(amax_bits, (unsigned long long)__double_as_longlong(mx));
+}
+
+__global__ __launch_bounds__(256) void k_pack_p16(MapP m, double inv_scale, uint32_t *out, int64_t out_ld)
 {
     const int64_t n = (int64_t)m.T * m.F;
     for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < n; i += (int64_t)gridDim.x * 256) {
@@ -1370,8 +1465,11 @@ __global__ __launch_bounds__(256) void k_pack_p16(MapP m, float inv_scale, __hal
         const int64_t e = t * m.ld + r;
         const float2 y = m.Y[e];
         const float sg = m.sig[e];
-        out[t * out_ld + r] = __halves2half2(__float2half_rn((y.x / sg) * inv_scale),
-                                             __float2half_rn((y.y / sg) * inv_scale));
+        const float px = y.x / sg, py = y.y / sg;
+        const uint32_t mag = f64_to_f16_rne(p_mag64(px, py) * inv_scale);
+        const double turns = atan2((double)py, (double)px) * 0.15915494309189535;  // 1 / (2 pi), rounded
+        const uint32_t arg = (uint32_t)(int64_t)rint(turns * 65536.0) & 0xFFFFu;
+        out[t * out_ld + r] = arg | (mag << 16);
     }
 }
 

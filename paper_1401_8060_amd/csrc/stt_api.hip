@@ -165,9 +165,19 @@ stt_status ensure_mdbuf(stt_ctx *c, size_t bytes)
 }
 
 // Column stride of a folded map and the slab depth that two buffers of it allow.
-int64_t fold_ld(int F) { return ((int64_t)F + kDmaPix - 1) / kDmaPix * kDmaPix; }
-int dma_slab_cols(int lds_bytes, int64_t ldc) { return (int)std::min<int64_t>(64, (lds_bytes - 256) / (16 * ldc)); }
-int dma_slab_cols(const stt_ctx *c, int64_t ldc) { return dma_slab_cols(c->lds_bytes, ldc); }
+// Bytes per pixel of the folded map the scorers read: 8 for an FP32 map (polar FP32 pair), 4 for
+// an FP16 map (its words).
+int fold_esize(int dtype) { return dtype == STT_P16 ? 4 : 8; }
+int64_t fold_ld(int F, int esize = 8)
+{
+    const int64_t per = kDmaBytes / esize;  // pixels per 1 KB piece
+    return ((int64_t)F + per - 1) / per * per;
+}
+int dma_slab_cols(int lds_bytes, int64_t ldc, int esize = 8)
+{
+    return (int)std::min<int64_t>(64, (lds_bytes - 256) / (2 * ldc * esize));
+}
+int dma_slab_cols(const stt_ctx *c, int64_t ldc, int esize = 8) { return dma_slab_cols(c->lds_bytes, ldc, esize); }
 
 stt_status check_map(stt_ctx *c, const stt_map *m)
 {
@@ -273,11 +283,11 @@ int bucket_shift(int T, int64_t n)
     return wb;
 }
 
-template <int WG, int TPT, bool EXPL, bool HW, int MAPT, int SC>
+template <int WG, int TPT, bool HW, int MAPT, int SC>
 stt_status launch_slab_t(stt_ctx *c, const MapP &m, const GenP &g, const Trk *tr, const uint32_t *order,
                          int64_t first, int64_t n, int S, size_t shm, int32_t norm, float *snr, uint64_t *wg_keys)
 {
-    auto kern = k_score_slab<WG, TPT, EXPL, HW, MAPT, SC>;
+    auto kern = k_score_slab<WG, TPT, HW, MAPT, SC>;
     if (shm > 64 * 1024)
         STT_HIP(c, hipFuncSetAttribute((const void *)kern, hipFuncAttributeMaxDynamicSharedMemorySize, (int)shm));
     const unsigned grid = (unsigned)((n + WG * TPT - 1) / (WG * TPT));
@@ -290,14 +300,14 @@ stt_status launch_slab_t(stt_ctx *c, const MapP &m, const GenP &g, const Trk *tr
 // The (workgroup size, templates per lane) shapes compiled into the library.
 static const int kShapes[][2] = {{1024, 4}, {512, 4}, {256, 4}, {1024, 2}, {512, 2}};
 
-template <bool EXPL, bool HW, int MAPT, int SC>
+template <bool HW, int MAPT, int SC>
 stt_status launch_slab_h(stt_ctx *c, int wg, int tpt, const MapP &m, const GenP &g, const Trk *tr,
                          const uint32_t *order, int64_t first, int64_t n, int S, size_t shm, int32_t norm, float *snr,
                          uint64_t *wg_keys)
 {
 #define STT_SLAB_CASE(W, P)                                                                                     \
     if (wg == W && tpt == P)                                                                                    \
-        return launch_slab_t<W, P, EXPL, HW, MAPT, SC>(c, m, g, tr, order, first, n, S, shm, norm, snr, wg_keys);
+        return launch_slab_t<W, P, HW, MAPT, SC>(c, m, g, tr, order, first, n, S, shm, norm, snr, wg_keys);
     STT_SLAB_CASE(1024, 4)
     STT_SLAB_CASE(512, 4)
     STT_SLAB_CASE(256, 4)
@@ -307,39 +317,38 @@ stt_status launch_slab_h(stt_ctx *c, int wg, int tpt, const MapP &m, const GenP 
     return fail(c, STT_EUNSUPPORTED, "no slab scorer compiled for workgroup %d x %d templates", wg, tpt);
 }
 
-template <bool EXPL, int MAPT, int SC>
+template <int MAPT, int SC>
 stt_status launch_slab_sc(stt_ctx *c, int wg, int tpt, const MapP &m, const GenP &g, const Trk *tr,
                           const uint32_t *order, int64_t first, int64_t n, int S, size_t shm, int32_t norm, float *snr,
                           uint64_t *wg_keys)
 {
     if (c->hw_trig)
-        return launch_slab_h<EXPL, true, MAPT, SC>(c, wg, tpt, m, g, tr, order, first, n, S, shm, norm, snr, wg_keys);
-    return launch_slab_h<EXPL, false, MAPT, SC>(c, wg, tpt, m, g, tr, order, first, n, S, shm, norm, snr, wg_keys);
+        return launch_slab_h<true, MAPT, SC>(c, wg, tpt, m, g, tr, order, first, n, S, shm, norm, snr, wg_keys);
+    return launch_slab_h<false, MAPT, SC>(c, wg, tpt, m, g, tr, order, first, n, S, shm, norm, snr, wg_keys);
 }
 
-// The widest aligned slab (a power of two dividing the 16-column flush grid) of which two fit
-// `cols` columns of LDS; 0 when not even two single columns fit.
+// The widest aligned slab (a power of two dividing the 16-column flush grid) not wider than
+// `cols`, the columns two buffers fit; 0 below 2 (then the slabs stage through registers).
 int aligned_slab(int cols)
 {
     int sc = 16;
     while (sc > cols) sc >>= 1;
-    return sc;
+    return sc >= 2 ? sc : 0;
 }
 
-// sc > 0: LDS-DMA slabs of sc aligned columns (sc in 1, 2, 4, 8, 16); sc = 0: register staging of
-// S columns.
-template <bool EXPL, int MAPT>
+// sc > 0: LDS-DMA slabs of sc aligned columns (sc in 2, 4, 8, 16); sc = 0: register staging of
+// S columns. Templates are drawn (tr == NULL) or given.
+template <int MAPT>
 stt_status launch_slab(stt_ctx *c, int sc, int wg, int tpt, const MapP &m, const GenP &g, const Trk *tr,
                        const uint32_t *order, int64_t first, int64_t n, int S, size_t shm, int32_t norm, float *snr,
                        uint64_t *wg_keys)
 {
     switch (sc) {
-    case 0: return launch_slab_sc<EXPL, MAPT, 0>(c, wg, tpt, m, g, tr, order, first, n, S, shm, norm, snr, wg_keys);
-    case 1: return launch_slab_sc<EXPL, MAPT, 1>(c, wg, tpt, m, g, tr, order, first, n, S, shm, norm, snr, wg_keys);
-    case 2: return launch_slab_sc<EXPL, MAPT, 2>(c, wg, tpt, m, g, tr, order, first, n, S, shm, norm, snr, wg_keys);
-    case 4: return launch_slab_sc<EXPL, MAPT, 4>(c, wg, tpt, m, g, tr, order, first, n, S, shm, norm, snr, wg_keys);
-    case 8: return launch_slab_sc<EXPL, MAPT, 8>(c, wg, tpt, m, g, tr, order, first, n, S, shm, norm, snr, wg_keys);
-    case 16: return launch_slab_sc<EXPL, MAPT, 16>(c, wg, tpt, m, g, tr, order, first, n, S, shm, norm, snr, wg_keys);
+    case 0: return launch_slab_sc<MAPT, 0>(c, wg, tpt, m, g, tr, order, first, n, S, shm, norm, snr, wg_keys);
+    case 2: return launch_slab_sc<MAPT, 2>(c, wg, tpt, m, g, tr, order, first, n, S, shm, norm, snr, wg_keys);
+    case 4: return launch_slab_sc<MAPT, 4>(c, wg, tpt, m, g, tr, order, first, n, S, shm, norm, snr, wg_keys);
+    case 8: return launch_slab_sc<MAPT, 8>(c, wg, tpt, m, g, tr, order, first, n, S, shm, norm, snr, wg_keys);
+    case 16: return launch_slab_sc<MAPT, 16>(c, wg, tpt, m, g, tr, order, first, n, S, shm, norm, snr, wg_keys);
     default: return fail(c, STT_EUNSUPPORTED, "no slab scorer for %d-column slabs", sc);
     }
 }
@@ -366,9 +375,12 @@ struct FixedBufs {
     void *pbuf;     // folded map
 };
 
-// p of the map in polar form (k_fold_polar) into the context's folded-map buffer, or into fb's:
-// every scorer of Eq. 8 reads this copy. mf is its view (kMapPol, column stride fold_ld(F)).
+// The map folded for the scorers into the context's folded-map buffer, or into fb's: an FP32 map
+// as p in polar form (k_fold_polar, kMapPol), an FP16 map as its words in padded columns
+// (k_fold_words, kMapPolH). Every scorer of Eq. 8 reads this copy; mf is its view (column stride
+// fold_ld(F, element size)).
 stt_status fold_polar(stt_ctx *c, const stt_map *map, const FixedBufs *fb, MapP &mf);
+size_t folded_bytes(const stt_map *map);
 
 // Scratch of a scoring call of n templates: bucket totals and cursors, the
 // binned order (padded to an even count), then one best-key slot per scorer
@@ -462,14 +474,59 @@ stt_status bin_templates(stt_ctx *c, const MapP &m, const GenP &g, const Trk *tr
     return STT_OK;
 }
 
+// The scorers of one call on the folded map m (format MAPT: kMapPol or kMapPolH).
+template <bool EXPL, int MAPT>
+stt_status score_folded(stt_ctx *c, const MapP &m, const GenP &g, const Trk *tr, int64_t first, int64_t n,
+                        int32_t norm, float *snr, uint64_t *best, const FixedBufs *fb, bool slab, bool per_wave)
+{
+    constexpr int esize = (int)sizeof(elem_t<MAPT>);
+    stt_status s;
+    if (!slab) {
+        ev_record(c, 0);
+        if (c->hw_trig)
+            launch_direct<EXPL, true, MAPT>(c, per_wave, m, g, tr, first, n, norm, snr, best);
+        else
+            launch_direct<EXPL, false, MAPT>(c, per_wave, m, g, tr, first, n, norm, snr, best);
+        STT_HIP(c, hipGetLastError());
+        ev_record(c, 1);
+        c->used[0] = true;
+        return STT_OK;
+    }
+    uint32_t *order = nullptr;
+    uint64_t *wg_keys = nullptr;
+    if ((s = bin_templates<EXPL>(c, m, g, tr, first, n, fb, order, wg_keys)) != STT_OK) return s;
+    const int64_t ldc = m.ld;
+    const int sc = c->dma ? aligned_slab(dma_slab_cols(c, ldc, esize)) : 0;
+    if (sc > 0) {
+        // aligned slabs of the folded map streamed into LDS with double-buffered DMA
+        const size_t shm = 2 * (size_t)esize * (size_t)sc * ldc;
+        ev_record(c, 0);
+        s = launch_slab<MAPT>(c, sc, c->slab_wg, c->slab_tpt, m, g, tr, order, first, n, sc, shm, norm, snr, wg_keys);
+    } else {
+        // one slab buffer, staged through registers (maps too wide for two DMA slabs)
+        const int S = std::min<int>(std::min<int>(64, (c->lds_bytes - 256) / (esize * m.F)), m.T);
+        const size_t shm = (size_t)esize * (size_t)S * m.F;
+        ev_record(c, 0);
+        s = launch_slab<MAPT>(c, 0, c->slab_wg, c->slab_tpt, m, g, tr, order, first, n, S, shm, norm, snr, wg_keys);
+    }
+    if (s != STT_OK) return s;
+    ev_record(c, 1);
+    c->used[0] = true;
+    if (best) {
+        const int64_t n_wg = (n + (int64_t)c->slab_wg * c->slab_tpt - 1) / ((int64_t)c->slab_wg * c->slab_tpt);
+        hipLaunchKernelGGL(k_reduce_keys, dim3(1), dim3(1024), 0, c->stream, (const uint64_t *)wg_keys, n_wg, best);
+        STT_HIP(c, hipGetLastError());
+    }
+    return STT_OK;
+}
+
 template <bool EXPL>
 stt_status score_impl(stt_ctx *c, const stt_map *map, const GenP &g, const Trk *tr, int64_t first, int64_t n,
                       int32_t norm, float *snr, uint64_t *best, const FixedBufs *fb = nullptr)
 {
-    const int F = map->F;
+    const int F = map->F, esize = fold_esize(map->dtype);
     // the slab plus the kernel's few static LDS words must fit the 160 KB of a CU
-    const int slab_cols = std::min<int>(64, (c->lds_bytes - 256) / (8 * F));
-    bool slab = slab_cols >= 1;
+    bool slab = (c->lds_bytes - 256) / (esize * F) >= 1;
     if (c->path == 1 || c->path == 3) slab = false;
     if (c->path == 0 && n < 4096) slab = false;
     // without slabs: one wave per template for calls too small to fill the chip lane by lane
@@ -482,87 +539,115 @@ stt_status score_impl(stt_ctx *c, const stt_map *map, const GenP &g, const Trk *
     ev_record(c, 4);
     MapP m;
     if ((s = fold_polar(c, map, fb, m)) != STT_OK) return s;
-    if (!slab) {
-        ev_record(c, 0);
-        if (c->hw_trig)
-            launch_direct<EXPL, true, kMapPol>(c, per_wave, m, g, tr, first, n, norm, snr, best);
-        else
-            launch_direct<EXPL, false, kMapPol>(c, per_wave, m, g, tr, first, n, norm, snr, best);
-        STT_HIP(c, hipGetLastError());
-        ev_record(c, 1);
-        c->used[0] = true;
-    } else {
-        uint32_t *order = nullptr;
-        uint64_t *wg_keys = nullptr;
-        if ((s = bin_templates<EXPL>(c, m, g, tr, first, n, fb, order, wg_keys)) != STT_OK) return s;
-        const int64_t ldc = m.ld;
-        if (c->dma && dma_slab_cols(c, ldc) >= 1) {
-            // aligned slabs of the folded map streamed into LDS with double-buffered DMA
-            const int S = aligned_slab(dma_slab_cols(c, ldc));
-            const size_t shm = 2 * sizeof(float2) * (size_t)S * ldc;
-            ev_record(c, 0);
-            s = launch_slab<EXPL, kMapPol>(c, S, c->slab_wg, c->slab_tpt, m, g, tr, order, first, n, S, shm, norm,
-                                           snr, wg_keys);
-        } else {
-            // one slab buffer, staged through registers (maps too wide for two DMA slabs)
-            const int S = std::min(slab_cols, m.T);
-            const size_t shm = sizeof(float2) * (size_t)S * F;
-            ev_record(c, 0);
-            s = launch_slab<EXPL, kMapPol>(c, 0, c->slab_wg, c->slab_tpt, m, g, tr, order, first, n, S, shm, norm,
-                                           snr, wg_keys);
-        }
-        if (s != STT_OK) return s;
-        ev_record(c, 1);
-        c->used[0] = true;
-        if (best) {
-            const int64_t n_wg = (n + (int64_t)c->slab_wg * c->slab_tpt - 1) / ((int64_t)c->slab_wg * c->slab_tpt);
-            hipLaunchKernelGGL(k_reduce_keys, dim3(1), dim3(1024), 0, c->stream, (const uint64_t *)wg_keys, n_wg, best);
-            STT_HIP(c, hipGetLastError());
-        }
-    }
+    s = map->dtype == STT_P16 ? score_folded<EXPL, kMapPolH>(c, m, g, tr, first, n, norm, snr, best, fb, slab, per_wave)
+                              : score_folded<EXPL, kMapPol>(c, m, g, tr, first, n, norm, snr, best, fb, slab, per_wave);
+    if (s != STT_OK) return s;
     ev_record(c, 5);
     c->used[2] = true;
     ev_end(c);
     return STT_OK;
 }
 
+// Bytes of the folded copy of a map.
+size_t folded_bytes(const stt_map *map)
+{
+    const int esize = fold_esize(map->dtype);
+    return (size_t)esize * (size_t)map->T * (size_t)fold_ld(map->F, esize);
+}
+
 stt_status fold_polar(stt_ctx *c, const stt_map *map, const FixedBufs *fb, MapP &mf)
 {
     const MapP m = to_mapp(map);
-    const int64_t ldc = fold_ld(m.F);
+    const int esize = fold_esize(map->dtype);
+    const int64_t ldc = fold_ld(m.F, esize);
     if (!fb) {
-        const stt_status s = ensure_pbuf(c, sizeof(float2) * (size_t)m.T * (size_t)ldc);
+        const stt_status s = ensure_pbuf(c, folded_bytes(map));
         if (s != STT_OK) return s;
     }
-    float2 *pbuf = (float2 *)(fb ? fb->pbuf : c->pbuf);
+    void *pbuf = fb ? fb->pbuf : c->pbuf;
     const unsigned fg = (unsigned)std::min<int64_t>(((int64_t)m.T * ldc + 255) / 256, 8192);
     if (map->dtype == STT_P16)
-        hipLaunchKernelGGL(k_fold_polar<kMapP16>, dim3(fg), dim3(256), 0, c->stream, m, pbuf, ldc);
+        hipLaunchKernelGGL(k_fold_words, dim3(fg), dim3(256), 0, c->stream, m, (uint32_t *)pbuf, ldc);
     else
-        hipLaunchKernelGGL(k_fold_polar<kMapF32>, dim3(fg), dim3(256), 0, c->stream, m, pbuf, ldc);
+        hipLaunchKernelGGL(k_fold_polar<kMapF32>, dim3(fg), dim3(256), 0, c->stream, m, (float2 *)pbuf, ldc);
     STT_HIP(c, hipGetLastError());
-    mf = m;
-    mf.Y = pbuf;
+    mf = m;  // an FP16 map keeps its scale 2^e
+    mf.Y = (const float2 *)pbuf;
     mf.sig = nullptr;
     mf.ld = ldc;
-    mf.scale = 1.0f;
     return STT_OK;
 }
 
 // The delay grid in launches of kMD delays. Slabs (binned templates, folded map,
 // LDS-DMA) from 4096 templates on when two slabs of a column fit; otherwise one
 // lane per template with direct gathers. Both give bit-identical results.
+template <bool EXPL, int MAPT>
+stt_status maxdelay_folded(stt_ctx *c, const MapP &mf, const GenP &g, const Trk *tr, int64_t first, int64_t n,
+                           int32_t d0, int32_t step, int32_t n_tau, int32_t norm, float *snr, int32_t *tidx,
+                           uint64_t *best, bool slab, int lds)
+{
+    // 1024 lanes x 1 template, at most 80 KB of slabs (measured on the search map: 512 x 2, 1024 x 2,
+    // 256 x 4 and smaller slabs were 15-75 % slower; one template per lane leaves room for more waves)
+    constexpr int kMdWG = 1024, kMdTPT = 1;
+    constexpr int esize = (int)sizeof(elem_t<MAPT>);
+    const int64_t ldc = mf.ld;
+    const int n_launch = (n_tau + kMD - 1) / kMD;
+    stt_status s;
+    if (!slab) {
+        ev_record(c, 0);
+        const unsigned grid = (unsigned)((n + kWG - 1) / kWG);
+        for (int l = 0; l < n_launch; ++l) {
+            const int32_t m0 = l * kMD, cnt = std::min(kMD, n_tau - m0), last = l == n_launch - 1;
+            if (c->hw_trig)
+                hipLaunchKernelGGL((k_score_md_direct<EXPL, true, MAPT>), dim3(grid), dim3(kWG), 0, c->stream, mf, g,
+                                   tr, (uint64_t)first, n, norm, d0, step, m0, cnt, last, snr, tidx, best);
+            else
+                hipLaunchKernelGGL((k_score_md_direct<EXPL, false, MAPT>), dim3(grid), dim3(kWG), 0, c->stream, mf,
+                                   g, tr, (uint64_t)first, n, norm, d0, step, m0, cnt, last, snr, tidx, best);
+        }
+        STT_HIP(c, hipGetLastError());
+        ev_record(c, 1);
+        c->used[0] = true;
+        return STT_OK;
+    }
+    uint32_t *order = nullptr;
+    uint64_t *wg_keys = nullptr;
+    if ((s = bin_templates<EXPL>(c, mf, g, tr, first, n, nullptr, order, wg_keys)) != STT_OK) return s;
+    const int S = std::min(dma_slab_cols(lds, ldc, esize), mf.T);
+    const size_t shm = 2 * (size_t)esize * (size_t)S * ldc;
+    const unsigned grid = (unsigned)((n + kMdWG * kMdTPT - 1) / (kMdWG * kMdTPT));
+    auto kh = k_score_md_slab<kMdWG, kMdTPT, EXPL, true, MAPT>;
+    auto kp = k_score_md_slab<kMdWG, kMdTPT, EXPL, false, MAPT>;
+    auto kern = c->hw_trig ? kh : kp;
+    if (shm > 64 * 1024)
+        STT_HIP(c, hipFuncSetAttribute((const void *)kern, hipFuncAttributeMaxDynamicSharedMemorySize, (int)shm));
+    ev_record(c, 0);
+    for (int l = 0; l < n_launch; ++l) {
+        const int32_t m0 = l * kMD, cnt = std::min(kMD, n_tau - m0), last = l == n_launch - 1;
+        hipLaunchKernelGGL(kern, dim3(grid), dim3(kMdWG), shm, c->stream, mf, g, tr, (const uint32_t *)order,
+                           (uint64_t)first, n, S, norm, d0, step, m0, cnt, last, snr, tidx, wg_keys);
+    }
+    STT_HIP(c, hipGetLastError());
+    ev_record(c, 1);
+    c->used[0] = true;
+    if (best) {
+        hipLaunchKernelGGL(k_reduce_keys, dim3(1), dim3(1024), 0, c->stream, (const uint64_t *)wg_keys, (int64_t)grid,
+                           best);
+        STT_HIP(c, hipGetLastError());
+    }
+    return STT_OK;
+}
+
 template <bool EXPL>
 stt_status maxdelay_impl(stt_ctx *c, const stt_map *map, const GenP &g, const Trk *tr, int64_t first, int64_t n,
                          int32_t d0, int32_t step, int32_t n_tau, int32_t norm, float *snr, int32_t *tidx,
                          uint64_t *best)
 {
-    // 1024 lanes x 1 template, at most 80 KB of slabs (measured on the search map: 512 x 2, 1024 x 2,
-    // 256 x 4 and smaller slabs were 15-75 % slower; one template per lane leaves room for more waves)
-    constexpr int kMdWG = 1024, kMdTPT = 1;
     const int lds = std::min(c->lds_bytes, 80 * 1024);
-    const int64_t ldc = fold_ld(map->F);
-    bool slab = c->dma && dma_slab_cols(lds, ldc) >= 1 && c->path != 1 && c->path != 3 && (c->path == 2 || n >= 4096);
+    const int esize = fold_esize(map->dtype);
+    const int64_t ldc = fold_ld(map->F, esize);
+    bool slab = c->dma && dma_slab_cols(lds, ldc, esize) >= 1 && c->path != 1 && c->path != 3 &&
+                (c->path == 2 || n >= 4096);
     if (c->path == 2 && !slab)
         return fail(c, STT_EUNSUPPORTED, "F=%d too wide for two LDS slabs of %d bytes", map->F, lds);
     stt_status s;
@@ -575,52 +660,61 @@ stt_status maxdelay_impl(stt_ctx *c, const stt_map *map, const GenP &g, const Tr
     ev_record(c, 4);
     MapP mf;
     if ((s = fold_polar(c, map, nullptr, mf)) != STT_OK) return s;
-    const int n_launch = (n_tau + kMD - 1) / kMD;
-    if (!slab) {
-        ev_record(c, 0);
-        const unsigned grid = (unsigned)((n + kWG - 1) / kWG);
-        for (int l = 0; l < n_launch; ++l) {
-            const int32_t m0 = l * kMD, cnt = std::min(kMD, n_tau - m0), last = l == n_launch - 1;
-            if (c->hw_trig)
-                hipLaunchKernelGGL((k_score_md_direct<EXPL, true, kMapPol>), dim3(grid), dim3(kWG), 0, c->stream, mf,
-                                   g, tr, (uint64_t)first, n, norm, d0, step, m0, cnt, last, snr, tidx, best);
-            else
-                hipLaunchKernelGGL((k_score_md_direct<EXPL, false, kMapPol>), dim3(grid), dim3(kWG), 0, c->stream,
-                                   mf, g, tr, (uint64_t)first, n, norm, d0, step, m0, cnt, last, snr, tidx, best);
-        }
-        STT_HIP(c, hipGetLastError());
-        ev_record(c, 1);
-        c->used[0] = true;
-    } else {
-        uint32_t *order = nullptr;
-        uint64_t *wg_keys = nullptr;
-        if ((s = bin_templates<EXPL>(c, mf, g, tr, first, n, nullptr, order, wg_keys)) != STT_OK) return s;
-        const int S = std::min(dma_slab_cols(lds, ldc), mf.T);
-        const size_t shm = 2 * sizeof(float2) * (size_t)S * ldc;
-        const unsigned grid = (unsigned)((n + kMdWG * kMdTPT - 1) / (kMdWG * kMdTPT));
-        auto kh = k_score_md_slab<kMdWG, kMdTPT, EXPL, true>;
-        auto kp = k_score_md_slab<kMdWG, kMdTPT, EXPL, false>;
-        auto kern = c->hw_trig ? kh : kp;
-        if (shm > 64 * 1024)
-            STT_HIP(c, hipFuncSetAttribute((const void *)kern, hipFuncAttributeMaxDynamicSharedMemorySize, (int)shm));
-        ev_record(c, 0);
-        for (int l = 0; l < n_launch; ++l) {
-            const int32_t m0 = l * kMD, cnt = std::min(kMD, n_tau - m0), last = l == n_launch - 1;
-            hipLaunchKernelGGL(kern, dim3(grid), dim3(kMdWG), shm, c->stream, mf, g, tr, (const uint32_t *)order,
-                               (uint64_t)first, n, S, norm, d0, step, m0, cnt, last, snr, tidx, wg_keys);
-        }
-        STT_HIP(c, hipGetLastError());
-        ev_record(c, 1);
-        c->used[0] = true;
-        if (best) {
-            hipLaunchKernelGGL(k_reduce_keys, dim3(1), dim3(1024), 0, c->stream, (const uint64_t *)wg_keys,
-                               (int64_t)grid, best);
-            STT_HIP(c, hipGetLastError());
-        }
-    }
+    s = map->dtype == STT_P16
+            ? maxdelay_folded<EXPL, kMapPolH>(c, mf, g, tr, first, n, d0, step, n_tau, norm, snr, tidx, best, slab, lds)
+            : maxdelay_folded<EXPL, kMapPol>(c, mf, g, tr, first, n, d0, step, n_tau, norm, snr, tidx, best, slab, lds);
+    if (s != STT_OK) return s;
     ev_record(c, 5);
     c->used[2] = true;
     ev_end(c);
+    return STT_OK;
+}
+
+// The free-t_mid scorers of one call on the folded map mf (format MAPT).
+template <int MAPT>
+stt_status score_tm_folded(stt_ctx *c, const MapP &mf, const GenP &g, const TrkTm *tr, int64_t first, int64_t n,
+                           int32_t norm, float *snr_dev, uint64_t *best_key_dev, bool slab, int lds)
+{
+    constexpr int kTmWG = 512, kTmTPT = 2;
+    constexpr int esize = (int)sizeof(elem_t<MAPT>);
+    stt_status s;
+    if (slab) {
+        uint32_t *order = nullptr;
+        uint64_t *wg_keys = nullptr;
+        if ((s = bin_templates<false>(c, mf, g, nullptr, first, n, nullptr, order, wg_keys)) != STT_OK) return s;
+        const int S = std::min(dma_slab_cols(lds, mf.ld, esize), mf.T);
+        const size_t shm = 2 * (size_t)esize * (size_t)S * mf.ld;
+        const unsigned grid = (unsigned)((n + kTmWG * kTmTPT - 1) / (kTmWG * kTmTPT));
+        auto kern = c->hw_trig ? k_score_tm_slab<kTmWG, kTmTPT, true, MAPT> : k_score_tm_slab<kTmWG, kTmTPT, false, MAPT>;
+        if (shm > 64 * 1024)
+            STT_HIP(c, hipFuncSetAttribute((const void *)kern, hipFuncAttributeMaxDynamicSharedMemorySize, (int)shm));
+        ev_record(c, 0);
+        hipLaunchKernelGGL(kern, dim3(grid), dim3(kTmWG), shm, c->stream, mf, g, (const uint32_t *)order,
+                           (uint64_t)first, n, S, norm, snr_dev, wg_keys);
+        STT_HIP(c, hipGetLastError());
+        ev_record(c, 1);
+        c->used[0] = true;
+        if (best_key_dev) {
+            hipLaunchKernelGGL(k_reduce_keys, dim3(1), dim3(1024), 0, c->stream, (const uint64_t *)wg_keys,
+                               (int64_t)grid, best_key_dev);
+            STT_HIP(c, hipGetLastError());
+        }
+        return STT_OK;
+    }
+    const dim3 grid((unsigned)((n + 3) / 4)), block(256);
+    ev_record(c, 0);
+#define STT_TM_LAUNCH(E, H)                                                                                     \
+    hipLaunchKernelGGL((k_score_tm<E, H, MAPT>), grid, block, 0, c->stream, mf, g, tr, (uint64_t)first, n, norm, \
+                       snr_dev, best_key_dev)
+    if (tr) {
+        if (c->hw_trig) STT_TM_LAUNCH(true, true); else STT_TM_LAUNCH(true, false);
+    } else {
+        if (c->hw_trig) STT_TM_LAUNCH(false, true); else STT_TM_LAUNCH(false, false);
+    }
+#undef STT_TM_LAUNCH
+    STT_HIP(c, hipGetLastError());
+    ev_record(c, 1);
+    c->used[0] = true;
     return STT_OK;
 }
 
@@ -868,7 +962,7 @@ stt_status stt_score_noalloc(stt_ctx *c, const stt_map *map, const stt_gen *gen,
     if (n > kNaMaxTracks)
         return fail(c, STT_ERANGE, "n=%lld exceeds the %lld templates of the fixed scratch", (long long)n,
                     (long long)kNaMaxTracks);
-    const size_t map_bytes = sizeof(float2) * (size_t)map->T * (size_t)fold_ld(map->F);
+    const size_t map_bytes = folded_bytes(map);
     if (map_bytes > kNaMapBytes)
         return fail(c, STT_ERANGE, "the folded %dx%d map needs %zu bytes; the fixed scratch holds %zu", map->T,
                     map->F, map_bytes, kNaMapBytes);
@@ -951,58 +1045,23 @@ stt_status stt_score_tm(stt_ctx *c, const stt_map *map, const stt_gen *gen, cons
     }
     if (n == 0) return STT_OK;
     STT_HIP(c, hipSetDevice(c->device));
-    const TrkTm *tr = (const TrkTm *)tracks_dev;
     // generated templates: binned by time extent (a free t_mid keeps it) and scored from LDS slabs
     // (512 lanes x 2 templates, at most 80 KB of slabs) when a column fits; otherwise one wave each
-    constexpr int kTmWG = 512, kTmTPT = 2;
     const int lds = std::min(c->lds_bytes, 80 * 1024);
-    const int64_t ldc = fold_ld(map->F);
-    const bool slab = !tracks_dev && c->dma && dma_slab_cols(lds, ldc) >= 1 && c->path != 1 && c->path != 3 &&
+    const int esize = fold_esize(map->dtype);
+    const int64_t ldc = fold_ld(map->F, esize);
+    const bool slab = !tracks_dev && c->dma && dma_slab_cols(lds, ldc, esize) >= 1 && c->path != 1 && c->path != 3 &&
                       (c->path == 2 || n >= 4096);
     if ((s = ev_begin(c)) != STT_OK) return s;
     ev_record(c, 4);
     MapP mf;
     if ((s = fold_polar(c, map, nullptr, mf)) != STT_OK) return s;
-    if (slab) {
-        uint32_t *order = nullptr;
-        uint64_t *wg_keys = nullptr;
-        if ((s = bin_templates<false>(c, mf, g, nullptr, first, n, nullptr, order, wg_keys)) != STT_OK) return s;
-        const int S = std::min(dma_slab_cols(lds, ldc), mf.T);
-        const size_t shm = 2 * sizeof(float2) * (size_t)S * ldc;
-        const unsigned grid = (unsigned)((n + kTmWG * kTmTPT - 1) / (kTmWG * kTmTPT));
-        auto kern = c->hw_trig ? k_score_tm_slab<kTmWG, kTmTPT, true> : k_score_tm_slab<kTmWG, kTmTPT, false>;
-        if (shm > 64 * 1024)
-            STT_HIP(c, hipFuncSetAttribute((const void *)kern, hipFuncAttributeMaxDynamicSharedMemorySize, (int)shm));
-        ev_record(c, 0);
-        hipLaunchKernelGGL(kern, dim3(grid), dim3(kTmWG), shm, c->stream, mf, g, (const uint32_t *)order,
-                           (uint64_t)first, n, S, norm, snr_dev, wg_keys);
-        STT_HIP(c, hipGetLastError());
-        ev_record(c, 1);
-        c->used[0] = true;
-        if (best_key_dev) {
-            hipLaunchKernelGGL(k_reduce_keys, dim3(1), dim3(1024), 0, c->stream, (const uint64_t *)wg_keys,
-                               (int64_t)grid, best_key_dev);
-            STT_HIP(c, hipGetLastError());
-        }
-        ev_record(c, 5);
-        c->used[2] = true;
-        ev_end(c);
-        return STT_OK;
-    }
-    const dim3 grid((unsigned)((n + 3) / 4)), block(256);
-    ev_record(c, 0);
-#define STT_TM_LAUNCH(E, H)                                                                                        \
-    hipLaunchKernelGGL((k_score_tm<E, H, kMapPol>), grid, block, 0, c->stream, mf, g, tr, (uint64_t)first, n, norm, \
-                       snr_dev, best_key_dev)
-    if (tracks_dev) {
-        if (c->hw_trig) STT_TM_LAUNCH(true, true); else STT_TM_LAUNCH(true, false);
-    } else {
-        if (c->hw_trig) STT_TM_LAUNCH(false, true); else STT_TM_LAUNCH(false, false);
-    }
-#undef STT_TM_LAUNCH
-    STT_HIP(c, hipGetLastError());
-    ev_record(c, 1);
-    c->used[0] = true;
+    s = map->dtype == STT_P16
+            ? score_tm_folded<kMapPolH>(c, mf, g, (const TrkTm *)tracks_dev, first, n, norm, snr_dev, best_key_dev,
+                                        slab, lds)
+            : score_tm_folded<kMapPol>(c, mf, g, (const TrkTm *)tracks_dev, first, n, norm, snr_dev, best_key_dev,
+                                       slab, lds);
+    if (s != STT_OK) return s;
     ev_record(c, 5);
     c->used[2] = true;
     ev_end(c);
@@ -1034,21 +1093,28 @@ stt_status stt_map_pack_p16(stt_ctx *c, const stt_map *map, void *out_dev, int64
     if (out_ld < map->F) return fail(c, STT_EINVAL, "out_ld=%lld < F=%d", (long long)out_ld, map->F);
     STT_HIP(c, hipSetDevice(c->device));
     if ((s = ensure_aux(c, sizeof(TopkState))) != STT_OK) return s;
-    uint32_t *amax = (uint32_t *)c->aux;
+    unsigned long long *amax = (unsigned long long *)c->aux;
     const MapP m = to_mapp(map);
     const int64_t n = (int64_t)map->T * map->F;
     const unsigned grid = (unsigned)std::min<int64_t>((n + 255) / 256, 2048);
-    hipLaunchKernelGGL(k_fill_u32, dim3(1), dim3(256), 0, c->stream, amax, (int64_t)1, 0u);
+    hipLaunchKernelGGL(k_fill_u32, dim3(1), dim3(256), 0, c->stream, (uint32_t *)amax, (int64_t)2, 0u);
     hipLaunchKernelGGL(k_absmax_p, dim3(grid), dim3(256), 0, c->stream, m, amax);
     STT_HIP(c, hipGetLastError());
-    uint32_t bits = 0;
+    unsigned long long bits = 0;
     STT_HIP(c, hipMemcpyAsync(&bits, amax, sizeof bits, hipMemcpyDeviceToHost, c->stream));
     STT_HIP(c, hipStreamSynchronize(c->stream));
-    float amaxf;
-    std::memcpy(&amaxf, &bits, sizeof amaxf);
-    if (!std::isfinite(amaxf)) return fail(c, STT_EINVAL, "map holds a non-finite Y/sigma");
-    const int e = amaxf > 0.0f ? (int)std::ceil(std::log2((double)amaxf)) - 15 : 0;
-    hipLaunchKernelGGL(k_pack_p16, dim3(grid), dim3(256), 0, c->stream, m, std::ldexp(1.0f, -e), (__half2 *)out_dev,
+    double amaxd;
+    std::memcpy(&amaxd, &bits, sizeof amaxd);
+    if (!std::isfinite(amaxd)) return fail(c, STT_EINVAL, "map holds a non-finite Y/sigma");
+    // e = ceil(log2(max |p|)) - 15, exactly: with max = fr 2^k, fr in [1/2, 1), the ceiling is k
+    // unless fr = 1/2 (a power of two, its own ceiling k - 1)
+    int e = 0;
+    if (amaxd > 0.0) {
+        int k = 0;
+        const double fr = std::frexp(amaxd, &k);
+        e = (fr > 0.5 ? k : k - 1) - 15;
+    }
+    hipLaunchKernelGGL(k_pack_p16, dim3(grid), dim3(256), 0, c->stream, m, std::ldexp(1.0, -e), (uint32_t *)out_dev,
                        out_ld);
     STT_HIP(c, hipGetLastError());
     *scale_exp = e;
@@ -1292,12 +1358,12 @@ stt_status stt_form_maps(stt_ctx *c, const stt_spectro *p, int32_t T, const floa
 
 namespace {
 
-template <int WG, int TPT, bool HW, int SC>
+template <int WG, int TPT, bool HW, int MAPT, int SC>
 stt_status launch_batch_t(stt_ctx *c, hipStream_t st, const BatchMap *maps, int n_maps, const uint32_t *item_start,
                           uint32_t total_items, uint32_t *queue, const uint32_t *order, int32_t norm, uint64_t *best,
                           size_t shm)
 {
-    auto kern = k_score_batch<WG, TPT, HW, kMapPol, SC>;
+    auto kern = k_score_batch<WG, TPT, HW, MAPT, SC>;
     if (shm > 64 * 1024)
         STT_HIP(c, hipFuncSetAttribute((const void *)kern, hipFuncAttributeMaxDynamicSharedMemorySize, (int)shm));
     int per_cu = 0;
@@ -1310,15 +1376,15 @@ stt_status launch_batch_t(stt_ctx *c, hipStream_t st, const BatchMap *maps, int 
     return STT_OK;
 }
 
-template <bool HW, int SC>
+template <bool HW, int MAPT, int SC>
 stt_status launch_batch_h(stt_ctx *c, hipStream_t st, const BatchMap *maps, int n_maps, const uint32_t *item_start,
                           uint32_t total_items, uint32_t *queue, const uint32_t *order, int32_t norm, uint64_t *best,
                           size_t shm)
 {
-#define STT_BATCH_CASE(W, P)                                                                                   \
-    if (c->slab_wg == W && c->slab_tpt == P)                                                                   \
-        return launch_batch_t<W, P, HW, SC>(c, st, maps, n_maps, item_start, total_items, queue, order, norm, best, \
-                                            shm);
+#define STT_BATCH_CASE(W, P)                                                                                        \
+    if (c->slab_wg == W && c->slab_tpt == P)                                                                        \
+        return launch_batch_t<W, P, HW, MAPT, SC>(c, st, maps, n_maps, item_start, total_items, queue, order, norm, \
+                                                  best, shm);
     STT_BATCH_CASE(1024, 4)
     STT_BATCH_CASE(512, 4)
     STT_BATCH_CASE(256, 4)
@@ -1357,6 +1423,7 @@ stt_status stt_score_batch(stt_ctx *c, const stt_map *maps_host, int32_t n_maps,
     if (!best_key_per_map_dev) return fail(c, STT_EINVAL, "best_key_per_map_dev must be non-NULL");
     if (norm != STT_NORM_SQRT_N && norm != STT_NORM_N) return fail(c, STT_EINVAL, "norm=%d", norm);
     const int dtype = maps_host[0].dtype;
+    const int esize = fold_esize(dtype);
     std::vector<BatchMap> bm(n_maps);
     std::vector<uint32_t> chunk_start(n_maps + 1), item_start(n_maps + 1);
     const int per_item = c->slab_wg * c->slab_tpt;
@@ -1383,12 +1450,11 @@ stt_status stt_score_batch(stt_ctx *c, const stt_map *maps_host, int32_t n_maps,
         d.wb = bucket_shift(mp->T, n);
         const int nb = ((mp->T - 1) >> d.wb) + 1;
         d.nbins = nb * (nb + 1) / 2;
-        d.S = std::min(std::min<int>(64, (c->lds_bytes - 256) / (8 * mp->F)), mp->T);
+        d.S = std::min(std::min<int>(64, (c->lds_bytes - 256) / (esize * mp->F)), mp->T);
         if (d.S < 1) return fail(c, STT_EUNSUPPORTED, "map %d: F=%d too wide for the LDS slab", i, mp->F);
-        shm = std::max(shm, sizeof(float2) * (size_t)d.S * mp->F);
         {
-            const int64_t ldc = fold_ld(mp->F);
-            dma_ok = dma_ok && dma_slab_cols(c, ldc) >= 1;
+            const int64_t ldc = fold_ld(mp->F, esize);
+            dma_ok = dma_ok && aligned_slab(dma_slab_cols(c, ldc, esize)) >= 2;
             fold_off[i] = fold_px;
             fold_px += (uint64_t)mp->T * (uint64_t)ldc;
         }
@@ -1410,7 +1476,7 @@ stt_status stt_score_batch(stt_ctx *c, const stt_map *maps_host, int32_t n_maps,
     std::vector<MapP> orig(n_maps);
     for (int i = 0; i < n_maps; ++i) orig[i] = bm[i].m;
     {
-        stt_status sf = ensure_pbuf(c, sizeof(float2) * (size_t)fold_px);
+        stt_status sf = ensure_pbuf(c, (size_t)esize * (size_t)fold_px);
         if (sf != STT_OK) return sf;
     }
     std::vector<FoldJob> jobs(n_maps + 1);
@@ -1418,20 +1484,21 @@ stt_status stt_score_batch(stt_ctx *c, const stt_map *maps_host, int32_t n_maps,
     // one aligned slab width for the whole batch: the narrowest any map's columns allow
     int sc_all = 16;
     if (dma_ok)
-        for (int i = 0; i < n_maps; ++i) sc_all = std::min(sc_all, aligned_slab(dma_slab_cols(c, fold_ld(bm[i].m.F))));
+        for (int i = 0; i < n_maps; ++i)
+            sc_all = std::min(sc_all, aligned_slab(dma_slab_cols(c, fold_ld(bm[i].m.F, esize), esize)));
     for (int i = 0; i < n_maps; ++i) {
         BatchMap &d = bm[i];
-        const int64_t ldc = fold_ld(d.m.F);
-        jobs[i] = FoldJob{orig[i], (float2 *)c->pbuf + fold_off[i], ldc, fold_off[i]};
-        d.m.Y = (const float2 *)c->pbuf + fold_off[i];
+        const int64_t ldc = fold_ld(d.m.F, esize);
+        void *dst = (char *)c->pbuf + (size_t)esize * fold_off[i];
+        jobs[i] = FoldJob{orig[i], dst, ldc, fold_off[i]};
+        d.m.Y = (const float2 *)dst;  // an FP16 map keeps its scale 2^e
         d.m.sig = nullptr;
         d.m.ld = ldc;
-        d.m.scale = 1.0f;
         if (dma_ok) {
             d.S = sc_all;
-            shm = std::max(shm, 2 * sizeof(float2) * (size_t)d.S * (size_t)ldc);
+            shm = std::max(shm, 2 * (size_t)esize * (size_t)d.S * (size_t)ldc);
         } else {
-            shm = std::max(shm, sizeof(float2) * (size_t)d.S * (size_t)d.m.F);
+            shm = std::max(shm, (size_t)esize * (size_t)d.S * (size_t)d.m.F);
         }
     }
     jobs[n_maps] = FoldJob{MapP{}, nullptr, 0, fold_px};
@@ -1497,11 +1564,11 @@ stt_status stt_score_batch(stt_ctx *c, const stt_map *maps_host, int32_t n_maps,
             {
                 const unsigned fg = (unsigned)std::min<uint64_t>((fold_px + 255) / 256, 16384);
                 if (dtype == STT_P16)
-                    hipLaunchKernelGGL(k_fold_polar_batch<kMapP16>, dim3(fg), dim3(256), 0, st,
-                                       (const FoldJob *)djobs, n_maps);
+                    hipLaunchKernelGGL(k_fold_batch<kMapP16>, dim3(fg), dim3(256), 0, st, (const FoldJob *)djobs,
+                                       n_maps);
                 else
-                    hipLaunchKernelGGL(k_fold_polar_batch<kMapF32>, dim3(fg), dim3(256), 0, st,
-                                       (const FoldJob *)djobs, n_maps);
+                    hipLaunchKernelGGL(k_fold_batch<kMapF32>, dim3(fg), dim3(256), 0, st, (const FoldJob *)djobs,
+                                       n_maps);
             }
             hipLaunchKernelGGL(k_fill_u32, dim3((unsigned)((nb_all + 64 + 255) / 256)), dim3(256), 0, st, totals,
                                (int64_t)(nb_all), 0u);
@@ -1523,20 +1590,22 @@ stt_status stt_score_batch(stt_ctx *c, const stt_map *maps_host, int32_t n_maps,
             stt_status r;
             const uint32_t ni = (uint32_t)nitems;
             const int sc = dma_ok ? sc_all : 0;
-#define STT_BATCH_SC(SCV)                                                                                      \
-    r = c->hw_trig ? launch_batch_h<true, SCV>(c, st, dmaps, n_maps, ditem, ni, queue, order, norm,            \
-                                               best_key_per_map_dev, shm)                                     \
-                   : launch_batch_h<false, SCV>(c, st, dmaps, n_maps, ditem, ni, queue, order, norm,           \
-                                                best_key_per_map_dev, shm)
-            switch (sc) {
-            case 0: STT_BATCH_SC(0); break;
-            case 1: STT_BATCH_SC(1); break;
-            case 2: STT_BATCH_SC(2); break;
-            case 4: STT_BATCH_SC(4); break;
-            case 8: STT_BATCH_SC(8); break;
-            case 16: STT_BATCH_SC(16); break;
-            default: r = fail(c, STT_EUNSUPPORTED, "no batch scorer for %d-column slabs", sc);
-            }
+#define STT_BATCH_SC(MT, SCV)                                                                                  \
+    r = c->hw_trig ? launch_batch_h<true, MT, SCV>(c, st, dmaps, n_maps, ditem, ni, queue, order, norm,        \
+                                                   best_key_per_map_dev, shm)                                 \
+                   : launch_batch_h<false, MT, SCV>(c, st, dmaps, n_maps, ditem, ni, queue, order, norm,       \
+                                                    best_key_per_map_dev, shm)
+#define STT_BATCH_MT(MT)                                                                                       \
+    switch (sc) {                                                                                              \
+    case 0: STT_BATCH_SC(MT, 0); break;                                                                        \
+    case 2: STT_BATCH_SC(MT, 2); break;                                                                        \
+    case 4: STT_BATCH_SC(MT, 4); break;                                                                        \
+    case 8: STT_BATCH_SC(MT, 8); break;                                                                        \
+    case 16: STT_BATCH_SC(MT, 16); break;                                                                      \
+    default: r = fail(c, STT_EUNSUPPORTED, "no batch scorer for %d-column slabs", sc);                        \
+    }
+            if (dtype == STT_P16) { STT_BATCH_MT(kMapPolH) } else { STT_BATCH_MT(kMapPol) }
+#undef STT_BATCH_MT
 #undef STT_BATCH_SC
             if (timed) ev_record(c, 1);
             return r;

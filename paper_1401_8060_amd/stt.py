@@ -175,11 +175,13 @@ class Map:
 
 
 class P16Map:
-    """An FP16 map of the complex SNR p = Y/sigma: data [T][ld][2] float16, p = data * 2^scale_exp."""
+    """An FP16 map of the complex SNR p = Y/sigma in polar form: data [T][ld][2] int16 halves of one
+    32-bit word per pixel, [..., 0] arg p in units of 2^-16 turn, [..., 1] the binary16 bits of
+    |p| * 2^-scale_exp."""
 
     def __init__(self, data: torch.Tensor, scale_exp: int, fq4_lo: int = 1600, dfq4: int = 16):
-        if data.dtype != torch.float16 or data.dim() != 3 or data.shape[2] != 2 or not data.is_cuda:
-            raise ValueError("data must be a [T][F][2] float16 tensor on the GPU")
+        if data.dtype != torch.int16 or data.dim() != 3 or data.shape[2] != 2 or not data.is_cuda:
+            raise ValueError("data must be a [T][F][2] int16 tensor on the GPU")
         if data.stride(2) != 1 or data.stride(1) != 2:
             raise ValueError("pairs must be contiguous and frequency-contiguous")
         self.data = data
@@ -424,8 +426,9 @@ class Context:
         return snr, tau_idx, best_key
 
     def pack_p16(self, m: Map) -> P16Map:
-        """FP16 copy of the map's complex SNR p = Y/sigma with a per-map 2^e scale (synchronises)."""
-        out = torch.empty((m.T, m.F, 2), dtype=torch.float16, device=m.Y.device)
+        """FP16 copy of the map's complex SNR p = Y/sigma in polar form with a per-map 2^e scale
+        (synchronises)."""
+        out = torch.empty((m.T, m.F, 2), dtype=torch.int16, device=m.Y.device)
         e = C.c_int32()
         mc = m.c()
         self._chk(self._L.stt_map_pack_p16(self.h, C.byref(mc), C.c_void_p(out.data_ptr()), m.F, C.byref(e)))

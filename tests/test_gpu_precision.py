@@ -71,7 +71,8 @@ def test_p16_scores_match_oracle_on_the_stored_map(orc, stt, ctx, path, dma):
 
 def test_p16_error_against_fp64_truth_within_storage_bound(orc, stt, ctx):
     """FP16 storage error vs the FP64 score of the FP32 map, bounded per track by
-    2^-11 * sum(|Re p|+|Im p|)/sqrt(N) (each component rounded to 11 bits) plus FP32 slack."""
+    (2^-11 + pi 2^-16) * sum|p|/sqrt(N) (the magnitude rounded to 11 significant bits, the argument
+    to the nearest 2^-16 turn, at most pi 2^-16 rad away) plus FP32 slack."""
     _say("p16 error")
     T, F, n = 500, 400, 5000
     Y, s = synth.noise_map(T, F, seed=6, sigma=("loguniform", 0.5, 2.0))
@@ -88,7 +89,7 @@ def test_p16_error_against_fp64_truth_within_storage_bound(orc, stt, ctx):
         r = orc.rows(t, F)
         cols = np.arange(int(t["t0"]), int(t["t2"]) + 1)
         pk = p[cols, r]
-        bound[i] = 2.0 ** -11 * (np.abs(pk.real) + np.abs(pk.imag)).sum() / math.sqrt(cols.size)
+        bound[i] = (2.0 ** -11 + math.pi * 2.0 ** -16) * np.abs(pk).sum() / math.sqrt(cols.size)
     err = np.abs(z16 - z64)
     assert (err <= bound + 1e-5).all()
     _say(f"FP16 vs FP64: max |dz| {err.max():.2e}, mean {err.mean():.2e}")

@@ -32,16 +32,46 @@ def test_topk_matches_a_library_sort(orc):
 # --------------------------------------------------------------------------- FP16 storage
 
 def test_fp16_storage_within_half_ulp(orc):
+    """Magnitude within half a binary16 ulp (relative 2^-11) or the subnormal step, argument within
+    half of 2^-16 turn, of the FP64 p; the exponent puts the largest magnitude in (2^14, 2^15]."""
     Y, s = synth.noise_map(60, 50, seed=3, sigma=("loguniform", 0.5, 2.0))
     Y[10, 7] = np.complex64(1000.0 * s[10, 7])  # a loud pixel sets the exponent
     q, e, deq = orc.quantize_p16(Y, s)
     p = Y.astype(np.complex128) / s.astype(np.float64)
-    assert 2.0 ** 14 < np.abs(deq.real).max() / 2.0 ** e <= 2.0 ** 15
-    # round to nearest: each component within half an FP16 ulp (relative 2^-11) or the subnormal step
-    for a, b in ((deq.real, p.real), (deq.imag, p.imag)):
-        err = np.abs(a - b)
-        lim = np.maximum(np.abs(b) * 2.0 ** -11, 2.0 ** (e - 25)) + np.abs(b) * 2.0 ** -23
-        assert (err <= lim).all()
+    assert 2.0 ** 14 < np.abs(deq).max() / 2.0 ** e <= 2.0 ** 15
+    mag16 = q[..., 1].view(np.float16).astype(np.float64) * 2.0 ** e
+    # the FP32 division that forms p adds at most 2^-24 relative
+    lim = np.maximum(np.abs(p) * 2.0 ** -11, 2.0 ** (e - 25)) + np.abs(p) * 2.0 ** -23
+    assert (np.abs(mag16 - np.abs(p)) <= lim).all()
+    d_turn = (q[..., 0].astype(np.float64) / 65536.0 - np.angle(p) / (2 * np.pi) + 0.5) % 1.0 - 0.5
+    assert (np.abs(d_turn) <= 2.0 ** -17 + 2.0 ** -22).all()
+    assert np.allclose(deq, mag16 * np.exp(2j * np.pi * q[..., 0] / 65536.0), rtol=0, atol=1e-12 * 2.0 ** e)
+
+
+def test_fp16_storage_exact_cases(orc):
+    """Worked values: magnitudes that binary16 holds exactly are kept; the four axis directions and
+    the diagonals take exact arguments (0, 1/8, 1/4, 1/2, 3/4 turn); ties of the magnitude go to
+    even; the exponent is ceil(log2 max|p|) - 15 (a power-of-two maximum is its own ceiling)."""
+    one = np.ones((1, 9), dtype=np.float32)
+    Y = np.array([[4.0, 4j, -4.0, -4j, 3 + 3j, 2.0, 1.0 + 2.0 ** -11, 1.0 + 3 * 2.0 ** -11, 0.0]],
+                 dtype=np.complex64)
+    q, e, deq = orc.quantize_p16(Y, one)
+    assert e == 3 - 15  # max |p| = 3 sqrt(2) = 4.24: ceil(log2) = 3
+    mag = q[0, :, 1].view(np.float16).astype(np.float64) * 2.0 ** e
+    assert list(q[0, :5, 0]) == [0, 16384, 32768, 49152, 8192]
+    assert mag[0] == mag[1] == mag[2] == mag[3] == 4.0 and mag[5] == 2.0
+    # 3 sqrt(2) * 2^12 = 17378.9: binary16 steps by 16 there, to 17376
+    assert mag[4] * 2.0 ** -e == 17376.0
+    # 1 + 2^-11 scaled by 2^12 is 4098, halfway between the neighbours 4096 (even) and 4100: 4096;
+    # 1 + 3 2^-11 is 4102, halfway between 4100 and 4104 (even): 4104
+    assert mag[6] == 1.0 and mag[7] * 2.0 ** -e == 4104.0
+    assert q[0, 8, 0] == 0 and mag[8] == 0.0 and deq[0, 8] == 0
+    # an exact power of two as the maximum is its own ceiling: max |p| = 8 gives e = 3 - 15
+    _, e8, _ = orc.quantize_p16(np.array([[8.0, 1.0]], np.complex64), np.ones((1, 2), np.float32))
+    assert e8 == 3 - 15
+    # a map of zeros: exponent 0, everything zero
+    q0, e0, d0 = orc.quantize_p16(np.zeros((2, 3), np.complex64), np.ones((2, 3), np.float32))
+    assert e0 == 0 and not q0.any() and not d0.any()
 
 
 # --------------------------------------------------------------------------- smooth SNR
