@@ -98,68 +98,94 @@ __global__ __launch_bounds__(256) void k_fold_p(MapP m, float2 *out, int64_t ld_
     }
 }
 
+// arg (x + iy) as a 32-bit fraction of a turn, from FP32 components. The first
+// octant's angle atan(a), a = min(|x|, |y|) / max(|x|, |y|), is reduced to
+// |t| <= tan(pi/8) (atan(a) = pi/4 + atan((a - 1)/(a + 1)) above), evaluated as
+// atan(t)/(2 pi) = t P(t^2) in FP32 (coefficients from gen_atan_coeffs.py) and
+// rounded to 2^-32 turn; the octant and quadrant are then undone in integers
+// (eighths of a turn are exact). The polynomial in FP32 is within 41 units of
+// 2^-32 turn; with the FP32 division and reduction about 100 units (2.3e-8
+// turn) in all -- well below the 2^-24-turn rounding of the phase each term
+// takes before its cosine. arg 0 = 0 (its magnitude is 0 then).
+__device__ __forceinline__ uint32_t arg_turns(float x, float y)
+{
+    const float ax = fabsf(x), ay = fabsf(y);
+    const bool swap = ay > ax;  // the angle from the nearer axis is atan(min/max)
+    const float num = swap ? ax : ay, den = swap ? ay : ax;
+    const float a = den > 0.0f ? num / den : 0.0f;
+    const bool hi = a > 0.41421356f;
+    const float t = hi ? (a - 1.0f) / (a + 1.0f) : a;
+    const float s = t * t;
+    float q = -9.602202103e-03f;
+    q = fmaf(q, s, 1.682715677e-02f);
+    q = fmaf(q, s, -2.266363613e-02f);
+    q = fmaf(q, s, 3.182814270e-02f);
+    q = fmaf(q, s, -5.305160582e-02f);
+    q = fmaf(q, s, 1.591549367e-01f);
+    const int32_t f = (int32_t)rintf(t * q * 4294967296.0f);  // |t q| <= 1/16 turn
+    uint32_t u = (uint32_t)((hi ? (1 << 29) : 0) + f);        // first-octant angle
+    if (swap) u = (1u << 30) - u;                               // first quadrant
+    if (x < 0.0f) u = (1u << 31) - u;                           // second quadrant
+    if (y < 0.0f) u = 0u - u;                                   // lower half, modulo one turn
+    return u;
+}
+
 // Polar form of p: (|p| rounded to FP32, arg p in 2^-32 turn as the bits of the second word).
-// The FP32 components are exact in FP64, so |p|^2 = x^2 + y^2 is rounded once, its square root
-// once more and the result once to FP32; the FP64 argument is within a few 1e-16 turn of arg p
-// before its rounding to the 2^-32 grid (wrapping modulo one turn).
+// The FP32 components square exactly in FP64, so |p|^2 = x^2 + y^2 is rounded once, its square
+// root once more and the result once to FP32.
 __device__ __forceinline__ float2 polar_of(float2 p)
 {
     const double x = p.x, y = p.y;
     const float mag = (float)sqrt(fma(x, x, y * y));
-    const double turns = atan2(y, x) * 0.15915494309189535;  // in [-1/2, 1/2]
-    const uint32_t arg = (uint32_t)(int64_t)rint(turns * 4294967296.0);
-    return make_float2(mag, __uint_as_float(arg));
+    return make_float2(mag, __uint_as_float(arg_turns(p.x, p.y)));
 }
 
 // p of every pixel in polar form into a map with column stride ld_out (pixels F..ld_out-1 of a
 // column are zero): from Y/sigma of an FP32 map, or from the exact FP32 values of an FP16 map's
-// entries (load_p's expression).
+// entries (load_p's expression). Grid: column blockIdx.x, y strides over its rows.
 template <int MAPT>
 __global__ __launch_bounds__(256) void k_fold_polar(MapP m, float2 *out, int64_t ld_out)
 {
-    const int64_t n = (int64_t)m.T * ld_out;
-    for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < n; i += (int64_t)gridDim.x * 256) {
-        const int64_t t = i / ld_out, r = i - t * ld_out;
-        out[i] = r < m.F ? polar_of(load_p<MAPT>(m, t * m.ld + r)) : make_float2(0.0f, 0.0f);
-    }
+    const int64_t t = blockIdx.x;
+    for (int64_t r = (int64_t)blockIdx.y * 256 + threadIdx.x; r < ld_out; r += (int64_t)gridDim.y * 256)
+        out[t * ld_out + r] = r < m.F ? polar_of(load_p<MAPT>(m, t * m.ld + r)) : make_float2(0.0f, 0.0f);
 }
 
 // The words of an FP16 map into the folded layout (column stride ld_out, pixels F..ld_out-1 zero).
+// Grid: column blockIdx.x, y strides over its rows.
 __global__ __launch_bounds__(256) void k_fold_words(MapP m, uint32_t *out, int64_t ld_out)
 {
-    const int64_t n = (int64_t)m.T * ld_out;
+    const int64_t t = blockIdx.x;
     const uint32_t *w = reinterpret_cast<const uint32_t *>(m.Y);
-    for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < n; i += (int64_t)gridDim.x * 256) {
-        const int64_t t = i / ld_out, r = i - t * ld_out;
-        out[i] = r < m.F ? w[t * m.ld + r] : 0u;
-    }
+    for (int64_t r = (int64_t)blockIdx.y * 256 + threadIdx.x; r < ld_out; r += (int64_t)gridDim.y * 256)
+        out[t * ld_out + r] = r < m.F ? w[t * m.ld + r] : 0u;
 }
 
-// One fold of a batch: map src into dst (column stride ld_out); its pixels are px0 .. px0 +
-// T*ld_out - 1 of the batch's run (px0 ascending over the maps).
+// One fold of a batch: map src into dst (column stride ld_out); its columns are col0 .. col0 +
+// T - 1 of the batch's column run (col0 ascending over the maps).
 struct FoldJob {
     MapP src;
     void *dst;
     int64_t ld_out;
-    uint64_t px0;
+    uint32_t col0;
 };
 
-// Every map of a batch in one launch: the grid strides over the batch's pixel run and finds
-// each pixel's map by bisection of px0 (jobs[n_jobs].px0 = the total). FP32 maps fold to polar
-// form (k_fold_polar), FP16 maps copy their words (k_fold_words).
+// Every map of a batch in one launch: blockIdx.x runs over the batch's columns, each workgroup
+// finds its map once by bisection of col0 (jobs[n_jobs].col0 = the total), y strides over rows.
+// FP32 maps fold to polar form (k_fold_polar), FP16 maps copy their words (k_fold_words).
 template <int MAPT>
 __global__ __launch_bounds__(256) void k_fold_batch(const FoldJob *jobs, int n_jobs)
 {
-    const uint64_t total = jobs[n_jobs].px0;
-    for (uint64_t i = (uint64_t)blockIdx.x * 256 + threadIdx.x; i < total; i += (uint64_t)gridDim.x * 256) {
-        int lo = 0, hi = n_jobs;  // jobs[lo].px0 <= i < jobs[hi].px0
-        while (hi - lo > 1) {
-            const int mid = (lo + hi) >> 1;
-            if (jobs[mid].px0 <= i) lo = mid; else hi = mid;
-        }
-        const FoldJob &j = jobs[lo];
-        const int64_t k = (int64_t)(i - j.px0);
-        const int64_t t = k / j.ld_out, r = k - t * j.ld_out;
+    const uint32_t col = blockIdx.x;
+    int lo = 0, hi = n_jobs;  // jobs[lo].col0 <= col < jobs[hi].col0
+    while (hi - lo > 1) {
+        const int mid = (lo + hi) >> 1;
+        if (jobs[mid].col0 <= col) lo = mid; else hi = mid;
+    }
+    const FoldJob &j = jobs[lo];
+    const int64_t t = (int64_t)(col - j.col0);
+    for (int64_t r = (int64_t)blockIdx.y * 256 + threadIdx.x; r < j.ld_out; r += (int64_t)gridDim.y * 256) {
+        const int64_t k = t * j.ld_out + r;
         if constexpr (MAPT == kMapP16) {
             ((uint32_t *)j.dst)[k] = r < j.src.F ? reinterpret_cast<const uint32_t *>(j.src.Y)[t * j.src.ld + r] : 0u;
         } else {

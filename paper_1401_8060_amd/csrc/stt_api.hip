@@ -565,11 +565,11 @@ stt_status fold_polar(stt_ctx *c, const stt_map *map, const FixedBufs *fb, MapP 
         if (s != STT_OK) return s;
     }
     void *pbuf = fb ? fb->pbuf : c->pbuf;
-    const unsigned fg = (unsigned)std::min<int64_t>(((int64_t)m.T * ldc + 255) / 256, 8192);
+    const dim3 fg((unsigned)m.T, (unsigned)((ldc + 255) / 256));  // one column per x, rows over y
     if (map->dtype == STT_P16)
-        hipLaunchKernelGGL(k_fold_words, dim3(fg), dim3(256), 0, c->stream, m, (uint32_t *)pbuf, ldc);
+        hipLaunchKernelGGL(k_fold_words, fg, dim3(256), 0, c->stream, m, (uint32_t *)pbuf, ldc);
     else
-        hipLaunchKernelGGL(k_fold_polar<kMapF32>, dim3(fg), dim3(256), 0, c->stream, m, (float2 *)pbuf, ldc);
+        hipLaunchKernelGGL(k_fold_polar<kMapF32>, fg, dim3(256), 0, c->stream, m, (float2 *)pbuf, ldc);
     STT_HIP(c, hipGetLastError());
     mf = m;  // an FP16 map keeps its scale 2^e
     mf.Y = (const float2 *)pbuf;
@@ -1430,8 +1430,9 @@ stt_status stt_score_batch(stt_ctx *c, const stt_map *maps_host, int32_t n_maps,
     uint64_t norder = 0, nchunks = 0, nitems = 0;
     size_t shm = 0;
     bool dma_ok = c->dma;  // every map's column fits two DMA slabs
-    uint64_t fold_px = 0;
-    std::vector<uint64_t> fold_off(n_maps, 0);
+    uint64_t fold_px = 0, fold_cols = 0;
+    std::vector<uint64_t> fold_off(n_maps, 0), fold_col(n_maps, 0);
+    int64_t max_ldc = 0;
     for (int i = 0; i < n_maps; ++i) {
         const stt_map *mp = &maps_host[i];
         stt_status s = check_map(c, mp);
@@ -1457,6 +1458,8 @@ stt_status stt_score_batch(stt_ctx *c, const stt_map *maps_host, int32_t n_maps,
             dma_ok = dma_ok && aligned_slab(dma_slab_cols(c, ldc, esize)) >= 2;
             fold_off[i] = fold_px;
             fold_px += (uint64_t)mp->T * (uint64_t)ldc;
+            fold_col[i] = fold_cols;
+            fold_cols += (uint64_t)mp->T;
         }
         d.snr = snr_dev_host ? snr_dev_host[i] : nullptr;
         chunk_start[i] = (uint32_t)nchunks;
@@ -1490,7 +1493,8 @@ stt_status stt_score_batch(stt_ctx *c, const stt_map *maps_host, int32_t n_maps,
         BatchMap &d = bm[i];
         const int64_t ldc = fold_ld(d.m.F, esize);
         void *dst = (char *)c->pbuf + (size_t)esize * fold_off[i];
-        jobs[i] = FoldJob{orig[i], dst, ldc, fold_off[i]};
+        jobs[i] = FoldJob{orig[i], dst, ldc, (uint32_t)fold_col[i]};
+        max_ldc = std::max(max_ldc, ldc);
         d.m.Y = (const float2 *)dst;  // an FP16 map keeps its scale 2^e
         d.m.sig = nullptr;
         d.m.ld = ldc;
@@ -1501,7 +1505,7 @@ stt_status stt_score_batch(stt_ctx *c, const stt_map *maps_host, int32_t n_maps,
             shm = std::max(shm, (size_t)esize * (size_t)d.S * (size_t)d.m.F);
         }
     }
-    jobs[n_maps] = FoldJob{MapP{}, nullptr, 0, fold_px};
+    jobs[n_maps] = FoldJob{MapP{}, nullptr, 0, (uint32_t)fold_cols};
     if (!c->n_cu) STT_HIP(c, hipDeviceGetAttribute(&c->n_cu, hipDeviceAttributeMultiprocessorCount, c->device));
 
     // scratch: [totals | cursor | queue | order]
@@ -1562,7 +1566,7 @@ stt_status stt_score_batch(stt_ctx *c, const stt_map *maps_host, int32_t n_maps,
             const bool timed = st == c->stream;  // events only outside graph capture
             if (timed) ev_record(c, 2);
             {
-                const unsigned fg = (unsigned)std::min<uint64_t>((fold_px + 255) / 256, 16384);
+                const dim3 fg((unsigned)fold_cols, (unsigned)((max_ldc + 255) / 256));  // columns over x, rows over y
                 if (dtype == STT_P16)
                     hipLaunchKernelGGL(k_fold_batch<kMapP16>, dim3(fg), dim3(256), 0, st, (const FoldJob *)djobs,
                                        n_maps);
