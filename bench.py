@@ -27,24 +27,45 @@ HBM_PEAK_GBS = 8000.0
 TUNE_CACHE = os.path.join(ROOT, "paper_1401_8060_amd", "tuning", "gfx950.json")
 KERNEL_SOURCES = [os.path.join(ROOT, "paper_1401_8060_amd", "csrc", f) for f in ("kernels.hpp", "dev_common.hpp")]
 MAPFORM_SOURCES = [os.path.join(ROOT, "paper_1401_8060_amd", "csrc", "mapform.hpp")]
-BYTES_F32 = 12  # complex64 Y + float32 sigma: the pixel record one template pixel reads
-BYTES_P16 = 4   # FP16 (re, im) of p = Y/sigma
-# Arithmetic of one template pixel (Eq. 6 row, Eq. 8 term), counted as flops:
-# row floor(num/Q) by the second-order recurrence (2 adds) and one scaled
-# rounding (fused multiply-add, 2); phase f*dtau (multiply-add, 2); sine and
-# cosine (1 each); Re[e^{i phi} p] = cos*p_re - sin*p_im (2 multiplies, 1 add);
-# accumulation (1 add).
-FLOPS_PER_TRACK_PX = 12
-# The scorer's core loop per template pixel, as issued on gfx950: FP64 fma + 2 FP64 adds (row),
-# a VOP3 shift-add (LDS address), v_mad_u64_u32 and v_alignbit_b32 (phase), hardware sine and
-# cosine, 2 FP32 FMAs (term). With the issue rates measured by a probe of independent instructions
-# (lanes per clock per CU: FP64 46, VOP3 integer 57, mad_u64 51, sin/cos 28, FP32 FMA 81), one CU
-# completes 1 / sum(1 / rate) template pixels per clock.
-CORE_MIX = {"f64": (3, 46.0), "vop3_int": (2, 57.0), "mad_u64": (1, 51.0), "trans": (2, 28.0), "fma_f32": (2, 81.0)}
-ISSUE_CEILING_PX_S = 256 * 2.4e9 / sum(k / r for k, r in CORE_MIX.values())
-# Vector ALU peak without packed FP32 (the build disables packed FP32 ops):
-# 256 CUs x 64 lanes x 2 flops (FMA) x 2.4 GHz, also the FP64 vector peak.
-ALU_PEAK_TFLOPS = 78.6
+BYTES_F32 = 12  # complex64 Y + float32 sigma: the caller's pixel record of one template pixel
+BYTES_P16 = 4   # one 32-bit polar word of an FP16 map
+
+# ---- the roofline: vector-ALU issue, from gfx950's unit counts and clock -----------------------
+# 256 CUs, each 4 SIMDs of 16 lanes; per clock a CU completes 64 lanes of a full-rate instruction
+# (FP64 add and FMA, 32-bit integer multiply and three-operand add, shift-add, funnel shift, FP32
+# with a 16-bit operand), 128 lanes of an FP32 FMA or add or a 32-bit integer add, 32 lanes of a
+# transcendental (sine, cosine, square root, reciprocal). The probe library measures these rates
+# at the live shader clock (bench.py --issue-rates; profiles/issue_rates_gfx950.md): 60-61, 103-114
+# and 31 lanes per clock per CU.
+N_CU, CLOCK_HZ = 256, 2.4e9
+LANES_PER_CLK = {"full": 64, "double": 128, "trans": 32}
+FP32_PEAK_TFLOPS = 157.3              # 256 x 128 lanes x 2 flops x 2.4 GHz
+LDS_PEAK_GBS = N_CU * 128 * CLOCK_HZ / 1e9  # 128 bytes per clock per CU: 78.6 TB/s
+# Instructions of the inner loop per template pixel (one template, one column), by issue class:
+#   plain scorer, FP32 map (polar fold): the row of Eq. 6 by the exact FP64 recurrence (1 FMA,
+#   2 adds), its LDS address (shift-add), the phase of Eq. 8 plus arg p (integer multiply, add3),
+#   the phase as FP32 turns (funnel shift): 7 full-rate; the cosine: 1 transcendental; the term's
+#   FMA: 1 double-rate. FP16 map: the term takes its binary16 magnitude in a mixed FMA (full rate).
+CORE_MIX = {"full": 7, "double": 1, "trans": 1}
+CORE_MIX_P16 = {"full": 8, "double": 0, "trans": 1}
+#   free t_mid: the row is an independent root per column -- FP32 argument of the square root and
+#   its conversions, the reduced root 2 dt / (b + sqrt(D)) and its Bezier value, the floor and the
+#   certified-window test: 9 full, 6 double, square root and reciprocal; then the plain term
+#   (address, phase, turns: 4 full; cosine; FMA).
+CORE_MIX_TM = {"full": 13, "double": 7, "trans": 3}
+#   delay grid, per template pixel of one launch of 8 delays: row and address (4 full); first
+#   delay's phase (3 full), sine and cosine; the grid step's phase (3 full), sine and cosine; 7
+#   rotations of (cos, sin) (4 double each) and 8 term FMAs (double).
+CORE_MIX_MD = {"full": 10, "double": 36, "trans": 4}
+# Algorithmic flops per template pixel (the statistic of Eq. 8 as counted for this path: about 6
+# FP32 flops and one sine-cosine pair, each of sine and cosine counted as one).
+FLOPS_PER_TRACK_PX = 8
+
+
+def issue_ceiling_px_s(mix):
+    """Template pixels per second at which `mix` keeps every SIMD issuing (unit counts x clock)."""
+    return N_CU * CLOCK_HZ / sum(n / LANES_PER_CLK[k] for k, n in mix.items() if n)
+
 
 WORKLOADS = {
     # search-scale plain map: T=1000 x F=1000, 1 s x 1 Hz pixels from 100 Hz, 10^7 tracks, FP32
@@ -188,23 +209,36 @@ def measured_traffic(workload, shape, sources=None):
     return float(kv["traffic_bytes_per_launch"])
 
 
-def roofline(kernel, kernel_ms, px, bpp, traffic=None):
-    """The scorer stages map columns in LDS and re-reads them from there, so its HBM traffic is
-    a small fraction of the pixel records it consumes; what binds it is vector ALU issue. The
-    roofline is therefore ALU flops; the gather line (pixel-record bytes against HBM bandwidth,
-    the metric's "% gather roofline") is reported beside it."""
+def roofline(kernel, kernel_ms, px, bpp, traffic=None, mix=None, lds_bpp=8, units=1, mix_units=1):
+    """Roofline record of a scoring kernel (kernel_ms: its mean launch time; px: template pixels per
+    launch, times `units` evaluations of the statistic per pixel for the delay grid; `mix` counts
+    the instructions of `mix_units` such evaluations).
+
+    The scorers keep map columns in LDS and re-read them there, so HBM carries a small part of the
+    pixel records they consume (measured: `traffic`); what binds them is vector-ALU issue. The
+    peak is the flop rate at which the inner loop's instruction mix (`mix`) keeps every SIMD of the
+    chip issuing (unit counts x 2.4 GHz), with FLOPS_PER_TRACK_PX algorithmic flops per pixel, so
+    frac = achieved pixel rate / issue ceiling. Beside it, not binding: the same flops against the
+    FP32 vector peak; the LDS bytes the kernel reads against the LDS bandwidth; the caller's pixel
+    record against HBM bandwidth (the metric's "% gather roofline", above 1 because pixels come
+    from LDS)."""
+    mix = mix or CORE_MIX
     sec = kernel_ms * 1e-3
-    achieved = px * FLOPS_PER_TRACK_PX / sec / 1e12
-    gather = px * bpp / sec / 1e9
-    return {"bound": "alu", "achieved": achieved, "peak": ALU_PEAK_TFLOPS, "unit": "TFLOP/s",
-            "frac": achieved / ALU_PEAK_TFLOPS, "traffic": traffic, "kernel": kernel, "kernel_ms": kernel_ms,
+    rate = px * units / sec
+    ceiling = issue_ceiling_px_s(mix) * mix_units
+    achieved = rate * FLOPS_PER_TRACK_PX / 1e12
+    return {"bound": "alu", "achieved": achieved, "peak": ceiling * FLOPS_PER_TRACK_PX / 1e12, "unit": "TFLOP/s",
+            "frac": rate / ceiling, "traffic": traffic, "kernel": kernel, "kernel_ms": kernel_ms,
             "flops_per_track_px": FLOPS_PER_TRACK_PX,
-            "gather_line": {"bytes_per_track_px": bpp, "achieved": gather, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                            "frac": gather / HBM_PEAK_GBS},
-            # the same kernel against the issue rate of its own instruction mix (sine, cosine and FP64
-            # issue below the FP32 FMA rate, so the flop peak above is out of its reach)
-            "issue_model": {"achieved_px_s": px / sec, "ceiling_px_s": ISSUE_CEILING_PX_S,
-                            "frac": px / sec / ISSUE_CEILING_PX_S}}
+            "peak_derivation": {"issue_mix_per_px": mix, "lanes_per_clk_per_cu": LANES_PER_CLK, "cus": N_CU,
+                                "clock_hz": CLOCK_HZ, "ceiling_px_s": ceiling},
+            "not_binding": {
+                "fp32_flops": {"achieved": achieved, "peak": FP32_PEAK_TFLOPS, "unit": "TFLOP/s",
+                               "frac": achieved / FP32_PEAK_TFLOPS},
+                "lds_read": {"bytes_per_track_px": lds_bpp, "achieved": rate * lds_bpp / 1e9,
+                             "peak": LDS_PEAK_GBS, "unit": "GB/s", "frac": rate * lds_bpp / 1e9 / LDS_PEAK_GBS},
+                "gather_line": {"bytes_per_track_px": bpp, "achieved": rate * bpp / 1e9, "peak": HBM_PEAK_GBS,
+                                "unit": "GB/s", "frac": rate * bpp / 1e9 / HBM_PEAK_GBS}}}
 
 
 def timed(args, fn, torch):
@@ -315,7 +349,8 @@ def run_batch(args, name, w):
                           "tracks_per_map": w["n"], "map_dtype": args.map_dtype, "graph": True,
                           "slab_shape": list(choice)})
     out["roofline"] = roofline("k_score_batch", kern_ms, px, BYTES_P16 if fp16 else BYTES_F32,
-                               measured_traffic(name + ("_p16" if fp16 else ""), choice))
+                               measured_traffic(name + ("_p16" if fp16 else ""), choice),
+                               mix=CORE_MIX_P16 if fp16 else CORE_MIX, lds_bpp=4 if fp16 else 8)
     if fp16:
         # error of FP16 storage against plain FP32 scoring of the same maps, on two maps in full
         errs = []
@@ -368,7 +403,8 @@ def run_precision(args, name, w):
     out = base_record(args, name, w, n, ms_step, px, "f16")
     out["config"].update({"T": w["T"], "F": w["F"], "n_tracks": n, "map_dtype": "p16", "scale_exp": pm.scale_exp,
                           "top_k": K, "rescore": "f64", "map_sha256": sha[:16], "slab_shape": list(choice)})
-    out["roofline"] = roofline("k_score_slab", kern_ms, px, BYTES_P16, measured_traffic(name, choice))
+    out["roofline"] = roofline("k_score_slab", kern_ms, px, BYTES_P16, measured_traffic(name, choice),
+                               mix=CORE_MIX_P16, lds_bpp=4)
     out["topk_fp16_vs_fp64"] = {"max_abs_dz": err.max().item(), "mean_abs_dz": err.mean().item(),
                                 "reference": "the library's FP64 re-score (k_rescore_f64) of the same templates"}
     if not args.no_cpu_baseline:
@@ -426,13 +462,7 @@ def run_tmid(args, name, w):
     out = base_record(args, name, w, n, ms_step, px, "f32")
     out["config"].update({"T": w["T"], "F": w["F"], "n_tracks": n, "templates": "free t_mid",
                           "map_sha256": sha[:16]})
-    # per template pixel: the root and the Bezier (sqrt, divide, 2 FMA, scale: about 10 flops), the
-    # phase and term as in the plain scorer (8)
-    fl = 18
-    sec = kern_ms * 1e-3
-    out["roofline"] = {"bound": "alu", "achieved": px * fl / sec / 1e12, "peak": ALU_PEAK_TFLOPS, "unit": "TFLOP/s",
-                       "frac": px * fl / sec / 1e12 / ALU_PEAK_TFLOPS, "traffic": None, "kernel": "k_score_tm_slab",
-                       "kernel_ms": kern_ms, "flops_per_track_px": fl}
+    out["roofline"] = roofline("k_score_tm_slab", kern_ms, px, BYTES_F32, None, mix=CORE_MIX_TM)
     out["best"] = {"z": zk, "j": jk}
     ctx.close()
     return out
@@ -476,17 +506,12 @@ def run_maxdelay(args, name, w):
     out["config"].update({"T": w["T"], "F": w["F"], "n_tracks": n, "n_tau": nt, "dtau0": d0, "dtau_step": step,
                           "map_sha256": sha[:16]})
     out["template_delays_per_s"] = n * nt / (ms_step * 1e-3)
-    # one template-delay pixel: phase (2), sine and cosine (2), term (3), accumulation (1); the row (4)
-    # is shared by the delays
     # the grid runs in launches of up to 8 delays; the stage time covers all of them, so one launch
-    # averages kern_ms / launches over (on average) that share of the flops
+    # averages kern_ms / launches over (on average) nt / launches delays of every template pixel
     launches = (nt + 7) // 8
-    flops = px * (4 + 8 * nt)
-    sec = kern_ms * 1e-3
-    out["roofline"] = {"bound": "alu", "achieved": flops / sec / 1e12, "peak": ALU_PEAK_TFLOPS, "unit": "TFLOP/s",
-                       "frac": flops / sec / 1e12 / ALU_PEAK_TFLOPS, "traffic": None, "kernel": "k_score_md_slab",
-                       "kernel_ms": kern_ms / launches, "launches_per_step": launches,
-                       "flops_per_track_px": 4 + 8 * nt}
+    out["roofline"] = roofline("k_score_md_slab", kern_ms / launches, px, BYTES_F32, None, mix=CORE_MIX_MD,
+                               units=nt / launches, mix_units=8)
+    out["roofline"]["launches_per_step"] = launches
     out["best"] = {"z": zk, "j": jk, "delay_index": mk}
     ctx.close()
     return out

@@ -811,16 +811,21 @@ __device__ __forceinline__ uint64_t score_block(const MapP &m, const GenP &g, co
 // One block of binned templates per workgroup. Each workgroup stores its best
 // key in its own slot of wg_keys (no atomics: many same-address atomics from
 // every wave serialise across the chip); k_reduce_keys folds the slots.
+// At least 4 waves per SIMD (at most 128 VGPRs), so that two workgroups of 512 lanes, or four of
+// 256, can share a CU when their slabs fit its LDS.
+constexpr int kSlabWavesPerSimd = 4;
+
 template <int WG, int TPT, bool HW, int MAPT, int SC>
-__global__ __launch_bounds__(WG) void k_score_slab(MapP m, GenP g, const Trk *tr, const uint32_t *order,
-                                                   uint64_t first, int64_t n, int S, int32_t norm, float *snr,
-                                                   uint64_t *wg_keys)
+__global__ __launch_bounds__(WG, kSlabWavesPerSimd) void k_score_slab(MapP m, GenP g, const Trk *tr,
+                                                                      const uint32_t *order, uint64_t first,
+                                                                      int64_t n, int S, int32_t norm, float *snr,
+                                                                      uint64_t *wg_keys)
 {
     extern __shared__ float2 slab[];
     __shared__ int bnd[2];
     __shared__ uint64_t kred[WG / 64];
-    const uint64_t key = score_block<WG, TPT, HW, MAPT, SC>(m, g, tr, order, first, n, (int64_t)blockIdx.x,
-                                                                   S, norm, snr, slab, bnd, kred);
+    const uint64_t key = score_block<WG, TPT, HW, MAPT, SC>(m, g, tr, order, first, n, (int64_t)blockIdx.x, S, norm,
+                                                            snr, slab, bnd, kred);
     if (threadIdx.x == 0) wg_keys[blockIdx.x] = key;
 }
 
@@ -1410,9 +1415,10 @@ __global__ __launch_bounds__(256) void k_bin_scatter_batch(const BatchMap *maps,
 }
 
 template <int WG, int TPT, bool HW, int MAPT, int SC>
-__global__ __launch_bounds__(WG) void k_score_batch(const BatchMap *maps, int n_maps, const uint32_t *item_start,
-                                                    uint32_t *queue, const uint32_t *order, int32_t norm,
-                                                    uint64_t *best)
+__global__ __launch_bounds__(WG, kSlabWavesPerSimd) void k_score_batch(const BatchMap *maps, int n_maps,
+                                                                       const uint32_t *item_start, uint32_t *queue,
+                                                                       const uint32_t *order, int32_t norm,
+                                                                       uint64_t *best)
 {
     extern __shared__ float2 slab[];
     __shared__ int bnd[2];

@@ -1824,8 +1824,9 @@ int log2_floor(int64_t v)
 }
 
 // Generation of the scorers' inner loop: part of every cache key, so that choices timed on an
-// earlier loop are searched again. "pol1": polar folded map, one cosine per pixel.
-constexpr const char *kCoreTag = "pol1";
+// earlier loop are searched again. "pol2": polar folded map, one cosine per pixel, slab scorers
+// held to 128 VGPRs (4 waves per SIMD).
+constexpr const char *kCoreTag = "pol2";
 
 // maps of similar duration (power-of-two bucket) and call size share a choice
 std::string tune_key(const stt_ctx *c, const stt_map *m, int64_t n)
