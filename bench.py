@@ -48,11 +48,12 @@ LDS_PEAK_GBS = N_CU * 128 * CLOCK_HZ / 1e9  # 128 bytes per clock per CU: 78.6 T
 #   FMA: 1 double-rate. FP16 map: the term takes its binary16 magnitude in a mixed FMA (full rate).
 CORE_MIX = {"full": 7, "double": 1, "trans": 1}
 CORE_MIX_P16 = {"full": 8, "double": 0, "trans": 1}
-#   free t_mid: the row is an independent root per column -- FP32 argument of the square root and
-#   its conversions, the reduced root 2 dt / (b + sqrt(D)) and its Bezier value, the floor and the
-#   certified-window test: 9 full, 6 double, square root and reciprocal; then the plain term
-#   (address, phase, turns: 4 full; cosine; FMA).
-CORE_MIX_TM = {"full": 13, "double": 7, "trans": 3}
+#   free t_mid: the row is an independent root per column -- D = b^2 + 4 a dt and 2 dt carried by
+#   one add each (2 double), D as FP32 (full), square root and reciprocal of the reduced root
+#   2 dt / (b + sqrt(D)) (2 transcendental; its add, multiply and the two FMAs of the Bezier value:
+#   4 double), the fraction, truncation and certified-window test (fraction, convert, compare: 3
+#   full; subtract: 1 double); then the plain term (address, phase, turns: 4 full; cosine; FMA).
+CORE_MIX_TM = {"full": 8, "double": 8, "trans": 3}
 #   delay grid, per template pixel of one launch of 8 delays: row and address (4 full); first
 #   delay's phase (3 full), sine and cosine; the grid step's phase (3 full), sine and cosine; 7
 #   rotations of (cos, sin) (4 double each) and 8 term FMAs (double).

@@ -185,6 +185,7 @@ struct RowTm {
     int32_t bb, a4;        // b^2 and 4 a: D = bb + a4 dt, exact in 32 bits for T <= 2896
     float bf, fs, Bs, Cs;  // b, f0/256, B/256, C/256
     float tol;             // bound on |y32 - f(xi)/256| over the template, in rows
+    float hw;              // |fract(y32) - 1/2| < hw certifies tol < fract(y32) < 1 - tol
 };
 
 STT_HD RowTm row_tm_init(const TrkTm &t)
@@ -200,16 +201,27 @@ STT_HD RowTm row_tm_init(const TrkTm &t)
     k.fs = (float)t.f0 * (1.0f / 256.0f);
     k.Bs = (float)B * (1.0f / 256.0f);
     k.Cs = (float)C * (1.0f / 256.0f);
-    // Error of the FP32 pass, to first order in u = 2^-24, with each of sqrt and rcp within
-    // 1 ulp (2u relative): (float)D, sqrt, b + s (b, sqrt(D) >= 0: no cancellation), rcp and
-    // * 2dt leave xi = xi_exact (1 + e), |e| <= 6.5u. The rounded B/256 and C/256 (u each) and
-    // the two FMAs (u each) then give, for xi <= 1,
-    //   |g32 - g| <= 8.5u xi |C'| + 2u |B'|             (g = B' + C' xi)
-    //   |y32 - y| <= 9.5u |B'| + 16u |C'| + u f0'       (y = f0' + g xi, primes: / 256).
-    // The window is 1.5 times (10u |B'| + 17u |C'| + u f0'), plus 2^-20.
+    // Error of the FP32 pass, to first order in u = 2^-24. B/256, C/256 and f0/256 are exact
+    // (|B|, |C| < 2^24 for F <= 32767). With each of sqrt and rcp within 1 ulp (2u relative),
+    // (float)D, sqrt, b + s (b, sqrt(D) >= 0: no cancellation), rcp and * 2dt leave
+    // xi32 = xi (1 + e), |e| <= 6.5u. Then g32 = fl(xi32 C' + B') = (g + C' xi e)(1 + e1) and
+    // y32 = fl(xi32 g32 + f0') = (xi32 g32 + f0')(1 + e2) (primes: / 256, g = B' + C' xi), so
+    //   y32 - y = xi e f'(xi) + xi g e1 + y e2 + O(u^2),   f'(xi) = B' + 2 C' xi.
+    // f' is linear in xi, so |f'| <= max(|B'|, |B' + 2C'|) on [0, 1]; y and f0' + xi g = y lie in
+    // [0, M'] (M' = max(f0, f1, f2) / 256: y is a convex combination of the control values), so
+    // |xi g| <= M' and
+    //   |y32 - y| <= 6.5u max(|B'|, |B' + 2C'|) + 2u M'.
+    // The window is 1.25 times that, plus 2^-20 for the second-order terms.
     const double u = 1.0 / 16777216.0;
-    const double aB = std::fabs((double)B) / 256.0, aC = std::fabs((double)C) / 256.0;
-    k.tol = (float)(1.5 * (10.0 * u * aB + 17.0 * u * aC + u * (double)t.f0 / 256.0) + 1.0 / 1048576.0);
+    const double d0 = std::fabs((double)B) / 256.0, d1 = std::fabs((double)(B + 2 * C)) / 256.0;
+    const double M = (double)std::max(t.f0, std::max(t.f1, t.f2)) / 256.0;
+    k.tol = (float)(1.25 * (6.5 * u * std::max(d0, d1) + 2.0 * u * M) + 1.0 / 1048576.0);
+    // fr - 1/2 is exact for fr >= 1/4 and within 2^-26 below (its result lies in (-1/2, -1/4]),
+    // so hw = 1/2 - tol - 2^-26, rounded towards zero, keeps the certified fractions inside
+    // (tol, 1 - tol).
+    const double hw = 0.5 - (double)k.tol - 1.0 / 67108864.0;
+    k.hw = (float)hw;
+    if ((double)k.hw > hw) k.hw = nextafterf(k.hw, 0.0f);
     return k;
 }
 
@@ -266,19 +278,45 @@ STT_HD int32_t row_tm_exact(const RowTm &k, int32_t dt, int32_t D, float s32)
     return row_tm_decide(k, dt, D, y);
 }
 
-// Row of column t0 + dt (0 <= dt <= t2 - t0): an FP32 pass whose result stands when it lies
-// farther than tol from a row boundary (the FP32 error is below tol, so the exact value is on the
-// same side); otherwise the exact path.
-STT_HD int32_t row_tm(const RowTm &k, int32_t dt)
+// Row of column t0 + dt (0 <= dt <= t2 - t0) by the FP32 pass: the floor of y32, and in `ok`
+// whether it stands, i.e. y32 lies farther than tol from a row boundary (the FP32 error is below
+// tol, so the exact value is on the same side). A row that does not stand may be off by one and
+// lie outside [0, F).
+// The pass from D = b^2 + 4 a dt and dt2 = 2 dt (as a float, exact) given by the caller.
+STT_HD int32_t row_tm_fp32_d(const RowTm &k, int32_t D, float dt2, bool &ok)
+{
+    const float s32 = sqrt_1ulp((float)D);
+    const float xi = dt2 * rcp_1ulp(k.bf + s32);
+    const float y = fmaf(xi, fmaf(xi, k.Cs, k.Bs), k.fs);
+    // A value that stands lies above tol > 0 (the exact value is >= 0), where truncation is the
+    // floor and the fraction y - floor(y) is exact.
+#if defined(__HIP_DEVICE_COMPILE__)
+    const float fr = __builtin_amdgcn_fractf(y);
+#else
+    const float fr = y - floorf(y);
+#endif
+    ok = fabsf(fr - 0.5f) < k.hw;
+    return (int32_t)y;
+}
+
+STT_HD int32_t row_tm_fp32(const RowTm &k, int32_t dt, bool &ok)
+{
+    return row_tm_fp32_d(k, k.bb + mul_i24(k.a4, dt), (float)(2 * dt), ok);
+}
+
+// The row where the FP32 pass does not stand: its square root again (the same bits), then the
+// exact path.
+STT_HD int32_t row_tm_fallback(const RowTm &k, int32_t dt)
 {
     const int32_t D = k.bb + mul_i24(k.a4, dt);
-    const float s32 = sqrt_1ulp((float)D);
-    const float xi = (float)(2 * dt) * rcp_1ulp(k.bf + s32);
-    const float y = fmaf(xi, fmaf(xi, k.Cs, k.Bs), k.fs);
-    const float r = floorf(y);
-    const float fr = y - r;  // exact
-    if (fr > k.tol && fr < 1.0f - k.tol) return (int32_t)r;
-    return row_tm_exact(k, dt, D, s32);
+    return row_tm_exact(k, dt, D, sqrt_1ulp((float)D));
+}
+
+STT_HD int32_t row_tm(const RowTm &k, int32_t dt)
+{
+    bool ok;
+    const int32_t r = row_tm_fp32(k, dt, ok);
+    return ok ? r : row_tm_fallback(k, dt);
 }
 
 // ----------------------------------------------------------------------------

@@ -911,23 +911,62 @@ __global__ __launch_bounds__(256) void k_score_tm(MapP m, GenP g, const TrkTm *t
     merge_key(best, key);
 }
 
-// Column walk of the free-t_mid slab scorer (as walk, with an independent row per column).
+// Column walk of the free-t_mid slab scorer (as walk, with an independent row per column). The
+// FP32 pass takes every template's row of the column, with D = b^2 + 4 a dt and 2 dt carried from
+// column to column by one add each; where it does not stand for some lane (about one template
+// pixel in a thousand on the search band), the whole wave takes one uniform branch in which those
+// lanes settle their rows exactly. A lane outside its template's columns works on column t0 + 1
+// (valid for every template) and drops the term.
+// Column walk of the free-t_mid slab scorer (as walk, with an independent row per column). The
+// FP32 pass takes every template's row of the column, with D = b^2 + 4 a dt and 2 dt carried from
+// column to column by one add each; where it does not stand for some lane (about one template
+// pixel in a thousand on the search band), the whole wave takes one uniform branch in which those
+// lanes settle their rows exactly. A lane outside its template's columns works on column t0 + 1
+// (valid for every template) and drops the term.
 template <int TPT, bool MASK, bool HW, typename E>
 __device__ __forceinline__ void walk_tm(int ca, int cb, int c0, const E *slab, int ldc, const int32_t (&t0)[TPT],
                                         const uint32_t (&span)[TPT], const RowTm (&rk)[TPT],
                                         const PhaseK (&pk)[TPT], float (&part)[TPT], double (&acc)[TPT])
 {
+    int32_t Dc[TPT];
+    float dt2c[TPT];
+#pragma unroll
+    for (int q = 0; q < TPT; ++q) {
+        // modulo 2^32: a lane that holds no template (t0 = INT_MAX) only ever takes the masked walk
+        const uint32_t dt = (uint32_t)ca - (uint32_t)t0[q];
+        Dc[q] = (int32_t)((uint32_t)rk[q].bb + (uint32_t)rk[q].a4 * dt);
+        dt2c[q] = 2.0f * (float)(int32_t)dt;
+    }
     for (int c = ca; c <= cb;) {
         const int ce = min(cb, c | (kFlush - 1));
         for (; c <= ce; ++c) {
+            int32_t row[TPT];
+            bool act[TPT], ok[TPT];
+            bool redo = false;
+#pragma unroll
+            for (int q = 0; q < TPT; ++q) {
+                act[q] = !MASK || (uint32_t)(c - t0[q]) <= span[q];
+                const int32_t D = act[q] ? Dc[q] : rk[q].bb + rk[q].a4;
+                row[q] = row_tm_fp32_d(rk[q], D, act[q] ? dt2c[q] : 2.0f, ok[q]);
+                ok[q] = ok[q] || !act[q];
+                redo = redo || !ok[q];
+                Dc[q] = (int32_t)((uint32_t)Dc[q] + (uint32_t)rk[q].a4);
+                dt2c[q] += 2.0f;
+            }
+            if (__builtin_amdgcn_ballot_w64(redo)) {  // wave-uniform
+                // the column through readfirstlane: no induction variables for this rare branch
+                // are kept up to date in the loop
+                const int cu = __builtin_amdgcn_readfirstlane(c);
+#pragma unroll
+                for (int q = 0; q < TPT; ++q)
+                    if (!ok[q]) row[q] = row_tm_fallback(rk[q], cu - t0[q]);
+            }
             const E *col = slab + (c - c0) * ldc;
 #pragma unroll
             for (int q = 0; q < TPT; ++q) {
-                const int32_t dt = c - t0[q];
-                const bool act = !MASK || (uint32_t)dt <= span[q];
-                const int32_t row = row_tm(rk[q], act ? dt : 1);  // dt = 1 is valid for every template
-                const float v = add_term_pol<HW>(part[q], pk[q], row, col[row]);
-                part[q] = act ? v : part[q];
+                const int32_t r = MASK && !act[q] ? 0 : row[q];
+                const float v = add_term_pol<HW>(part[q], pk[q], r, col[r]);
+                part[q] = act[q] ? v : part[q];
             }
         }
         if ((ce & (kFlush - 1)) == kFlush - 1) {  // wave-uniform
@@ -940,9 +979,13 @@ __device__ __forceinline__ void walk_tm(int ca, int cb, int c0, const E *slab, i
     }
 }
 
+// With one template per lane the scorer fits 64 VGPRs, so that 8 waves share each SIMD (two
+// workgroups of 1024 lanes per CU with 80 KB of slabs each): the more waves, the more of the
+// latency of the root's square root and reciprocal and of the LDS gathers is hidden.
 template <int WG, int TPT, bool HW, int MAPT>
-__global__ __launch_bounds__(WG) void k_score_tm_slab(MapP m, GenP g, const uint32_t *order, uint64_t first,
-                                                      int64_t n, int S, int32_t norm, float *snr, uint64_t *wg_keys)
+__global__ __launch_bounds__(WG, TPT == 1 ? 8 : 1) void k_score_tm_slab(MapP m, GenP g, const uint32_t *order,
+                                                                         uint64_t first, int64_t n, int S, int32_t norm,
+                                                                         float *snr, uint64_t *wg_keys)
 {
     extern __shared__ float2 slab[];
     __shared__ int bnd[2];

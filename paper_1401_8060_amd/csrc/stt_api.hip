@@ -675,7 +675,7 @@ template <int MAPT>
 stt_status score_tm_folded(stt_ctx *c, const MapP &mf, const GenP &g, const TrkTm *tr, int64_t first, int64_t n,
                            int32_t norm, float *snr_dev, uint64_t *best_key_dev, bool slab, int lds)
 {
-    constexpr int kTmWG = 512, kTmTPT = 2;
+    constexpr int kTmWG = 1024, kTmTPT = 1;
     constexpr int esize = (int)sizeof(elem_t<MAPT>);
     stt_status s;
     if (slab) {
@@ -1046,7 +1046,7 @@ stt_status stt_score_tm(stt_ctx *c, const stt_map *map, const stt_gen *gen, cons
     if (n == 0) return STT_OK;
     STT_HIP(c, hipSetDevice(c->device));
     // generated templates: binned by time extent (a free t_mid keeps it) and scored from LDS slabs
-    // (512 lanes x 2 templates, at most 80 KB of slabs) when a column fits; otherwise one wave each
+    // (1024 lanes x 1 template, at most 80 KB of slabs) when a column fits; otherwise one wave each
     const int lds = std::min(c->lds_bytes, 80 * 1024);
     const int esize = fold_esize(map->dtype);
     const int64_t ldc = fold_ld(map->F, esize);

@@ -92,11 +92,9 @@ int main()
             const RowTm k = row_tm_init(t);
             int nfb = 0;
             for (int dt = 1; dt <= t.t2 - t.t0; ++dt) {
-                const int32_t D = k.bb + k.a4 * dt;
-                const float xi = (float)(2 * dt) * rcp_1ulp(k.bf + sqrt_1ulp((float)D));
-                const float y = fmaf(xi, fmaf(xi, k.Cs, k.Bs), k.fs);
-                const float fr = y - floorf(y);
-                nfb += !(fr > k.tol && fr < 1.0f - k.tol);
+                bool ok;
+                (void)row_tm_fp32(k, dt, ok);
+                nfb += !ok;
             }
             std::printf("%d %.6e\n", nfb, (double)k.tol);
         } else if (!std::strcmp(cmd, "tmerr")) {
