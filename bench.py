@@ -295,7 +295,26 @@ def run_single(args, name, w):
                           "slab_shape": list(choice) if choice else None})
     out["best"] = {"z": zk, "j": jk}
     out["roofline"] = roofline("k_score_slab" if n >= 4096 else "k_score_direct", kern_ms, px, BYTES_F32,
-                               measured_traffic(name, choice))
+                               measured_traffic(name + ("_argmax" if snr is None else ""), choice))
+    if snr is not None and not args.no_argmax_leg:
+        # the search proper keeps only the loudest template (Sec. III, V): the same steps with no
+        # per-template output, whose scattered 4-byte stores dominate the kernel's HBM writes
+        def step_argmax():
+            key.zero_()
+            ctx.score(m, gen=g, n=n, snr=None, best_key=key)
+
+        for _ in range(args.warmup):
+            step_argmax()
+        torch.cuda.synchronize()
+        ctx.set_timing(True)
+        ms_a = timed(argparse.Namespace(warmup=0, steps=args.steps), step_argmax, torch)
+        sa, ca = ctx.kernel_ms_total(stt.STAGE_SCORE)
+        ctx.set_timing(False)
+        za, ja = stt.decode_best(key)
+        log(f"bench: argmax only {ms_a:.3f} ms/step, scoring kernel {sa / max(ca, 1):.3f} ms; best z={za:.4f} j={ja}")
+        out["argmax_only"] = {"value": n / (ms_a * 1e-3), "ms_per_step": ms_a, "kernel_ms": sa / max(ca, 1),
+                              "track_px_per_s": px / (ms_a * 1e-3), "best": {"z": za, "j": ja},
+                              "traffic": measured_traffic(name + "_argmax", choice)}
     if not args.no_cpu_baseline:
         log("bench: timing the CPU oracle on a sample")
         out["cpu_baseline"] = cpu_baseline(w, Y, s, dtau_max)
@@ -463,7 +482,8 @@ def run_tmid(args, name, w):
     out = base_record(args, name, w, n, ms_step, px, "f32")
     out["config"].update({"T": w["T"], "F": w["F"], "n_tracks": n, "templates": "free t_mid",
                           "map_sha256": sha[:16]})
-    out["roofline"] = roofline("k_score_tm_slab", kern_ms, px, BYTES_F32, None, mix=CORE_MIX_TM)
+    out["roofline"] = roofline("k_score_tm_slab", kern_ms, px, BYTES_F32, measured_traffic(name, None),
+                               mix=CORE_MIX_TM)
     out["best"] = {"z": zk, "j": jk}
     ctx.close()
     return out
@@ -510,7 +530,8 @@ def run_maxdelay(args, name, w):
     # the grid runs in launches of up to 8 delays; the stage time covers all of them, so one launch
     # averages kern_ms / launches over (on average) nt / launches delays of every template pixel
     launches = (nt + 7) // 8
-    out["roofline"] = roofline("k_score_md_slab", kern_ms / launches, px, BYTES_F32, None, mix=CORE_MIX_MD,
+    out["roofline"] = roofline("k_score_md_slab", kern_ms / launches, px, BYTES_F32, measured_traffic(name, None),
+                               mix=CORE_MIX_MD,
                                units=nt / launches, mix_units=8)
     out["roofline"]["launches_per_step"] = launches
     out["best"] = {"z": zk, "j": jk, "delay_index": mk}
@@ -807,6 +828,8 @@ def main():
     ap.add_argument("--map-dtype", default="f32", choices=["f32", "p16"], help="batch workload map storage")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-snr", action="store_true", help="reduce to the argmax only (no per-track output)")
+    ap.add_argument("--no-argmax-leg", action="store_true",
+                    help="search workloads: skip the second, argmax-only timing (counter runs of one mode)")
     ap.add_argument("--tune-cache", default=TUNE_CACHE,
                     help="autotuner cache (JSON); a missing entry is searched on the GPU and stored")
     ap.add_argument("--copy-probe-mb", type=int, default=0,

@@ -1946,7 +1946,9 @@ void cache_store(const char *path, const std::string &key, const TuneChoice &t)
         while (fgets(line, sizeof line, f)) {
             std::string l(line);
             while (!l.empty() && (l.back() == '\n' || l.back() == ',')) l.pop_back();
-            if (l.empty() || l == "{" || l == "}" || l.find(pat) != std::string::npos) continue;
+            // keep the other entries only: braces (also "{}" of an empty cache) are written anew
+            const size_t q = l.find_first_not_of(" \t");
+            if (q == std::string::npos || l[q] != '"' || l.find(pat) != std::string::npos) continue;
             lines.push_back(l);
         }
         fclose(f);

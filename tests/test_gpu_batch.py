@@ -149,10 +149,15 @@ def test_autotune_applies_and_caches(stt, ctx, tmp_path):
     m = stt.Map(*to_dev(Y, s))
     g = stt.Gen(seed=1, min_len=10, dtau_max=D10MS)
     cache = str(tmp_path / "tune.json")
+    with open(cache, "w") as fh:  # an empty cache as a user would start one
+        fh.write("{}\n")
     choice = ctx.autotune(m, g, 200_000, cache)
     assert choice[0] in (256, 512, 1024) and choice[1] in (2, 4) and 1024 <= choice[2] <= 160 * 1024
     text = open(cache).read()
     assert f'"wg": {choice[0]}' in text and "F=250" in text
+    import json
+    entries = json.loads(text)  # still one JSON object
+    assert len(entries) == 1 and list(entries.values())[0]["wg"] == choice[0]
     # a second call finds the entry (same choice), and results stay those of the oracle-checked scorer
     assert ctx.autotune(m, g, 200_000, cache) == choice
     z_tuned, k_tuned = ctx.score(m, gen=g, n=50_000)
