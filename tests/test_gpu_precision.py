@@ -133,9 +133,14 @@ def test_rescore_f64_matches_oracle(orc, stt, ctx):
 
 def test_precision_pipeline_full_scale(orc, stt, ctx, tmp_path):
     """T=2000 x F=2000 map stored in FP16, 10^8 tracks with FP32 accumulation, top-1024
-    re-scored in FP64 from the FP32 map. Checked: sampled FP16 scores against the oracle on
-    the stored map, the top-1024 against a CPU selection over the same score array, every
-    re-scored value against the oracle, and the final argmax against the oracle's."""
+    re-scored in FP64 from the FP32 map. Checked: the first 3x10^7 FP16 scores, every one, a
+    sample of the rest and the GPU's 20 best against the oracle on the stored map (run over
+    disjoint template ranges on the host cores; all 10^8 take the oracle about 150 s on 16
+    threads), the GPU's argmax against the oracle's over all of those, the top-1024 against a CPU
+    selection over the same score array, every re-scored value against the oracle, and the final
+    argmax against the oracle's."""
+    import time
+    from oracle import shard
     _say("precision pipeline")
     import torch
     T, F, n, K = 2000, 2000, 100_000_000, 1024
@@ -155,12 +160,26 @@ def test_precision_pipeline_full_scale(orc, stt, ctx, tmp_path):
     part = np.argpartition(-np.nan_to_num(zs, nan=-np.inf), K)[:K]
     want = part[np.lexsort((part, -zs[part]))]
     assert np.array_equal(idx.cpu().numpy(), want)
-    # sampled FP16 scores vs the oracle on the stored map
+    # every FP16 score vs the oracle on the stored map
     q, e, deq = orc.quantize_p16(Y, s)
     assert e == pm.scale_exp
     om16 = orc.Map(deq, np.ones((T, F)))
-    samp = np.concatenate([np.random.default_rng(4).choice(n, 400, replace=False), want[:20]]).astype(np.uint64)
-    assert_close(zs[samp.astype(np.int64)], orc.score_gen_idx(om16, 4, 0, 10, D10MS, samp), what="p16 sample")
+    n_full = 30_000_000
+    t = time.time()
+    z16 = shard.score_gen(om16, 4, 0, 10, D10MS, 0, n_full)
+    _say(f"  oracle: {n_full} templates on the stored map in {time.time() - t:.1f} s on {shard.host_threads()} threads")
+    assert_close(zs[:n_full], z16, what="p16 first 3e7")
+    rest = np.concatenate([n_full + np.random.default_rng(4).choice(n - n_full, 2000, replace=False),
+                           want[:20]]).astype(np.uint64)
+    z16r = orc.score_gen_idx(om16, 4, 0, 10, D10MS, rest)
+    assert_close(zs[rest.astype(np.int64)], z16r, what="p16 sample and top 20")
+    jk = stt.key_decode(key_to_host(key))[1]
+    assert jk == int(want[0])  # the key is the best of the score array
+    # over every template the oracle scored, the GPU's argmax is the oracle's (up to a certified tie)
+    cand = np.concatenate([z16, z16r])
+    cand_idx = np.concatenate([np.arange(n_full), rest.astype(np.int64)])
+    assert_argmax(int(np.where(cand_idx == jk)[0][0]), cand)
+    del z16, cand
     # FP64 re-score vs the oracle on the FP32 map; final argmax among the K
     om = orc.Map(Y, s)
     z_orc = orc.score_gen_idx(om, 4, 0, 10, D10MS, want.astype(np.uint64))
