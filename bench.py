@@ -40,7 +40,12 @@ BYTES_P16 = 4   # one 32-bit polar word of an FP16 map
 N_CU, CLOCK_HZ = 256, 2.4e9
 LANES_PER_CLK = {"full": 64, "double": 128, "trans": 32}
 FP32_PEAK_TFLOPS = 157.3              # 256 x 128 lanes x 2 flops x 2.4 GHz
-LDS_PEAK_GBS = N_CU * 128 * CLOCK_HZ / 1e9  # 128 bytes per clock per CU: 78.6 TB/s
+# Memory-side ceilings measured by the probe library (bench.py --mem-rates;
+# profiles/memory_rates_gfx950.md): 8-byte LDS reads at random rows, as the scorers' gathers (the
+# conflict-free rate, about twice that, is a lower bound of the LDS peak), and streaming reads of
+# buffers beyond the 32 MB of L2 -- 6.5-7.2 TB/s up to 192 MB (the MALL), 6.1-6.5 TB/s from HBM.
+LDS_RANDOM_GBS = 51000.0
+FAR_READ_GBS = 6800.0
 # Instructions of the inner loop per template pixel (one template, one column), by issue class:
 #   plain scorer, FP32 map (polar fold): the row of Eq. 6 by the exact FP64 recurrence (1 FMA,
 #   2 adds), its LDS address (shift-add), the phase of Eq. 8 plus arg p (integer multiply, add3),
@@ -220,9 +225,11 @@ def roofline(kernel, kernel_ms, px, bpp, traffic=None, mix=None, lds_bpp=8, unit
     peak is the flop rate at which the inner loop's instruction mix (`mix`) keeps every SIMD of the
     chip issuing (unit counts x 2.4 GHz), with FLOPS_PER_TRACK_PX algorithmic flops per pixel, so
     frac = achieved pixel rate / issue ceiling. Beside it, not binding: the same flops against the
-    FP32 vector peak; the LDS bytes the kernel reads against the LDS bandwidth; the caller's pixel
-    record against HBM bandwidth (the metric's "% gather roofline", above 1 because pixels come
-    from LDS)."""
+    FP32 vector peak; the LDS bytes the kernel reads against the measured random-row LDS read rate;
+    the caller's pixel record against HBM bandwidth (the metric's "% gather roofline", above 1
+    because pixels come from LDS). With a measured `traffic`, `memory_side` rates the bytes that
+    left the L2s (slab staging, served by the MALL or HBM) against the measured streaming-read
+    rate beyond the L2s: near 1, the kernel is bound by staging rather than by issue."""
     mix = mix or CORE_MIX
     sec = kernel_ms * 1e-3
     rate = px * units / sec
@@ -237,9 +244,14 @@ def roofline(kernel, kernel_ms, px, bpp, traffic=None, mix=None, lds_bpp=8, unit
                 "fp32_flops": {"achieved": achieved, "peak": FP32_PEAK_TFLOPS, "unit": "TFLOP/s",
                                "frac": achieved / FP32_PEAK_TFLOPS},
                 "lds_read": {"bytes_per_track_px": lds_bpp, "achieved": rate * lds_bpp / 1e9,
-                             "peak": LDS_PEAK_GBS, "unit": "GB/s", "frac": rate * lds_bpp / 1e9 / LDS_PEAK_GBS},
+                             "peak": LDS_RANDOM_GBS, "unit": "GB/s", "frac": rate * lds_bpp / 1e9 / LDS_RANDOM_GBS,
+                             "peak_is": "measured 8-byte LDS reads at random rows"},
                 "gather_line": {"bytes_per_track_px": bpp, "achieved": rate * bpp / 1e9, "peak": HBM_PEAK_GBS,
-                                "unit": "GB/s", "frac": rate * bpp / 1e9 / HBM_PEAK_GBS}}}
+                                "unit": "GB/s", "frac": rate * bpp / 1e9 / HBM_PEAK_GBS}},
+            "memory_side": None if traffic is None else {
+                "achieved": traffic / sec / 1e9, "peak": FAR_READ_GBS, "unit": "GB/s",
+                "frac": traffic / sec / 1e9 / FAR_READ_GBS,
+                "peak_is": "measured streaming reads beyond the L2s (MALL-resident buffers)"}}
 
 
 def timed(args, fn, torch):
@@ -797,6 +809,39 @@ def issue_rates(iters: int = 4096) -> dict:
                       f"{iters} iterations; clock from the cycle and wall counters of the first wave"}
 
 
+def mem_rates() -> dict:
+    """Memory-side ceilings from the probe library: streaming reads of buffers from 8 MB (inside
+    the 8 x 4 MB of L2) through 32-256 MB (beyond the L2s, inside the 256 MB MALL) to 4 GB (HBM);
+    8-byte LDS reads at random rows and at conflict-free rows."""
+    import ctypes as C
+    path = os.path.join(ROOT, "paper_1401_8060_amd", "libstt_probe.so")
+    if not os.path.exists(path):
+        raise ImportError(f"{path} is missing: build it with __graft_entry__.build()")
+    L = C.CDLL(path)
+    L.stt_probe_stream.argtypes = [C.c_int, C.c_int64, C.c_int, C.POINTER(C.c_double), C.POINTER(C.c_double)]
+    L.stt_probe_lds.argtypes = [C.c_int, C.c_int, C.c_int, C.POINTER(C.c_double), C.POINTER(C.c_double)]
+    out = {}
+    sizes_mb = (8, 16, 32, 48, 64, 96, 128, 192, 256, 384, 1024, 4096)
+    for name, nbytes, reps in ((f"{mb}MB", mb << 20, max(2, 3000 // mb)) for mb in sizes_mb):
+        g, ms = C.c_double(), C.c_double()
+        rc = L.stt_probe_stream(0, nbytes, reps, C.byref(g), C.byref(ms))
+        if rc != 0:
+            raise RuntimeError(f"stream probe {name} failed ({rc})")
+        out[f"stream_read_{name}_GBs"] = round(g.value, 1)
+        log(f"bench: stream read {name:11s} {g.value:9.1f} GB/s ({ms.value:.3f} ms, {reps} passes)")
+    for name, rnd in (("random_rows", 1), ("conflict_free", 0)):
+        g, ms = C.c_double(), C.c_double()
+        rc = L.stt_probe_lds(0, rnd, 4096, C.byref(g), C.byref(ms))
+        if rc != 0:
+            raise RuntimeError(f"LDS probe {name} failed ({rc})")
+        out[f"lds_read_8B_{name}_GBs"] = round(g.value, 1)
+        log(f"bench: LDS 8-byte reads, {name:13s} {g.value:9.1f} GB/s ({ms.value:.3f} ms)")
+    out["method"] = ("streaming: float4 grid-stride reads, 8 workgroups of 256 lanes per CU, timed after one "
+                     "untimed launch; LDS: ds_read_b64 from a 16 KB table per workgroup, 8 waves per SIMD, "
+                     "8 independent rows per lane per iteration")
+    return out
+
+
 def summarize_pmc(paths: list[str], kernel: str) -> dict:
     """Mean per dispatch of every counter that rocprofv3 --pmc wrote (counter_collection.csv files)
     for the kernels whose name contains ``kernel``, with the dispatch count and register counts."""
@@ -836,6 +881,8 @@ def main():
                     help="after the run, copy this many MiB device-to-device (a known-size kernel for counter scaling)")
     ap.add_argument("--issue-rates", action="store_true",
                     help="measure the vector-ALU issue rates of the scorers' instructions and exit")
+    ap.add_argument("--mem-rates", action="store_true",
+                    help="measure the streaming-read (L2, MALL, HBM) and LDS-read ceilings and exit")
     ap.add_argument("--summarize-pmc", nargs="+", metavar="CSV",
                     help="print the mean per dispatch of the counters in rocprofv3 counter_collection.csv files "
                          "for the kernel named by --kernel, and exit (no GPU needed)")
@@ -846,6 +893,9 @@ def main():
         return
     if args.issue_rates:
         print(json.dumps({"issue_rates": issue_rates()}), flush=True)
+        return
+    if args.mem_rates:
+        print(json.dumps({"mem_rates": mem_rates()}), flush=True)
         return
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for {args.gpus}); the search shards by template range "

@@ -1,5 +1,7 @@
 // probe_issue.hip -- vector-ALU issue rates of the instructions in the scorers'
-// inner loops, measured on the device (gfx950).
+// inner loops, and the memory-side ceilings the scorers are measured against
+// (streaming reads served by HBM or by the MALL, LDS reads at random rows and
+// conflict-free), measured on the device (gfx950).
 //
 // Each probe kernel runs, in every lane, eight independent chains of one
 // instruction (register operands only, no memory), unrolled four times, so the
@@ -144,9 +146,135 @@ hipError_t launch_op(int op, int grid, int iters, uint32_t *sink, uint64_t *clk,
     }
 }
 
+// ---------------------------------------------------------------- memory-side probes
+
+// Streaming read of n4 16-byte words, `reps` passes, every lane a grid-stride walk; the sum keeps
+// the loads live.
+__global__ __launch_bounds__(256) void k_stream_read(const float4 *p, int64_t n4, int reps, float *sink)
+{
+    float acc = 0.0f;
+    const int64_t stride = (int64_t)gridDim.x * 256;
+    for (int r = 0; r < reps; ++r)
+        for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < n4; i += stride) {
+            const float4 v = p[i];
+            acc += (v.x + v.y) + (v.z + v.w);
+        }
+    if (acc == 1.2345e-30f) sink[0] = acc;
+}
+
+// LDS reads of 8 bytes per lane from a 16 KB table (2048 elements): at rows drawn by a per-lane
+// linear congruential sequence (random banks, as the scorers' gathers) or at consecutive rows
+// (lane l reads element base + l: conflict-free). Eight independent sequences per lane.
+template <bool RANDOM>
+__global__ __launch_bounds__(256) void k_lds_read(int iters, float *sink)
+{
+    __shared__ float2 tab[2048];
+    for (int i = threadIdx.x; i < 2048; i += 256) tab[i] = make_float2((float)i, 1.0f);
+    __syncthreads();
+    uint32_t st[8];
+#pragma unroll
+    for (int c = 0; c < 8; ++c) st[c] = (blockIdx.x * 256u + threadIdx.x) * 2654435761u + c * 40503u + 1u;
+    float acc = 0.0f;
+    for (int it = 0; it < iters; ++it) {
+#pragma unroll
+        for (int c = 0; c < 8; ++c) {
+            uint32_t e;
+            if (RANDOM) {
+                st[c] = st[c] * 1664525u + 1013904223u;
+                e = st[c] >> 21;  // 11 bits: 0 .. 2047
+            } else {
+                e = ((uint32_t)(it * 8 + c) * 64u + threadIdx.x) & 2047u;
+            }
+            const float2 v = tab[e];
+            acc += v.x * v.y;
+        }
+    }
+    if (acc == 1.2345e-30f) sink[0] = acc;
+}
+
 }  // namespace
 
 extern "C" {
+
+// Bytes per second of a streaming read of `bytes` (a multiple of 16) repeated `reps` times per
+// launch, after one untimed launch (which leaves the buffer in the caches it fits). A buffer larger
+// than the MALL measures HBM; one between the L2s and the MALL measures the MALL. Returns 0, or a
+// negative value on a HIP error or a bad argument.
+int stt_probe_stream(int device, int64_t bytes, int reps, double *gbps_out, double *ms_out)
+{
+    if (bytes < 16 || bytes % 16 || reps < 1 || !gbps_out || !ms_out) return -1;
+    if (hipSetDevice(device) != hipSuccess) return -2;
+    hipDeviceProp_t prop;
+    if (hipGetDeviceProperties(&prop, device) != hipSuccess) return -2;
+    void *buf = nullptr;
+    float *sink = nullptr;
+    if (hipMalloc(&buf, (size_t)bytes) != hipSuccess) return -3;
+    if (hipMalloc(&sink, 64) != hipSuccess) { (void)hipFree(buf); return -3; }
+    int rc = 0;
+    if (hipMemset(buf, 0, (size_t)bytes) != hipSuccess) rc = -4;
+    const int grid = prop.multiProcessorCount * 8;
+    const int64_t n4 = bytes / 16;
+    hipEvent_t e0, e1;
+    (void)hipEventCreate(&e0);
+    (void)hipEventCreate(&e1);
+    if (!rc) {
+        hipLaunchKernelGGL(k_stream_read, dim3(grid), dim3(256), 0, nullptr, (const float4 *)buf, n4, reps, sink);
+        (void)hipEventRecord(e0, nullptr);
+        hipLaunchKernelGGL(k_stream_read, dim3(grid), dim3(256), 0, nullptr, (const float4 *)buf, n4, reps, sink);
+        (void)hipEventRecord(e1, nullptr);
+        if (hipGetLastError() != hipSuccess) rc = -4;
+    }
+    float ms = 0.0f;
+    if (!rc && hipEventSynchronize(e1) != hipSuccess) rc = -5;
+    if (!rc && hipEventElapsedTime(&ms, e0, e1) != hipSuccess) rc = -5;
+    if (!rc) {
+        *ms_out = ms;
+        *gbps_out = (double)bytes * reps / (ms * 1e-3) / 1e9;
+    }
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    (void)hipFree(sink);
+    (void)hipFree(buf);
+    return rc;
+}
+
+// Bytes per second of 8-byte LDS reads, every CU running 8 workgroups of 256 lanes (each with its
+// own 16 KB table: 8 waves per SIMD), `iters` x 8 reads per lane: random rows (random = 1) or
+// conflict-free rows.
+int stt_probe_lds(int device, int random, int iters, double *gbps_out, double *ms_out)
+{
+    if (iters < 1 || !gbps_out || !ms_out) return -1;
+    if (hipSetDevice(device) != hipSuccess) return -2;
+    hipDeviceProp_t prop;
+    if (hipGetDeviceProperties(&prop, device) != hipSuccess) return -2;
+    float *sink = nullptr;
+    if (hipMalloc(&sink, 64) != hipSuccess) return -3;
+    const int grid = prop.multiProcessorCount * 8;
+    hipEvent_t e0, e1;
+    (void)hipEventCreate(&e0);
+    (void)hipEventCreate(&e1);
+    int rc = 0;
+    auto go = [&](int it) {
+        if (random) hipLaunchKernelGGL(k_lds_read<true>, dim3(grid), dim3(256), 0, nullptr, it, sink);
+        else hipLaunchKernelGGL(k_lds_read<false>, dim3(grid), dim3(256), 0, nullptr, it, sink);
+    };
+    go(iters / 8 + 1);
+    (void)hipEventRecord(e0, nullptr);
+    go(iters);
+    (void)hipEventRecord(e1, nullptr);
+    if (hipGetLastError() != hipSuccess) rc = -4;
+    float ms = 0.0f;
+    if (!rc && hipEventSynchronize(e1) != hipSuccess) rc = -5;
+    if (!rc && hipEventElapsedTime(&ms, e0, e1) != hipSuccess) rc = -5;
+    if (!rc) {
+        *ms_out = ms;
+        *gbps_out = (double)grid * 256.0 * iters * 8.0 * 8.0 / (ms * 1e-3) / 1e9;
+    }
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    (void)hipFree(sink);
+    return rc;
+}
 
 int stt_probe_count(void) { return kNumOps; }
 
