@@ -919,24 +919,18 @@ __global__ __launch_bounds__(256) void k_score_tm(MapP m, GenP g, const TrkTm *t
 // (valid for every template) and drops the term.
 // Column walk of the free-t_mid slab scorer (as walk, with an independent row per column). The
 // FP32 pass takes every template's row of the column, with D = b^2 + 4 a dt and 2 dt carried from
-// column to column by one add each; where it does not stand for some lane (about one template
-// pixel in a thousand on the search band), the whole wave takes one uniform branch in which those
-// lanes settle their rows exactly. A lane outside its template's columns works on column t0 + 1
-// (valid for every template) and drops the term.
+// column to column by one add each (Dc, dt2c: their values at column ca, advanced past cb on
+// return, so that the wave's walks over consecutive column ranges carry them through); where it
+// does not stand for some lane (about one template pixel in a thousand on the search band), the
+// whole wave takes one uniform branch in which those lanes settle their rows exactly. A lane
+// outside its template's columns works on column t0 + 1 (valid for every template) and drops the
+// term.
 template <int TPT, bool MASK, bool HW, typename E>
 __device__ __forceinline__ void walk_tm(int ca, int cb, int c0, const E *slab, int ldc, const int32_t (&t0)[TPT],
                                         const uint32_t (&span)[TPT], const RowTm (&rk)[TPT],
-                                        const PhaseK (&pk)[TPT], float (&part)[TPT], double (&acc)[TPT])
+                                        const PhaseK (&pk)[TPT], int32_t (&Dc)[TPT], float (&dt2c)[TPT],
+                                        float (&part)[TPT], double (&acc)[TPT])
 {
-    int32_t Dc[TPT];
-    float dt2c[TPT];
-#pragma unroll
-    for (int q = 0; q < TPT; ++q) {
-        // modulo 2^32: a lane that holds no template (t0 = INT_MAX) only ever takes the masked walk
-        const uint32_t dt = (uint32_t)ca - (uint32_t)t0[q];
-        Dc[q] = (int32_t)((uint32_t)rk[q].bb + (uint32_t)rk[q].a4 * dt);
-        dt2c[q] = 2.0f * (float)(int32_t)dt;
-    }
     for (int c = ca; c <= cb;) {
         const int ce = min(cb, c | (kFlush - 1));
         for (; c <= ce; ++c) {
@@ -1027,8 +1021,18 @@ __global__ __launch_bounds__(WG, TPT == 1 ? 8 : 1) void k_score_tm_slab(MapP m, 
     if (clo > chi) { clo = hi + 1; chi = hi; }
     float part[TPT];
     double acc[TPT];
+    // D and 2 dt at the wave's first column; the walks then carry them column by column. Modulo
+    // 2^32: a lane that holds no template (t0 = INT_MAX) only ever takes the masked walk.
+    int32_t Dc[TPT];
+    float dt2c[TPT];
 #pragma unroll
-    for (int q = 0; q < TPT; ++q) { part[q] = 0.0f; acc[q] = 0.0; }
+    for (int q = 0; q < TPT; ++q) {
+        part[q] = 0.0f;
+        acc[q] = 0.0;
+        const uint32_t dt = (uint32_t)lo - (uint32_t)t0[q];
+        Dc[q] = (int32_t)((uint32_t)rk[q].bb + (uint32_t)rk[q].a4 * dt);
+        dt2c[q] = 2.0f * (float)(int32_t)dt;
+    }
     __syncthreads();
     if (lane == 0) {
         atomicMin(&bnd[0], lo);
@@ -1056,9 +1060,9 @@ __global__ __launch_bounds__(WG, TPT == 1 ? 8 : 1) void k_score_tm_slab(MapP m, 
         const E *cur = reinterpret_cast<const E *>(slab + (size_t)(kk & 1) * S * col8);
         const int ncol = min(S, c_last - c0 + 1);
         const int ca = max(c0, lo), cb = min(c0 + ncol - 1, hi);
-        walk_tm<TPT, true, HW>(ca, min(cb, clo - 1), c0, cur, ldc, t0, span, rk, pk, part, acc);
-        walk_tm<TPT, false, HW>(max(ca, clo), min(cb, chi), c0, cur, ldc, t0, span, rk, pk, part, acc);
-        walk_tm<TPT, true, HW>(max(ca, chi + 1), cb, c0, cur, ldc, t0, span, rk, pk, part, acc);
+        walk_tm<TPT, true, HW>(ca, min(cb, clo - 1), c0, cur, ldc, t0, span, rk, pk, Dc, dt2c, part, acc);
+        walk_tm<TPT, false, HW>(max(ca, clo), min(cb, chi), c0, cur, ldc, t0, span, rk, pk, Dc, dt2c, part, acc);
+        walk_tm<TPT, true, HW>(max(ca, chi + 1), cb, c0, cur, ldc, t0, span, rk, pk, Dc, dt2c, part, acc);
     }
     uint64_t key = 0;
 #pragma unroll
