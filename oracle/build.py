@@ -9,7 +9,9 @@ SOURCES = ["stt_oracle.c", "stt_oracle_ext.c"]
 
 
 def lib_path() -> str:
-    return os.path.join(HERE, "libstt_oracle.so")
+    """The built library; STT_ORACLE_LIB names another build of these sources instead (the tests'
+    planted-mistake copies)."""
+    return os.environ.get("STT_ORACLE_LIB") or os.path.join(HERE, "libstt_oracle.so")
 
 
 def build(verbose: bool = False) -> str:
