@@ -1,7 +1,8 @@
 """The oracle's pins catch plausible mistakes: each case plants one mistake (a flipped sign, a
-dropped term or pixel, a transposed operand, an off-by-one, a wrong constant) in a copy of the C
-oracle, builds it on the CPU, and runs the pin tests against that copy in a fresh process. The
-run must fail; the unchanged copy must pass. Nothing here touches a GPU or the HIP library."""
+dropped term or pixel, a transposed operand, an off-by-one, a wrong constant) in a copy of the
+oracle -- the C oracle rebuilt with gcc, or a Python module of the oracle package in a copy of
+the test tree -- and runs the pin tests against that copy in a fresh process. The run must fail;
+the unchanged copy must pass. Nothing here touches a GPU or the HIP library."""
 from __future__ import annotations
 
 import os
@@ -125,4 +126,72 @@ def test_planted_mistake_is_caught(gcc, tmp_path, name, src, old, new, files, ex
     srcs[src] = srcs[src].replace(old, new)
     lib = _build(str(tmp_path), srcs)
     rc, log = _run_pins(lib, files, extra)
+    assert rc == 1, f"{name}: the pins did not fail (exit {rc})\n{log}"
+
+
+# Mistakes in the oracle's Python modules: (name, module file, exact text, replacement, pin file)
+PY_MUTANTS = [
+    ("FAP counts strictly louder maps only", "significance.py",
+     "return key_score(kr) >= key_score(kq)", "return key_score(kr) > key_score(kq)",
+     "tests/test_oracle_significance_pins.py"),
+    ("threshold at the floor(alpha n)-th map", "significance.py",
+     "m = max(1, math.ceil(alpha * len(z)))", "m = max(1, math.floor(alpha * len(z)))",
+     "tests/test_oracle_significance_pins.py"),
+    ("symmetric instead of periodic Hann window", "mapform.py",
+     "return np.sin(np.pi * n / M) ** 2", "return np.sin(np.pi * n / (M - 1)) ** 2",
+     "tests/test_oracle_mapform_pins.py"),
+    ("conjugate on J instead of I", "mapform.py",
+     "np.conj(spec_i) * spec_j[tj]", "spec_i * np.conj(spec_j[tj])", "tests/test_oracle_mapform_pins.py"),
+    ("P' averages the half-overlapping neighbours too", "mapform.py",
+     "abs(u - t) >= 2 and 0 <= u < T", "abs(u - t) >= 1 and 0 <= u < T", "tests/test_oracle_mapform_pins.py"),
+    ("window mean square 1/2 instead of 3/8", "mapform.py",
+     "HANN_MEAN_SQUARE = 3.0 / 8.0", "HANN_MEAN_SQUARE = 1.0 / 2.0", "tests/test_oracle_mapform_pins.py"),
+    ("patch delay moved the wrong way", "oracle.py",
+     'out["dtau"] = out["dtau"].astype(np.int64) + center', 'out["dtau"] = out["dtau"].astype(np.int64) - center',
+     "tests/test_oracle_patch_pins.py"),
+    ("FP16 scale exponent one too high", "oracle.py",
+     "e = (k if fr > 0.5 else k - 1) - 15", "e = (k if fr > 0.5 else k - 1) - 14", "tests/test_oracle_ext_pins.py"),
+    ("FP16 phase truncated instead of rounded", "oracle.py",
+     "np.rint(turns * 65536.0)", "np.floor(turns * 65536.0)", "tests/test_oracle_ext_pins.py"),
+]
+
+
+def _tree_copy(tmp):
+    ign = shutil.ignore_patterns("__pycache__", "*.pyc")
+    for d in ("tests", "oracle", "synth"):
+        shutil.copytree(os.path.join(ROOT, d), os.path.join(tmp, d), ignore=ign)
+    return tmp
+
+
+def _run_in(tree, pin):
+    env = {k: v for k, v in os.environ.items() if k != "STT_ORACLE_LIB"}
+    r = subprocess.run([sys.executable, "-m", "pytest", "-x", "-q", "-p", "no:cacheprovider", "-m", "not gpu", pin],
+                       cwd=tree, env=env, capture_output=True, text=True, timeout=600)
+    return r.returncode, r.stdout[-1500:]
+
+
+@pytest.fixture(scope="module")
+def built_oracle(gcc):
+    import oracle
+    if not os.path.exists(os.path.join(ORACLE, "libstt_oracle.so")):
+        oracle.build()
+
+
+def test_unchanged_tree_copy_passes_the_python_pins(built_oracle, tmp_path):
+    tree = _tree_copy(str(tmp_path))
+    for pin in sorted({m[4] for m in PY_MUTANTS}):
+        rc, log = _run_in(tree, pin)
+        assert rc == 0, log
+
+
+@pytest.mark.parametrize("name,mod,old,new,pin", PY_MUTANTS, ids=[m[0] for m in PY_MUTANTS])
+def test_planted_mistake_in_python_oracle_is_caught(built_oracle, tmp_path, name, mod, old, new, pin):
+    tree = _tree_copy(str(tmp_path))
+    path = os.path.join(tree, "oracle", mod)
+    with open(path) as fh:
+        text = fh.read()
+    assert text.count(old) == 1, f"the text to change is not unique in {mod}"
+    with open(path, "w") as fh:
+        fh.write(text.replace(old, new))
+    rc, log = _run_in(tree, pin)
     assert rc == 1, f"{name}: the pins did not fail (exit {rc})\n{log}"

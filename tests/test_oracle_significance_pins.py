@@ -56,6 +56,12 @@ def test_ladder_fap_and_threshold(sg):
     assert sg.threshold(bg, 0.01) == 991.0
     assert sg.threshold(bg, 1e-6) == 1000.0  # fewer maps than 1/alpha: the loudest one
     assert sg.threshold(bg, 1.0) == 1.0
+    assert sg.threshold(bg, 0.0025) == 998.0  # alpha n = 2.5: the 3rd largest
+    # the threshold separates by FAP: at it FAP >= alpha, just above it FAP < alpha
+    for alpha in (0.0025, 0.0137, 0.3333):
+        zt = sg.threshold(bg, alpha)
+        above = float(np.nextafter(np.float32(zt), np.float32(np.inf)))
+        assert sg.fap(bg, [_key_of(above)])[0] < alpha <= sg.fap(bg, [_key_of(zt)])[0]
 
 
 def test_gumbel_maxima_fap(sg):
