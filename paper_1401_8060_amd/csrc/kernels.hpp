@@ -5,9 +5,11 @@
 //   k_bin_count     \  counting sort of templates by (start, end) column bucket,
 //   k_bin_scan       > so that a workgroup's templates cover nearly the same
 //   k_bin_scatter   /  columns and its lanes stay busy through a time sweep
-//   k_score_slab    time-slab scorer: the workgroup stages S columns of the map
-//                   (coalesced along frequency, p = Y/sigma folded on the way)
-//                   into LDS and every lane gathers its templates' pixels there
+//   k_fold_polar    p = Y/sigma of every pixel in polar form (|p|, arg p in
+//                   2^-32 turn), the layout the scorers stage: one cosine per term
+//   k_score_slab    time-slab scorer: the workgroup copies slabs of consecutive
+//                   columns of the folded map into LDS (LDS DMA, double-buffered)
+//                   and every lane gathers its templates' pixels there
 //   k_score_direct  one lane per template, pixels gathered straight from the
 //                   map in global memory (small calls, very wide maps)
 //   k_reduce_keys   max of the slab scorer's per-workgroup best keys
