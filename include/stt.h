@@ -191,7 +191,7 @@ stt_status stt_score(stt_ctx *ctx, const stt_map *map, const stt_gen *gen, const
  * (code under HIP graph capture, tight serving loops, harnesses that forbid
  * hipMalloc). Arguments, results and errors as stt_score; the scores are the
  * same bits. The binning scratch and the folded map live in one static
- * device array per GPU (about 48.1 MB, held from library load until the
+ * device array per GPU (about 71.7 MB, held from library load until the
  * process ends; its address is taken by stt_create), so this call makes no
  * allocation, records no timing events, and limits the call to
  * n <= 4194304 templates and maps whose folded copy (T x F rounded up to a

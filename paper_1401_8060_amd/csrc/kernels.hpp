@@ -3,8 +3,9 @@
 // Hot path of the template search (paper Sec. III, Eq. 6 and Eq. 8):
 //   k_make_tracks   materialise templates (Philox4x32-10 + exact unranking)
 //   k_bin_count     \  counting sort of templates by (start, end) column bucket,
-//   k_bin_scan       > so that a workgroup's templates cover nearly the same
-//   k_bin_scatter   /  columns and its lanes stay busy through a time sweep
+//   k_bin_scan       | so that a workgroup's templates cover nearly the same
+//   k_bin_group      | columns and its lanes stay busy through a time sweep;
+//   k_bin_fine      /  scattered in two passes, to groups of buckets, then buckets
 //   k_fold_polar    p = Y/sigma of every pixel in polar form (|p|, arg p in
 //                   2^-32 turn), the layout the scorers stage: one cosine per term
 //   k_score_slab    time-slab scorer: the workgroup copies slabs of consecutive
@@ -142,25 +143,59 @@ __device__ __forceinline__ float2 polar_of(float2 p)
     return make_float2(mag, __uint_as_float(arg_turns(p.x, p.y)));
 }
 
+constexpr int kFoldRows = 4;  // rows per thread of the fold kernels: all their loads in flight at once
+
+// Column t, rows r0 + 256 i + threadIdx.x (i < kFoldRows) of a fold: every load first, then the
+// polar forms and stores (pixels F .. ld_out-1 zero).
+template <int MAPT>
+__device__ __forceinline__ void fold_rows(const MapP &m, int64_t t, int64_t r0, float2 *out, int64_t ld_out)
+{
+    float2 p[kFoldRows];
+#pragma unroll
+    for (int i = 0; i < kFoldRows; ++i) {
+        const int64_t r = r0 + i * 256 + threadIdx.x;
+        p[i] = r < m.F ? load_p<MAPT>(m, t * m.ld + r) : make_float2(0.0f, 0.0f);
+    }
+#pragma unroll
+    for (int i = 0; i < kFoldRows; ++i) {
+        const int64_t r = r0 + i * 256 + threadIdx.x;
+        if (r < ld_out) out[t * ld_out + r] = r < m.F ? polar_of(p[i]) : make_float2(0.0f, 0.0f);
+    }
+}
+
+// The same rows of an FP16 map: its words as they are.
+__device__ __forceinline__ void fold_words_rows(const MapP &m, int64_t t, int64_t r0, uint32_t *out, int64_t ld_out)
+{
+    const uint32_t *w = reinterpret_cast<const uint32_t *>(m.Y);
+    uint32_t v[kFoldRows];
+#pragma unroll
+    for (int i = 0; i < kFoldRows; ++i) {
+        const int64_t r = r0 + i * 256 + threadIdx.x;
+        v[i] = r < m.F ? w[t * m.ld + r] : 0u;
+    }
+#pragma unroll
+    for (int i = 0; i < kFoldRows; ++i) {
+        const int64_t r = r0 + i * 256 + threadIdx.x;
+        if (r < ld_out) out[t * ld_out + r] = v[i];
+    }
+}
+
 // p of every pixel in polar form into a map with column stride ld_out (pixels F..ld_out-1 of a
 // column are zero): from Y/sigma of an FP32 map, or from the exact FP32 values of an FP16 map's
 // entries (load_p's expression). Grid: column blockIdx.x, y strides over its rows.
 template <int MAPT>
 __global__ __launch_bounds__(256) void k_fold_polar(MapP m, float2 *out, int64_t ld_out)
 {
-    const int64_t t = blockIdx.x;
-    for (int64_t r = (int64_t)blockIdx.y * 256 + threadIdx.x; r < ld_out; r += (int64_t)gridDim.y * 256)
-        out[t * ld_out + r] = r < m.F ? polar_of(load_p<MAPT>(m, t * m.ld + r)) : make_float2(0.0f, 0.0f);
+    for (int64_t r0 = (int64_t)blockIdx.y * 256 * kFoldRows; r0 < ld_out; r0 += (int64_t)gridDim.y * 256 * kFoldRows)
+        fold_rows<MAPT>(m, blockIdx.x, r0, out, ld_out);
 }
 
 // The words of an FP16 map into the folded layout (column stride ld_out, pixels F..ld_out-1 zero).
 // Grid: column blockIdx.x, y strides over its rows.
 __global__ __launch_bounds__(256) void k_fold_words(MapP m, uint32_t *out, int64_t ld_out)
 {
-    const int64_t t = blockIdx.x;
-    const uint32_t *w = reinterpret_cast<const uint32_t *>(m.Y);
-    for (int64_t r = (int64_t)blockIdx.y * 256 + threadIdx.x; r < ld_out; r += (int64_t)gridDim.y * 256)
-        out[t * ld_out + r] = r < m.F ? w[t * m.ld + r] : 0u;
+    for (int64_t r0 = (int64_t)blockIdx.y * 256 * kFoldRows; r0 < ld_out; r0 += (int64_t)gridDim.y * 256 * kFoldRows)
+        fold_words_rows(m, blockIdx.x, r0, out, ld_out);
 }
 
 // One fold of a batch: map src into dst (column stride ld_out); its columns are col0 .. col0 +
@@ -186,14 +221,11 @@ __global__ __launch_bounds__(256) void k_fold_batch(const FoldJob *jobs, int n_j
     }
     const FoldJob &j = jobs[lo];
     const int64_t t = (int64_t)(col - j.col0);
-    for (int64_t r = (int64_t)blockIdx.y * 256 + threadIdx.x; r < j.ld_out; r += (int64_t)gridDim.y * 256) {
-        const int64_t k = t * j.ld_out + r;
-        if constexpr (MAPT == kMapP16) {
-            ((uint32_t *)j.dst)[k] = r < j.src.F ? reinterpret_cast<const uint32_t *>(j.src.Y)[t * j.src.ld + r] : 0u;
-        } else {
-            ((float2 *)j.dst)[k] =
-                r < j.src.F ? polar_of(load_p<MAPT>(j.src, t * j.src.ld + r)) : make_float2(0.0f, 0.0f);
-        }
+    for (int64_t r0 = (int64_t)blockIdx.y * 256 * kFoldRows; r0 < j.ld_out; r0 += (int64_t)gridDim.y * 256 * kFoldRows) {
+        if constexpr (MAPT == kMapP16)
+            fold_words_rows(j.src, t, r0, (uint32_t *)j.dst, j.ld_out);
+        else
+            fold_rows<MAPT>(j.src, t, r0, (float2 *)j.dst, j.ld_out);
     }
 }
 
@@ -439,29 +471,73 @@ __global__ __launch_bounds__(256) void k_argmax(const float *z, int64_t n, uint6
 // of binned templates are dispatched in that order, so the longest-running
 // blocks start first and the launch ends on short ones. Invalid given
 // templates go to bucket 0 (they are skipped when scored).
+//
+// The sort: count, scans, two scatters. Buckets form groups of 2^kGroupShift
+// consecutive ones. The count (one workgroup per chunk of kBinChunk templates)
+// draws each template's bucket once and keeps it (2 bytes, in the space the
+// binned order fills last), adds its chunk's bucket histogram to the totals
+// and writes the chunk's count per group. The scans give every bucket its
+// start, every group its region and every chunk its run in each group. The
+// first scatter moves each index, with its bucket within the group, to its
+// chunk's run in its group's region (no atomics: the place of every run is
+// known). The second takes each group's region in chunks of kFineChunk and
+// moves each index to its bucket, the runs reserved by atomics on the bucket
+// cursors. Each scatter workgroup first orders its chunk by key in LDS, then
+// stores it run by run: consecutive lanes write consecutive addresses, so a
+// store instruction touches one or two cache lines (a single scatter into all
+// buckets would store about one index per bucket per workgroup: one cache
+// line per lane).
 
-constexpr int kBinPerThread = 32;                 // templates per thread in the sort passes
-constexpr int kBinChunk = 256 * kBinPerThread;    // templates per workgroup
+constexpr int kBinPerThread = 32;                 // templates per thread: count, first scatter
+constexpr int kBinChunk = 256 * kBinPerThread;    // templates per workgroup: count, first scatter
+constexpr int kFinePerThread = 16;                // templates per thread: second scatter
+constexpr int kFineChunk = 256 * kFinePerThread;
 constexpr int kMaxBins = 128 * 129 / 2;           // at most 128 buckets per axis
+constexpr int kGroupShift = 6;                    // buckets per group: 64
+constexpr int kGroupMask = (1 << kGroupShift) - 1;
+constexpr int kMaxGroups = (kMaxBins + kGroupMask) >> kGroupShift;
+constexpr int kGroupSlots = kMaxGroups + 1 + (kMaxGroups & 1 ? 0 : 1);  // groups + 1 entries, an even count
+static_assert(kMaxGroups << kGroupShift == kMaxBins, "bucket tables are whole groups");
+static_assert(kMaxGroups <= 3 * 64, "one wave scans the group table");
 
-// Reserve this workgroup's run in every bucket: cnt[b] (its count, in LDS)
-// becomes the global start of its run, taken from cursor[b]. All of a thread's
-// atomics are issued before any result is used, so their round trips overlap.
-__device__ __forceinline__ void reserve_runs(uint32_t *cnt, int nbins, uint32_t *cursor)
+// The slot of item in a table of ascending starts: start[k] <= item < start[k + 1], 0 <= k < n.
+__device__ __forceinline__ int find_slot(const uint32_t *start, int n, uint32_t item)
 {
-    constexpr int kPer = (kMaxBins + 255) / 256;
-    uint32_t got[kPer];
-#pragma unroll
-    for (int j = 0; j < kPer; ++j) {
-        const int b = threadIdx.x + j * 256;
-        const uint32_t c = b < nbins ? cnt[b] : 0u;
-        got[j] = c ? atomicAdd(&cursor[b], c) : 0u;
+    int lo = 0, hi = n;  // start[lo] <= item < start[hi]
+    while (hi - lo > 1) {
+        const int mid = (lo + hi) >> 1;
+        if (start[mid] <= item) lo = mid; else hi = mid;
     }
+    return lo;
+}
+
+// Exclusive prefix sums by one wave (the caller's lanes 0..63) of val(0 .. cnt-1),
+// cnt <= 192: out[k] = val(0) + ... + val(k-1), out[cnt] = the total.
+template <typename F>
+__device__ __forceinline__ void wave_prefix(F val, int cnt, uint32_t *out)
+{
+    const int lane = threadIdx.x & 63;
+    uint32_t v[3], s = 0;
 #pragma unroll
-    for (int j = 0; j < kPer; ++j) {
-        const int b = threadIdx.x + j * 256;
-        if (b < nbins) cnt[b] = got[j];  // empty buckets are never read
+    for (int j = 0; j < 3; ++j) {
+        const int k = 3 * lane + j;
+        v[j] = k < cnt ? val(k) : 0u;
+        s += v[j];
     }
+    uint32_t incl = s;
+#pragma unroll
+    for (int off = 1; off < 64; off <<= 1) {
+        const uint32_t y = __shfl_up(incl, off);
+        if (lane >= off) incl += y;
+    }
+    uint32_t run = incl - s;
+#pragma unroll
+    for (int j = 0; j < 3; ++j) {
+        const int k = 3 * lane + j;
+        if (k < cnt) out[k] = run;
+        run += v[j];
+    }
+    if (lane == 63) out[cnt] = incl;
 }
 
 template <bool EXPL>
@@ -482,9 +558,33 @@ __device__ __forceinline__ uint32_t bin_of(const GenP &g, const Trk *tr, const M
     return e * (e + 1) / 2 + b0;
 }
 
+// The count's step for one chunk, after its histogram hist[0 .. nbins-1] is
+// complete in LDS: totals[b] += hist[b], and ccnt[k * stride] = the chunk's
+// templates in group k (a thread per group; thread k starts its sum at bucket
+// k mod 64 of the group, so the lanes of a wave read 64 different banks).
+__device__ __forceinline__ void count_out(const uint32_t *hist, int nbins, uint32_t *totals, uint32_t *ccnt,
+                                          size_t stride)
+{
+    for (int b = threadIdx.x; b < nbins; b += 256)
+        if (hist[b]) atomicAdd(&totals[b], hist[b]);
+    const int ngroups = (nbins + kGroupMask) >> kGroupShift;
+    for (int k = threadIdx.x; k < ngroups; k += 256) {
+        const int b0 = k << kGroupShift, nb = min(1 << kGroupShift, nbins - b0);
+        uint32_t v = 0;
+#pragma unroll 8
+        for (int i = 0; i <= kGroupMask; ++i) {
+            const int j = (i + k) & kGroupMask;
+            if (j < nb) v += hist[b0 + j];
+        }
+        ccnt[(size_t)k * stride] = v;
+    }
+}
+
+// Count: bins[i] = the bucket of template i; count_out for workgroup (chunk) c
+// at ccnt + c with stride gridDim.x (row k of ccnt: group k's count per chunk).
 template <bool EXPL>
 __global__ __launch_bounds__(256) void k_bin_count(MapP m, GenP g, const Trk *tr, uint64_t first, int64_t n, int wb,
-                                                   int nbins, uint32_t *totals)
+                                                   int nbins, uint32_t *totals, uint16_t *bins, uint32_t *ccnt)
 {
     __shared__ uint32_t hist[kMaxBins];
     for (int b = threadIdx.x; b < nbins; b += 256) hist[b] = 0;
@@ -492,63 +592,244 @@ __global__ __launch_bounds__(256) void k_bin_count(MapP m, GenP g, const Trk *tr
     const int64_t base = (int64_t)blockIdx.x * kBinChunk;
     for (int q = 0; q < kBinPerThread; ++q) {
         const int64_t i = base + q * 256 + threadIdx.x;
-        if (i < n) atomicAdd(&hist[bin_of<EXPL>(g, tr, m, first, i, wb)], 1u);
-    }
-    __syncthreads();
-    for (int b = threadIdx.x; b < nbins; b += 256)
-        if (hist[b]) atomicAdd(&totals[b], hist[b]);
-}
-
-// Exclusive scan of the bucket totals into the scatter cursors (one workgroup).
-__global__ __launch_bounds__(1024) void k_bin_scan(const uint32_t *totals, int nbins, uint32_t *cursor)
-{
-    __shared__ uint32_t part[1024];
-    const int per = (nbins + 1023) / 1024;
-    const int lo = threadIdx.x * per, hi = min(nbins, lo + per);
-    uint32_t s = 0;
-    for (int b = lo; b < hi; ++b) s += totals[b];
-    part[threadIdx.x] = s;
-    __syncthreads();
-    for (int off = 1; off < 1024; off <<= 1) {
-        const uint32_t v = threadIdx.x >= off ? part[threadIdx.x - off] : 0;
-        __syncthreads();
-        part[threadIdx.x] += v;
-        __syncthreads();
-    }
-    uint32_t run = part[threadIdx.x] - s;
-    for (int b = lo; b < hi; ++b) {
-        cursor[b] = run;
-        run += totals[b];
-    }
-}
-
-template <bool EXPL>
-__global__ __launch_bounds__(256) void k_bin_scatter(MapP m, GenP g, const Trk *tr, uint64_t first, int64_t n, int wb,
-                                                     int nbins, uint32_t *cursor, uint32_t *order)
-{
-    __shared__ uint32_t cnt[kMaxBins];
-    for (int b = threadIdx.x; b < nbins; b += 256) cnt[b] = 0;
-    __syncthreads();
-    const int64_t base = (int64_t)blockIdx.x * kBinChunk;
-    uint32_t bin[kBinPerThread], rank[kBinPerThread];
-#pragma unroll
-    for (int q = 0; q < kBinPerThread; ++q) {
-        const int64_t i = base + q * 256 + threadIdx.x;
-        bin[q] = 0;
-        rank[q] = 0;
         if (i < n) {
-            bin[q] = bin_of<EXPL>(g, tr, m, first, i, wb);
-            rank[q] = atomicAdd(&cnt[bin[q]], 1u);
+            const uint32_t b = bin_of<EXPL>(g, tr, m, first, i, wb);
+            bins[i] = (uint16_t)b;
+            atomicAdd(&hist[b], 1u);
         }
     }
     __syncthreads();
-    reserve_runs(cnt, nbins, cursor);
+    count_out(hist, nbins, totals, ccnt + blockIdx.x, gridDim.x);
+}
+
+// The bucket scan of one call or map (1024 or 256 threads, nbins <= kMaxBins):
+// cursor[b] = base + the templates in buckets before b; gstart[k] = cursor of
+// group k's first bucket, gstart[ngroups] = base + all; fitem[k] = the first
+// second-scatter chunk of group k, fitem[ngroups] = their count.
+template <int NT>
+__device__ __forceinline__ void scan_buckets(const uint32_t *totals, int nbins, uint32_t base, uint32_t *cursor,
+                                             uint32_t *gstart, uint32_t *fitem)
+{
+    constexpr int kPer = (kMaxBins + NT - 1) / NT;
+    __shared__ uint32_t wsum[NT / 64];
+    __shared__ uint32_t gs[kGroupSlots];
+    const int per = (nbins + NT - 1) / NT;
+    const int lo = threadIdx.x * per;
+    uint32_t v[kPer], s = 0;
+#pragma unroll
+    for (int j = 0; j < kPer; ++j) {
+        const int b = lo + j;
+        v[j] = j < per && b < nbins ? totals[b] : 0u;
+        s += v[j];
+    }
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+    uint32_t incl = s;
+#pragma unroll
+    for (int off = 1; off < 64; off <<= 1) {
+        const uint32_t y = __shfl_up(incl, off);
+        if (lane >= off) incl += y;
+    }
+    if (lane == 63) wsum[wv] = incl;
+    __syncthreads();
+    uint32_t run = base + incl - s;
+    for (int w = 0; w < wv; ++w) run += wsum[w];
+    const int ngroups = (nbins + kGroupMask) >> kGroupShift;
+    if (threadIdx.x == NT - 1) gs[ngroups] = run + s;
+#pragma unroll
+    for (int j = 0; j < kPer; ++j) {
+        const int b = lo + j;
+        if (j < per && b < nbins) {
+            if (!(b & kGroupMask)) gs[b >> kGroupShift] = run;
+            cursor[b] = run;
+            run += v[j];
+        }
+    }
+    __syncthreads();
+    if ((int)threadIdx.x <= ngroups) gstart[threadIdx.x] = gs[threadIdx.x];
+    if (threadIdx.x < 64)
+        wave_prefix([&](int k) { return (gs[k + 1] - gs[k] + (uint32_t)kFineChunk - 1) / (uint32_t)kFineChunk; }, ngroups,
+                    fitem);
+}
+
+// Exclusive scan, in place, of row[0 .. len-1] by one workgroup of 256 threads.
+__device__ __forceinline__ void scan_row(uint32_t *row, int len)
+{
+    __shared__ uint32_t wsum[4];
+    uint32_t carry = 0;
+    for (int t0 = 0; t0 < len; t0 += 1024) {
+        const int lo = t0 + 4 * (int)threadIdx.x;
+        uint32_t v[4], s = 0;
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+            v[j] = lo + j < len ? row[lo + j] : 0u;
+            s += v[j];
+        }
+        const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+        uint32_t incl = s;
+#pragma unroll
+        for (int off = 1; off < 64; off <<= 1) {
+            const uint32_t y = __shfl_up(incl, off);
+            if (lane >= off) incl += y;
+        }
+        if (lane == 63) wsum[wv] = incl;
+        __syncthreads();
+        uint32_t run = carry + incl - s;
+        for (int w = 0; w < wv; ++w) run += wsum[w];
+#pragma unroll
+        for (int j = 0; j < 4; ++j)
+            if (lo + j < len) {
+                row[lo + j] = run;
+                run += v[j];
+            }
+        carry += wsum[0] + wsum[1] + wsum[2] + wsum[3];
+        __syncthreads();
+    }
+}
+
+// The scans of one call: workgroup 0 scans the buckets (scan_buckets), and
+// workgroup k + 1 scans row k of ccnt (nchunks long), which becomes the offset
+// of each chunk's run within group k's region.
+__global__ __launch_bounds__(256) void k_bin_scan(const uint32_t *totals, int nbins, uint32_t *cursor, uint32_t *gstart,
+                                                  uint32_t *fitem, uint32_t *ccnt, int nchunks)
+{
+    if (blockIdx.x == 0)
+        scan_buckets<256>(totals, nbins, 0u, cursor, gstart, fitem);
+    else
+        scan_row(ccnt + (size_t)(blockIdx.x - 1) * nchunks, nchunks);
+}
+
+// The common steps of both scatters, for one chunk of count <= 256 * PER
+// templates: element q of a thread (present when q*256 + threadIdx.x < count)
+// has value kv[q] < 2^16 whose key is kv[q] >> shift (< nkeys <= kMaxGroups).
+// Ranks the elements within their keys (kv[q] gets its rank in the high half),
+// sets lst[k] = the first position of key k in the chunk ordered by key, and
+// cnt[k] = start(k, c) for each key k present c times: the global start of the
+// chunk's run of key k. Called by all 256 threads; cnt is read back only after
+// a later barrier.
+template <int PER, typename StartF>
+__device__ __forceinline__ void rank_chunk(uint32_t *cnt, uint32_t *lst, int nkeys, int count, uint32_t (&kv)[PER],
+                                           int shift, StartF start)
+{
+    for (int b = threadIdx.x; b < nkeys; b += 256) cnt[b] = 0;
     __syncthreads();
 #pragma unroll
-    for (int q = 0; q < kBinPerThread; ++q) {
-        const int64_t i = base + q * 256 + threadIdx.x;
-        if (i < n) order[cnt[bin[q]] + rank[q]] = (uint32_t)i;
+    for (int q = 0; q < PER; ++q)
+        if (q * 256 + (int)threadIdx.x < count) kv[q] |= atomicAdd(&cnt[kv[q] >> shift], 1u) << 16;
+    __syncthreads();
+    if (threadIdx.x < 64) wave_prefix([&](int k) { return cnt[k]; }, nkeys, lst);
+    __syncthreads();
+    static_assert(kMaxGroups <= 256, "one key per thread");
+    if ((int)threadIdx.x < nkeys) {
+        const uint32_t c = cnt[threadIdx.x];
+        if (c) cnt[threadIdx.x] = start((int)threadIdx.x, c);
     }
+}
+
+// LDS of a first-scatter workgroup: the chunk ordered by group, each entry
+// (position in the chunk << 16) | bucket.
+struct GroupLds {
+    uint32_t cnt[kGroupSlots];
+    uint32_t lst[kGroupSlots];
+    uint32_t sval[kBinChunk];
+};
+
+// LDS of a second-scatter workgroup: the chunk ordered by bucket (index and
+// bucket within the group).
+struct FineLds {
+    uint32_t cnt[kGroupSlots];
+    uint32_t lst[kGroupSlots];
+    uint32_t sidx[kFineChunk];
+    uint8_t skey[kFineChunk];
+};
+
+// First scatter of chunk c: templates base + j (j < count), buckets bins[base
+// + j], to tmp at gstart[k] + crun[k * stride] (group k's region, this chunk's
+// run in it) in the order of their ranks; the bucket within the group to tsub
+// at the same position.
+__device__ __forceinline__ void group_chunk(GroupLds &L, int ngroups, int64_t base, int count, const uint16_t *bins,
+                                            const uint32_t *gstart, const uint32_t *crun, size_t stride, uint32_t *tmp,
+                                            uint8_t *tsub)
+{
+    uint32_t kv[kBinPerThread];
+#pragma unroll
+    for (int q = 0; q < kBinPerThread; ++q) {
+        const int j = q * 256 + threadIdx.x;
+        kv[q] = j < count ? bins[base + j] : 0u;
+    }
+    rank_chunk<kBinPerThread>(L.cnt, L.lst, ngroups, count, kv, kGroupShift,
+                              [&](int k, uint32_t) { return gstart[k] + crun[(size_t)k * stride]; });
+#pragma unroll
+    for (int q = 0; q < kBinPerThread; ++q) {
+        const int j = q * 256 + threadIdx.x;
+        if (j < count) {
+            const uint32_t b = kv[q] & 0xffffu;
+            L.sval[L.lst[b >> kGroupShift] + (kv[q] >> 16)] = ((uint32_t)j << 16) | b;
+        }
+    }
+    __syncthreads();
+    for (int p = threadIdx.x; p < count; p += 256) {
+        const uint32_t v = L.sval[p], b = v & 0xffffu, k = b >> kGroupShift;
+        const uint32_t at = L.cnt[k] + ((uint32_t)p - L.lst[k]);
+        tmp[at] = (uint32_t)(base + (v >> 16));
+        tsub[at] = (uint8_t)(b & kGroupMask);
+    }
+}
+
+// Second scatter of one chunk: entries src[j] (index) and ssub[j] (bucket
+// within the group), j < count, to order at their bucket's cursor cur[sub].
+__device__ __forceinline__ void fine_chunk(FineLds &L, int nkeys, int count, const uint32_t *src, const uint8_t *ssub,
+                                           uint32_t *cur, uint32_t *order)
+{
+    uint32_t idx[kFinePerThread], kv[kFinePerThread];
+#pragma unroll
+    for (int q = 0; q < kFinePerThread; ++q) {
+        const int j = q * 256 + threadIdx.x;
+        idx[q] = j < count ? src[j] : 0u;
+        kv[q] = j < count ? ssub[j] : 0u;
+    }
+    rank_chunk<kFinePerThread>(L.cnt, L.lst, nkeys, count, kv, 0,
+                               [&](int k, uint32_t c) { return atomicAdd(&cur[k], c); });
+#pragma unroll
+    for (int q = 0; q < kFinePerThread; ++q)
+        if (q * 256 + (int)threadIdx.x < count) {
+            const uint32_t k = kv[q] & 0xffffu, p = L.lst[k] + (kv[q] >> 16);
+            L.sidx[p] = idx[q];
+            L.skey[p] = (uint8_t)k;
+        }
+    __syncthreads();
+    for (int p = threadIdx.x; p < count; p += 256) {
+        const uint32_t k = L.skey[p];
+        order[L.cnt[k] + ((uint32_t)p - L.lst[k])] = L.sidx[p];
+    }
+}
+
+// First scatter: workgroup c takes the chunk of templates c * kBinChunk .. of
+// the call (ccnt as scanned by k_bin_scan, row stride gridDim.x).
+__global__ __launch_bounds__(256) void k_bin_group(int64_t n, int ngroups, const uint16_t *bins, const uint32_t *gstart,
+                                                   const uint32_t *ccnt, uint32_t *tmp, uint8_t *tsub)
+{
+    __shared__ GroupLds L;
+    const int64_t base = (int64_t)blockIdx.x * kBinChunk;
+    group_chunk(L, ngroups, base, (int)min<int64_t>(kBinChunk, n - base), bins, gstart, ccnt + blockIdx.x, gridDim.x,
+                tmp, tsub);
+}
+
+// Second scatter: workgroup w takes chunk w - fitem[k] (of kFineChunk) of group
+// k's region of tmp (fitem[k] <= w < fitem[k + 1]) to the group's buckets;
+// workgroups from fitem[ngroups] on have nothing to do.
+__global__ __launch_bounds__(256) void k_bin_fine(int nbins, const uint32_t *gstart, const uint32_t *fitem,
+                                                  uint32_t *cursor, const uint32_t *tmp, const uint8_t *tsub,
+                                                  uint32_t *order)
+{
+    __shared__ FineLds L;
+    const int ngroups = (nbins + kGroupMask) >> kGroupShift;
+    const uint32_t w = blockIdx.x;
+    if (w >= fitem[ngroups]) return;
+    const int k = find_slot(fitem, ngroups, w);
+    const uint32_t e0 = gstart[k] + (w - fitem[k]) * (uint32_t)kFineChunk;
+    const int b0 = k << kGroupShift;
+    fine_chunk(L, min(1 << kGroupShift, nbins - b0), (int)min<uint32_t>(kFineChunk, gstart[k + 1] - e0), tmp + e0,
+               tsub + e0, cursor + b0, order);
 }
 
 // One LDS-DMA copy of 16 bytes per lane: lane i's 16 bytes at src land at
@@ -1378,89 +1659,86 @@ struct BatchMap {
     int32_t wb, nbins;  // bucket shift and count of this map
     int32_t S;          // slab columns
     int32_t chunk0;     // first sort chunk of this map
+    uint64_t cc0;       // offset of this map's counts per group and sort chunk
     float *snr;         // optional per-template output
 };
 
-__device__ __forceinline__ int find_map(const uint32_t *start, int n_maps, uint32_t item)
-{
-    int lo = 0, hi = n_maps;  // start[lo] <= item < start[hi]
-    while (hi - lo > 1) {
-        const int mid = (lo + hi) >> 1;
-        if (start[mid] <= item) lo = mid; else hi = mid;
-    }
-    return lo;
-}
-
 __global__ __launch_bounds__(256) void k_bin_count_batch(const BatchMap *maps, int n_maps, const uint32_t *chunk_start,
-                                                         uint32_t *totals)
+                                                         uint32_t *totals, uint16_t *bins, uint32_t *ccnt)
 {
     __shared__ uint32_t hist[kMaxBins];
-    const int mi = find_map(chunk_start, n_maps, blockIdx.x);
+    const int mi = find_slot(chunk_start, n_maps, blockIdx.x);
     const BatchMap &d = maps[mi];
     for (int b = threadIdx.x; b < d.nbins; b += 256) hist[b] = 0;
     __syncthreads();
-    const int64_t base = (int64_t)(blockIdx.x - chunk_start[mi]) * kBinChunk;
+    const uint32_t c = blockIdx.x - chunk_start[mi];
+    const int64_t base = (int64_t)c * kBinChunk;
     for (int q = 0; q < kBinPerThread; ++q) {
         const int64_t i = base + q * 256 + threadIdx.x;
-        if (i < d.n) atomicAdd(&hist[bin_of<false>(d.g, nullptr, d.m, 0, i, d.wb)], 1u);
-    }
-    __syncthreads();
-    for (int b = threadIdx.x; b < d.nbins; b += 256)
-        if (hist[b]) atomicAdd(&totals[d.bin0 + b], hist[b]);
-}
-
-// One workgroup per map: exclusive scan of its bucket totals, offset by the map's order0.
-__global__ __launch_bounds__(256) void k_bin_scan_batch(const BatchMap *maps, const uint32_t *totals, uint32_t *cursor)
-{
-    __shared__ uint32_t part[256];
-    const BatchMap &d = maps[blockIdx.x];
-    const int per = (d.nbins + 255) / 256;
-    const int lo = threadIdx.x * per, hi = min(d.nbins, lo + per);
-    uint32_t s = 0;
-    for (int b = lo; b < hi; ++b) s += totals[d.bin0 + b];
-    part[threadIdx.x] = s;
-    __syncthreads();
-    for (int off = 1; off < 256; off <<= 1) {
-        const uint32_t v = threadIdx.x >= off ? part[threadIdx.x - off] : 0;
-        __syncthreads();
-        part[threadIdx.x] += v;
-        __syncthreads();
-    }
-    uint32_t run = (uint32_t)d.order0 + part[threadIdx.x] - s;
-    for (int b = lo; b < hi; ++b) {
-        cursor[d.bin0 + b] = run;
-        run += totals[d.bin0 + b];
-    }
-}
-
-__global__ __launch_bounds__(256) void k_bin_scatter_batch(const BatchMap *maps, int n_maps, const uint32_t *chunk_start,
-                                                           uint32_t *cursor, uint32_t *order)
-{
-    __shared__ uint32_t cnt[kMaxBins];
-    const int mi = find_map(chunk_start, n_maps, blockIdx.x);
-    const BatchMap &d = maps[mi];
-    for (int b = threadIdx.x; b < d.nbins; b += 256) cnt[b] = 0;
-    __syncthreads();
-    const int64_t base = (int64_t)(blockIdx.x - chunk_start[mi]) * kBinChunk;
-    uint32_t bin[kBinPerThread], rank[kBinPerThread];
-#pragma unroll
-    for (int q = 0; q < kBinPerThread; ++q) {
-        const int64_t i = base + q * 256 + threadIdx.x;
-        bin[q] = 0;
-        rank[q] = 0;
         if (i < d.n) {
-            bin[q] = bin_of<false>(d.g, nullptr, d.m, 0, i, d.wb);
-            rank[q] = atomicAdd(&cnt[bin[q]], 1u);
+            const uint32_t b = bin_of<false>(d.g, nullptr, d.m, 0, i, d.wb);
+            bins[d.order0 + i] = (uint16_t)b;
+            atomicAdd(&hist[b], 1u);
         }
     }
     __syncthreads();
-    reserve_runs(cnt, d.nbins, cursor + d.bin0);
-    __syncthreads();
-#pragma unroll
-    for (int q = 0; q < kBinPerThread; ++q) {
-        const int64_t i = base + q * 256 + threadIdx.x;
-        if (i < d.n) order[cnt[bin[q]] + rank[q]] = (uint32_t)i;
+    count_out(hist, d.nbins, totals + d.bin0, ccnt + d.cc0 + c, chunk_start[mi + 1] - chunk_start[mi]);
+}
+
+// The scans of a batch, 1 + max_groups workgroups per map: the first scans the
+// map's buckets, offset by its order0 (tables at gstart/fitem + map index *
+// kGroupSlots); workgroup k + 1 scans row k of the map's chunk counts.
+__global__ __launch_bounds__(256) void k_bin_scan_batch(const BatchMap *maps, const uint32_t *chunk_start,
+                                                        int max_groups, const uint32_t *totals, uint32_t *cursor,
+                                                        uint32_t *gstart, uint32_t *fitem, uint32_t *ccnt)
+{
+    const int mi = blockIdx.x / (max_groups + 1), k = (int)(blockIdx.x % (max_groups + 1)) - 1;
+    const BatchMap &d = maps[mi];
+    if (k < 0) {
+        const size_t t0 = (size_t)mi * kGroupSlots;
+        scan_buckets<256>(totals + d.bin0, d.nbins, (uint32_t)d.order0, cursor + d.bin0, gstart + t0, fitem + t0);
+    } else if (k < (d.nbins + kGroupMask) >> kGroupShift) {
+        const uint32_t nc = chunk_start[mi + 1] - chunk_start[mi];
+        scan_row(ccnt + d.cc0 + (size_t)k * nc, (int)nc);
     }
+}
+
+// The scatters of k_bin_group and k_bin_fine, each workgroup on one map's
+// templates: sort chunks in map order (chunk_start), and for the second,
+// fine_start[mi] = the map's first workgroup (it has its second-scatter chunk
+// count plus its group count of them, an upper bound of its chunks of group
+// regions).
+__global__ __launch_bounds__(256) void k_bin_group_batch(const BatchMap *maps, int n_maps, const uint32_t *chunk_start,
+                                                         const uint16_t *bins, const uint32_t *gstart,
+                                                         const uint32_t *ccnt, uint32_t *tmp, uint8_t *tsub)
+{
+    __shared__ GroupLds L;
+    const int mi = find_slot(chunk_start, n_maps, blockIdx.x);
+    const BatchMap &d = maps[mi];
+    const uint32_t c = blockIdx.x - chunk_start[mi];
+    const int64_t base = (int64_t)c * kBinChunk;
+    group_chunk(L, (d.nbins + kGroupMask) >> kGroupShift, base, (int)min<int64_t>(kBinChunk, d.n - base),
+                bins + d.order0, gstart + (size_t)mi * kGroupSlots, ccnt + d.cc0 + c,
+                chunk_start[mi + 1] - chunk_start[mi], tmp, tsub);
+}
+
+__global__ __launch_bounds__(256) void k_bin_fine_batch(const BatchMap *maps, int n_maps, const uint32_t *fine_start,
+                                                        const uint32_t *gstart, const uint32_t *fitem, uint32_t *cursor,
+                                                        const uint32_t *tmp, const uint8_t *tsub, uint32_t *order)
+{
+    __shared__ FineLds L;
+    const int mi = find_slot(fine_start, n_maps, blockIdx.x);
+    const BatchMap &d = maps[mi];
+    const int ngroups = (d.nbins + kGroupMask) >> kGroupShift;
+    const uint32_t *fi = fitem + (size_t)mi * kGroupSlots;
+    const uint32_t *gs = gstart + (size_t)mi * kGroupSlots;
+    const uint32_t w = blockIdx.x - fine_start[mi];
+    if (w >= fi[ngroups]) return;
+    const int k = find_slot(fi, ngroups, w);
+    const uint32_t e0 = gs[k] + (w - fi[k]) * (uint32_t)kFineChunk;
+    const int b0 = k << kGroupShift;
+    fine_chunk(L, min(1 << kGroupShift, d.nbins - b0), (int)min<uint32_t>(kFineChunk, gs[k + 1] - e0), tmp + e0,
+               tsub + e0, cursor + d.bin0 + b0, order);
 }
 
 template <int WG, int TPT, bool HW, int MAPT, int SC>
@@ -1480,7 +1758,7 @@ __global__ __launch_bounds__(WG, kSlabWavesPerSimd) void k_score_batch(const Bat
         __syncthreads();
         const uint32_t item = item_s;
         if (item >= total) break;  // every workgroup reaches this: the queue only grows
-        const int mi = find_map(item_start, n_maps, item);
+        const int mi = find_slot(item_start, n_maps, item);
         const BatchMap d = maps[mi];
         const uint64_t key = score_block<WG, TPT, HW, MAPT, SC>(d.m, d.g, nullptr, order + d.order0, 0, d.n,
                                                                    (int64_t)(item - item_start[mi]), d.S, norm,

@@ -383,12 +383,18 @@ stt_status fold_polar(stt_ctx *c, const stt_map *map, const FixedBufs *fb, MapP 
 size_t folded_bytes(const stt_map *map);
 
 // Scratch of a scoring call of n templates: bucket totals and cursors, the
-// binned order (padded to an even count), then one best-key slot per scorer
-// workgroup (each takes at least 1024 templates, whatever the shape).
-size_t score_scratch_bytes(int64_t n)
+// group starts and second-scatter chunk table, the binned order (padded to an
+// even count; the count pass keeps each template's bucket there until the
+// last scatter), one best-key slot per scorer workgroup (each takes at least
+// 1024 templates, whatever the shape), the group regions of the first scatter
+// (4 B index per template), the counts per group and sort chunk, then the
+// bucket within the group of each entry of the group regions (1 B).
+constexpr size_t score_scratch_bytes(int64_t n)
 {
     const size_t n_order = ((size_t)n + 1) & ~(size_t)1;
-    return sizeof(uint32_t) * (2 * (size_t)kMaxBins + n_order) + sizeof(uint64_t) * (size_t)((n + 1023) / 1024);
+    const size_t n_chunks = ((size_t)n + kBinChunk - 1) / kBinChunk;
+    return sizeof(uint32_t) * (2 * (size_t)kMaxBins + 2 * (size_t)kGroupSlots + 2 * n_order + kMaxGroups * n_chunks) +
+           n_order + sizeof(uint64_t) * (size_t)((n + 1023) / 1024);
 }
 
 }  // namespace
@@ -401,8 +407,7 @@ size_t score_scratch_bytes(int64_t n)
 // that device current) by stt_create and kept in g_na_ptr.
 constexpr size_t kNaMapBytes = (size_t)32 << 20;
 constexpr int64_t kNaMaxTracks = (int64_t)1 << 22;
-constexpr size_t kNaScratchBytes =
-    sizeof(uint32_t) * (2 * (size_t)kMaxBins + (size_t)kNaMaxTracks) + sizeof(uint64_t) * (size_t)(kNaMaxTracks / 1024);
+constexpr size_t kNaScratchBytes = score_scratch_bytes(kNaMaxTracks);
 constexpr size_t kNaBytes = kNaMapBytes + kNaScratchBytes;
 static __device__ __align__(256) unsigned char scratch[kNaBytes];
 
@@ -456,18 +461,31 @@ stt_status bin_templates(stt_ctx *c, const MapP &m, const GenP &g, const Trk *tr
         stt_status s = ensure_scratch(c, score_scratch_bytes(n));
         if (s != STT_OK) return s;
     }
+    const int ngroups = (nbins + (1 << kGroupShift) - 1) >> kGroupShift;
     uint32_t *totals = (uint32_t *)(fb ? fb->scratch : c->scratch);
     uint32_t *cursor = totals + kMaxBins;
-    order = cursor + kMaxBins;
-    wg_keys = (uint64_t *)(order + n_order);
     const unsigned bgrid = (unsigned)((n + kBinChunk - 1) / kBinChunk);
+    uint32_t *gstart = cursor + kMaxBins;
+    uint32_t *fitem = gstart + kGroupSlots;
+    order = fitem + kGroupSlots;
+    wg_keys = (uint64_t *)(order + n_order);
+    uint32_t *tmp = (uint32_t *)(wg_keys + (n + 1023) / 1024);
+    uint32_t *ccnt = tmp + n_order;  // [group][chunk], ngroups rows of bgrid
+    uint8_t *tsub = (uint8_t *)(ccnt + (size_t)kMaxGroups * bgrid);
+    uint16_t *bins = (uint16_t *)order;
     ev_record(c, 2);
     hipLaunchKernelGGL(k_fill_u32, dim3((nbins + 255) / 256), dim3(256), 0, c->stream, totals, nbins, 0u);
     hipLaunchKernelGGL(k_bin_count<EXPL>, dim3(bgrid), dim3(256), 0, c->stream, m, g, tr, (uint64_t)first, n, wb,
-                       nbins, totals);
-    hipLaunchKernelGGL(k_bin_scan, dim3(1), dim3(1024), 0, c->stream, (const uint32_t *)totals, nbins, cursor);
-    hipLaunchKernelGGL(k_bin_scatter<EXPL>, dim3(bgrid), dim3(256), 0, c->stream, m, g, tr, (uint64_t)first, n, wb,
-                       nbins, cursor, order);
+                       nbins, totals, bins, ccnt);
+    hipLaunchKernelGGL(k_bin_scan, dim3(1 + (unsigned)ngroups), dim3(256), 0, c->stream, (const uint32_t *)totals, nbins,
+                       cursor, gstart, fitem, ccnt, (int)bgrid);
+    hipLaunchKernelGGL(k_bin_group, dim3(bgrid), dim3(256), 0, c->stream, n, ngroups, (const uint16_t *)bins,
+                       (const uint32_t *)gstart, (const uint32_t *)ccnt, tmp, tsub);
+    // a group of c templates has ceil(c / kFineChunk) chunks: at most ceil(n / kFineChunk) + ngroups in all
+    hipLaunchKernelGGL(k_bin_fine, dim3((unsigned)((n + kFineChunk - 1) / kFineChunk) + (unsigned)ngroups), dim3(256), 0,
+                       c->stream, nbins,
+                       (const uint32_t *)gstart, (const uint32_t *)fitem, cursor, (const uint32_t *)tmp,
+                       (const uint8_t *)tsub, order);
     STT_HIP(c, hipGetLastError());
     ev_record(c, 3);
     c->used[1] = true;
@@ -565,7 +583,7 @@ stt_status fold_polar(stt_ctx *c, const stt_map *map, const FixedBufs *fb, MapP 
         if (s != STT_OK) return s;
     }
     void *pbuf = fb ? fb->pbuf : c->pbuf;
-    const dim3 fg((unsigned)m.T, (unsigned)((ldc + 255) / 256));  // one column per x, rows over y
+    const dim3 fg((unsigned)m.T, (unsigned)((ldc + 256 * kFoldRows - 1) / (256 * kFoldRows)));  // one column per x, rows over y
     if (map->dtype == STT_P16)
         hipLaunchKernelGGL(k_fold_words, fg, dim3(256), 0, c->stream, m, (uint32_t *)pbuf, ldc);
     else
@@ -1425,9 +1443,11 @@ stt_status stt_score_batch(stt_ctx *c, const stt_map *maps_host, int32_t n_maps,
     const int dtype = maps_host[0].dtype;
     const int esize = fold_esize(dtype);
     std::vector<BatchMap> bm(n_maps);
-    std::vector<uint32_t> chunk_start(n_maps + 1), item_start(n_maps + 1);
+    std::vector<uint32_t> chunk_start(n_maps + 1), item_start(n_maps + 1), fine_start(n_maps + 1);
     const int per_item = c->slab_wg * c->slab_tpt;
-    uint64_t norder = 0, nchunks = 0, nitems = 0;
+    uint64_t norder = 0, nchunks = 0, nitems = 0, nfine = 0;
+    size_t ncc = 0;     // counts per group and sort chunk, all maps
+    int max_groups = 1;  // most groups of any map
     size_t shm = 0;
     bool dma_ok = c->dma;  // every map's column fits two DMA slabs
     uint64_t fold_px = 0, fold_cols = 0;
@@ -1463,15 +1483,24 @@ stt_status stt_score_batch(stt_ctx *c, const stt_map *maps_host, int32_t n_maps,
         }
         d.snr = snr_dev_host ? snr_dev_host[i] : nullptr;
         chunk_start[i] = (uint32_t)nchunks;
+        fine_start[i] = (uint32_t)nfine;
         item_start[i] = (uint32_t)nitems;
         d.chunk0 = (int32_t)nchunks;
         norder += (uint64_t)n;
         nchunks += (uint64_t)((n + kBinChunk - 1) / kBinChunk);
+        {
+            const int ng = (d.nbins + kGroupMask) >> kGroupShift;
+            nfine += (uint64_t)((n + kFineChunk - 1) / kFineChunk) + (uint64_t)ng;
+            d.cc0 = ncc;
+            ncc += (size_t)ng * (size_t)((n + kBinChunk - 1) / kBinChunk);
+            max_groups = std::max(max_groups, ng);
+        }
         nitems += (uint64_t)((n + per_item - 1) / per_item);
         if (norder >= ((uint64_t)1 << 32) || nitems >= ((uint64_t)1 << 31))
             return fail(c, STT_ERANGE, "a batch holds fewer than 2^32 templates");
     }
     chunk_start[n_maps] = (uint32_t)nchunks;
+    fine_start[n_maps] = (uint32_t)nfine;
     item_start[n_maps] = (uint32_t)nitems;
     STT_HIP(c, hipSetDevice(c->device));
     // every map is scored from its polar fold (one launch folds them all); slabs stream in by DMA
@@ -1508,15 +1537,23 @@ stt_status stt_score_batch(stt_ctx *c, const stt_map *maps_host, int32_t n_maps,
     jobs[n_maps] = FoldJob{MapP{}, nullptr, 0, (uint32_t)fold_cols};
     if (!c->n_cu) STT_HIP(c, hipDeviceGetAttribute(&c->n_cu, hipDeviceAttributeMultiprocessorCount, c->device));
 
-    // scratch: [totals | cursor | queue | order]
+    // scratch: [totals | cursor | queue | order (first the buckets of the count) | group starts | second-
+    // scatter chunk tables | group regions | counts per group and sort chunk | buckets within the group]
     const size_t nb_all = (size_t)n_maps * kMaxBins;
-    const size_t need = sizeof(uint32_t) * (2 * nb_all + 64 + norder);
+    const size_t ng_all = (size_t)n_maps * kGroupSlots;
+    const size_t need = sizeof(uint32_t) * (2 * nb_all + 64 + 2 * norder + 2 * ng_all + ncc) + norder;
     stt_status s = ensure_scratch(c, need);
     if (s != STT_OK) return s;
     uint32_t *totals = (uint32_t *)c->scratch;
     uint32_t *cursor = totals + nb_all;
     uint32_t *queue = cursor + nb_all;
     uint32_t *order = queue + 64;
+    uint32_t *gstart = order + norder;
+    uint32_t *fitem = gstart + ng_all;
+    uint32_t *tmp = fitem + ng_all;
+    uint32_t *ccnt = tmp + norder;
+    uint8_t *tsub = (uint8_t *)(ccnt + ncc);
+    uint16_t *bins = (uint16_t *)order;
 
     // the argument key: a repeat of the last batch replays its graph
     std::vector<uint8_t> key;
@@ -1537,7 +1574,7 @@ stt_status stt_score_batch(stt_ctx *c, const stt_map *maps_host, int32_t n_maps,
 
     if (!same) {
         // descriptor tables to the device (synchronous: they must outlive the call)
-        const size_t tbl = sizeof(BatchMap) * n_maps + sizeof(FoldJob) * (n_maps + 1) + sizeof(uint32_t) * 2 * (n_maps + 1);
+        const size_t tbl = sizeof(BatchMap) * n_maps + sizeof(FoldJob) * (n_maps + 1) + sizeof(uint32_t) * 3 * (n_maps + 1);
         if (tbl > c->bdev_bytes) {
             STT_HIP(c, hipStreamSynchronize(c->stream));
             if (c->bdev) (void)hipFree(c->bdev);
@@ -1554,10 +1591,12 @@ stt_status stt_score_batch(stt_ctx *c, const stt_map *maps_host, int32_t n_maps,
         FoldJob *djobs = (FoldJob *)(dmaps + n_maps);
         uint32_t *dchunk = (uint32_t *)(djobs + (n_maps + 1));
         uint32_t *ditem = dchunk + (n_maps + 1);
+        uint32_t *dfine = ditem + (n_maps + 1);
         STT_HIP(c, hipMemcpy(dmaps, bm.data(), sizeof(BatchMap) * n_maps, hipMemcpyHostToDevice));
         STT_HIP(c, hipMemcpy(djobs, jobs.data(), sizeof(FoldJob) * (n_maps + 1), hipMemcpyHostToDevice));
         STT_HIP(c, hipMemcpy(dchunk, chunk_start.data(), sizeof(uint32_t) * (n_maps + 1), hipMemcpyHostToDevice));
         STT_HIP(c, hipMemcpy(ditem, item_start.data(), sizeof(uint32_t) * (n_maps + 1), hipMemcpyHostToDevice));
+        STT_HIP(c, hipMemcpy(dfine, fine_start.data(), sizeof(uint32_t) * (n_maps + 1), hipMemcpyHostToDevice));
         if (c->gexec) { (void)hipGraphExecDestroy(c->gexec); c->gexec = nullptr; }
         if (c->graph) { (void)hipGraphDestroy(c->graph); c->graph = nullptr; }
         c->bkey.clear();
@@ -1566,7 +1605,7 @@ stt_status stt_score_batch(stt_ctx *c, const stt_map *maps_host, int32_t n_maps,
             const bool timed = st == c->stream;  // events only outside graph capture
             if (timed) ev_record(c, 2);
             {
-                const dim3 fg((unsigned)fold_cols, (unsigned)((max_ldc + 255) / 256));  // columns over x, rows over y
+                const dim3 fg((unsigned)fold_cols, (unsigned)((max_ldc + 256 * kFoldRows - 1) / (256 * kFoldRows)));  // columns over x, rows over y
                 if (dtype == STT_P16)
                     hipLaunchKernelGGL(k_fold_batch<kMapP16>, dim3(fg), dim3(256), 0, st, (const FoldJob *)djobs,
                                        n_maps);
@@ -1579,11 +1618,17 @@ stt_status stt_score_batch(stt_ctx *c, const stt_map *maps_host, int32_t n_maps,
             hipLaunchKernelGGL(k_fill_u32, dim3(1), dim3(256), 0, st, queue, (int64_t)1, 0u);
             if (nchunks) {
                 hipLaunchKernelGGL(k_bin_count_batch, dim3((unsigned)nchunks), dim3(256), 0, st,
-                                   (const BatchMap *)dmaps, n_maps, (const uint32_t *)dchunk, totals);
-                hipLaunchKernelGGL(k_bin_scan_batch, dim3(n_maps), dim3(256), 0, st, (const BatchMap *)dmaps,
-                                   (const uint32_t *)totals, cursor);
-                hipLaunchKernelGGL(k_bin_scatter_batch, dim3((unsigned)nchunks), dim3(256), 0, st,
-                                   (const BatchMap *)dmaps, n_maps, (const uint32_t *)dchunk, cursor, order);
+                                   (const BatchMap *)dmaps, n_maps, (const uint32_t *)dchunk, totals, bins, ccnt);
+                hipLaunchKernelGGL(k_bin_scan_batch, dim3((unsigned)(max_groups + 1) * (unsigned)n_maps), dim3(256), 0,
+                                   st, (const BatchMap *)dmaps, (const uint32_t *)dchunk, max_groups,
+                                   (const uint32_t *)totals, cursor, gstart, fitem, ccnt);
+                hipLaunchKernelGGL(k_bin_group_batch, dim3((unsigned)nchunks), dim3(256), 0, st,
+                                   (const BatchMap *)dmaps, n_maps, (const uint32_t *)dchunk, (const uint16_t *)bins,
+                                   (const uint32_t *)gstart, (const uint32_t *)ccnt, tmp, tsub);
+                hipLaunchKernelGGL(k_bin_fine_batch, dim3((unsigned)nfine), dim3(256), 0, st,
+                                   (const BatchMap *)dmaps, n_maps, (const uint32_t *)dfine,
+                                   (const uint32_t *)gstart, (const uint32_t *)fitem, cursor, (const uint32_t *)tmp,
+                                   (const uint8_t *)tsub, order);
             }
             STT_HIP(c, hipGetLastError());
             if (timed) {
