@@ -1,5 +1,6 @@
 // stt_api.hip -- host side of libstt: contexts, argument validation, scratch,
 // launch configuration and the extern "C" entry points declared in stt.h.
+#include <hip/hip_ext.h>
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -49,6 +50,8 @@ struct stt_ctx {
     size_t next = 0;         // first free event of the pool
     size_t last = 0;         // first event of the last call
     bool used[3] = {false, false, false};
+    // events that the next launch_ev records from its own dispatch (its start, its end)
+    hipEvent_t kev_start = nullptr, kev_stop = nullptr;
     std::vector<Rec> recs;   // calls since the last total query
     // Batches: descriptor tables on the device, and the captured graph of the
     // last batch (replayed while the arguments stay the same).
@@ -243,6 +246,7 @@ MapP to_mapp(const stt_map *m)
 stt_status ev_begin(stt_ctx *c)
 {
     for (bool &u : c->used) u = false;
+    c->kev_start = c->kev_stop = nullptr;
     if (!c->timing) return STT_OK;
     while (c->pool.size() < c->next + 6) {
         hipEvent_t e;
@@ -257,6 +261,23 @@ stt_status ev_begin(stt_ctx *c)
 void ev_record(stt_ctx *c, int i)
 {
     if (c->timing) (void)hipEventRecord(c->pool[c->last + i], c->stream);
+}
+
+// Events i (start) and j (end) of this call, -1 for none, taken by the next launch_ev from its
+// kernel's own dispatch. (hipEventRecord enqueues a marker, which waits for the stream to drain:
+// about 6 us between two kernels.)
+void ev_attach(stt_ctx *c, int i, int j)
+{
+    c->kev_start = c->timing && i >= 0 ? c->pool[c->last + i] : nullptr;
+    c->kev_stop = c->timing && j >= 0 ? c->pool[c->last + j] : nullptr;
+}
+
+// A kernel launch on the context's stream that records the attached events, if any.
+template <typename K, typename... A>
+void launch_ev(stt_ctx *c, K kern, dim3 grid, dim3 block, size_t shm, A... args)
+{
+    hipExtLaunchKernelGGL(kern, grid, block, (uint32_t)shm, c->stream, c->kev_start, c->kev_stop, 0u, args...);
+    c->kev_start = c->kev_stop = nullptr;
 }
 
 void ev_end(stt_ctx *c)
@@ -291,8 +312,7 @@ stt_status launch_slab_t(stt_ctx *c, const MapP &m, const GenP &g, const Trk *tr
     if (shm > 64 * 1024)
         STT_HIP(c, hipFuncSetAttribute((const void *)kern, hipFuncAttributeMaxDynamicSharedMemorySize, (int)shm));
     const unsigned grid = (unsigned)((n + WG * TPT - 1) / (WG * TPT));
-    hipLaunchKernelGGL(kern, dim3(grid), dim3(WG), shm, c->stream, m, g, tr, order, (uint64_t)first, n, S, norm, snr,
-                       wg_keys);
+    launch_ev(c, kern, dim3(grid), dim3(WG), shm, m, g, tr, order, (uint64_t)first, n, S, norm, snr, wg_keys);
     STT_HIP(c, hipGetLastError());
     return STT_OK;
 }
@@ -473,8 +493,8 @@ stt_status bin_templates(stt_ctx *c, const MapP &m, const GenP &g, const Trk *tr
     uint32_t *ccnt = tmp + n_order;  // [group][chunk], ngroups rows of bgrid
     uint8_t *tsub = (uint8_t *)(ccnt + (size_t)kMaxGroups * bgrid);
     uint16_t *bins = (uint16_t *)order;
-    ev_record(c, 2);
-    hipLaunchKernelGGL(k_fill_u32, dim3((nbins + 255) / 256), dim3(256), 0, c->stream, totals, nbins, 0u);
+    ev_attach(c, 2, -1);
+    launch_ev(c, k_fill_u32, dim3((nbins + 255) / 256), dim3(256), 0, totals, (int64_t)nbins, 0u);
     hipLaunchKernelGGL(k_bin_count<EXPL>, dim3(bgrid), dim3(256), 0, c->stream, m, g, tr, (uint64_t)first, n, wb,
                        nbins, totals, bins, ccnt);
     hipLaunchKernelGGL(k_bin_scan, dim3(1 + (unsigned)ngroups), dim3(256), 0, c->stream, (const uint32_t *)totals, nbins,
@@ -482,12 +502,11 @@ stt_status bin_templates(stt_ctx *c, const MapP &m, const GenP &g, const Trk *tr
     hipLaunchKernelGGL(k_bin_group, dim3(bgrid), dim3(256), 0, c->stream, n, ngroups, (const uint16_t *)bins,
                        (const uint32_t *)gstart, (const uint32_t *)ccnt, tmp, tsub);
     // a group of c templates has ceil(c / kFineChunk) chunks: at most ceil(n / kFineChunk) + ngroups in all
-    hipLaunchKernelGGL(k_bin_fine, dim3((unsigned)((n + kFineChunk - 1) / kFineChunk) + (unsigned)ngroups), dim3(256), 0,
-                       c->stream, nbins,
-                       (const uint32_t *)gstart, (const uint32_t *)fitem, cursor, (const uint32_t *)tmp,
-                       (const uint8_t *)tsub, order);
+    ev_attach(c, -1, 3);
+    launch_ev(c, k_bin_fine, dim3((unsigned)((n + kFineChunk - 1) / kFineChunk) + (unsigned)ngroups), dim3(256), 0,
+              nbins, (const uint32_t *)gstart, (const uint32_t *)fitem, cursor, (const uint32_t *)tmp,
+              (const uint8_t *)tsub, order);
     STT_HIP(c, hipGetLastError());
-    ev_record(c, 3);
     c->used[1] = true;
     return STT_OK;
 }
@@ -507,6 +526,7 @@ stt_status score_folded(stt_ctx *c, const MapP &m, const GenP &g, const Trk *tr,
             launch_direct<EXPL, false, MAPT>(c, per_wave, m, g, tr, first, n, norm, snr, best);
         STT_HIP(c, hipGetLastError());
         ev_record(c, 1);
+        ev_record(c, 5);
         c->used[0] = true;
         return STT_OK;
     }
@@ -518,22 +538,24 @@ stt_status score_folded(stt_ctx *c, const MapP &m, const GenP &g, const Trk *tr,
     if (sc > 0) {
         // aligned slabs of the folded map streamed into LDS with double-buffered DMA
         const size_t shm = 2 * (size_t)esize * (size_t)sc * ldc;
-        ev_record(c, 0);
+        ev_attach(c, 0, 1);
         s = launch_slab<MAPT>(c, sc, c->slab_wg, c->slab_tpt, m, g, tr, order, first, n, sc, shm, norm, snr, wg_keys);
     } else {
         // one slab buffer, staged through registers (maps too wide for two DMA slabs)
         const int S = std::min<int>(std::min<int>(64, (c->lds_bytes - 256) / (esize * m.F)), m.T);
         const size_t shm = (size_t)esize * (size_t)S * m.F;
-        ev_record(c, 0);
+        ev_attach(c, 0, 1);
         s = launch_slab<MAPT>(c, 0, c->slab_wg, c->slab_tpt, m, g, tr, order, first, n, S, shm, norm, snr, wg_keys);
     }
     if (s != STT_OK) return s;
-    ev_record(c, 1);
     c->used[0] = true;
     if (best) {
         const int64_t n_wg = (n + (int64_t)c->slab_wg * c->slab_tpt - 1) / ((int64_t)c->slab_wg * c->slab_tpt);
-        hipLaunchKernelGGL(k_reduce_keys, dim3(1), dim3(1024), 0, c->stream, (const uint64_t *)wg_keys, n_wg, best);
+        ev_attach(c, -1, 5);
+        launch_ev(c, k_reduce_keys, dim3(1), dim3(1024), 0, (const uint64_t *)wg_keys, n_wg, best);
         STT_HIP(c, hipGetLastError());
+    } else {
+        ev_record(c, 5);
     }
     return STT_OK;
 }
@@ -554,13 +576,13 @@ stt_status score_impl(stt_ctx *c, const stt_map *map, const GenP &g, const Trk *
 
     stt_status s = ev_begin(c);
     if (s != STT_OK) return s;
-    ev_record(c, 4);
+    ev_attach(c, 4, -1);  // taken by the fold's launch
     MapP m;
     if ((s = fold_polar(c, map, fb, m)) != STT_OK) return s;
+    // score_folded records event 5 at the end of its last kernel
     s = map->dtype == STT_P16 ? score_folded<EXPL, kMapPolH>(c, m, g, tr, first, n, norm, snr, best, fb, slab, per_wave)
                               : score_folded<EXPL, kMapPol>(c, m, g, tr, first, n, norm, snr, best, fb, slab, per_wave);
     if (s != STT_OK) return s;
-    ev_record(c, 5);
     c->used[2] = true;
     ev_end(c);
     return STT_OK;
@@ -585,9 +607,9 @@ stt_status fold_polar(stt_ctx *c, const stt_map *map, const FixedBufs *fb, MapP 
     void *pbuf = fb ? fb->pbuf : c->pbuf;
     const dim3 fg((unsigned)m.T, (unsigned)((ldc + 256 * kFoldRows - 1) / (256 * kFoldRows)));  // one column per x, rows over y
     if (map->dtype == STT_P16)
-        hipLaunchKernelGGL(k_fold_words, fg, dim3(256), 0, c->stream, m, (uint32_t *)pbuf, ldc);
+        launch_ev(c, k_fold_words, fg, dim3(256), 0, m, (uint32_t *)pbuf, (int64_t)ldc);
     else
-        hipLaunchKernelGGL(k_fold_polar<kMapF32>, fg, dim3(256), 0, c->stream, m, (float2 *)pbuf, ldc);
+        launch_ev(c, k_fold_polar<kMapF32>, fg, dim3(256), 0, m, (float2 *)pbuf, (int64_t)ldc);
     STT_HIP(c, hipGetLastError());
     mf = m;  // an FP16 map keeps its scale 2^e
     mf.Y = (const float2 *)pbuf;
