@@ -234,3 +234,36 @@ def test_batch_full_scale_sampled(orc, stt, ctx, tmp_path):
             assert_close(z, z_orc, what=f"map {k} (T={Ts[k]}) full")
             assert_argmax(jk, z_orc)
         del om
+
+
+def test_batch_sort_against_direct(stt, ctx):
+    """The batch's own bucket sort, at several sort chunks and groups per map: every
+    template's score equals the direct scorer's (index order, no sort) bit for bit. The
+    outputs start as a NaN payload no scorer writes, so a template left unscored shows."""
+    import torch
+    _say("batch sort vs direct")
+    sentinel = np.uint32(0x7FBADBAD)
+    Ts = [1000, 1024, 130, 2000, 60]
+    ns = [3_000_000, 2 * 8192, 65537, 1_000_001, 1]
+    host = _maps(Ts, 64, seed=44)
+    maps = [stt.Map(*to_dev(Y, s)) for Y, s in host]
+    g = stt.Gen(seed=12, stream=7, min_len=10, dtau_max=D10MS)
+
+    def fresh(n):
+        return torch.from_numpy(np.full(n, sentinel, dtype=np.uint32).view(np.float32)).cuda()
+
+    snr = [fresh(n) for n in ns]
+    keys = ctx.score_batch(maps, g, ns, snr=snr).cpu().numpy().view(np.uint64).tolist()
+    ctx.set_path(stt.PATH_DIRECT)
+    try:
+        for k, (m, n) in enumerate(zip(maps, ns)):
+            gk = stt.Gen(seed=g.seed, stream=g.stream + k, min_len=g.min_len, dtau_max=g.dtau_max)
+            want = fresh(n)
+            _, key = ctx.score(m, gen=gk, n=n, snr=want)
+            got_b = snr[k].cpu().numpy().view(np.uint32)
+            want_b = want.cpu().numpy().view(np.uint32)
+            assert not (got_b == sentinel).any(), f"map {k}: templates left unscored"
+            assert np.array_equal(got_b, want_b), f"map {k}"
+            assert keys[k] == key_to_host(key), f"map {k}"
+    finally:
+        ctx.set_path(stt.PATH_AUTO)

@@ -389,3 +389,52 @@ def test_dma_and_register_staging_identical(orc, stt, ctx, F):
         keys.append(ctx.score_batch(maps, g, [20_000, 9_999]).clone())
     ctx.set_staging(True)
     assert torch.equal(keys[0], keys[1])
+
+
+# The slab scorers take templates in the order of the two-pass bucket sort; the direct
+# scorer takes them in index order. Their arithmetic is the same, so every template's score
+# and the best key must agree bit for bit. The outputs start as a NaN payload that no scorer
+# writes: a template the sort lost would keep it.
+SENTINEL = np.uint32(0x7FBADBAD)
+
+
+def _slab_and_direct(stt, ctx, m, count, **kw):
+    import torch
+    out = {}
+    for path in (stt.PATH_DIRECT, stt.PATH_SLAB):
+        ctx.set_path(path)
+        snr = torch.from_numpy(np.full(count, SENTINEL, dtype=np.uint32).view(np.float32)).cuda()
+        _, key = ctx.score(m, snr=snr, **kw)
+        out[path] = (snr.cpu().numpy().view(np.uint32), key_to_host(key))
+    ctx.set_path(stt.PATH_AUTO)
+    d, sl = out[stt.PATH_DIRECT], out[stt.PATH_SLAB]
+    assert not (d[0] == SENTINEL).any() and not (sl[0] == SENTINEL).any(), "templates left unscored"
+    assert np.array_equal(sl[0], d[0])
+    assert sl[1] == d[1]
+
+
+@pytest.mark.parametrize("T,n,L", [
+    (1000, 10_000_000, 10),   # the search map: 7875 buckets, 124 groups, 1221 sort chunks
+    (1000, 3 * 8192, 10),     # whole sort chunks; 36 buckets of 128 columns
+    (1024, 3_000_001, 10),    # 128 buckets per axis: the full 8256 buckets, 129 groups
+    (130, 65537, 120),        # templates of at least 120 of 130 columns: most buckets empty
+    (2000, 1_048_577, 500),   # a ragged tail of one template
+])
+def test_bucket_sort_slab_equals_direct(stt, ctx, T, n, L):
+    _say("sort", T, n, L)
+    F = 64
+    Y, s = synth.noise_map(T, F, seed=T + L, sigma=("loguniform", 0.5, 2.0))
+    m = stt.Map(*to_dev(Y, s))
+    _slab_and_direct(stt, ctx, m, n, gen=_gen(stt, seed=T + 3, stream=1, L=L), n=n)
+
+
+def test_bucket_sort_explicit_tracks_slab_equals_direct(stt, ctx):
+    """The sort of a given template list (buckets from the records, invalid records in bucket 0)."""
+    import torch
+    _say("sort explicit")
+    T, F, n = 700, 90, 200_003
+    Y, s = synth.noise_map(T, F, seed=5, sigma=("loguniform", 0.5, 2.0))
+    m = stt.Map(*to_dev(Y, s))
+    tracks = ctx.make_tracks(_gen(stt, seed=8, stream=3), T, F, 0, n)
+    tracks[torch.arange(0, n, 97, device=tracks.device), 1] = T + 5  # t2 past the map: invalid
+    _slab_and_direct(stt, ctx, m, n, tracks=tracks)
