@@ -479,8 +479,8 @@ __global__ __launch_bounds__(256) void k_argmax(const float *z, int64_t n, uint6
 // and writes the chunk's count per group. The scans give every bucket its
 // start, every group its region and every chunk its run in each group. The
 // first scatter moves each index, with its bucket within the group, to its
-// chunk's run in its group's region (no atomics: the place of every run is
-// known). The second takes each group's region in chunks of kFineChunk and
+// chunk's run in its group's region (no cursor atomics: the place of every run
+// is known). The second takes each group's region in chunks of kFineChunk and
 // moves each index to its bucket, the runs reserved by atomics on the bucket
 // cursors. Each scatter workgroup first orders its chunk by key in LDS, then
 // stores it run by run: consecutive lanes write consecutive addresses, so a
@@ -602,7 +602,7 @@ __global__ __launch_bounds__(256) void k_bin_count(MapP m, GenP g, const Trk *tr
     count_out(hist, nbins, totals, ccnt + blockIdx.x, gridDim.x);
 }
 
-// The bucket scan of one call or map (1024 or 256 threads, nbins <= kMaxBins):
+// The bucket scan of one call or map by NT threads (nbins <= kMaxBins):
 // cursor[b] = base + the templates in buckets before b; gstart[k] = cursor of
 // group k's first bucket, gstart[ngroups] = base + all; fitem[k] = the first
 // second-scatter chunk of group k, fitem[ngroups] = their count.
