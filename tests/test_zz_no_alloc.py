@@ -87,6 +87,20 @@ def test_noalloc_given_tracks_and_small_calls(stt, ctx):
     del torch
 
 
+def test_noalloc_at_its_largest_call(stt, ctx):
+    """n = 4194304 templates on a map whose fold takes 31.25 MiB of the 32: the sort's
+    regions reach the end of the fixed array."""
+    T, F, n = 2000, 2000, NA_MAX_TRACKS
+    _say(f"noalloc largest call T={T} F={F} n={n}")
+    Y, s = synth.noise_map(T, F, seed=35, sigma=("loguniform", 0.5, 2.0))
+    m = stt.Map(*to_dev(Y, s))
+    g = stt.Gen(seed=14, min_len=10, dtau_max=D10MS)
+    z_ref, k_ref, z, k = _both(stt, ctx, m, n, gen=g)
+    assert not np.isnan(z).any()
+    assert np.array_equal(z.view(np.uint32), z_ref.view(np.uint32))
+    assert np.array_equal(k, k_ref)
+
+
 def test_noalloc_rejects_sizes_beyond_its_scratch(stt, ctx):
     import torch
     Y, s = synth.noise_map(100, 128, seed=34, sigma="unit")
