@@ -488,10 +488,10 @@ __global__ __launch_bounds__(256) void k_argmax(const float *z, int64_t n, uint6
 // buckets would store about one index per bucket per workgroup: one cache
 // line per lane).
 
-constexpr int kBinPerThread = 32;                 // templates per thread: count, first scatter
-constexpr int kBinChunk = 256 * kBinPerThread;    // templates per workgroup: count, first scatter
-constexpr int kFinePerThread = 16;                // templates per thread: second scatter
-constexpr int kFineChunk = 256 * kFinePerThread;
+constexpr int kBinPerThread = 32;                 // templates per thread of the count (256 lanes)
+constexpr int kBinChunk = 256 * kBinPerThread;    // templates per sort chunk: count, first scatter
+constexpr int kFineChunk = 4096;                  // templates per chunk of the second scatter
+constexpr int kScatterWG = 512;                   // lanes of a scatter workgroup
 constexpr int kMaxBins = 128 * 129 / 2;           // at most 128 buckets per axis
 constexpr int kGroupShift = 6;                    // buckets per group: 64
 constexpr int kGroupMask = (1 << kGroupShift) - 1;
@@ -698,23 +698,23 @@ __global__ __launch_bounds__(256) void k_bin_scan(const uint32_t *totals, int nb
         scan_row(ccnt + (size_t)(blockIdx.x - 1) * nchunks, nchunks);
 }
 
-// The common steps of both scatters, for one chunk of count <= 256 * PER
-// templates: element q of a thread (present when q*256 + threadIdx.x < count)
+// The common steps of both scatters, for one chunk of count <= NT * PER
+// templates: element q of a thread (present when q*NT + threadIdx.x < count)
 // has value kv[q] < 2^16 whose key is kv[q] >> shift (< nkeys <= kMaxGroups).
 // Ranks the elements within their keys (kv[q] gets its rank in the high half),
 // sets lst[k] = the first position of key k in the chunk ordered by key, and
 // cnt[k] = start(k, c) for each key k present c times: the global start of the
-// chunk's run of key k. Called by all 256 threads; cnt is read back only after
+// chunk's run of key k. Called by all NT threads; cnt is read back only after
 // a later barrier.
-template <int PER, typename StartF>
+template <int PER, typename StartF, int NT>
 __device__ __forceinline__ void rank_chunk(uint32_t *cnt, uint32_t *lst, int nkeys, int count, uint32_t (&kv)[PER],
                                            int shift, StartF start)
 {
-    for (int b = threadIdx.x; b < nkeys; b += 256) cnt[b] = 0;
+    for (int b = threadIdx.x; b < nkeys; b += NT) cnt[b] = 0;
     __syncthreads();
 #pragma unroll
     for (int q = 0; q < PER; ++q)
-        if (q * 256 + (int)threadIdx.x < count) kv[q] |= atomicAdd(&cnt[kv[q] >> shift], 1u) << 16;
+        if (q * NT + (int)threadIdx.x < count) kv[q] |= atomicAdd(&cnt[kv[q] >> shift], 1u) << 16;
     __syncthreads();
     if (threadIdx.x < 64) wave_prefix([&](int k) { return cnt[k]; }, nkeys, lst);
     __syncthreads();
@@ -746,28 +746,30 @@ struct FineLds {
 // + j], to tmp at gstart[k] + crun[k * stride] (group k's region, this chunk's
 // run in it) in the order of their ranks; the bucket within the group to tsub
 // at the same position.
+template <int NT>
 __device__ __forceinline__ void group_chunk(GroupLds &L, int ngroups, int64_t base, int count, const uint16_t *bins,
                                             const uint32_t *gstart, const uint32_t *crun, size_t stride, uint32_t *tmp,
                                             uint8_t *tsub)
 {
-    uint32_t kv[kBinPerThread];
+    constexpr int PER = kBinChunk / NT;
+    uint32_t kv[PER];
 #pragma unroll
-    for (int q = 0; q < kBinPerThread; ++q) {
-        const int j = q * 256 + threadIdx.x;
+    for (int q = 0; q < PER; ++q) {
+        const int j = q * NT + threadIdx.x;
         kv[q] = j < count ? bins[base + j] : 0u;
     }
-    rank_chunk<kBinPerThread>(L.cnt, L.lst, ngroups, count, kv, kGroupShift,
-                              [&](int k, uint32_t) { return gstart[k] + crun[(size_t)k * stride]; });
+    auto st = [&](int k, uint32_t) { return gstart[k] + crun[(size_t)k * stride]; };
+    rank_chunk<PER, decltype(st), NT>(L.cnt, L.lst, ngroups, count, kv, kGroupShift, st);
 #pragma unroll
-    for (int q = 0; q < kBinPerThread; ++q) {
-        const int j = q * 256 + threadIdx.x;
+    for (int q = 0; q < PER; ++q) {
+        const int j = q * NT + threadIdx.x;
         if (j < count) {
             const uint32_t b = kv[q] & 0xffffu;
             L.sval[L.lst[b >> kGroupShift] + (kv[q] >> 16)] = ((uint32_t)j << 16) | b;
         }
     }
     __syncthreads();
-    for (int p = threadIdx.x; p < count; p += 256) {
+    for (int p = threadIdx.x; p < count; p += NT) {
         const uint32_t v = L.sval[p], b = v & 0xffffu, k = b >> kGroupShift;
         const uint32_t at = L.cnt[k] + ((uint32_t)p - L.lst[k]);
         tmp[at] = (uint32_t)(base + (v >> 16));
@@ -777,27 +779,29 @@ __device__ __forceinline__ void group_chunk(GroupLds &L, int ngroups, int64_t ba
 
 // Second scatter of one chunk: entries src[j] (index) and ssub[j] (bucket
 // within the group), j < count, to order at their bucket's cursor cur[sub].
+template <int NT>
 __device__ __forceinline__ void fine_chunk(FineLds &L, int nkeys, int count, const uint32_t *src, const uint8_t *ssub,
                                            uint32_t *cur, uint32_t *order)
 {
-    uint32_t idx[kFinePerThread], kv[kFinePerThread];
+    constexpr int PER = kFineChunk / NT;
+    uint32_t idx[PER], kv[PER];
 #pragma unroll
-    for (int q = 0; q < kFinePerThread; ++q) {
-        const int j = q * 256 + threadIdx.x;
+    for (int q = 0; q < PER; ++q) {
+        const int j = q * NT + threadIdx.x;
         idx[q] = j < count ? src[j] : 0u;
         kv[q] = j < count ? ssub[j] : 0u;
     }
-    rank_chunk<kFinePerThread>(L.cnt, L.lst, nkeys, count, kv, 0,
-                               [&](int k, uint32_t c) { return atomicAdd(&cur[k], c); });
+    auto st = [&](int k, uint32_t c) { return atomicAdd(&cur[k], c); };
+    rank_chunk<PER, decltype(st), NT>(L.cnt, L.lst, nkeys, count, kv, 0, st);
 #pragma unroll
-    for (int q = 0; q < kFinePerThread; ++q)
-        if (q * 256 + (int)threadIdx.x < count) {
+    for (int q = 0; q < PER; ++q)
+        if (q * NT + (int)threadIdx.x < count) {
             const uint32_t k = kv[q] & 0xffffu, p = L.lst[k] + (kv[q] >> 16);
             L.sidx[p] = idx[q];
             L.skey[p] = (uint8_t)k;
         }
     __syncthreads();
-    for (int p = threadIdx.x; p < count; p += 256) {
+    for (int p = threadIdx.x; p < count; p += NT) {
         const uint32_t k = L.skey[p];
         order[L.cnt[k] + ((uint32_t)p - L.lst[k])] = L.sidx[p];
     }
@@ -805,19 +809,19 @@ __device__ __forceinline__ void fine_chunk(FineLds &L, int nkeys, int count, con
 
 // First scatter: workgroup c takes the chunk of templates c * kBinChunk .. of
 // the call (ccnt as scanned by k_bin_scan, row stride gridDim.x).
-__global__ __launch_bounds__(256) void k_bin_group(int64_t n, int ngroups, const uint16_t *bins, const uint32_t *gstart,
+__global__ __launch_bounds__(kScatterWG) void k_bin_group(int64_t n, int ngroups, const uint16_t *bins, const uint32_t *gstart,
                                                    const uint32_t *ccnt, uint32_t *tmp, uint8_t *tsub)
 {
     __shared__ GroupLds L;
     const int64_t base = (int64_t)blockIdx.x * kBinChunk;
-    group_chunk(L, ngroups, base, (int)min<int64_t>(kBinChunk, n - base), bins, gstart, ccnt + blockIdx.x, gridDim.x,
+    group_chunk<kScatterWG>(L, ngroups, base, (int)min<int64_t>(kBinChunk, n - base), bins, gstart, ccnt + blockIdx.x, gridDim.x,
                 tmp, tsub);
 }
 
 // Second scatter: workgroup w takes chunk w - fitem[k] (of kFineChunk) of group
 // k's region of tmp (fitem[k] <= w < fitem[k + 1]) to the group's buckets;
 // workgroups from fitem[ngroups] on have nothing to do.
-__global__ __launch_bounds__(256) void k_bin_fine(int nbins, const uint32_t *gstart, const uint32_t *fitem,
+__global__ __launch_bounds__(kScatterWG) void k_bin_fine(int nbins, const uint32_t *gstart, const uint32_t *fitem,
                                                   uint32_t *cursor, const uint32_t *tmp, const uint8_t *tsub,
                                                   uint32_t *order)
 {
@@ -828,7 +832,7 @@ __global__ __launch_bounds__(256) void k_bin_fine(int nbins, const uint32_t *gst
     const int k = find_slot(fitem, ngroups, w);
     const uint32_t e0 = gstart[k] + (w - fitem[k]) * (uint32_t)kFineChunk;
     const int b0 = k << kGroupShift;
-    fine_chunk(L, min(1 << kGroupShift, nbins - b0), (int)min<uint32_t>(kFineChunk, gstart[k + 1] - e0), tmp + e0,
+    fine_chunk<kScatterWG>(L, min(1 << kGroupShift, nbins - b0), (int)min<uint32_t>(kFineChunk, gstart[k + 1] - e0), tmp + e0,
                tsub + e0, cursor + b0, order);
 }
 
@@ -1708,7 +1712,7 @@ __global__ __launch_bounds__(256) void k_bin_scan_batch(const BatchMap *maps, co
 // fine_start[mi] = the map's first workgroup (it has its second-scatter chunk
 // count plus its group count of them, an upper bound of its chunks of group
 // regions).
-__global__ __launch_bounds__(256) void k_bin_group_batch(const BatchMap *maps, int n_maps, const uint32_t *chunk_start,
+__global__ __launch_bounds__(kScatterWG) void k_bin_group_batch(const BatchMap *maps, int n_maps, const uint32_t *chunk_start,
                                                          const uint16_t *bins, const uint32_t *gstart,
                                                          const uint32_t *ccnt, uint32_t *tmp, uint8_t *tsub)
 {
@@ -1717,12 +1721,12 @@ __global__ __launch_bounds__(256) void k_bin_group_batch(const BatchMap *maps, i
     const BatchMap &d = maps[mi];
     const uint32_t c = blockIdx.x - chunk_start[mi];
     const int64_t base = (int64_t)c * kBinChunk;
-    group_chunk(L, (d.nbins + kGroupMask) >> kGroupShift, base, (int)min<int64_t>(kBinChunk, d.n - base),
+    group_chunk<kScatterWG>(L, (d.nbins + kGroupMask) >> kGroupShift, base, (int)min<int64_t>(kBinChunk, d.n - base),
                 bins + d.order0, gstart + (size_t)mi * kGroupSlots, ccnt + d.cc0 + c,
                 chunk_start[mi + 1] - chunk_start[mi], tmp, tsub);
 }
 
-__global__ __launch_bounds__(256) void k_bin_fine_batch(const BatchMap *maps, int n_maps, const uint32_t *fine_start,
+__global__ __launch_bounds__(kScatterWG) void k_bin_fine_batch(const BatchMap *maps, int n_maps, const uint32_t *fine_start,
                                                         const uint32_t *gstart, const uint32_t *fitem, uint32_t *cursor,
                                                         const uint32_t *tmp, const uint8_t *tsub, uint32_t *order)
 {
@@ -1737,7 +1741,7 @@ __global__ __launch_bounds__(256) void k_bin_fine_batch(const BatchMap *maps, in
     const int k = find_slot(fi, ngroups, w);
     const uint32_t e0 = gs[k] + (w - fi[k]) * (uint32_t)kFineChunk;
     const int b0 = k << kGroupShift;
-    fine_chunk(L, min(1 << kGroupShift, d.nbins - b0), (int)min<uint32_t>(kFineChunk, gs[k + 1] - e0), tmp + e0,
+    fine_chunk<kScatterWG>(L, min(1 << kGroupShift, d.nbins - b0), (int)min<uint32_t>(kFineChunk, gs[k + 1] - e0), tmp + e0,
                tsub + e0, cursor + d.bin0 + b0, order);
 }
 

@@ -499,11 +499,11 @@ stt_status bin_templates(stt_ctx *c, const MapP &m, const GenP &g, const Trk *tr
                        nbins, totals, bins, ccnt);
     hipLaunchKernelGGL(k_bin_scan, dim3(1 + (unsigned)ngroups), dim3(256), 0, c->stream, (const uint32_t *)totals, nbins,
                        cursor, gstart, fitem, ccnt, (int)bgrid);
-    hipLaunchKernelGGL(k_bin_group, dim3(bgrid), dim3(256), 0, c->stream, n, ngroups, (const uint16_t *)bins,
+    hipLaunchKernelGGL(k_bin_group, dim3(bgrid), dim3(kScatterWG), 0, c->stream, n, ngroups, (const uint16_t *)bins,
                        (const uint32_t *)gstart, (const uint32_t *)ccnt, tmp, tsub);
     // a group of c templates has ceil(c / kFineChunk) chunks: at most ceil(n / kFineChunk) + ngroups in all
     ev_attach(c, -1, 3);
-    launch_ev(c, k_bin_fine, dim3((unsigned)((n + kFineChunk - 1) / kFineChunk) + (unsigned)ngroups), dim3(256), 0,
+    launch_ev(c, k_bin_fine, dim3((unsigned)((n + kFineChunk - 1) / kFineChunk) + (unsigned)ngroups), dim3(kScatterWG), 0,
               nbins, (const uint32_t *)gstart, (const uint32_t *)fitem, cursor, (const uint32_t *)tmp,
               (const uint8_t *)tsub, order);
     STT_HIP(c, hipGetLastError());
@@ -1644,10 +1644,10 @@ stt_status stt_score_batch(stt_ctx *c, const stt_map *maps_host, int32_t n_maps,
                 hipLaunchKernelGGL(k_bin_scan_batch, dim3((unsigned)(max_groups + 1) * (unsigned)n_maps), dim3(256), 0,
                                    st, (const BatchMap *)dmaps, (const uint32_t *)dchunk, max_groups,
                                    (const uint32_t *)totals, cursor, gstart, fitem, ccnt);
-                hipLaunchKernelGGL(k_bin_group_batch, dim3((unsigned)nchunks), dim3(256), 0, st,
+                hipLaunchKernelGGL(k_bin_group_batch, dim3((unsigned)nchunks), dim3(kScatterWG), 0, st,
                                    (const BatchMap *)dmaps, n_maps, (const uint32_t *)dchunk, (const uint16_t *)bins,
                                    (const uint32_t *)gstart, (const uint32_t *)ccnt, tmp, tsub);
-                hipLaunchKernelGGL(k_bin_fine_batch, dim3((unsigned)nfine), dim3(256), 0, st,
+                hipLaunchKernelGGL(k_bin_fine_batch, dim3((unsigned)nfine), dim3(kScatterWG), 0, st,
                                    (const BatchMap *)dmaps, n_maps, (const uint32_t *)dfine,
                                    (const uint32_t *)gstart, (const uint32_t *)fitem, cursor, (const uint32_t *)tmp,
                                    (const uint8_t *)tsub, order);
